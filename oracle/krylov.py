@@ -1,0 +1,122 @@
+"""Restarted (F)GMRES and block-Jacobi (oracle; test infrastructure only).
+
+Section 3.1 / 4.4: restarted GMRES(m) with Arnoldi (classical or modified
+Gram-Schmidt), Hessenberg reduction by Givens rotations and back substitution;
+the update x += V y (here x += Z y for the flexible, right-preconditioned form).
+Sections 3.2 / 4.5: block-Jacobi inverts the diagonal face blocks K_ff and
+applies z_f = P_f^{-1} y_f face by face.
+
+The paper preconditions on the left; the GPU path uses right-preconditioned
+FGMRES so that the stopping test sees the true residual. Both are here:
+`fgmres` (right) is the parity reference, `gmres_left` the paper's form.
+"""
+import numpy as np
+
+
+def bj_inverses(K):
+    """P_f^{-1} for every face: inverse of the slot-0 block. K is [f][s][col][row];
+    the result is stored the same way, [f][col][row]."""
+    nf = K.shape[0]
+    out = np.zeros((nf,) + K.shape[2:])
+    for f in range(nf):
+        Kff = K[f, 0].T                      # [row][col]
+        out[f] = np.linalg.inv(Kff).T
+    return out
+
+
+def bj_apply(Binv, y):
+    nf, nb, _ = Binv.shape
+    Y = y.reshape(nf, nb)
+    return np.einsum("fcr,fc->fr", Binv, Y).reshape(-1)
+
+
+def _orth(V, w, j, method):
+    """Orthogonalise w against V[:j+1]; returns coefficients h (j+1,) and w."""
+    if method == "mgs":
+        h = np.zeros(j + 1)
+        for i in range(j + 1):
+            h[i] = V[i] @ w
+            w = w - h[i] * V[i]
+        return h, w
+    h = V[:j + 1] @ w
+    w = w - V[:j + 1].T @ h
+    if method == "cgs2":
+        h2 = V[:j + 1] @ w
+        w = w - V[:j + 1].T @ h2
+        h = h + h2
+    return h, w
+
+
+def _givens(a, b):
+    if b == 0.0:
+        return 1.0, 0.0
+    r = np.hypot(a, b)
+    return a / r, b / r
+
+
+def fgmres(matvec, b, prec=None, x0=None, restart=50, rtol=1e-10, atol=0.0, max_iters=1000,
+           orth="cgs2", hist=None):
+    """Right-preconditioned flexible GMRES(m). Stops when the true residual
+    ||b - K x|| <= max(rtol ||b||, atol), checked at every restart and whenever the
+    Givens estimate says so. Returns (x, info dict)."""
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.copy()
+    prec = prec if prec is not None else (lambda v: v)
+    bnorm = np.linalg.norm(b)
+    target = max(rtol * bnorm, atol)
+    its = 0
+    cycles = 0
+    while True:
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+        if hist is not None:
+            hist.append(beta)
+        if beta <= target or its >= max_iters:
+            return x, dict(iters=its, cycles=cycles, converged=beta <= target, resid=beta / bnorm)
+        cycles += 1
+        m = restart
+        V = np.zeros((m + 1, n))
+        Z = np.zeros((m, n))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for j in range(m):
+            Z[j] = prec(V[j])
+            w = matvec(Z[j])
+            h, w = _orth(V, w, j, orth)
+            H[:j + 1, j] = h
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = _givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            k = j + 1
+            if hist is not None:
+                hist.append(abs(g[j + 1]))
+            if abs(g[j + 1]) <= target or its >= max_iters:
+                break
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        x = x + Z[:k].T @ y
+
+
+def gmres_left(matvec, b, prec, restart=50, rtol=1e-6, max_iters=1000, orth="cgs"):
+    """Left-preconditioned GMRES(m) as the paper states it (Section 3.1):
+    GMRES on P^{-1} K x = P^{-1} b, stopping on the preconditioned residual."""
+    op = lambda v: prec(matvec(v))
+    pb = prec(b)
+    x, info = fgmres(op, pb, None, None, restart, rtol, 0.0, max_iters, orth)
+    return x, info

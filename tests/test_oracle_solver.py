@@ -1,0 +1,148 @@
+"""Pins of the oracle's Krylov solver and preconditioners against mathematics.
+
+FGMRES: identity in one iteration, termination within N iterations with a full
+Krylov space, monotone residual estimates within a cycle, agreement with a
+direct solve. Block-Jacobi: P_f^{-1} K_ff = I. Polynomial preconditioner
+(Section 4.7): closed form on diagonal matrices, the residual polynomial
+vanishing at every harmonic Ritz value, p(B) = B^{-1} when P = N, the
+harmonic Ritz values as roots of the GMRES(P) residual polynomial, the
+real paired recurrence equal to the complex product form. Chebyshev: the
+textbook error bound on an SPD diagonal matrix.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle
+from oracle import krylov, poly
+from workloads import configs
+
+from helpers import oracle_pipeline
+
+
+def test_fgmres_identity_one_iteration():
+    b = np.random.default_rng(0).standard_normal(50)
+    x, info = krylov.fgmres(lambda v: v, b, rtol=1e-13)
+    assert info["iters"] == 1 and info["converged"]
+    assert np.allclose(x, b, atol=1e-14)
+
+
+@pytest.mark.parametrize("orth", ["mgs", "cgs", "cgs2"])
+def test_fgmres_full_space_terminates(orth):
+    rng = np.random.default_rng(1)
+    N = 30
+    A = rng.standard_normal((N, N)) + N * np.eye(N) * 0.3
+    b = rng.standard_normal(N)
+    hist = []
+    x, info = krylov.fgmres(lambda v: A @ v, b, restart=N, rtol=1e-12, orth=orth, hist=hist)
+    assert info["converged"] and info["iters"] <= N
+    assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
+    est = hist[1:info["iters"] + 1]
+    assert all(est[i + 1] <= est[i] * (1 + 1e-12) for i in range(len(est) - 1))
+
+
+def test_fgmres_bj_matches_direct_on_c1():
+    pb = configs.c1()
+    out = oracle_pipeline(pb)
+    A = out["A"]
+    Binv = krylov.bj_inverses(out["K"])
+    for f in range(out["K"].shape[0]):
+        assert np.allclose(Binv[f].T @ out["K"][f, 0].T, np.eye(pb.nb), atol=1e-12)
+    x, info = krylov.fgmres(lambda v: A @ v, out["r"], prec=lambda v: krylov.bj_apply(Binv, v),
+                            restart=50, rtol=1e-12)
+    assert info["converged"]
+    assert np.linalg.norm(x - out["x"]) <= 1e-10 * np.linalg.norm(out["x"])
+
+
+def test_pp_diagonal_closed_form():
+    lam = np.linspace(0.5, 4.0, 40)
+    theta = poly.leja_order(np.array([0.7, 1.5, 2.5 + 0.3j, 2.5 - 0.3j, 3.6]))
+    y = np.random.default_rng(2).standard_normal(40)
+    z = poly.apply_product(lambda v: lam * v, theta, y)
+    assert np.allclose(z, poly.p_scalar(theta, lam).real * y, rtol=1e-12, atol=1e-13)
+    # 1 - lam p(lam) = prod (1 - lam/theta_j) vanishes at every theta_j
+    assert np.abs(1 - theta * poly.p_scalar(theta, theta)).max() < 1e-12
+    assert np.abs(poly.residual_poly(theta, theta)).max() < 1e-12
+
+
+def test_pp_full_degree_is_exact_inverse():
+    rng = np.random.default_rng(3)
+    N = 12
+    Bm = rng.standard_normal((N, N)) * 0.2 + np.diag(np.linspace(1, 3, N))
+    H, V = poly.arnoldi_mgs(lambda v: Bm @ v, rng.standard_normal(N), N)
+    th = poly.leja_order(poly.harmonic_ritz(H))
+    ev = np.sort_complex(np.linalg.eigvals(Bm))
+    assert np.allclose(np.sort_complex(th), ev, atol=1e-8)
+    y = rng.standard_normal(N)
+    z = poly.apply_product(lambda v: Bm @ v, th, y)
+    assert np.allclose(z, np.linalg.solve(Bm, y), rtol=1e-8, atol=1e-9)
+
+
+def test_harmonic_ritz_are_gmres_residual_roots():
+    rng = np.random.default_rng(4)
+    N, P = 60, 8
+    Bm = rng.standard_normal((N, N)) * 0.1 + np.diag(np.linspace(1, 5, N))
+    v = rng.standard_normal(N)
+    H, V = poly.arnoldi_mgs(lambda u: Bm @ u, v, P)
+    th = poly.harmonic_ritz(H)
+    # || pi(B) v || equals the GMRES(P) residual norm min_y || beta e1 - H y ||
+    r = v.astype(complex)
+    for t in th:
+        r = r - (Bm @ r) / t
+    beta = np.linalg.norm(v)
+    e1 = np.zeros(P + 1)
+    e1[0] = beta
+    y, *_ = np.linalg.lstsq(H, e1, rcond=None)
+    gm = np.linalg.norm(e1 - H @ y)
+    assert abs(np.linalg.norm(r) - gm) < 1e-10 * beta
+
+
+def test_paired_real_recurrence_equals_product_form():
+    rng = np.random.default_rng(5)
+    N = 40
+    Bm = rng.standard_normal((N, N)) * 0.1 + np.diag(np.linspace(1, 4, N))
+    H, V = poly.arnoldi_mgs(lambda u: Bm @ u, rng.standard_normal(N), 10)
+    th = poly.leja_order(poly.harmonic_ritz(H))
+    assert np.any(th.imag != 0)
+    y = rng.standard_normal(N)
+    # real recurrence: w += q/theta, q -= Bq/theta; pairs: w += (2a q - Bq)/|t|^2,
+    # q -= (2a/|t|^2) Bq - (1/|t|^2) B^2 q
+    q, w = y.copy(), np.zeros(N)
+    j = 0
+    while j < len(th):
+        t = th[j]
+        last = (j + (2 if t.imag != 0 else 1)) >= len(th)
+        if t.imag == 0:
+            w = w + q / t.real
+            if not last:
+                q = q - (Bm @ q) / t.real
+            j += 1
+        else:
+            a, m2 = t.real, abs(t) ** 2
+            Bq = Bm @ q
+            w = w + (2 * a * q - Bq) / m2
+            if not last:
+                q = q - (2 * a / m2) * Bq + (Bm @ Bq) / m2
+            j += 2
+    z = poly.apply_product(lambda u: Bm @ u, th, y)
+    assert np.allclose(w, z, rtol=1e-11, atol=1e-12)
+
+
+def test_chebyshev_bound_spd_diagonal():
+    lam = np.linspace(1.0, 100.0, 200)
+    b = np.random.default_rng(6).standard_normal(200)
+    for P in (3, 6, 10):
+        x = poly.chebyshev(lambda v: lam * v, b, 1.0, 100.0, P)
+        # residual after P iterates: b - A x_P; bound 2 ((sqrt(k)-1)/(sqrt(k)+1))^P
+        kap = 100.0
+        bound = 2 * ((np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)) ** P
+        assert np.linalg.norm(b - lam * x) <= bound * np.linalg.norm(b) * (1 + 1e-12)
+
+
+def test_leja_keeps_pairs_adjacent_and_starts_at_max_modulus():
+    th = np.array([1.0, 2 + 1j, 2 - 1j, 0.5, 3.0])
+    o = poly.leja_order(th)
+    assert abs(o[0]) == max(abs(th))
+    for k, t in enumerate(o):
+        if t.imag > 0:
+            assert o[k + 1] == np.conj(t)
