@@ -1,0 +1,264 @@
+"""Benchmark of the HDG hot path on one MI355X.
+
+A step is one pass of the whole hot path over the resident element blocks of the
+3D linear-elasticity workload (unit cube, 24^3 hexes jittered +-0.05h, p=3,
+16 dofs/face x 3 components, 288x288 element Schur blocks):
+  condensation -> face assembly -> FGMRES(50)+block-Jacobi to rtol 1e-8 -> recovery.
+The headline value is the mixed-precision step (FP32 matrix and block inverses in
+the Krylov cycles, FP64 residual/Arnoldi/Givens/update); the FP64 step, the solve
+times and the block-matvec bandwidth are reported next to it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "time-to-1e-8 solve + block-matvec HBM GB/s, mixed-precision vs FP64, 1 GPU"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def gen_blocks(pb, chunk=256):
+    import torch
+    d = pb.dims()
+    ne = d["ne"]
+    M, D, P, PF, L = d["ncomp"], d["dim"], d["npe"], d["npf"], d["nlfe"]
+    nu, nq, nt = M * P, M * D * P, L * M * PF
+    shapes = dict(Minv=(P, P), Bd=(D, P, P), Cd=(D, P, L * PF), D=(nu, nq), E=(nu, nu), F=(nu, nt), G=(nt, nq),
+                  H=(nt, nu), J=(nt, nt), ru=(nu,), rt=(nt,))
+    blk = {k: torch.empty((ne,) + s, dtype=torch.float64, device="cuda") for k, s in shapes.items()}
+    for e0 in range(0, ne, chunk):
+        e1 = min(ne, e0 + chunk)
+        b = pb.element_blocks(e0, e1)
+        for k in blk:
+            blk[k][e0:e1].copy_(b[k])
+        del b
+    torch.cuda.synchronize()
+    return blk
+
+
+def matvec_bytes(nbr_np, nb, wbytes):
+    """Algorithmic bytes of one block matvec: non-empty K blocks, nbr, x once, y once."""
+    import numpy as np
+    nf, S = nbr_np.shape
+    nblocks = int((nbr_np >= 0).sum())
+    return nblocks * nb * nb * wbytes + nf * S * 4 + 2 * nf * nb * 8
+
+
+def time_matvec(ctx, pl, precision, reps=100):
+    import torch
+    x = torch.randn(pl.x.numel(), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    K64 = pl.K64 if precision == "fp64" else None
+    K32 = pl.K32 if precision == "mixed" else None
+    for _ in range(3):
+        ctx.matvec(pl.dims, K64, K32, pl.nbr, x, y, precision)
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ctx.matvec(pl.dims, K64, K32, pl.nbr, x, y, precision)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(pb, blk, pl, iters, budget_s=20.0):
+    """The FP64 oracle timed on the host on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle import krylov
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    d = pb.dims()
+    ne, nf = d["ne"], d["nf"]
+    nb = d["ncomp"] * d["npf"]
+    # condensation: dense solve per element
+    def sample(n):
+        return {k: v[:n].cpu().numpy() for k, v in blk.items()}
+    s = sample(2)
+    t = time.perf_counter()
+    oracle.condense.condense(s, d)
+    t_el = (time.perf_counter() - t) / 2
+    n_el = int(max(2, min(ne, (0.5 * budget_s) / max(t_el, 1e-6))))
+    s = sample(n_el)
+    t = time.perf_counter()
+    oracle.condense.condense(s, d)
+    t_el = (time.perf_counter() - t) / n_el
+    # recovery costs the same dense solve per element
+    s1 = {k: v[:2] for k, v in s.items()}
+    t = time.perf_counter()
+    oracle.condense.recover(s1, np.zeros(nf * nb), pb.mesh.e2f, d, elems=[0, 1])
+    t_rec = (time.perf_counter() - t) / 2
+    # one FGMRES iteration: CSR matvec (sampled face rows, scaled), block-Jacobi, CGS2 at j = 25
+    nfs = min(nf, 2000)
+    K = pl.K64[:nfs].cpu().numpy()
+    nbr = pl.nbr[:nfs].cpu().numpy().astype(np.int64)
+    A = oracle.assemble.to_sparse(K, nbr, n_col_faces=nf)
+    x = np.random.default_rng(0).standard_normal(nf * nb)
+    t = time.perf_counter()
+    for _ in range(5):
+        A @ x
+    t_mv = (time.perf_counter() - t) / 5 * nf / nfs
+    Binv = krylov.bj_inverses(K[:200])
+    t = time.perf_counter()
+    krylov.bj_apply(Binv, x[:200 * nb])
+    t_bj = (time.perf_counter() - t) * nf / 200
+    V = np.random.default_rng(1).standard_normal((26, nf * nb))
+    t = time.perf_counter()
+    krylov._orth(V, x.copy(), 24, "cgs2")
+    t_orth = time.perf_counter() - t
+    t_iter = t_mv + t_bj + t_orth
+    total = ne * (t_el + t_rec) + iters * t_iter
+    return {"value": total, "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"dense-solve condensation of {n_el} elements ({t_el * 1e3:.2f} ms/element) and recovery "
+                       f"of 2 elements scaled to {ne}; one FGMRES iteration = CSR matvec on {nfs} face rows "
+                       f"scaled to {nf} ({t_mv:.3f} s) + block-Jacobi on 200 faces scaled ({t_bj:.3f} s) + CGS2 at "
+                       f"j=25 ({t_orth:.3f} s), times the GPU's {iters} iterations; FP64 numpy/scipy")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=24, help="hexes per direction")
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the hot path is "
+              f"single-GPU; multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2512_13619_amd import hdg
+    from paper_2512_13619_amd.pipeline import Pipeline
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    pb = configs.c2(n=args.n, p=args.p, device="cuda")
+    d = pb.dims()
+    log("workload", d)
+    blk = gen_blocks(pb)
+    log(f"element blocks resident: {sum(v.numel() for v in blk.values()) * 8 / 1e9:.1f} GB "
+        f"({time.perf_counter() - t0:.1f} s)")
+    ctx = hdg.Context(0)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    stream = torch.cuda.current_stream()
+
+    def step(precision):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        pl.condense(blk)
+        ev[1].record(stream)
+        pl.assemble()
+        ev[2].record(stream)
+        st = pl.solve(restart=50, max_iters=20000, rtol=1e-8, prec="bj", orth="cgs2", precision=precision)
+        ev[3].record(stream)
+        pl.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+        ev[4].record(stream)
+        torch.cuda.synchronize()
+        ph = dict(condense=ev[0].elapsed_time(ev[1]) / 1e3, assemble=ev[1].elapsed_time(ev[2]) / 1e3,
+                  solve=ev[2].elapsed_time(ev[3]) / 1e3, recover=ev[3].elapsed_time(ev[4]) / 1e3)
+        if not st["converged"]:
+            raise RuntimeError(f"{precision} solve did not converge: {st}")
+        return st, ph
+
+    for _ in range(args.warmup):
+        st, ph = step("mixed")
+        log("warmup mixed", st["iters"], ph)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    phs = []
+    for _ in range(args.steps):
+        st, ph = step("mixed")
+        phs.append(ph)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - ts) / max(args.steps, 1)
+    st_mixed = st
+    ph_mixed = {k: float(np.mean([p[k] for p in phs])) for k in phs[0]} if phs else ph
+    log("mixed step", t_mixed, st_mixed["iters"], ph_mixed)
+    x_mixed = pl.x.clone()
+    t_fp64 = None
+    st64 = None
+    ph64 = None
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st64, ph64 = step("fp64")
+        torch.cuda.synchronize()
+        t_fp64 = time.perf_counter() - ts
+        log("fp64 step", t_fp64, st64["iters"], ph64)
+        dx = float(((x_mixed - pl.x).norm() / pl.x.norm()).item())
+    else:
+        dx = None
+    # block matvec bandwidth (live HIP-event timing on the library's stream)
+    nbr_np = pl.nbr.cpu().numpy()
+    nb = d["ncomp"] * d["npf"]
+    t_mv32 = time_matvec(ctx, pl, "mixed")
+    t_mv64 = time_matvec(ctx, pl, "fp64")
+    b32 = matvec_bytes(nbr_np, nb, 4)
+    b64 = matvec_bytes(nbr_np, nb, 8)
+    gbs32 = b32 / t_mv32 / 1e9
+    gbs64 = b64 / t_mv64 / 1e9
+    log(f"matvec fp32 {t_mv32 * 1e3:.3f} ms {gbs32:.0f} GB/s, fp64 {t_mv64 * 1e3:.3f} ms {gbs64:.0f} GB/s")
+    line = {
+        "metric": METRIC,
+        "value": t_mixed,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 matrix/f64 vectors (mixed)",
+        "data": "synthetic (seeded jittered mesh, manufactured elasticity load)",
+        "config": {"workload": f"3D linear elasticity E=1 nu=0.3, unit cube {args.n}^3 hexes jitter 0.05h, p={args.p}, "
+                               f"tau=1; FGMRES(50)+block-Jacobi rtol 1e-8",
+                   "ne": d["ne"], "nf": d["nf"], "ndof": d["nf"] * nb, "face_block": nb,
+                   "element_schur": pl.nt},
+        "solve_s_mixed": ph_mixed["solve"],
+        "phases_s_mixed": ph_mixed,
+        "iters_mixed": st_mixed["iters"],
+        "rel_resid_mixed": st_mixed["rel_resid_true"],
+        "step_s_fp64": t_fp64,
+        "solve_s_fp64": ph64["solve"] if ph64 else None,
+        "phases_s_fp64": ph64,
+        "iters_fp64": st64["iters"] if st64 else None,
+        "rel_resid_fp64": st64["rel_resid_true"] if st64 else None,
+        "mixed_vs_fp64_solution_reldiff": dx,
+        "matvec_fp32_GBs": gbs32,
+        "matvec_fp64_GBs": gbs64,
+        "matvec_fp32_ms": t_mv32 * 1e3,
+        "matvec_fp64_ms": t_mv64 * 1e3,
+        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs32 / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_face_op<float,float,256,false,0> (FP32 block matvec)",
+                     "bytes_per_launch": b32},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pb, blk, pl, st_mixed["iters"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

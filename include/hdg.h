@@ -1,0 +1,232 @@
+/*
+ * hdg.h -- C ABI of the MI355X (gfx950) HDG hot-path library (libhdg.so).
+ *
+ * The library implements the data-parallel hot path of an HDG solver:
+ *   (1) static condensation of element unknowns into element trace Schur
+ *       complements                          Section 2.3 (eq. 13-b, 13-c), Section 4.1-4.2 (eq. w15-w22)
+ *   (2) face-based assembly of the trace system in dense face blocks
+ *                                              Section 2.4, Section 4.2
+ *   (3) preconditioned restarted (F)GMRES on the face-block matrix with
+ *       block-Jacobi and polynomial (harmonic-Ritz/Leja or Chebyshev)
+ *       preconditioners                      Sections 3.1-3.4, 4.3-4.7
+ *   (4) local recovery of (du, dq)           Section 2.3 (recovery equation), eq. w19, eq. w16
+ *   (5) the Newton update                    Section 2.3 (Newton iterate), Section 4.4
+ *
+ * Conventions (all entry points):
+ *   - Array arguments are DEVICE pointers (gfx950 global memory) owned by the
+ *     caller, unless the name ends in _h (host memory). The library never frees
+ *     caller memory. It owns only the opaque context and its internal workspace.
+ *   - Arrays are C row-major (last index fastest) unless stated otherwise.
+ *   - Work is enqueued on the context's stream; entry points that must read a
+ *     device status (singular pivots, convergence) synchronise that stream.
+ *   - Errors: argument and shape errors are detected on the host before any
+ *     launch and leave every output untouched. A negative status is an error,
+ *     a positive status is a warning with valid outputs. hdg_last_error()
+ *     returns a message naming the offending element/face when there is one.
+ *     No C++ exception crosses this interface.
+ *   - A context is used by one host thread at a time.
+ *
+ * Dimensions (the paper's symbols): M components, D space dimensions, P_E
+ * element basis functions, P_F face basis functions, N_lfe faces per element.
+ *   nq = M*D*P_E, nu = M*P_E, nt = M*P_F*N_lfe, nb = M*P_F, S = 2*N_lfe - 1,
+ *   N_dof = nb * N_F.
+ * Dof orders: u (m, i) -> m*P_E + i; q (m, d, i) -> (m*D + d)*P_E + i;
+ *   element trace (l, m, j) -> (l*M + m)*P_F + j; face vector (m, j) -> m*P_F + j.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_ctx_s* hdg_ctx;
+
+typedef enum {
+    HDG_OK = 0,
+    HDG_NOT_CONVERGED = 1,      /* warning: solve stopped at max_iters; x holds the last iterate */
+    HDG_ERR_ARG = -1,           /* null pointer / bad option value */
+    HDG_ERR_SHAPE = -2,         /* inconsistent dimensions or unsupported size */
+    HDG_ERR_SINGULAR = -3,      /* zero or non-finite pivot (element or face named in hdg_last_error) */
+    HDG_ERR_NONFINITE = -4,     /* NaN/Inf in a residual or right-hand side */
+    HDG_ERR_HIP = -5,           /* HIP runtime error */
+    HDG_ERR_NOMEM = -6          /* device workspace allocation failed */
+} hdg_status;
+
+/* Mesh/space sizes: N_E, N_F, M, D, P_E, P_F, N_lfe (Section 2.4, Section 4.1). */
+typedef struct {
+    int32_t ne, nf, ncomp, dim, npe, npf, nlfe;
+} hdg_dims;
+
+/* Context. `device` is the HIP device ordinal; `hip_stream` a hipStream_t or NULL
+ * for the null stream. The context allocates its workspace lazily on that device. */
+hdg_status  hdg_create(hdg_ctx* out, int device, void* hip_stream);
+hdg_status  hdg_destroy(hdg_ctx ctx);
+hdg_status  hdg_set_stream(hdg_ctx ctx, void* hip_stream);
+const char* hdg_last_error(hdg_ctx ctx);
+/* Releases the context's cached device workspace (it is re-allocated on demand). */
+hdg_status  hdg_release_workspace(hdg_ctx ctx);
+
+/* ---------------------------------------------------------------------------
+ * (1) Static condensation -- Section 2.3 eq. 13-b/13-c, Section 4.1 eq. w15-w19,
+ *     Section 4.2 eq. w21-w22.
+ *
+ * Per element e (the caller may pass a chunk of elements by offsetting every
+ * pointer and setting ne_chunk):
+ *   Minv [ne][P_E][P_E]        inverse element mass matrix (M^e)^{-1}
+ *   Bd   [ne][D][P_E][P_E]     B_d[i][j] = int dphi_i/dx_d phi_j  (derivative on the test
+ *                              function: the q-equation reads M q_dm + B_d u_m + C_d uhat_m = 0)
+ *   Cd   [ne][D][P_E][N_lfe*P_F]  C_d[i][(l,j)] = -int_{face l} phi_i psi_j n_d
+ *   D [ne][nu][nq], E [ne][nu][nu], F [ne][nu][nt]     u-equation blocks
+ *   G [ne][nt][nq], H [ne][nt][nu], J [ne][nt][nt]     trace-equation blocks
+ *   ru [ne][nu], rt [ne][nt]                           right-hand sides (r_q = 0)
+ * The q block is A = I_{MD} (x) M^e and B, C are component-diagonal (eq. w16).
+ *
+ * Computes  Ebar = E - D A^{-1} B,  Fbar = F - D A^{-1} C,  Hbar = H - G A^{-1} B,
+ *           Jbar = J - G A^{-1} C,  Kbar = Jbar - Hbar Ebar^{-1} Fbar,
+ *           rbar = rt - Hbar Ebar^{-1} ru.
+ * Outputs:
+ *   Kbar  [ne][nt][nt]   element trace Schur complement (row = trace test dof)
+ *   rbar  [ne][nt]
+ *   local [ne][nu][nu+nt+1]   factorised local solver for recovery: rows hold
+ *         [U | L^{-1} P Fbar | L^{-1} P ru] with P Ebar = L U (partial pivoting);
+ *         only the upper triangle of the first nu columns is meaningful.
+ * Errors: HDG_ERR_SINGULAR if some Ebar has a zero/non-finite pivot (first
+ * such element named). Synchronises the stream to read that status. */
+typedef struct {
+    const double *Minv, *Bd, *Cd, *D, *E, *F, *G, *H, *J, *ru, *rt;
+} hdg_elem_blocks;
+
+size_t     hdg_local_size(const hdg_dims* dims);   /* doubles per element of `local` */
+hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
+                        const hdg_elem_blocks* in, double* Kbar, double* rbar, double* local);
+
+/* ---------------------------------------------------------------------------
+ * (2) Face-block assembly -- Section 2.4, Section 4.2.
+ *
+ *   f2e  [nf][4]  (e1, l1, e2, l2); e2 = l2 = -1 on boundary faces. e1 < e2.
+ *   e2f  [ne][N_lfe]  global face of local face l of element e.
+ *   perm [ne][N_lfe][P_F] or NULL: element-local face dof holding canonical face
+ *        dof j (NULL = identity: element traces already in face order).
+ *   Kbar, rbar as produced by hdg_condense.
+ * Outputs (face f, slot s):
+ *   K64 [nf][S][nb][nb]  block coupling face f to face nbr[f][s], stored
+ *        COLUMN-major: K64[f][s][col][row] (the paper's order M x P_F x M x P_F x S x N_F,
+ *        first index fastest). Slot 0 = f itself (sum of both elements' diagonal
+ *        blocks); slots 1..N_lfe-1 = the other faces of e1 in local order; slots
+ *        N_lfe..2N_lfe-2 = the other faces of e2 (empty on boundary faces).
+ *   K32 [nf][S][nb][nb]  optional (NULL to skip) FP32 rounding of K64.
+ *   nbr [nf][S]  neighbour face per slot, -1 = empty slot (never read).
+ *   r   [nf][nb] assembled right-hand side. */
+hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
+                               const int32_t* f2e, const int32_t* e2f, const int32_t* perm,
+                               const double* Kbar, const double* rbar,
+                               double* K64, float* K32, int32_t* nbr, double* r);
+
+/* ---------------------------------------------------------------------------
+ * (3) Preconditioned restarted FGMRES on K x = r -- Sections 3.1-3.4, 4.3-4.7.
+ *
+ * Right-preconditioned flexible GMRES(restart): every cycle starts from the true
+ * FP64 residual r - K64 x; it stops when ||r - K64 x||_2 <= max(rtol*||r||_2, atol)
+ * or after max_iters Arnoldi steps. The Hessenberg/Givens update runs on the
+ * device in FP64; the host reads one status word per cycle.
+ *
+ * precision = HDG_FP64: every operator application uses K64 and FP64 inverses.
+ * precision = HDG_MIXED: inside a cycle the matvec and the preconditioner use K32
+ *   and FP32 block inverses (FP64 vectors and accumulation); the cycle-start
+ *   residual uses K64, so each restart is one step of iterative refinement.
+ *   K32 must then be non-NULL.
+ * prec: HDG_PREC_NONE, HDG_PREC_BJ (Section 4.5), HDG_PREC_BJ_POLY (BJ-PP(P):
+ *   z = p(B) M^{-1} y, B = M^{-1} K, harmonic Ritz values from one MGS Arnoldi
+ *   cycle of length poly_degree on B started at poly_v0, Leja order, Section 4.7),
+ *   HDG_PREC_BJ_CHEB (Chebyshev acceleration of degree poly_degree on B over a real
+ *   interval estimated from the same Ritz values).
+ * poly_v0: device vector [N_dof], the random Arnoldi start (required for the
+ *   polynomial preconditioners; the caller draws it so both sides of a parity
+ *   test use the same vector).
+ * x: on entry the initial guess, on exit the solution.
+ * Returns HDG_NOT_CONVERGED (positive) when max_iters is reached. */
+enum { HDG_PREC_NONE = 0, HDG_PREC_BJ = 1, HDG_PREC_BJ_POLY = 2, HDG_PREC_BJ_CHEB = 3 };
+enum { HDG_ORTH_CGS2 = 0, HDG_ORTH_CGS = 1, HDG_ORTH_MGS = 2 };
+enum { HDG_FP64 = 0, HDG_MIXED = 1 };
+
+typedef struct {
+    int32_t restart;            /* Krylov dimension m (1..200), default 50 */
+    int32_t max_iters;          /* Arnoldi steps over all cycles, default 1000 */
+    double  rtol, atol;
+    int32_t prec;               /* HDG_PREC_* */
+    int32_t poly_degree;        /* P (1..64) for BJ_POLY / BJ_CHEB */
+    const double* poly_v0;      /* device [N_dof]; required for BJ_POLY / BJ_CHEB */
+    int32_t orth;               /* HDG_ORTH_* */
+    int32_t precision;          /* HDG_FP64 or HDG_MIXED */
+    double* resid_hist_h;       /* host, optional: ||r|| at each cycle start and Givens estimates */
+    int32_t resid_hist_len;
+} hdg_solve_opts;
+
+typedef struct {
+    int32_t iters, cycles, converged, npoly;
+    double  rel_resid_true;     /* ||r - K64 x|| / ||r||, FP64 */
+    double  rel_resid_est;      /* last Givens estimate / ||r|| */
+    double  t_setup, t_total;   /* seconds (host clock around the stream work) */
+    double  theta_re[64], theta_im[64];   /* Leja-ordered Ritz values (polynomial preconditioners) */
+    int32_t hist_len;           /* entries written to resid_hist_h */
+} hdg_solve_stats;
+
+void       hdg_solve_opts_default(hdg_solve_opts* opts_h);
+hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims,
+                           const double* K64, const float* K32, const int32_t* nbr,
+                           const double* r, double* x,
+                           const hdg_solve_opts* opts_h, hdg_solve_stats* stats_h);
+
+/* ---------------------------------------------------------------------------
+ * (4) Local recovery -- Section 2.3 (recovery equation), eq. w19, eq. w16.
+ *   du^e = Ebar^{-1}(r_u - Fbar uhat^e),  dq_{m,d} = -Minv (B_d du_m + C_d uhat_m)
+ * from `local` (hdg_condense), Minv/Bd/Cd (as for hdg_condense), e2f/perm (as for
+ * hdg_assemble_blocks) and the face solution xhat [nf][nb].
+ * Outputs du [ne][nu], dq [ne][nq]. */
+hdg_status hdg_recover_local(hdg_ctx ctx, const hdg_dims* dims, const double* local,
+                             const double* Minv, const double* Bd, const double* Cd,
+                             const int32_t* e2f, const int32_t* perm, const double* xhat,
+                             double* du, double* dq);
+
+/* (5) Newton update state += alpha * delta over n entries -- Section 2.3, Section 4.4. */
+hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double* delta, double* state);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks exposed for tests and benchmarks (same kernels as the solver).
+ *
+ * hdg_matvec: y = K x with K64 (precision HDG_FP64) or K32 (HDG_MIXED) -- Section 4.3.
+ * hdg_bj_setup: block-Jacobi inverses Binv64 [nf][nb][nb] (column-major like K) and,
+ *   if Binv32 != NULL, their FP32 rounding -- Section 4.5. HDG_ERR_SINGULAR names the face.
+ * hdg_bj_apply: z_f = P_f^{-1} y_f with Binv64 or Binv32 -- Section 4.5.
+ * hdg_poly_apply: z = p(B) M^{-1} y for given Leja-ordered Ritz values (host arrays;
+ *   conjugate pairs adjacent, positive imaginary part first) -- Section 4.7.
+ */
+hdg_status hdg_matvec(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
+                      const int32_t* nbr, int32_t precision, const double* x, double* y);
+hdg_status hdg_bj_setup(hdg_ctx ctx, const hdg_dims* dims, const double* K64,
+                        double* Binv64, float* Binv32);
+hdg_status hdg_bj_apply(hdg_ctx ctx, const hdg_dims* dims, const double* Binv64, const float* Binv32,
+                        int32_t precision, const double* y, double* z);
+hdg_status hdg_poly_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
+                          const int32_t* nbr, const double* Binv64, const float* Binv32,
+                          int32_t precision, int32_t npoly, const double* theta_re_h,
+                          const double* theta_im_h, const double* y, double* z);
+
+/* Host-only helpers (no device work; usable without a GPU) -- Section 4.7.
+ * hdg_hessenberg_eigvals: eigenvalues of an n x n upper Hessenberg matrix H (row-major,
+ *   leading dimension ld) by the shifted QR algorithm; returns 0 on success.
+ * hdg_harmonic_ritz: from H_{P+1,P} (row-major (P+1) x P) the harmonic Ritz values
+ *   (eigenvalues of H_P + h_{P+1,P}^2 H_P^{-T} e_P e_P^T) in Leja order with conjugate
+ *   pairs adjacent; values below drop_rel * max|theta| are dropped. Writes *n_out. */
+int hdg_hessenberg_eigvals(int n, const double* H_h, int ld, double* wr_h, double* wi_h);
+int hdg_harmonic_ritz(int P, const double* H_h, double drop_rel,
+                      double* theta_re_h, double* theta_im_h, int* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

@@ -90,9 +90,12 @@ def assemble(Kbar, rbar, f2e, e2f, dims, perm=None):
     return K, nbr, r
 
 
-def to_sparse(K, nbr):
-    """scipy CSR matrix of the face-block system (row block f, column block nbr[f][s])."""
+def to_sparse(K, nbr, n_col_faces=None):
+    """scipy CSR matrix of the face-block system (row block f, column block nbr[f][s]).
+
+    K/nbr may hold a subset of face rows; n_col_faces then gives the column count."""
     nf, S, nb, _ = K.shape
+    ncf = nf if n_col_faces is None else n_col_faces
     rows, cols, vals = [], [], []
     rr, cc = np.meshgrid(np.arange(nb), np.arange(nb), indexing="ij")
     for f in range(nf):
@@ -107,7 +110,7 @@ def to_sparse(K, nbr):
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(nf * nb, nf * nb))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf * nb, ncf * nb))
 
 
 def uncondensed_system(blk, e2f, dims, perm=None):

@@ -1,0 +1,55 @@
+"""Compile libhdg.so for gfx950 with hipcc (in-tree, next to this file)."""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libhdg.so")
+SOURCES = ["k_face.hip", "k_krylov.hip", "k_bj.hip", "k_assemble.hip", "k_recover.hip", "k_condense.hip",
+           "solver.cpp", "ritz.cpp", "abi.cpp"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result",
+         "-Wno-unknown-pragmas"]
+
+
+def _compile(src):
+    obj = os.path.join(BUILD, src + ".o")
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, r
+
+
+def build(verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        results = list(ex.map(_compile, SOURCES))
+    objs = []
+    failed = False
+    for src, obj, r in results:
+        msg = (r.stdout + r.stderr).strip()
+        # the host pass does not know the device-only target feature: harmless
+        lines = [l for l in msg.splitlines() if "packed-fp32-ops" not in l and "not a recognized feature" not in l]
+        if r.returncode != 0:
+            failed = True
+            sys.stderr.write(f"[build] {src} failed:\n" + "\n".join(lines) + "\n")
+        elif verbose and lines:
+            sys.stderr.write(f"[build] {src}:\n" + "\n".join(lines) + "\n")
+        objs.append(obj)
+    if failed:
+        raise RuntimeError("libhdg build failed")
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("libhdg link failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

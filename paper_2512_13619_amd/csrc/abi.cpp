@@ -1,0 +1,318 @@
+// C ABI entry points of libhdg.so: argument validation on the host, then the
+// launchers. No C++ exception crosses this boundary.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <vector>
+
+#include "hdg_internal.hpp"
+
+hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const float* K32, const int32_t* nbr,
+                     const double* b, double* x, const hdg_solve_opts* o, hdg_solve_stats* stats);
+hdg_status poly_apply_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const float* K32, const int32_t* nbr,
+                          const double* B64, const float* B32, int precision, int npoly, const double* tre,
+                          const double* tim, const double* y, double* z);
+hdg_status op_apply_run(hdg_ctx ctx, const hdg_dims* d, const void* M1, bool m1_32, const int32_t* nbr, int S1,
+                        const double* x, double* y);
+
+void* ws_get(hdg_ctx ctx, WsSlot slot, size_t bytes, hdg_status* st) {
+    *st = HDG_OK;
+    if (bytes == 0) bytes = 64;
+    if (ctx->ws_bytes[slot] >= bytes) return ctx->ws[slot];
+    if (ctx->ws[slot]) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->ws[slot]);
+        ctx->ws[slot] = nullptr;
+        ctx->ws_bytes[slot] = 0;
+    }
+    void* p = nullptr;
+    const size_t rounded = (bytes + 4095) / 4096 * 4096;
+    if (hipMalloc(&p, rounded) != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        ctx->err = "device workspace allocation of " + std::to_string(rounded) + " bytes failed";
+        *st = HDG_ERR_NOMEM;
+        return nullptr;
+    }
+    ctx->ws[slot] = p;
+    ctx->ws_bytes[slot] = rounded;
+    return p;
+}
+
+namespace {
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                 \
+    }                                             \
+    catch (const std::bad_alloc&) {               \
+        ctx->err = "host allocation failed";      \
+        return HDG_ERR_NOMEM;                     \
+    }                                             \
+    catch (const std::exception& ex) {            \
+        ctx->err = ex.what();                     \
+        return HDG_ERR_ARG;                       \
+    }                                             \
+    catch (...) {                                 \
+        ctx->err = "unknown internal error";      \
+        return HDG_ERR_ARG;                       \
+    }
+
+hdg_status set_err(hdg_ctx ctx, hdg_status st, const char* msg) {
+    ctx->err = msg;
+    return st;
+}
+
+hdg_status check_dims(hdg_ctx ctx, const hdg_dims* d, bool need_elems, bool need_faces) {
+    if (!d) return set_err(ctx, HDG_ERR_ARG, "dims is NULL");
+    if (d->ncomp < 1 || d->dim < 1 || d->dim > 3 || d->npe < 1 || d->npf < 1 || d->nlfe < 2 || d->nlfe > 6)
+        return set_err(ctx, HDG_ERR_SHAPE, "dims: need ncomp>=1, 1<=dim<=3, npe>=1, npf>=1, 2<=nlfe<=6");
+    if (d->ne < 0 || d->nf < 0) return set_err(ctx, HDG_ERR_SHAPE, "dims: negative ne or nf");
+    if (need_elems && d->ne < 1) return set_err(ctx, HDG_ERR_SHAPE, "dims: ne must be >= 1");
+    if (need_faces && d->nf < 1) return set_err(ctx, HDG_ERR_SHAPE, "dims: nf must be >= 1");
+    if (d->ncomp * d->npf > 256) return set_err(ctx, HDG_ERR_SHAPE, "dims: face block edge M*P_F above 256");
+    return HDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hdg_status hdg_create(hdg_ctx* out, int device, void* hip_stream) {
+    if (!out) return HDG_ERR_ARG;
+    *out = nullptr;
+    hdg_ctx c = new (std::nothrow) hdg_ctx_s();
+    if (!c) return HDG_ERR_NOMEM;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        delete c;
+        return HDG_ERR_HIP;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return HDG_ERR_HIP;
+    }
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return HDG_OK;
+}
+
+hdg_status hdg_destroy(hdg_ctx ctx) {
+    if (!ctx) return HDG_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int s = 0; s < WS_NSLOTS; ++s)
+        if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
+    delete ctx;
+    return HDG_OK;
+}
+
+hdg_status hdg_set_stream(hdg_ctx ctx, void* hip_stream) {
+    if (!ctx) return HDG_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return HDG_OK;
+}
+
+const char* hdg_last_error(hdg_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hdg_status hdg_release_workspace(hdg_ctx ctx) {
+    if (!ctx) return HDG_ERR_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int s = 0; s < WS_NSLOTS; ++s) {
+        if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
+        ctx->ws[s] = nullptr;
+        ctx->ws_bytes[s] = 0;
+    }
+    return HDG_OK;
+}
+
+size_t hdg_local_size(const hdg_dims* d) {
+    if (!d) return 0;
+    const size_t nu = (size_t)d->ncomp * d->npe, nt = (size_t)d->nlfe * d->ncomp * d->npf;
+    return nu * (nu + nt + 1);
+}
+
+hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, const hdg_elem_blocks* in,
+                        double* Kbar, double* rbar, double* local) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, false);
+    if (st != HDG_OK) return st;
+    if (ne_chunk < 0) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk must be >= 0");
+    if (ne_chunk == 0) return HDG_OK;
+    if (ne_chunk > 0x7fffffff) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk too large");
+    if (!in || !in->Minv || !in->Bd || !in->Cd || !in->D || !in->E || !in->F || !in->G || !in->H || !in->J ||
+        !in->ru || !in->rt || !Kbar || !rbar || !local)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_condense: NULL input or output pointer");
+    if ((size_t)dims->ncomp * dims->npe > 4096)
+        return set_err(ctx, HDG_ERR_SHAPE, "hdg_condense: nu above 4096");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return condense_run(ctx, dims, ne_chunk, in, Kbar, rbar, local);
+    GUARD_END
+}
+
+hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const int32_t* e2f,
+                               const int32_t* perm, const double* Kbar, const double* rbar, double* K64, float* K32,
+                               int32_t* nbr, double* r) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, true, true);
+    if (st != HDG_OK) return st;
+    if (!f2e || !e2f || !Kbar || !rbar || !K64 || !nbr || !r)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_assemble_blocks: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return assemble_run(ctx, dims, f2e, e2f, perm, Kbar, rbar, K64, K32, nbr, r);
+    GUARD_END
+}
+
+hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
+                           const int32_t* nbr, const double* r, double* x, const hdg_solve_opts* o,
+                           hdg_solve_stats* stats) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    if (!o || !stats) return set_err(ctx, HDG_ERR_ARG, "hdg_gmres_solve: NULL opts or stats");
+    if (!K64 || !nbr || !r || !x) return set_err(ctx, HDG_ERR_ARG, "hdg_gmres_solve: NULL matrix/vector pointer");
+    if (o->restart < 1 || o->restart > 200) return set_err(ctx, HDG_ERR_ARG, "restart must be in [1, 200]");
+    if (o->max_iters < 0) return set_err(ctx, HDG_ERR_ARG, "max_iters must be >= 0");
+    if (!(o->rtol >= 0.0) || !(o->atol >= 0.0)) return set_err(ctx, HDG_ERR_ARG, "rtol/atol must be >= 0");
+    if (o->prec < HDG_PREC_NONE || o->prec > HDG_PREC_BJ_CHEB) return set_err(ctx, HDG_ERR_ARG, "unknown prec");
+    if (o->orth < HDG_ORTH_CGS2 || o->orth > HDG_ORTH_MGS) return set_err(ctx, HDG_ERR_ARG, "unknown orth");
+    if (o->precision != HDG_FP64 && o->precision != HDG_MIXED)
+        return set_err(ctx, HDG_ERR_ARG, "precision must be HDG_FP64 or HDG_MIXED");
+    if (o->precision == HDG_MIXED && !K32) return set_err(ctx, HDG_ERR_ARG, "mixed precision needs K32");
+    const bool poly = o->prec == HDG_PREC_BJ_POLY || o->prec == HDG_PREC_BJ_CHEB;
+    if (poly && (o->poly_degree < 1 || o->poly_degree > 64))
+        return set_err(ctx, HDG_ERR_ARG, "poly_degree must be in [1, 64]");
+    if (poly && !o->poly_v0) return set_err(ctx, HDG_ERR_ARG, "polynomial preconditioner needs poly_v0");
+    if (o->resid_hist_len > 0 && !o->resid_hist_h) return set_err(ctx, HDG_ERR_ARG, "resid_hist_h is NULL");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return solve_run(ctx, dims, K64, K32, nbr, r, x, o, stats);
+    GUARD_END
+}
+
+hdg_status hdg_recover_local(hdg_ctx ctx, const hdg_dims* dims, const double* local, const double* Minv,
+                             const double* Bd, const double* Cd, const int32_t* e2f, const int32_t* perm,
+                             const double* xhat, double* du, double* dq) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, false);
+    if (st != HDG_OK) return st;
+    if (dims->ne == 0) return HDG_OK;
+    if (!local || !Minv || !Bd || !Cd || !e2f || !xhat || !du || !dq)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_recover_local: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return recover_run(ctx, dims, local, Minv, Bd, Cd, e2f, perm, xhat, du, dq);
+    GUARD_END
+}
+
+hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double* delta, double* state) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    if (n < 0) return set_err(ctx, HDG_ERR_SHAPE, "n must be >= 0");
+    if (n == 0) return HDG_OK;
+    if (!delta || !state) return set_err(ctx, HDG_ERR_ARG, "hdg_newton_update: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return axpy_run(ctx, n, alpha, delta, state);
+    GUARD_END
+}
+
+hdg_status hdg_matvec(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32, const int32_t* nbr,
+                      int32_t precision, const double* x, double* y) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    const bool m32 = precision == HDG_MIXED;
+    if ((m32 ? (const void*)K32 : (const void*)K64) == nullptr || !nbr || !x || !y)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_matvec: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return op_apply_run(ctx, dims, m32 ? (const void*)K32 : (const void*)K64, m32, nbr, 2 * dims->nlfe - 1, x, y);
+    GUARD_END
+}
+
+hdg_status hdg_bj_setup(hdg_ctx ctx, const hdg_dims* dims, const double* K64, double* Binv64, float* Binv32) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    if (!K64 || !Binv64) return set_err(ctx, HDG_ERR_ARG, "hdg_bj_setup: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
+    if (!status) return st;
+    const int big = 0x7fffffff;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    st = bj_invert(ctx, dims->nf, dims->ncomp * dims->npf, 2 * dims->nlfe - 1, K64, Binv64, Binv32, status);
+    if (st != HDG_OK) return st;
+    int bad = big;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad != big) {
+        ctx->err = "block-Jacobi: zero or non-finite pivot in the diagonal block of face " + std::to_string(bad);
+        return HDG_ERR_SINGULAR;
+    }
+    return HDG_OK;
+    GUARD_END
+}
+
+hdg_status hdg_bj_apply(hdg_ctx ctx, const hdg_dims* dims, const double* Binv64, const float* Binv32,
+                        int32_t precision, const double* y, double* z) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    const bool m32 = precision == HDG_MIXED;
+    if ((m32 ? (const void*)Binv32 : (const void*)Binv64) == nullptr || !y || !z)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_bj_apply: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return op_apply_run(ctx, dims, m32 ? (const void*)Binv32 : (const void*)Binv64, m32, nullptr, 1, y, z);
+    GUARD_END
+}
+
+hdg_status hdg_poly_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
+                          const int32_t* nbr, const double* Binv64, const float* Binv32, int32_t precision,
+                          int32_t npoly, const double* tre, const double* tim, const double* y, double* z) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    const bool m32 = precision == HDG_MIXED;
+    if ((m32 ? (const void*)K32 : (const void*)K64) == nullptr || !nbr || !y || !z || y == z ||
+        (m32 ? (const void*)Binv32 : (const void*)Binv64) == nullptr)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_poly_apply: NULL or aliased pointer");
+    if (npoly < 0 || npoly > 64 || (npoly > 0 && (!tre || !tim)))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_poly_apply: npoly must be in [0, 64] with theta arrays");
+    for (int i = 0; i < npoly; ++i) {
+        if (tre[i] == 0.0 && tim[i] == 0.0) return set_err(ctx, HDG_ERR_ARG, "hdg_poly_apply: zero Ritz value");
+        if (tim[i] != 0.0 && (i + 1 >= npoly || tim[i] < 0.0 || tre[i + 1] != tre[i] || tim[i + 1] != -tim[i]))
+            return set_err(ctx, HDG_ERR_ARG, "hdg_poly_apply: complex values must come as adjacent (a+ib, a-ib)");
+        if (tim[i] != 0.0) ++i;
+    }
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return poly_apply_run(ctx, dims, K64, K32, nbr, Binv64, Binv32, precision, npoly, tre, tim, y, z);
+    GUARD_END
+}
+
+int hdg_hessenberg_eigvals(int n, const double* H_h, int ld, double* wr, double* wi) {
+    if (n < 1 || !H_h || !wr || !wi || ld < n) return -1;
+    try {
+        std::vector<double> H((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) H[(size_t)i * n + j] = (j >= i - 1) ? H_h[(size_t)i * ld + j] : 0.0;
+        return hessenberg_eigvals(n, H.data(), n, wr, wi);
+    } catch (...) {
+        return -3;
+    }
+}
+
+int hdg_harmonic_ritz(int P, const double* H_h, double drop_rel, double* tre, double* tim, int* n_out) {
+    if (P < 1 || !H_h || !tre || !tim || !n_out) return -1;
+    try {
+        return harmonic_ritz_leja(P, H_h, drop_rel, tre, tim, n_out);
+    } catch (...) {
+        return -3;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP translation units of libhdg.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "hdg.h"
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Context: stream, error text and a cache of device workspace buffers.
+enum WsSlot {
+    WS_T_BOTTOM = 0,   // condensation: bottom (trace) rows of the elimination matrix
+    WS_W,              // condensation: M^{-1}[B_d | C_d]
+    WS_STATUS,         // small int status words (singular element/face ...)
+    WS_BINV64,
+    WS_BINV32,
+    WS_KRYLOV_V,       // Arnoldi basis (m+1) x N
+    WS_KRYLOV_Z,       // preconditioned vectors m x N
+    WS_VEC,            // work vectors for the preconditioners
+    WS_PART,           // reduction partials
+    WS_CTL,            // GMRES device control block + Hessenberg/Givens state
+    WS_NSLOTS
+};
+
+struct hdg_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void* ws[WS_NSLOTS] = {};
+    size_t ws_bytes[WS_NSLOTS] = {};
+};
+
+// Returns a device buffer of at least `bytes` for `slot` (grows, never shrinks).
+void* ws_get(hdg_ctx ctx, WsSlot slot, size_t bytes, hdg_status* st);
+
+#define HDG_HIP_CHECK(ctx, call)                                                   \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            (ctx)->err = std::string("HIP error: ") + hipGetErrorString(e_) +      \
+                         " at " + __FILE__ + ":" + std::to_string(__LINE__);       \
+            return HDG_ERR_HIP;                                                    \
+        }                                                                          \
+    } while (0)
+
+#define HDG_LAUNCH_CHECK(ctx) HDG_HIP_CHECK(ctx, hipGetLastError())
+
+static inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Face-block operator (block matvec / block-Jacobi / fused polynomial step).
+//
+// For face f with neighbour slots s < S1 (nbr1 == nullptr: S1 = 1 and slot 0 = f):
+//   u_f = sum_s M1[f][s] x_{nbr1[f][s]}            (column-major nb x nb blocks)
+//   if M2: u_f <- M2[f] u_f                          (block-Jacobi after the product)
+// then for o = 0..2 with out[o] != nullptr:
+//   out[o]_f = s[o] u_f + a[o] X[o]_f + b[o] Y[o]_f  (X/Y may be nullptr = 0)
+// All outputs are computed from the inputs before any is written, so an output
+// may alias a face-local input (X or Y) but never the gathered vector x.
+struct FaceEpilogue {
+    double* out[3];
+    const double* X[3];
+    const double* Y[3];
+    double s[3], a[3], b[3];
+};
+
+hdg_status face_op(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1, bool m1_fp32,
+                   const int32_t* nbr1, const void* M2, bool m2_fp32, const double* x,
+                   const FaceEpilogue& epi, const int* skip_flag);
+
+// ---------------------------------------------------------------------------
+// Vector kernels (Krylov). `skip` (device flag, may be null): the kernel returns
+// at once when *skip != 0; `J_dev` (may be null) overrides J with a device value.
+hdg_status vec_multidot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* w, size_t n,
+                        double* part, int nblk, const int* skip);
+hdg_status vec_reduce(hdg_ctx ctx, const double* part, int J, int nblk, double* out, double* add_to,
+                      const int* skip);
+hdg_status vec_multiaxpy(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h, double sign,
+                         double* w, size_t n, const int* skip, const int* J_dev = nullptr);
+hdg_status vec_sumsq_partial(hdg_ctx ctx, const double* w, size_t n, double* part, int nblk, const int* skip);
+hdg_status vec_lincomb(hdg_ctx ctx, size_t n, double* out, double a, const double* X, double b,
+                       const double* Y, const int* skip);
+
+// GMRES device control block.
+struct GmresCtl {
+    int done;           // 1: stop the cycle (converged, breakdown or step budget)
+    int k;              // Arnoldi steps completed in this cycle
+    int jmax;           // step budget for this cycle
+    int nonfinite;
+    double target;      // absolute residual target
+    double beta;        // cycle-start residual norm
+    double est;         // latest Givens residual estimate
+    double pad;
+};
+hdg_status krylov_cycle_init(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, double* g,
+                             int jmax, double target);
+hdg_status krylov_scale_by(hdg_ctx ctx, double* v, const double* src, size_t n, const double* denom,
+                           const int* skip);
+hdg_status krylov_givens(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, double* H, int ldh,
+                         double* cs, double* sn, double* g, int j, double* hist);
+hdg_status krylov_backsolve(hdg_ctx ctx, const GmresCtl* ctl, const double* H, int ldh, const double* g,
+                            double* y);
+hdg_status krylov_store_norm(hdg_ctx ctx, const double* part, int nblk, double* dst);
+
+// ---------------------------------------------------------------------------
+// Block-Jacobi batched inverse (Gauss-Jordan with partial pivoting).
+hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, double* B64, float* B32,
+                     int* bad_face);
+
+// Condensation, assembly, recovery launchers.
+hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_elem_blocks* in,
+                        double* Kbar, double* rbar, double* local);
+hdg_status assemble_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* e2f,
+                        const int32_t* perm, const double* Kbar, const double* rbar, double* K64,
+                        float* K32, int32_t* nbr, double* r);
+hdg_status recover_run(hdg_ctx ctx, const hdg_dims* d, const double* local, const double* Minv,
+                       const double* Bd, const double* Cd, const int32_t* e2f, const int32_t* perm,
+                       const double* xhat, double* du, double* dq);
+hdg_status axpy_run(hdg_ctx ctx, int64_t n, double alpha, const double* x, double* y);
+
+// Host-side eigenvalues / harmonic Ritz values (ritz.cpp).
+int hessenberg_eigvals(int n, double* H, int ld, double* wr, double* wi);
+int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout);

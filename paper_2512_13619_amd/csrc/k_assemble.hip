@@ -1,0 +1,110 @@
+// Face-based assembly of the trace system (Section 4.2): each face is handled
+// by one workgroup that gathers the matching (nb x nb) blocks of the element
+// Schur complements of its one or two neighbours and writes the face's S slots
+// of K (column-major blocks) and its part of r. Every output entry has exactly
+// one writer, so there are no atomics and the result is deterministic.
+#include "hdg_internal.hpp"
+
+namespace {
+
+constexpr int BS = 256;
+
+__global__ __launch_bounds__(BS) void k_assemble(int nf, int M, int PF, int L, const int32_t* __restrict__ f2e,
+                                                 const int32_t* __restrict__ e2f, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ Kbar, const double* __restrict__ rbar,
+                                                 double* __restrict__ K64, float* __restrict__ K32,
+                                                 int32_t* __restrict__ nbr, double* __restrict__ r) {
+    const int nb = M * PF;
+    const int S = 2 * L - 1;
+    const int nt = L * nb;
+    const long long f = blockIdx.x;
+    if (f >= nf) return;
+    const int e1 = f2e[4 * f + 0], l1 = f2e[4 * f + 1];
+    const int e2 = f2e[4 * f + 2], l2 = f2e[4 * f + 3];
+    // slot -> (element, row local face, column local face)
+    __shared__ int se[64], slr[64], slc[64];
+    if (threadIdx.x == 0) {
+        int s = 0;
+        se[s] = e1; slr[s] = l1; slc[s] = l1; ++s;
+        for (int l = 0; l < L; ++l)
+            if (l != l1) { se[s] = e1; slr[s] = l1; slc[s] = l; ++s; }
+        for (int l = 0; l < L; ++l) {
+            if (e2 >= 0) {
+                if (l != l2) { se[s] = e2; slr[s] = l2; slc[s] = l; ++s; }
+            } else if (l != 0) {
+                se[s] = -1; slr[s] = 0; slc[s] = 0; ++s;
+            }
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < S; s += BS) {
+        int g = -1;
+        if (s == 0) g = (int)f;
+        else if (se[s] >= 0) g = e2f[(size_t)se[s] * L + slc[s]];
+        nbr[f * S + s] = g;
+    }
+    // local trace index of canonical face dof (m, j) on local face l of element e
+    auto tix = [&](int e, int l, int m, int j) -> int {
+        const int jl = perm ? perm[((size_t)e * L + l) * PF + j] : j;
+        return (l * M + m) * PF + jl;
+    };
+    const size_t blk = (size_t)nb * nb;
+    extern __shared__ double tile[];     // nb x (nb+1): row-major gather, column-major write
+    const int ldt = nb + 1;
+    for (int s = 0; s < S; ++s) {
+        const int e = se[s];
+        double* out = K64 + ((size_t)f * S + s) * blk;
+        float* out32 = K32 ? K32 + ((size_t)f * S + s) * blk : nullptr;
+        if (e < 0) {
+            for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
+                out[idx] = 0.0;
+                if (out32) out32[idx] = 0.0f;
+            }
+            continue;
+        }
+        // gather rows of the element block (consecutive threads read consecutive columns)
+        for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
+            const int rr = idx / nb, c = idx - rr * nb;
+            const int mr = rr / PF, jr = rr - mr * PF;
+            const int mc = c / PF, jc = c - mc * PF;
+            const double* Ke = Kbar + (size_t)e * nt * nt;
+            double v = Ke[(size_t)tix(e, slr[s], mr, jr) * nt + tix(e, slc[s], mc, jc)];
+            if (s == 0 && e2 >= 0) {
+                const double* K2 = Kbar + (size_t)e2 * nt * nt;
+                v += K2[(size_t)tix(e2, l2, mr, jr) * nt + tix(e2, l2, mc, jc)];
+            }
+            tile[rr * ldt + c] = v;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
+            const int c = idx / nb, rr = idx - c * nb;          // column-major: idx = c*nb + rr
+            const double v = tile[rr * ldt + c];
+            out[idx] = v;
+            if (out32) out32[idx] = (float)v;
+        }
+        __syncthreads();
+    }
+    for (int rr = threadIdx.x; rr < nb; rr += BS) {
+        const int m = rr / PF, j = rr - m * PF;
+        double v = rbar[(size_t)e1 * nt + tix(e1, l1, m, j)];
+        if (e2 >= 0) v += rbar[(size_t)e2 * nt + tix(e2, l2, m, j)];
+        r[f * nb + rr] = v;
+    }
+}
+
+}  // namespace
+
+hdg_status assemble_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* e2f,
+                        const int32_t* perm, const double* Kbar, const double* rbar, double* K64, float* K32,
+                        int32_t* nbr, double* r) {
+    if (d->nf == 0) return HDG_OK;
+    const int nb = d->ncomp * d->npf;
+    const size_t lds = sizeof(double) * (size_t)nb * (nb + 1);
+    if (lds > 64 * 1024)
+        HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_assemble, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds));
+    hipLaunchKernelGGL(k_assemble, dim3(d->nf), dim3(BS), lds, ctx->stream, d->nf, d->ncomp, d->npf, d->nlfe, f2e,
+                       e2f, perm, Kbar, rbar, K64, K32, nbr, r);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}

@@ -1,0 +1,98 @@
+// Block-Jacobi setup (Section 4.5): invert every diagonal face block K_ff by
+// Gauss-Jordan elimination with partial pivoting, one workgroup per face, the
+// augmented [K_ff | I] held in LDS. Inverses are written column-major like K
+// (Binv[f][col][row]) in FP64 and optionally rounded to FP32.
+#include <cmath>
+
+#include "hdg_internal.hpp"
+
+namespace {
+
+constexpr int BS = 256;
+
+__global__ __launch_bounds__(BS) void k_bj_invert(int nf, int nb, int S, const double* __restrict__ K,
+                                                  double* __restrict__ B64, float* __restrict__ B32,
+                                                  int* bad_face) {
+    extern __shared__ double sm[];
+    const int lda = 2 * nb + 1;          // odd stride: no LDS bank conflicts on column access
+    double* A = sm;                      // nb x (2nb) augmented, row-major
+    __shared__ int piv_s;
+    __shared__ double pval_s;
+    const long long f = blockIdx.x;
+    if (f >= nf) return;
+    const double* Kf = K + (size_t)f * S * nb * nb;   // slot 0, column-major
+    for (int idx = threadIdx.x; idx < nb * nb; idx += BS) {
+        const int c = idx / nb, r = idx - c * nb;
+        A[r * lda + c] = Kf[idx];
+        A[r * lda + nb + c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    bool singular = false;
+    for (int k = 0; k < nb; ++k) {
+        if (threadIdx.x < 64) {
+            double best = -1.0;
+            int bi = k;
+            for (int r = k + threadIdx.x; r < nb; r += 64) {
+                const double v = fabs(A[r * lda + k]);
+                if (v > best || (v == best && r < bi)) { best = v; bi = r; }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (threadIdx.x == 0) { piv_s = bi; pval_s = A[bi * lda + k]; }
+        }
+        __syncthreads();
+        const int p = piv_s;
+        double pv = pval_s;
+        if (!(fabs(pv) > 0.0) || !isfinite(pv)) { singular = true; pv = 1.0; }
+        if (p != k) {
+            for (int c = threadIdx.x; c < 2 * nb; c += BS) {
+                const double t = A[k * lda + c];
+                A[k * lda + c] = A[p * lda + c];
+                A[p * lda + c] = t;
+            }
+        }
+        __syncthreads();
+        const double inv = 1.0 / pv;
+        for (int c = threadIdx.x; c < 2 * nb; c += BS) A[k * lda + c] *= inv;
+        __syncthreads();
+        // eliminate column k from every other row
+        for (int idx = threadIdx.x; idx < nb * 2 * nb; idx += BS) {
+            const int r = idx / (2 * nb), c = idx - r * (2 * nb);
+            if (r == k || c == k) continue;
+            A[r * lda + c] -= A[r * lda + k] * A[k * lda + c];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < nb; r += BS)
+            if (r != k) A[r * lda + k] = 0.0;
+        __syncthreads();
+    }
+    if (singular && threadIdx.x == 0) atomicMin(bad_face, (int)f);
+    for (int idx = threadIdx.x; idx < nb * nb; idx += BS) {
+        const int c = idx / nb, r = idx - c * nb;
+        const double v = A[r * lda + nb + c];
+        B64[(size_t)f * nb * nb + idx] = v;
+        if (B32) B32[(size_t)f * nb * nb + idx] = (float)v;
+    }
+}
+
+}  // namespace
+
+hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, double* B64, float* B32,
+                     int* bad_face) {
+    if (nf == 0) return HDG_OK;
+    const size_t lds = sizeof(double) * (size_t)nb * (2 * nb + 1);
+    if (lds > 150 * 1024) {
+        ctx->err = "block-Jacobi: face block too large for LDS";
+        return HDG_ERR_SHAPE;
+    }
+    if (lds > 64 * 1024)
+        HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_bj_invert,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_bj_invert, dim3(nf), dim3(BS), lds, ctx->stream, nf, nb, S, K64, B64, B32, bad_face);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}

@@ -1,0 +1,272 @@
+// Krylov vector kernels: Gram-Schmidt multi-dot / multi-axpy, norms, and the
+// device-side Hessenberg/Givens update of GMRES (Section 4.4). The paper keeps
+// the Hessenberg system on the CPU; here one thread on the device performs the
+// same FP64 rotations so a whole restart cycle runs without host round trips.
+//
+// Reductions are two-stage with a fixed block count and fixed summation order,
+// so every run gives bitwise identical results.
+#include <cmath>
+
+#include "hdg_internal.hpp"
+
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// part[i*nblk + b] = sum_{k in chunk b} V[i][k] w[k],  i < J
+__global__ __launch_bounds__(BS) void k_multidot(const double* __restrict__ V, size_t ldv, int J,
+                                                 const double* __restrict__ w, size_t n,
+                                                 double* __restrict__ part, int nblk, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[64][BS / 64];
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i0 = 0; i0 < J; i0 += 64) {
+        const int ni = (J - i0) < 64 ? (J - i0) : 64;
+        for (int ii = 0; ii < ni; ++ii) {
+            const double* v = V + (size_t)(i0 + ii) * ldv;
+            double acc = 0.0;
+            for (size_t k = k0 + threadIdx.x; k < k1; k += BS) acc += v[k] * w[k];
+            acc = wave_sum(acc);
+            if (lane == 0) red[ii][wave] = acc;
+        }
+        __syncthreads();
+        if (threadIdx.x < ni) {
+            double s = 0.0;
+            for (int q = 0; q < BS / 64; ++q) s += red[threadIdx.x][q];
+            part[(size_t)(i0 + threadIdx.x) * nblk + blockIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// out[i] = sum_b part[i*nblk + b]; if add_to: add_to[i] += out[i]. One wave per i.
+__global__ void k_reduce(const double* __restrict__ part, int J, int nblk, double* out, double* add_to,
+                         const int* skip) {
+    if (skip && *skip) return;
+    const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= J) return;
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[(size_t)i * nblk + b];
+    s = wave_sum(s);
+    if (lane == 0) {
+        if (out) out[i] = s;
+        if (add_to) add_to[i] += s;
+    }
+}
+
+// w[k] += sign * sum_{i<J} V[i][k] h[i]
+__global__ __launch_bounds__(BS) void k_multiaxpy(const double* __restrict__ V, size_t ldv, int J,
+                                                  const double* __restrict__ h, double sign, double* w,
+                                                  size_t n, const int* skip, const int* J_dev) {
+    if (skip && *skip) return;
+    const size_t k = (size_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    const int JJ = J_dev ? *J_dev : J;
+    double acc = 0.0;
+    for (int i = 0; i < JJ; ++i) acc += V[(size_t)i * ldv + k] * h[i];
+    w[k] += sign * acc;
+}
+
+__global__ __launch_bounds__(BS) void k_sumsq(const double* __restrict__ w, size_t n, double* part, int nblk,
+                                              const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[BS / 64];
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    double acc = 0.0;
+    for (size_t k = k0 + threadIdx.x; k < k1; k += BS) acc += w[k] * w[k];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < BS / 64; ++q) s += red[q];
+        part[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_lincomb(size_t n, double* out, double a, const double* X, double b,
+                                                const double* Y, const int* skip) {
+    if (skip && *skip) return;
+    const size_t k = (size_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    double v = 0.0;
+    if (X) v += a * X[k];
+    if (Y) v += b * Y[k];
+    out[k] = v;
+}
+
+__global__ __launch_bounds__(BS) void k_scale_by(double* v, const double* src, size_t n, const double* denom,
+                                                 const int* skip) {
+    if (skip && *skip) return;
+    const size_t k = (size_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    v[k] = src[k] / *denom;
+}
+
+// Sum of the norm partials of the cycle-start residual; initialises the cycle.
+__global__ void k_cycle_init(GmresCtl* ctl, const double* part, int nblk, double* g, int jmax, double target) {
+    const int lane = threadIdx.x;
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[b];
+    s = wave_sum(s);
+    if (lane == 0) {
+        const double beta = sqrt(s);
+        ctl->beta = beta;
+        ctl->est = beta;
+        ctl->k = 0;
+        ctl->jmax = jmax;
+        ctl->target = target;
+        ctl->nonfinite = !isfinite(beta);
+        ctl->done = (beta <= target || !isfinite(beta) || jmax <= 0) ? 1 : 0;
+        g[0] = beta;
+    }
+}
+
+__global__ void k_store_norm(const double* part, int nblk, double* dst) {
+    const int lane = threadIdx.x;
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[b];
+    s = wave_sum(s);
+    if (lane == 0) *dst = sqrt(s);
+}
+
+// Step j: column j of H (rows 0..j already hold the Gram-Schmidt coefficients);
+// h_{j+1,j} from the norm partials; previous rotations, new rotation, residual estimate.
+__global__ void k_givens(GmresCtl* ctl, const double* part, int nblk, double* H, int ldh, double* cs,
+                         double* sn, double* g, int j, double* hist) {
+    if (ctl->done) return;
+    const int lane = threadIdx.x;
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[b];
+    s = wave_sum(s);
+    if (lane != 0) return;
+    const double hn = sqrt(s);
+    double* col = H + (size_t)j * ldh;     // column-major (ldh = m+1)
+    col[j + 1] = hn;   // the rotated subdiagonal is zero; the slot keeps h_{j+1,j} to scale v_{j+1}
+    double hjj = col[j];
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+    }
+    hjj = col[j];
+    double c = 1.0, sg = 0.0;
+    if (hn != 0.0) {
+        const double r = hypot(hjj, hn);
+        c = hjj / r;
+        sg = hn / r;
+    }
+    cs[j] = c;
+    sn[j] = sg;
+    col[j] = c * hjj + sg * hn;
+    const double gj = g[j];
+    g[j + 1] = -sg * gj;
+    g[j] = c * gj;
+    const double est = fabs(g[j + 1]);
+    ctl->est = est;
+    ctl->k = j + 1;
+    if (hist) hist[j] = est;
+    if (!isfinite(est) || !isfinite(col[j])) ctl->nonfinite = 1;
+    if (est <= ctl->target || hn == 0.0 || j + 1 >= ctl->jmax || !isfinite(est)) ctl->done = 1;
+}
+
+// y = R^{-1} g over the k steps of this cycle (upper triangular R in H, column-major).
+__global__ void k_backsolve(const GmresCtl* ctl, const double* H, int ldh, const double* g, double* y) {
+    if (threadIdx.x != 0) return;
+    const int k = ctl->k;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * ldh + i] * y[c];
+        y[i] = s / H[(size_t)i * ldh + i];
+    }
+    for (int i = k; i < ldh - 1; ++i) y[i] = 0.0;
+}
+
+}  // namespace
+
+hdg_status vec_multidot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* w, size_t n,
+                        double* part, int nblk, const int* skip) {
+    if (J <= 0) return HDG_OK;
+    hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, w, n, part, nblk, skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_reduce(hdg_ctx ctx, const double* part, int J, int nblk, double* out, double* add_to,
+                      const int* skip) {
+    if (J <= 0) return HDG_OK;
+    hipLaunchKernelGGL(k_reduce, dim3(div_up(J, 4)), dim3(256), 0, ctx->stream, part, J, nblk, out, add_to, skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_multiaxpy(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h, double sign,
+                         double* w, size_t n, const int* skip, const int* J_dev) {
+    if ((J <= 0 && !J_dev) || n == 0) return HDG_OK;
+    hipLaunchKernelGGL(k_multiaxpy, dim3(div_up((long long)n, BS)), dim3(BS), 0, ctx->stream, V, ldv, J, h, sign,
+                       w, n, skip, J_dev);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_sumsq_partial(hdg_ctx ctx, const double* w, size_t n, double* part, int nblk, const int* skip) {
+    hipLaunchKernelGGL(k_sumsq, dim3(nblk), dim3(BS), 0, ctx->stream, w, n, part, nblk, skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_lincomb(hdg_ctx ctx, size_t n, double* out, double a, const double* X, double b,
+                       const double* Y, const int* skip) {
+    if (n == 0) return HDG_OK;
+    hipLaunchKernelGGL(k_lincomb, dim3(div_up((long long)n, BS)), dim3(BS), 0, ctx->stream, n, out, a, X, b, Y,
+                       skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status krylov_cycle_init(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, double* g, int jmax,
+                             double target) {
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, ctx->stream, ctl, part, nblk, g, jmax, target);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status krylov_scale_by(hdg_ctx ctx, double* v, const double* src, size_t n, const double* denom,
+                           const int* skip) {
+    hipLaunchKernelGGL(k_scale_by, dim3(div_up((long long)n, BS)), dim3(BS), 0, ctx->stream, v, src, n, denom,
+                       skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status krylov_givens(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, double* H, int ldh,
+                         double* cs, double* sn, double* g, int j, double* hist) {
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, ctx->stream, ctl, part, nblk, H, ldh, cs, sn, g, j, hist);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status krylov_backsolve(hdg_ctx ctx, const GmresCtl* ctl, const double* H, int ldh, const double* g,
+                            double* y) {
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, ctx->stream, ctl, H, ldh, g, y);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status krylov_store_norm(hdg_ctx ctx, const double* part, int nblk, double* dst) {
+    hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(64), 0, ctx->stream, part, nblk, dst);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}

@@ -1,0 +1,317 @@
+"""ctypes binding of libhdg.so (include/hdg.h): argument marshalling only.
+
+Device arrays are torch tensors on a ROCm device; the binding checks dtype,
+contiguity, device and sizes and passes raw pointers. Every computation runs in
+the library's HIP kernels; there is no fallback: if libhdg.so is missing or the
+GPU is absent, calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+HDG_OK, HDG_NOT_CONVERGED = 0, 1
+PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3}
+ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+# every symbol declared in include/hdg.h
+SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
+           "hdg_local_size", "hdg_condense", "hdg_assemble_blocks", "hdg_solve_opts_default", "hdg_gmres_solve",
+           "hdg_recover_local", "hdg_newton_update", "hdg_matvec", "hdg_bj_setup", "hdg_bj_apply",
+           "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz"]
+
+
+class HdgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hdg status {status}: {msg}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe")]
+
+
+class ElemBlocks(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt")]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("atol", ctypes.c_double), ("prec", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
+                ("poly_v0", ctypes.c_void_p), ("orth", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("cycles", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("npoly", ctypes.c_int32), ("rel_resid_true", ctypes.c_double), ("rel_resid_est", ctypes.c_double),
+                ("t_setup", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("theta_re", ctypes.c_double * 64), ("theta_im", ctypes.c_double * 64),
+                ("hist_len", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhdg.so (built in-tree by __graft_entry__.build / paper_2512_13619_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HdgError(-5, f"{LIB_PATH} is missing: build it first (python -m paper_2512_13619_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pd = ctypes.POINTER(Dims)
+    lib.hdg_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.hdg_destroy.argtypes = [vp]
+    lib.hdg_set_stream.argtypes = [vp, vp]
+    lib.hdg_last_error.argtypes = [vp]
+    lib.hdg_last_error.restype = ctypes.c_char_p
+    lib.hdg_release_workspace.argtypes = [vp]
+    lib.hdg_local_size.argtypes = [pd]
+    lib.hdg_local_size.restype = ctypes.c_size_t
+    lib.hdg_condense.argtypes = [vp, pd, i64, ctypes.POINTER(ElemBlocks), vp, vp, vp]
+    lib.hdg_assemble_blocks.argtypes = [vp, pd, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+    lib.hdg_solve_opts_default.restype = None
+    lib.hdg_gmres_solve.argtypes = [vp, pd, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                    ctypes.POINTER(SolveStats)]
+    lib.hdg_recover_local.argtypes = [vp, pd, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_newton_update.argtypes = [vp, i64, dbl, vp, vp]
+    lib.hdg_matvec.argtypes = [vp, pd, vp, vp, vp, i32, vp, vp]
+    lib.hdg_bj_setup.argtypes = [vp, pd, vp, vp, vp]
+    lib.hdg_bj_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp]
+    lib.hdg_poly_apply.argtypes = [vp, pd, vp, vp, vp, vp, vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                   vp, vp]
+    pdbl = ctypes.POINTER(dbl)
+    lib.hdg_hessenberg_eigvals.argtypes = [ctypes.c_int, pdbl, ctypes.c_int, pdbl, pdbl]
+    lib.hdg_harmonic_ritz.argtypes = [ctypes.c_int, pdbl, dbl, pdbl, pdbl, ctypes.POINTER(ctypes.c_int)]
+    for name in SYMBOLS:
+        if name not in ("hdg_last_error", "hdg_local_size", "hdg_solve_opts_default",
+                        "hdg_hessenberg_eigvals", "hdg_harmonic_ritz"):
+            getattr(lib, name).restype = ctypes.c_int
+    lib.hdg_hessenberg_eigvals.restype = ctypes.c_int
+    lib.hdg_harmonic_ritz.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def make_dims(d):
+    return Dims(*(int(d[k]) for k in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe")))
+
+
+def _ptr(t, dtype, numel=None, name="array", allow_none=False):
+    import torch
+    if t is None:
+        if allow_none:
+            return None
+        raise HdgError(-1, f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise HdgError(-1, f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise HdgError(-1, f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise HdgError(-1, f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise HdgError(-1, f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise HdgError(-2, f"{name} has {t.numel()} entries, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- host-only helpers (no GPU needed) ----------------------------------------------------
+def hessenberg_eigvals(H):
+    lib = load()
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = H.shape[0]
+    wr = np.zeros(n)
+    wi = np.zeros(n)
+    pd = ctypes.POINTER(ctypes.c_double)
+    rc = lib.hdg_hessenberg_eigvals(n, H.ctypes.data_as(pd), n, wr.ctypes.data_as(pd), wi.ctypes.data_as(pd))
+    if rc != 0:
+        raise HdgError(rc, "eigenvalue iteration failed")
+    return wr + 1j * wi
+
+
+def harmonic_ritz(H, drop_rel=1e-12):
+    """H: (P+1) x P Arnoldi Hessenberg. Returns Leja-ordered harmonic Ritz values."""
+    lib = load()
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    P = H.shape[1]
+    tr = np.zeros(P + 1)
+    ti = np.zeros(P + 1)
+    n = ctypes.c_int(0)
+    pd = ctypes.POINTER(ctypes.c_double)
+    rc = lib.hdg_harmonic_ritz(P, H.ctypes.data_as(pd), drop_rel, tr.ctypes.data_as(pd), ti.ctypes.data_as(pd),
+                               ctypes.byref(n))
+    if rc != 0:
+        raise HdgError(rc, "harmonic Ritz computation failed")
+    return tr[:n.value] + 1j * ti[:n.value]
+
+
+# ---- device context -----------------------------------------------------------------------
+class Context:
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.lib = load()
+        self.device = device
+        self.h = ctypes.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = s
+        st = self.lib.hdg_create(ctypes.byref(self.h), device, ctypes.c_void_p(s.cuda_stream))
+        if st != HDG_OK:
+            raise HdgError(st, "hdg_create failed (no GPU or bad device)")
+
+    def close(self):
+        if self.h:
+            self.lib.hdg_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def _check(self, st):
+        if st < 0:
+            raise HdgError(st, self.lib.hdg_last_error(self.h).decode())
+        return st
+
+    def release_workspace(self):
+        self._check(self.lib.hdg_release_workspace(self.h))
+
+    # (1)
+    def condense(self, dims, blk, Kbar, rbar, local, ne_chunk=None):
+        import torch
+        d = make_dims(dims)
+        ne = int(dims["ne"]) if ne_chunk is None else int(ne_chunk)
+        M, D, P, PF, L = (int(dims[k]) for k in ("ncomp", "dim", "npe", "npf", "nlfe"))
+        nu, nq, nt = M * P, M * D * P, L * M * PF
+        f64 = torch.float64
+        sizes = dict(Minv=P * P, Bd=D * P * P, Cd=D * P * L * PF, D=nu * nq, E=nu * nu, F=nu * nt, G=nt * nq,
+                     H=nt * nu, J=nt * nt, ru=nu, rt=nt)
+        names = [f[0] for f in ElemBlocks._fields_]
+        eb = ElemBlocks(*[_ptr(blk[k], f64, ne * sizes[k], k) for k in names])
+        return self._check(self.lib.hdg_condense(self.h, ctypes.byref(d), ne, ctypes.byref(eb),
+                                                 _ptr(Kbar, f64, ne * nt * nt, "Kbar"), _ptr(rbar, f64, ne * nt, "rbar"),
+                                                 _ptr(local, f64, ne * nu * (nu + nt + 1), "local")))
+
+    # (2)
+    def assemble(self, dims, f2e, e2f, perm, Kbar, rbar, K64, K32, nbr, r):
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "npf", "nlfe"))
+        nb, S, nt = M * PF, 2 * L - 1, L * M * PF
+        return self._check(self.lib.hdg_assemble_blocks(
+            self.h, ctypes.byref(d), _ptr(f2e, torch.int32, nf * 4, "f2e"), _ptr(e2f, torch.int32, ne * L, "e2f"),
+            _ptr(perm, torch.int32, ne * L * PF, "perm", allow_none=True),
+            _ptr(Kbar, torch.float64, ne * nt * nt, "Kbar"), _ptr(rbar, torch.float64, ne * nt, "rbar"),
+            _ptr(K64, torch.float64, nf * S * nb * nb, "K64"),
+            _ptr(K32, torch.float32, nf * S * nb * nb, "K32", allow_none=True),
+            _ptr(nbr, torch.int32, nf * S, "nbr"), _ptr(r, torch.float64, nf * nb, "r")))
+
+    # (3)
+    def gmres_solve(self, dims, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0,
+                    prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0):
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        N = nf * nb
+        o = SolveOpts()
+        self.lib.hdg_solve_opts_default(ctypes.byref(o))
+        o.restart, o.max_iters, o.rtol, o.atol = restart, max_iters, rtol, atol
+        o.prec, o.poly_degree, o.orth, o.precision = PREC[prec], poly_degree, ORTH[orth], PRECISION[precision]
+        o.poly_v0 = _ptr(poly_v0, torch.float64, N, "poly_v0", allow_none=True)
+        hist = np.zeros(max(hist_len, 1))
+        if hist_len > 0:
+            o.resid_hist_h = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            o.resid_hist_len = hist_len
+        stats = SolveStats()
+        st = self._check(self.lib.hdg_gmres_solve(
+            self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64"),
+            _ptr(K32, torch.float32, nf * S * nb * nb, "K32", allow_none=True), _ptr(nbr, torch.int32, nf * S, "nbr"),
+            _ptr(r, torch.float64, N, "r"), _ptr(x, torch.float64, N, "x"), ctypes.byref(o), ctypes.byref(stats)))
+        out = {f[0]: getattr(stats, f[0]) for f in SolveStats._fields_ if f[0] not in ("theta_re", "theta_im")}
+        out["status"] = st
+        out["theta"] = np.array([stats.theta_re[i] + 1j * stats.theta_im[i] for i in range(stats.npoly)])
+        out["hist"] = hist[:stats.hist_len].copy() if hist_len > 0 else None
+        return out
+
+    # (4)
+    def recover(self, dims, local, Minv, Bd, Cd, e2f, perm, xhat, du, dq):
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, D, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe"))
+        nu, nq, nt, nb = M * P, M * D * P, L * M * PF, M * PF
+        f64 = torch.float64
+        return self._check(self.lib.hdg_recover_local(
+            self.h, ctypes.byref(d), _ptr(local, f64, ne * nu * (nu + nt + 1), "local"),
+            _ptr(Minv, f64, ne * P * P, "Minv"), _ptr(Bd, f64, ne * D * P * P, "Bd"),
+            _ptr(Cd, f64, ne * D * P * L * PF, "Cd"), _ptr(e2f, torch.int32, ne * L, "e2f"),
+            _ptr(perm, torch.int32, ne * L * PF, "perm", allow_none=True), _ptr(xhat, f64, nf * nb, "xhat"),
+            _ptr(du, f64, ne * nu, "du"), _ptr(dq, f64, ne * nq, "dq")))
+
+    # (5)
+    def newton_update(self, alpha, delta, state):
+        import torch
+        n = state.numel()
+        return self._check(self.lib.hdg_newton_update(self.h, n, float(alpha), _ptr(delta, torch.float64, n, "delta"),
+                                                      _ptr(state, torch.float64, n, "state")))
+
+    # building blocks
+    def matvec(self, dims, K64, K32, nbr, x, y, precision="fp64"):
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        return self._check(self.lib.hdg_matvec(
+            self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64", allow_none=True),
+            _ptr(K32, torch.float32, nf * S * nb * nb, "K32", allow_none=True), _ptr(nbr, torch.int32, nf * S, "nbr"),
+            PRECISION[precision], _ptr(x, torch.float64, nf * nb, "x"), _ptr(y, torch.float64, nf * nb, "y")))
+
+    def bj_setup(self, dims, K64, Binv64, Binv32=None):
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        return self._check(self.lib.hdg_bj_setup(
+            self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64"),
+            _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64"),
+            _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True)))
+
+    def bj_apply(self, dims, Binv64, Binv32, y, z, precision="fp64"):
+        import torch
+        d = make_dims(dims)
+        nf, nb = int(dims["nf"]), int(dims["ncomp"]) * int(dims["npf"])
+        return self._check(self.lib.hdg_bj_apply(
+            self.h, ctypes.byref(d), _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64", allow_none=True),
+            _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision],
+            _ptr(y, torch.float64, nf * nb, "y"), _ptr(z, torch.float64, nf * nb, "z")))
+
+    def poly_apply(self, dims, K64, K32, nbr, Binv64, Binv32, theta, y, z, precision="fp64"):
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        th = np.asarray(theta, complex)
+        tr = np.ascontiguousarray(th.real, dtype=np.float64)
+        ti = np.ascontiguousarray(th.imag, dtype=np.float64)
+        pd = ctypes.POINTER(ctypes.c_double)
+        return self._check(self.lib.hdg_poly_apply(
+            self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64", allow_none=True),
+            _ptr(K32, torch.float32, nf * S * nb * nb, "K32", allow_none=True), _ptr(nbr, torch.int32, nf * S, "nbr"),
+            _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64", allow_none=True),
+            _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision], len(th),
+            tr.ctypes.data_as(pd), ti.ctypes.data_as(pd), _ptr(y, torch.float64, nf * nb, "y"),
+            _ptr(z, torch.float64, nf * nb, "z")))

@@ -1,0 +1,50 @@
+"""Device buffers and the order of the four entry points (condense -> assemble
+-> solve -> recover). Allocation and sequencing only; all arithmetic runs in
+libhdg.so."""
+import torch
+
+from . import hdg
+
+
+class Pipeline:
+    """One mesh/space: owns K (FP64 and FP32), nbr, r, x and the recovery data."""
+
+    def __init__(self, ctx, dims, f2e, e2f, perm=None, device="cuda", keep_fp32=True):
+        self.ctx = ctx
+        self.dims = dict(dims)
+        d = self.dims
+        self.device = device
+        i32 = lambda a: torch.as_tensor(a, dtype=torch.int32).contiguous().to(device)
+        self.f2e = i32(f2e)
+        self.e2f = i32(e2f)
+        self.perm = None if perm is None else i32(perm)
+        M, D, P, PF, L = d["ncomp"], d["dim"], d["npe"], d["npf"], d["nlfe"]
+        self.nu, self.nq, self.nt, self.nb, self.S = M * P, M * D * P, L * M * PF, M * PF, 2 * L - 1
+        ne, nf = d["ne"], d["nf"]
+        z = lambda *s, dt=torch.float64: torch.zeros(*s, dtype=dt, device=device)
+        self.Kbar = z(ne, self.nt, self.nt)
+        self.rbar = z(ne, self.nt)
+        self.local = z(ne, self.nu, self.nu + self.nt + 1)
+        self.K64 = z(nf, self.S, self.nb, self.nb)
+        self.K32 = z(nf, self.S, self.nb, self.nb, dt=torch.float32) if keep_fp32 else None
+        self.nbr = torch.zeros(nf, self.S, dtype=torch.int32, device=device)
+        self.r = z(nf * self.nb)
+        self.x = z(nf * self.nb)
+        self.du = z(ne, self.nu)
+        self.dq = z(ne, self.nq)
+
+    def condense(self, blk, e0=0, e1=None):
+        """Condense elements [e0, e1) from device blocks that cover exactly that range."""
+        e1 = self.dims["ne"] if e1 is None else e1
+        self.ctx.condense(self.dims, blk, self.Kbar[e0:e1], self.rbar[e0:e1], self.local[e0:e1], ne_chunk=e1 - e0)
+
+    def assemble(self):
+        self.ctx.assemble(self.dims, self.f2e, self.e2f, self.perm, self.Kbar, self.rbar, self.K64, self.K32,
+                          self.nbr, self.r)
+
+    def solve(self, **kw):
+        self.x.zero_()
+        return self.ctx.gmres_solve(self.dims, self.K64, self.K32, self.nbr, self.r, self.x, **kw)
+
+    def recover(self, Minv, Bd, Cd):
+        self.ctx.recover(self.dims, self.local, Minv, Bd, Cd, self.e2f, self.perm, self.x, self.du, self.dq)
