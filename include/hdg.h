@@ -132,7 +132,10 @@ hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
  * Right-preconditioned flexible GMRES(restart): every cycle starts from the true
  * FP64 residual r - K64 x; it stops when ||r - K64 x||_2 <= max(rtol*||r||_2, atol)
  * or after max_iters Arnoldi steps. The Hessenberg/Givens update runs on the
- * device in FP64; the host reads one status word per cycle.
+ * device in FP64; a whole cycle is enqueued at once (or replayed as one captured
+ * hipGraph when use_graph = 1) and the host reads one status word per cycle.
+ * The context's stream must not be used by other work while a captured cycle is
+ * being recorded.
  *
  * precision = HDG_FP64: every operator application uses K64 and FP64 inverses.
  * precision = HDG_MIXED: inside a cycle the matvec and the preconditioner use K32
@@ -164,6 +167,7 @@ typedef struct {
     int32_t precision;          /* HDG_FP64 or HDG_MIXED */
     double* resid_hist_h;       /* host, optional: ||r|| at each cycle start and Givens estimates */
     int32_t resid_hist_len;
+    int32_t use_graph;          /* 1: capture one restart cycle in a hipGraph and replay it */
 } hdg_solve_opts;
 
 typedef struct {

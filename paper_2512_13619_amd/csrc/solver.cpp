@@ -7,9 +7,10 @@
 // of iterative refinement. Orthogonalisation (CGS2 / CGS / MGS), the Hessenberg
 // Givens update and the solution update are FP64.
 //
-// Host/device traffic: the host enqueues a whole cycle (all m Arnoldi steps);
+// Host/device traffic: the host enqueues a whole cycle (FP64 residual, all m
+// Arnoldi steps, back substitution, update), optionally as one captured hipGraph;
 // every in-cycle kernel reads a device "done" word and returns at once after
-// convergence, so the host synchronises twice per cycle (cycle start, cycle end).
+// convergence, so the host synchronises once per cycle.
 //
 // Preconditioners (z = Prec(y)):
 //   BJ       z_f = P_f^{-1} y_f                                   (Section 4.5)
@@ -385,57 +386,96 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     hdg_status result = HDG_NOT_CONVERGED;
     std::vector<double> hbuf(m + 2);
     const int* skip = &w.ctl->done;
-    while (true) {
-        // cycle-start residual in FP64
+    // One restart cycle, entirely on the stream: FP64 residual, Arnoldi steps
+    // (skipped on the device once converged), back substitution, x += Z y.
+    auto enqueue_cycle = [&](int jmax) -> hdg_status {
+        hdg_status s2;
         FaceEpilogue e = epi0();
         e.out[0] = w.V;
         e.s[0] = -1.0;
         e.X[0] = b;
         e.a[0] = 1.0;
-        if ((st = face_op(ctx, nf, nb, S, L, K64, false, nbr, nullptr, false, x, e, nullptr)) != HDG_OK) return st;
-        if ((st = vec_sumsq_partial(ctx, w.V, N, w.part, w.nblk, nullptr)) != HDG_OK) return st;
-        const int jmax = std::min(m, o->max_iters - iters);
-        if ((st = krylov_cycle_init(ctx, w.ctl, w.part, w.nblk, w.g, jmax, target)) != HDG_OK) return st;
-        HDG_HIP_CHECK(ctx, hipMemcpyAsync(&hc, w.ctl, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream));
-        HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-        hist_push(hc.beta);
-        stats->rel_resid_true = bnorm > 0 ? hc.beta / bnorm : 0.0;
-        if (hc.nonfinite) {
-            ctx->err = "residual became NaN or Inf";
-            result = HDG_ERR_NONFINITE;
-            break;
-        }
-        if (hc.beta <= target) { result = HDG_OK; break; }
-        if (jmax <= 0) { result = HDG_NOT_CONVERGED; break; }
-        if ((st = krylov_scale_by(ctx, w.V, w.V, N, &w.ctl->beta, nullptr)) != HDG_OK) return st;
+        if ((s2 = face_op(ctx, nf, nb, S, L, K64, false, nbr, nullptr, false, x, e, nullptr)) != HDG_OK) return s2;
+        if ((s2 = vec_sumsq_partial(ctx, w.V, N, w.part, w.nblk, nullptr)) != HDG_OK) return s2;
+        if ((s2 = krylov_cycle_init(ctx, w.ctl, w.part, w.nblk, w.g, jmax, target)) != HDG_OK) return s2;
+        if ((s2 = krylov_scale_by(ctx, w.V, w.V, N, &w.ctl->beta, skip)) != HDG_OK) return s2;
         for (int j = 0; j < jmax; ++j) {
             double* vj = w.V + (size_t)j * w.ld;
             double* zj = w.Z + (size_t)j * w.ld;
             double* wv = w.V + (size_t)(j + 1) * w.ld;
-            if ((st = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return st;
-            if ((st = op_matvec(ctx, op, zj, wv, skip)) != HDG_OK) return st;
-            if ((st = orthogonalise(ctx, w, N, j, o->orth, skip)) != HDG_OK) return st;
-            if ((st = vec_sumsq_partial(ctx, wv, N, w.part, w.nblk, skip)) != HDG_OK) return st;
-            if ((st = krylov_givens(ctx, w.ctl, w.part, w.nblk, w.H, w.ldh, w.cs, w.sn, w.g, j, w.hist)) != HDG_OK)
-                return st;
-            if ((st = krylov_scale_by(ctx, wv, wv, N, w.H + (size_t)j * w.ldh + j + 1, skip)) != HDG_OK) return st;
+            if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
+            if ((s2 = op_matvec(ctx, op, zj, wv, skip)) != HDG_OK) return s2;
+            if ((s2 = orthogonalise(ctx, w, N, j, o->orth, skip)) != HDG_OK) return s2;
+            if ((s2 = vec_sumsq_partial(ctx, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+            if ((s2 = krylov_givens(ctx, w.ctl, w.part, w.nblk, w.H, w.ldh, w.cs, w.sn, w.g, j, w.hist)) != HDG_OK)
+                return s2;
+            if ((s2 = krylov_scale_by(ctx, wv, wv, N, w.H + (size_t)j * w.ldh + j + 1, skip)) != HDG_OK) return s2;
         }
-        if ((st = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return st;
-        if ((st = vec_multiaxpy(ctx, w.Z, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k)) != HDG_OK) return st;
-        HDG_HIP_CHECK(ctx, hipMemcpyAsync(&hc, w.ctl, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream));
-        HDG_HIP_CHECK(ctx, hipMemcpyAsync(hbuf.data(), w.hist, sizeof(double) * (size_t)jmax, hipMemcpyDeviceToHost,
-                                          ctx->stream));
-        HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+        if ((s2 = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return s2;
+        return vec_multiaxpy(ctx, w.Z, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    auto drop_graph = [&]() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    };
+    while (true) {
+        const int jmax = std::max(0, std::min(m, o->max_iters - iters));
+        if (o->use_graph && jmax == m) {
+            if (!gexec) {
+                HDG_HIP_CHECK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                st = enqueue_cycle(jmax);
+                hipGraph_t g = nullptr;
+                const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+                if (st != HDG_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+                if (ec != hipSuccess) {
+                    ctx->err = std::string("graph capture failed: ") + hipGetErrorString(ec);
+                    return HDG_ERR_HIP;
+                }
+                graph = g;
+                if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                    drop_graph();
+                    ctx->err = "graph instantiation failed";
+                    return HDG_ERR_HIP;
+                }
+            }
+            if (hipGraphLaunch(gexec, ctx->stream) != hipSuccess) {
+                drop_graph();
+                ctx->err = "graph launch failed";
+                return HDG_ERR_HIP;
+            }
+        } else {
+            if ((st = enqueue_cycle(jmax)) != HDG_OK) { drop_graph(); return st; }
+        }
+        const hipError_t e1 = hipMemcpyAsync(&hc, w.ctl, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream);
+        const hipError_t e2 = hipMemcpyAsync(hbuf.data(), w.hist, sizeof(double) * (size_t)std::max(jmax, 1),
+                                             hipMemcpyDeviceToHost, ctx->stream);
+        const hipError_t e3 = hipStreamSynchronize(ctx->stream);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            drop_graph();
+            ctx->err = "reading the GMRES status failed";
+            return HDG_ERR_HIP;
+        }
+        hist_push(hc.beta);
         for (int i = 0; i < hc.k; ++i) hist_push(hbuf[i]);
-        iters += hc.k;
-        ++cycles;
-        stats->rel_resid_est = bnorm > 0 ? hc.est / bnorm : 0.0;
+        stats->rel_resid_true = bnorm > 0 ? hc.beta / bnorm : 0.0;
         if (hc.nonfinite) {
-            ctx->err = "Arnoldi produced NaN or Inf";
+            ctx->err = "residual or Arnoldi data became NaN or Inf";
             result = HDG_ERR_NONFINITE;
             break;
         }
+        if (hc.k == 0) {
+            result = hc.beta <= target ? HDG_OK : HDG_NOT_CONVERGED;
+            break;
+        }
+        iters += hc.k;
+        ++cycles;
+        stats->rel_resid_est = bnorm > 0 ? hc.est / bnorm : 0.0;
     }
+    drop_graph();
     stats->iters = iters;
     stats->cycles = cycles;
     stats->converged = result == HDG_OK;

@@ -43,7 +43,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("atol", ctypes.c_double), ("prec", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
                 ("poly_v0", ctypes.c_void_p), ("orth", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32)]
+                ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -222,7 +223,8 @@ class Context:
 
     # (3)
     def gmres_solve(self, dims, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0,
-                    prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0):
+                    prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0,
+                    use_graph=False):
         import torch
         d = make_dims(dims)
         nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
@@ -233,6 +235,7 @@ class Context:
         o.restart, o.max_iters, o.rtol, o.atol = restart, max_iters, rtol, atol
         o.prec, o.poly_degree, o.orth, o.precision = PREC[prec], poly_degree, ORTH[orth], PRECISION[precision]
         o.poly_v0 = _ptr(poly_v0, torch.float64, N, "poly_v0", allow_none=True)
+        o.use_graph = 1 if use_graph else 0
         hist = np.zeros(max(hist_len, 1))
         if hist_len > 0:
             o.resid_hist_h = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -233,6 +233,29 @@ def test_gmres_solution_c1(ctx, precision, prec):
     assert true <= 1e-13 * 1.01
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gmres_graph_replay_equals_direct(ctx, precision):
+    """A captured-and-replayed cycle gives bitwise the same iterates as direct launches."""
+    pb, out = case_data("c1")
+    say("graph", precision)
+    K, K32, nbr = _dev_matrix(out)
+    r = torch.as_tensor(out["r"]).cuda()
+    xa = torch.zeros_like(r)
+    xb = torch.zeros_like(r)
+    sa = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xa, restart=10, max_iters=2000, rtol=1e-12,
+                         precision=precision, use_graph=False)
+    sb = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xb, restart=10, max_iters=2000, rtol=1e-12,
+                         precision=precision, use_graph=True)
+    assert sa["converged"] and sb["converged"] and sa["iters"] == sb["iters"] and sb["cycles"] > 2
+    assert torch.equal(xa, xb)
+    # eager work between replays, then a second graph solve
+    xc = torch.zeros_like(r)
+    r2 = (r * 1.0).contiguous()
+    sc = ctx.gmres_solve(pb.dims(), K, K32, nbr, r2, xc, restart=10, max_iters=2000, rtol=1e-12,
+                         precision=precision, use_graph=True)
+    assert torch.equal(xa, xc) and sc["iters"] == sa["iters"]
+
+
 def test_gmres_history_matches_oracle_fgmres(ctx):
     pb, out = case_data("c1")
     K, K32, nbr = _dev_matrix(out)
