@@ -220,6 +220,53 @@ hdg_status hdg_poly_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, 
                           int32_t precision, int32_t npoly, const double* theta_re_h,
                           const double* theta_im_h, const double* y, double* z);
 
+/* ---------------------------------------------------------------------------
+ * Batched independent instances (many small meshes of different element types,
+ * degrees and sizes condensed and solved together) -- the same operations as
+ * (1)-(4) above, Sections 2.3-2.4, 3.1-3.2, 4.1-4.5.
+ *
+ * hdg_batch_create builds device descriptor tables for n_inst instances with
+ * sizes dims_h[i] (host array). Every array of the single-instance entry points
+ * becomes the concatenation of the instances' arrays, instance i's part starting
+ * at offset hdg_batch_offsets(b, id, off)[i] (elements of that array, prefix sums
+ * of the per-instance sizes); id is one of HDG_BATCH_ARRAY_*. Index arrays f2e,
+ * e2f and nbr hold instance-local element/face numbers; perm is not supported.
+ * Limits: M*P_F <= 8, (2N_lfe-1)*M*P_F <= 64, and (nu+nt)(nu+nt+1) + D P_E (P_E +
+ * N_lfe P_F) doubles per element within 150 KiB (whole element system in LDS).
+ *
+ * hdg_condense_batch: one persistent launch over all elements of all instances;
+ *   its grid size is chosen on the first call by timing candidate sizes on the real
+ *   data (hdg_batch_tuned_grid reports the choice).
+ * hdg_gmres_solve_batch: one FGMRES per instance (own Arnoldi basis segment,
+ *   Hessenberg, Givens rotations, tolerance relative to its own ||r_i||); finished
+ *   instances are masked while the others continue; opts as for hdg_gmres_solve
+ *   with prec NONE or BJ and orth CGS2 or CGS; stats_h has n_inst entries.
+ *   Returns HDG_NOT_CONVERGED if any instance did not converge.
+ */
+typedef struct hdg_batch_s* hdg_batch;
+enum {
+    HDG_BATCH_ARRAY_MINV = 0, HDG_BATCH_ARRAY_BD, HDG_BATCH_ARRAY_CD, HDG_BATCH_ARRAY_D, HDG_BATCH_ARRAY_E,
+    HDG_BATCH_ARRAY_F, HDG_BATCH_ARRAY_G, HDG_BATCH_ARRAY_H, HDG_BATCH_ARRAY_J, HDG_BATCH_ARRAY_RU,
+    HDG_BATCH_ARRAY_RT, HDG_BATCH_ARRAY_KBAR, HDG_BATCH_ARRAY_RBAR, HDG_BATCH_ARRAY_LOCAL, HDG_BATCH_ARRAY_DU,
+    HDG_BATCH_ARRAY_DQ, HDG_BATCH_ARRAY_K, HDG_BATCH_ARRAY_NBR, HDG_BATCH_ARRAY_VEC, HDG_BATCH_ARRAY_F2E,
+    HDG_BATCH_ARRAY_E2F, HDG_BATCH_ARRAY_BINV, HDG_BATCH_NARRAYS
+};
+hdg_status hdg_batch_create(hdg_ctx ctx, int32_t n_inst, const hdg_dims* dims_h, hdg_batch* out);
+hdg_status hdg_batch_destroy(hdg_batch b);
+hdg_status hdg_batch_offsets(hdg_batch b, int32_t array_id, int64_t* off_h /* [n_inst+1] */);
+int32_t    hdg_batch_tuned_grid(hdg_batch b);
+hdg_status hdg_condense_batch(hdg_ctx ctx, hdg_batch b, const hdg_elem_blocks* in,
+                              double* Kbar, double* rbar, double* local);
+hdg_status hdg_assemble_batch(hdg_ctx ctx, hdg_batch b, const int32_t* f2e, const int32_t* e2f,
+                              const double* Kbar, const double* rbar, double* K64, float* K32,
+                              int32_t* nbr, double* r);
+hdg_status hdg_gmres_solve_batch(hdg_ctx ctx, hdg_batch b, const double* K64, const float* K32,
+                                 const int32_t* nbr, const double* r, double* x,
+                                 const hdg_solve_opts* opts_h, hdg_solve_stats* stats_h);
+hdg_status hdg_recover_batch(hdg_ctx ctx, hdg_batch b, const double* local, const double* Minv,
+                             const double* Bd, const double* Cd, const int32_t* e2f, const double* xhat,
+                             double* du, double* dq);
+
 /* Host-only helpers (no device work; usable without a GPU) -- Section 4.7.
  * hdg_hessenberg_eigvals: eigenvalues of an n x n upper Hessenberg matrix H (row-major,
  *   leading dimension ld) by the shifted QR algorithm; returns 0 on success.

@@ -22,7 +22,12 @@ PRECISION = {"fp64": 0, "mixed": 1}
 SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
            "hdg_local_size", "hdg_condense", "hdg_assemble_blocks", "hdg_solve_opts_default", "hdg_gmres_solve",
            "hdg_recover_local", "hdg_newton_update", "hdg_matvec", "hdg_bj_setup", "hdg_bj_apply",
-           "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz"]
+           "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
+           "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
+           "hdg_gmres_solve_batch", "hdg_recover_batch"]
+
+BATCH_ARRAYS = ["Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "Kbar", "rbar", "local", "du", "dq",
+                "K", "nbr", "vec", "f2e", "e2f", "binv"]
 
 
 class HdgError(RuntimeError):
@@ -92,6 +97,15 @@ def load():
     pdbl = ctypes.POINTER(dbl)
     lib.hdg_hessenberg_eigvals.argtypes = [ctypes.c_int, pdbl, ctypes.c_int, pdbl, pdbl]
     lib.hdg_harmonic_ritz.argtypes = [ctypes.c_int, pdbl, dbl, pdbl, pdbl, ctypes.POINTER(ctypes.c_int)]
+    lib.hdg_batch_create.argtypes = [vp, i32, pd, ctypes.POINTER(vp)]
+    lib.hdg_batch_destroy.argtypes = [vp]
+    lib.hdg_batch_offsets.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.hdg_batch_tuned_grid.argtypes = [vp]
+    lib.hdg_condense_batch.argtypes = [vp, vp, ctypes.POINTER(ElemBlocks), vp, vp, vp]
+    lib.hdg_assemble_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_gmres_solve_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                          ctypes.POINTER(SolveStats)]
+    lib.hdg_recover_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("hdg_last_error", "hdg_local_size", "hdg_solve_opts_default",
                         "hdg_hessenberg_eigvals", "hdg_harmonic_ritz"):
@@ -318,3 +332,90 @@ class Context:
             _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision], len(th),
             tr.ctypes.data_as(pd), ti.ctypes.data_as(pd), _ptr(y, torch.float64, nf * nb, "y"),
             _ptr(z, torch.float64, nf * nb, "z")))
+
+
+class Batch:
+    """Device descriptor tables for many independent instances (hdg_batch_* entry points).
+
+    Arrays are the concatenation of the instances' arrays; `offsets(name)` gives each
+    instance's start (prefix sums of the per-instance sizes) in entries of that array."""
+
+    def __init__(self, ctx, dims_list):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.n = len(dims_list)
+        self.dims_list = [dict(d) for d in dims_list]
+        arr = (Dims * self.n)(*[make_dims(d) for d in dims_list])
+        self.h = ctypes.c_void_p()
+        ctx._check(self.lib.hdg_batch_create(ctx.h, self.n, arr, ctypes.byref(self.h)))
+        self._off = {}
+        for k, name in enumerate(BATCH_ARRAYS):
+            o = np.zeros(self.n + 1, dtype=np.int64)
+            self.lib.hdg_batch_offsets(self.h, k, o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+            self._off[name] = o
+
+    def offsets(self, name):
+        return self._off[name]
+
+    def total(self, name):
+        return int(self._off[name][-1])
+
+    def tuned_grid(self):
+        return int(self.lib.hdg_batch_tuned_grid(self.h))
+
+    def close(self):
+        if self.h:
+            self.lib.hdg_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def condense(self, blk, Kbar, rbar, local):
+        import torch
+        f64 = torch.float64
+        names = [f[0] for f in ElemBlocks._fields_]
+        eb = ElemBlocks(*[_ptr(blk[k], f64, self.total(k), k) for k in names])
+        return self.ctx._check(self.lib.hdg_condense_batch(
+            self.ctx.h, self.h, ctypes.byref(eb), _ptr(Kbar, f64, self.total("Kbar"), "Kbar"),
+            _ptr(rbar, f64, self.total("rbar"), "rbar"), _ptr(local, f64, self.total("local"), "local")))
+
+    def assemble(self, f2e, e2f, Kbar, rbar, K64, K32, nbr, r):
+        import torch
+        return self.ctx._check(self.lib.hdg_assemble_batch(
+            self.ctx.h, self.h, _ptr(f2e, torch.int32, self.total("f2e"), "f2e"),
+            _ptr(e2f, torch.int32, self.total("e2f"), "e2f"), _ptr(Kbar, torch.float64, self.total("Kbar"), "Kbar"),
+            _ptr(rbar, torch.float64, self.total("rbar"), "rbar"), _ptr(K64, torch.float64, self.total("K"), "K64"),
+            _ptr(K32, torch.float32, self.total("K"), "K32", allow_none=True),
+            _ptr(nbr, torch.int32, self.total("nbr"), "nbr"), _ptr(r, torch.float64, self.total("vec"), "r")))
+
+    def gmres_solve(self, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0, prec="bj",
+                    orth="cgs2", precision="fp64", use_graph=False):
+        import torch
+        o = SolveOpts()
+        self.lib.hdg_solve_opts_default(ctypes.byref(o))
+        o.restart, o.max_iters, o.rtol, o.atol = restart, max_iters, rtol, atol
+        o.prec, o.orth, o.precision = PREC[prec], ORTH[orth], PRECISION[precision]
+        o.use_graph = 1 if use_graph else 0
+        stats = (SolveStats * self.n)()
+        st = self.ctx._check(self.lib.hdg_gmres_solve_batch(
+            self.ctx.h, self.h, _ptr(K64, torch.float64, self.total("K"), "K64"),
+            _ptr(K32, torch.float32, self.total("K"), "K32", allow_none=True),
+            _ptr(nbr, torch.int32, self.total("nbr"), "nbr"), _ptr(r, torch.float64, self.total("vec"), "r"),
+            _ptr(x, torch.float64, self.total("vec"), "x"), ctypes.byref(o), stats))
+        out = [{k[0]: getattr(s_, k[0]) for k in SolveStats._fields_ if k[0] not in ("theta_re", "theta_im")}
+               for s_ in stats]
+        return st, out
+
+    def recover(self, local, Minv, Bd, Cd, e2f, xhat, du, dq):
+        import torch
+        f64 = torch.float64
+        return self.ctx._check(self.lib.hdg_recover_batch(
+            self.ctx.h, self.h, _ptr(local, f64, self.total("local"), "local"),
+            _ptr(Minv, f64, self.total("Minv"), "Minv"), _ptr(Bd, f64, self.total("Bd"), "Bd"),
+            _ptr(Cd, f64, self.total("Cd"), "Cd"), _ptr(e2f, torch.int32, self.total("e2f"), "e2f"),
+            _ptr(xhat, f64, self.total("vec"), "xhat"), _ptr(du, f64, self.total("du"), "du"),
+            _ptr(dq, f64, self.total("dq"), "dq")))

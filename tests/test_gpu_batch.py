@@ -1,0 +1,113 @@
+"""Batched independent instances (the 512-instance 2D Poisson/Burgers workload and
+subsets of it): every instance of the batched GPU path against its own oracle
+solve (condensation, assembly, FGMRES, recovery)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import configs
+
+from helpers import oracle_pipeline
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2512_13619_amd import hdg
+    assert torch.cuda.is_available()
+    return hdg.Context(0)
+
+
+def relerr(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+class BatchData:
+    def __init__(self, ctx, problems, device="cuda"):
+        from paper_2512_13619_amd import hdg
+        self.pbs = problems
+        self.bt = hdg.Batch(ctx, [pb.dims() for pb in problems])
+        bt = self.bt
+        names = ["Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt"]
+        parts = {k: [] for k in names}
+        for pb in problems:
+            b = pb.element_blocks()
+            for k in names:
+                parts[k].append(b[k].reshape(-1).to(device))
+        self.blk = {k: torch.cat(parts[k]).contiguous() for k in names}
+        i32 = lambda arrs: torch.as_tensor(np.concatenate([a.reshape(-1) for a in arrs]).astype(np.int32)).to(device)
+        self.f2e = i32([pb.mesh.f2e for pb in problems])
+        self.e2f = i32([pb.mesh.e2f for pb in problems])
+        z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device=device)
+        self.Kbar, self.rbar, self.local = z(bt.total("Kbar")), z(bt.total("rbar")), z(bt.total("local"))
+        self.K64, self.K32 = z(bt.total("K")), z(bt.total("K"), torch.float32)
+        self.nbr = torch.zeros(bt.total("nbr"), dtype=torch.int32, device=device)
+        self.r, self.x = z(bt.total("vec")), z(bt.total("vec"))
+        self.du, self.dq = z(bt.total("du")), z(bt.total("dq"))
+
+    def run(self, **kw):
+        bt = self.bt
+        bt.condense(self.blk, self.Kbar, self.rbar, self.local)
+        bt.assemble(self.f2e, self.e2f, self.Kbar, self.rbar, self.K64, self.K32, self.nbr, self.r)
+        self.x.zero_()
+        st, stats = bt.gmres_solve(self.K64, self.K32, self.nbr, self.r, self.x, **kw)
+        bt.recover(self.local, self.blk["Minv"], self.blk["Bd"], self.blk["Cd"], self.e2f, self.x, self.du, self.dq)
+        torch.cuda.synchronize()
+        return st, stats
+
+    def part(self, name, tensor, i):
+        o = self.bt.offsets(name)
+        return tensor[o[i]:o[i + 1]].cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_subset_matches_per_instance_oracle(ctx, precision):
+    pbs = [configs.c4_instance(i) for i in range(10)]
+    # keep the subset small: cap the largest meshes (oracle cost), sizes stay uneven
+    pbs = [pb for pb in pbs if pb.mesh.ne <= 800][:6]
+    say("batch subset", precision, [(pb.etype, pb.mesh.ne, pb.p) for pb in pbs])
+    bd = BatchData(ctx, pbs)
+    st, stats = bd.run(restart=30, max_iters=5000, rtol=1e-13, precision=precision, use_graph=True)
+    assert st == 0, stats
+    say("  tuned grid", bd.bt.tuned_grid(), "iters", [s["iters"] for s in stats])
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    for i, pb in enumerate(pbs):
+        out = oracle_pipeline(pb)
+        assert relerr(bd.part("Kbar", bd.Kbar, i), out["Kbar"].ravel()) < 1e-11
+        assert np.array_equal(bd.part("nbr", bd.nbr, i), out["nbr"].ravel())
+        ex = relerr(bd.part("vec", bd.x, i), out["x"])
+        eu = relerr(bd.part("du", bd.du, i), out["du"].ravel())
+        eq = relerr(bd.part("dq", bd.dq, i), out["dq"].ravel())
+        say("  inst", i, stats[i]["iters"], ex, eu, eq)
+        assert stats[i]["converged"] and ex < tol and eu < tol and eq < tol, (i, ex, eu, eq)
+
+
+def test_batch_512_instances(ctx):
+    pbs = [configs.c4_instance(i, device="cuda") for i in range(512)]
+    say("batch 512", sum(pb.mesh.ne for pb in pbs), "elements")
+    bd = BatchData(ctx, pbs)
+    st, stats = bd.run(restart=50, max_iters=20000, rtol=1e-12, precision="fp64", use_graph=True)
+    its = [s["iters"] for s in stats]
+    say("  converged", sum(s["converged"] for s in stats), "iters min/max", min(its), max(its),
+        "tuned grid", bd.bt.tuned_grid())
+    assert st == 0 and all(s["converged"] for s in stats)
+    rng = np.random.default_rng(5)
+    small = [i for i, pb in enumerate(pbs) if pb.mesh.ne <= 600]
+    for i in rng.choice(small, size=4, replace=False):
+        pb = configs.c4_instance(int(i))
+        out = oracle_pipeline(pb)
+        ex = relerr(bd.part("vec", bd.x, i), out["x"])
+        eu = relerr(bd.part("du", bd.du, i), out["du"].ravel())
+        say("  inst", int(i), pb.etype, pb.p, pb.mesh.ne, ex, eu)
+        assert ex < 1e-9 and eu < 1e-9
+    # mixed precision at the workload tolerance
+    st, stats = bd.run(restart=50, max_iters=20000, rtol=1e-8, precision="mixed", use_graph=True)
+    assert st == 0 and all(s["converged"] and s["rel_resid_true"] <= 1e-8 for s in stats)
