@@ -140,6 +140,9 @@ def main():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-matvec", type=int, default=0,
+                    help="build the workload's matrix, run this many FP32 and FP64 block matvecs and a 1 GiB "
+                         "device copy (counter calibration), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the hot path is "
@@ -162,6 +165,27 @@ def main():
     ctx = hdg.Context(0)
     pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
     stream = torch.cuda.current_stream()
+    if args.profile_matvec > 0:
+        pl.condense(blk)
+        pl.assemble()
+        del blk
+        torch.cuda.synchronize()
+        reps = args.profile_matvec
+        t32 = time_matvec(ctx, pl, "mixed", reps)
+        t64 = time_matvec(ctx, pl, "fp64", reps)
+        nbr_np = pl.nbr.cpu().numpy()
+        nb = d["ncomp"] * d["npf"]
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "block matvec", "fp32_ms": t32 * 1e3, "fp64_ms": t64 * 1e3,
+                          "fp32_bytes": matvec_bytes(nbr_np, nb, 4), "fp64_bytes": matvec_bytes(nbr_np, nb, 8),
+                          "fp32_GBs": matvec_bytes(nbr_np, nb, 4) / t32 / 1e9,
+                          "fp64_GBs": matvec_bytes(nbr_np, nb, 8) / t64 / 1e9,
+                          "copy_bytes_each_way": src.numel() * 8}), flush=True)
+        return
 
     def step(precision):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]

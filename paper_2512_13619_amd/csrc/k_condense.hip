@@ -14,9 +14,10 @@
 // one (nu+nt) x (D P_E) by (D P_E) x (P_E + N_lfe P_F) product per component,
 // with W = M^{-1}[B_d | C_d] formed first. All products run on the FP64 matrix
 // cores (v_mfma_f64_16x16x4f64, 32x32 tiles per wave). The elimination is
-// right-looking and blocked: the panel (NB columns) is factorised in LDS, the
-// panel rows of the trailing columns are solved with L11, and the trailing
-// matrix is updated with MFMA from LDS-resident L21 and U12.
+// right-looking and blocked: the panel (NB columns, up to 64) is factorised in
+// LDS, the panel rows of the trailing columns are solved with L11 and written
+// back, and the trailing matrix is updated with MFMA from the LDS-resident L21
+// and the just-written U12 rows (L2-resident).
 //
 // Storage of T per element: the top nu rows live directly in the caller's
 // `local` buffer (row stride nu+nt+1), the bottom nt rows in a workspace.
@@ -167,6 +168,9 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __
 }
 
 // ---- blocked elimination of the first nu columns ----------------------------------------------
+// NBT: compile-time bound of the panel width (the triangular solve keeps one
+// column of U12 in registers).
+template <int NBT>
 __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top,
                                                 double* __restrict__ bot, int* bad_elem, int e_off) {
     extern __shared__ double sm[];
@@ -179,9 +183,7 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
     double* Be = bot + (size_t)e * cd.nt * C;
     auto rowp = [&](int r) -> double* { return r < nu ? Te + (size_t)r * C : Be + (size_t)(r - nu) * C; };
     const int ldp = NB + 1;
-    double* Pn = sm;                                   // R x ldp
-    double* U12 = sm + (size_t)R * ldp;                // NB x ldu
-    const int ldu = C - NB + 1;
+    double* Pn = sm;                                   // R x ldp (panel; L21 stays here)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     bool singular = false;
     for (int k0 = 0; k0 < nu; k0 += NB) {
@@ -250,11 +252,18 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
                     rb[col] = t;
                 }
             }
-            for (int kk = 0; kk < nbk; ++kk) {
-                double v = rowp(k0 + kk)[col];
-                for (int q = 0; q < kk; ++q) v -= Pn[kk * ldp + q] * U12[q * ldu + cl];
-                U12[kk * ldu + cl] = v;
-                rowp(k0 + kk)[col] = v;
+            // forward substitution with the unit lower L11; U12 rows go straight back to T
+            // (this thread re-reads only entries it wrote itself)
+            double u[NBT];
+#pragma unroll
+            for (int kk = 0; kk < NBT; ++kk) {
+                if (kk < nbk) {
+                    double v = rowp(k0 + kk)[col];
+#pragma unroll
+                    for (int q = 0; q < kk; ++q) v -= Pn[kk * ldp + q] * u[q];
+                    u[kk] = v;
+                    rowp(k0 + kk)[col] = v;
+                }
             }
         }
         __syncthreads();
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
             };
             auto lb = [&](int k, int j) -> double {
                 const int c = c0 + j;
-                return (k < nbk && c < ncol) ? U12[k * ldu + c] : 0.0;
+                return (k < nbk && c < ncol) ? rowp(k0 + k)[cbeg + c] : 0.0;
             };
             mfma_32x32(la, lb, nbk, acc);
 #pragma unroll
@@ -311,9 +320,7 @@ __global__ __launch_bounds__(BS) void k_cond_copyout(CondDims cd, const double* 
     for (int i = threadIdx.x; i < nt; i += BS) rbar[(size_t)e * nt + i] = Be[(size_t)i * C + C - 1];
 }
 
-size_t lu_lds_bytes(const CondDims& cd, int NB) {
-    return sizeof(double) * ((size_t)cd.R * (NB + 1) + (size_t)NB * (cd.C - NB + 1));
-}
+size_t lu_lds_bytes(const CondDims& cd, int NB) { return sizeof(double) * (size_t)cd.R * (NB + 1); }
 
 }  // namespace
 
@@ -351,9 +358,10 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
     const int big = 0x7fffffff;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     const size_t lds = lu_lds_bytes(cd, NB);
+    const void* lu_fn = NB <= 16 ? (const void*)k_cond_lu<16> : NB <= 32 ? (const void*)k_cond_lu<32>
+                                                                          : (const void*)k_cond_lu<64>;
     if (lds > 64 * 1024)
-        HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_lu, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds));
+        HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
         const int64_t n = (ne - e0) < chunk ? (ne - e0) : chunk;
         const size_t P = cd.P, LPF = (size_t)cd.L * cd.PF;
@@ -365,8 +373,15 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
                            in->G + e0 * cd.nt * cd.nq, in->H + e0 * cd.nt * cd.nu, in->J + e0 * cd.nt * cd.nt,
                            in->ru + e0 * cd.nu, in->rt + e0 * cd.nt, W, local + e0 * cd.nu * cd.C, bot);
         HDG_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_cond_lu, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
-                           local + e0 * cd.nu * cd.C, bot, status, (int)e0);
+        if (NB <= 16)
+            hipLaunchKernelGGL(k_cond_lu<16>, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
+                               local + e0 * cd.nu * cd.C, bot, status, (int)e0);
+        else if (NB <= 32)
+            hipLaunchKernelGGL(k_cond_lu<32>, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
+                               local + e0 * cd.nu * cd.C, bot, status, (int)e0);
+        else
+            hipLaunchKernelGGL(k_cond_lu<64>, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
+                               local + e0 * cd.nu * cd.C, bot, status, (int)e0);
         HDG_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_cond_copyout, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,
                            Kbar + e0 * cd.nt * cd.nt, rbar + e0 * cd.nt);

@@ -70,24 +70,27 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
         const T1* Mf = static_cast<const T1*>(A.M1) + (size_t)f * S * nb * nb;
         const T1* p = Mf + (size_t)grp * nb + row;
         const size_t step = (size_t)G * nb;
+        // U independent streaming loads in flight per thread (more for 4-byte entries)
+        constexpr int U = sizeof(T1) == 4 ? 8 : 4;
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = 0.0;
         int k = grp;
-        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        for (; k + 3 * G < ncols; k += 4 * G) {
-            const double m0 = ld_stream(p);
-            const double m1 = ld_stream(p + step);
-            const double m2 = ld_stream(p + 2 * step);
-            const double m3 = ld_stream(p + 3 * step);
-            a0 += m0 * xs[k];
-            a1 += m1 * xs[k + G];
-            a2 += m2 * xs[k + 2 * G];
-            a3 += m3 * xs[k + 3 * G];
-            p += 4 * step;
+        for (; k + (U - 1) * G < ncols; k += U * G) {
+            T1 m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) m[u] = __builtin_nontemporal_load(p + u * step);
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] += (double)m[u] * xs[k + u * G];
+            p += U * step;
         }
         for (; k < ncols; k += G) {
-            a0 += ld_stream(p) * xs[k];
+            a[0] += ld_stream(p) * xs[k];
             p += step;
         }
-        acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+        for (int u = 1; u < U; ++u) a[0] += a[u];
+        acc = a[0];
     }
     red[threadIdx.x] = acc;
     __syncthreads();

@@ -90,6 +90,7 @@ def test_batch_subset_matches_per_instance_oracle(ctx, precision):
         assert stats[i]["converged"] and ex < tol and eu < tol and eq < tol, (i, ex, eu, eq)
 
 
+@pytest.mark.timeout(900)
 def test_batch_512_instances(ctx):
     pbs = [configs.c4_instance(i, device="cuda") for i in range(512)]
     say("batch 512", sum(pb.mesh.ne for pb in pbs), "elements")

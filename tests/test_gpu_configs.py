@@ -90,6 +90,7 @@ def _sample(n, k, rng):
     return base
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", list(FULL))
 def test_full_size_sampled(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
@@ -108,8 +109,6 @@ def test_full_size_sampled(ctx, name):
         e_need.add(int(e1))
         if e2 >= 0:
             e_need.add(int(e2))
-        for s in oasm.slot_faces(pb.mesh.f2e, pb.mesh.e2f, f)[0]:
-            pass
     samp_e = np.unique(np.concatenate([_sample(ne, 12, rng), np.array(sorted(e_need))]))
     host_blk = {}
     keep = {}
@@ -148,12 +147,15 @@ def test_full_size_sampled(ctx, name):
     K_g = pl.K64[torch.as_tensor(samp_f, device="cuda")].cpu().numpy()
     nbr_g = pl.nbr[torch.as_tensor(samp_f, device="cuda")].cpu().numpy()
     r_g = pl.r.view(nf, nb)[torch.as_tensor(samp_f, device="cuda")].cpu().numpy()
-    # oracle rows of the sampled faces from its own element Schur complements
-    Kfull = np.zeros((ne,) + Kb_o.shape[1:])
-    rfull = np.zeros((ne, Kb_o.shape[1]))
-    for e in order:
-        Kfull[e] = Kb_o[idx[e]]
-        rfull[e] = rb_o[idx[e]]
+    # oracle rows of the sampled faces from its own element Schur complements (sparse by element)
+    class _ByElem:
+        def __init__(self, arr):
+            self.arr = arr
+
+        def __getitem__(self, key):
+            return self.arr[(idx[key[0]],) + tuple(key[1:])]
+    Kfull = _ByElem(Kb_o)
+    rfull = _ByElem(rb_o)
     worst_k, worst_res = 0.0, 0.0
     for a, f in enumerate(samp_f):
         e1, l1, e2, l2 = pb.mesh.f2e[f]
