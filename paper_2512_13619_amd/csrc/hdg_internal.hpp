@@ -83,6 +83,11 @@ hdg_status vec_reduce(hdg_ctx ctx, const double* part, int J, int nblk, double* 
 hdg_status vec_multiaxpy(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h, double sign,
                          double* w, size_t n, const int* skip, const int* J_dev = nullptr);
 hdg_status vec_sumsq_partial(hdg_ctx ctx, const double* w, size_t n, double* part, int nblk, const int* skip);
+// Fused CGS2 second pass (J <= 64): w -= V h1 with partial dots V^T w; w -= V h2 with partial ||w||^2.
+hdg_status vec_axpy_dot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h1, double* w, size_t n,
+                        double* part, int nblk, const int* skip);
+hdg_status vec_axpy_sumsq(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h2, double* w, size_t n,
+                          double* part, int nblk, const int* skip);
 hdg_status vec_lincomb(hdg_ctx ctx, size_t n, double* out, double a, const double* X, double b,
                        const double* Y, const int* skip);
 

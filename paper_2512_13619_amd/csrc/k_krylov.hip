@@ -194,7 +194,110 @@ __global__ void k_backsolve(const GmresCtl* ctl, const double* H, int ldh, const
     for (int i = k; i < ldh - 1; ++i) y[i] = 0.0;
 }
 
+// Fused second Gram-Schmidt pass, part 1: w <- w - V h1 and partial dots V^T w
+// (the new w) in one read of V. Same chunking as k_multidot, so k_reduce applies.
+template <int JMAX>
+__global__ __launch_bounds__(BS) void k_axpy_dot(const double* __restrict__ V, size_t ldv, int J,
+                                                 const double* __restrict__ h1, double* __restrict__ w, size_t n,
+                                                 double* __restrict__ part, int nblk, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[JMAX][BS / 64];
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    double hh[JMAX], acc[JMAX];
+#pragma unroll
+    for (int i = 0; i < JMAX; ++i) {
+        hh[i] = i < J ? h1[i] : 0.0;
+        acc[i] = 0.0;
+    }
+    for (size_t k = k0 + threadIdx.x; k < k1; k += BS) {
+        double v[JMAX];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < JMAX; ++i) {
+            v[i] = i < J ? V[(size_t)i * ldv + k] : 0.0;
+            s += v[i] * hh[i];
+        }
+        const double wn = w[k] - s;
+        w[k] = wn;
+#pragma unroll
+        for (int i = 0; i < JMAX; ++i) acc[i] += v[i] * wn;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < JMAX; ++i) {
+        if (i < J) {
+            const double t = wave_sum(acc[i]);
+            if (lane == 0) red[i][wave] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < J) {
+        double t = 0.0;
+        for (int q = 0; q < BS / 64; ++q) t += red[threadIdx.x][q];
+        part[(size_t)threadIdx.x * nblk + blockIdx.x] = t;
+    }
+}
+
+// Fused second pass, part 2: w <- w - V h2 and partial sums of w^2 (the norm) in one read of V.
+template <int JMAX>
+__global__ __launch_bounds__(BS) void k_axpy_sumsq(const double* __restrict__ V, size_t ldv, int J,
+                                                   const double* __restrict__ h2, double* __restrict__ w, size_t n,
+                                                   double* __restrict__ part, int nblk, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[BS / 64];
+    const size_t chunk = (n + nblk - 1) / nblk;
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    double hh[JMAX];
+#pragma unroll
+    for (int i = 0; i < JMAX; ++i) hh[i] = i < J ? h2[i] : 0.0;
+    double acc = 0.0;
+    for (size_t k = k0 + threadIdx.x; k < k1; k += BS) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < JMAX; ++i)
+            if (i < J) s += V[(size_t)i * ldv + k] * hh[i];
+        const double wn = w[k] - s;
+        w[k] = wn;
+        acc += wn * wn;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < BS / 64; ++q) t += red[q];
+        part[blockIdx.x] = t;
+    }
+}
+
 }  // namespace
+
+hdg_status vec_axpy_dot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h1, double* w, size_t n,
+                        double* part, int nblk, const int* skip) {
+    if (J <= 16)
+        hipLaunchKernelGGL(k_axpy_dot<16>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h1, w, n, part, nblk, skip);
+    else if (J <= 32)
+        hipLaunchKernelGGL(k_axpy_dot<32>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h1, w, n, part, nblk, skip);
+    else
+        hipLaunchKernelGGL(k_axpy_dot<64>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h1, w, n, part, nblk, skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_axpy_sumsq(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h2, double* w, size_t n,
+                          double* part, int nblk, const int* skip) {
+    if (J <= 16)
+        hipLaunchKernelGGL(k_axpy_sumsq<16>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h2, w, n, part, nblk, skip);
+    else if (J <= 32)
+        hipLaunchKernelGGL(k_axpy_sumsq<32>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h2, w, n, part, nblk, skip);
+    else
+        hipLaunchKernelGGL(k_axpy_sumsq<64>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h2, w, n, part, nblk, skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
 
 hdg_status vec_multidot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* w, size_t n,
                         double* part, int nblk, const int* skip) {

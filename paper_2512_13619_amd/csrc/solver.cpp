@@ -405,8 +405,18 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             double* wv = w.V + (size_t)(j + 1) * w.ld;
             if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
             if ((s2 = op_matvec(ctx, op, zj, wv, skip)) != HDG_OK) return s2;
-            if ((s2 = orthogonalise(ctx, w, N, j, o->orth, skip)) != HDG_OK) return s2;
-            if ((s2 = vec_sumsq_partial(ctx, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+            if (o->orth == HDG_ORTH_CGS2 && j + 1 <= 64) {
+                // CGS2 with three reads of the basis: dots, (axpy + second dots), (axpy + norm)
+                double* col = w.H + (size_t)j * w.ldh;
+                if ((s2 = vec_multidot(ctx, w.V, w.ld, j + 1, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+                if ((s2 = vec_reduce(ctx, w.part, j + 1, w.nblk, col, nullptr, skip)) != HDG_OK) return s2;
+                if ((s2 = vec_axpy_dot(ctx, w.V, w.ld, j + 1, col, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+                if ((s2 = vec_reduce(ctx, w.part, j + 1, w.nblk, w.h2, col, skip)) != HDG_OK) return s2;
+                if ((s2 = vec_axpy_sumsq(ctx, w.V, w.ld, j + 1, w.h2, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+            } else {
+                if ((s2 = orthogonalise(ctx, w, N, j, o->orth, skip)) != HDG_OK) return s2;
+                if ((s2 = vec_sumsq_partial(ctx, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+            }
             if ((s2 = krylov_givens(ctx, w.ctl, w.part, w.nblk, w.H, w.ldh, w.cs, w.sn, w.g, j, w.hist)) != HDG_OK)
                 return s2;
             if ((s2 = krylov_scale_by(ctx, wv, wv, N, w.H + (size_t)j * w.ldh + j + 1, skip)) != HDG_OK) return s2;
