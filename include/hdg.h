@@ -134,8 +134,9 @@ hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
  * or after max_iters Arnoldi steps. The Hessenberg/Givens update runs on the
  * device in FP64; a whole cycle is enqueued at once (or replayed as one captured
  * hipGraph when use_graph = 1) and the host reads one status word per cycle.
- * The context's stream must not be used by other work while a captured cycle is
- * being recorded.
+ * With use_graph = 1 the solve drains the context's stream, runs on a private
+ * stream of the context (so the caller's stream may be the legacy null stream)
+ * and drains that stream before returning.
  *
  * precision = HDG_FP64: every operator application uses K64 and FP64 inverses.
  * precision = HDG_MIXED: inside a cycle the matvec and the preconditioner use K32

@@ -103,6 +103,7 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (int s = 0; s < WS_NSLOTS; ++s)
         if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return HDG_OK;
 }

@@ -275,6 +275,8 @@ hdg_status hdg_gmres_solve_batch(hdg_ctx ctx, hdg_batch b, const double* K64, co
     }
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
     const double t0 = now_s();
+    CaptureStreamScope cap;
+    if (o->use_graph) HDG_HIP_CHECK(ctx, cap.begin(ctx));
     const BatchDev& dv = b->dev;
     const int ni = dv.n_inst, m = o->restart, ldh = m + 1, ldg = m + 2;
     const size_t N = (size_t)dv.total_dof;

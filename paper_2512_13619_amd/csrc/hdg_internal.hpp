@@ -30,9 +30,38 @@ enum WsSlot {
 struct hdg_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
     std::string err;
     void* ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
+};
+
+// Runs the enclosing scope on the context's private capture stream: the caller's
+// stream (possibly the legacy null stream, which cannot be captured) is drained
+// first and the private stream is drained before the caller's is restored.
+struct CaptureStreamScope {
+    hdg_ctx ctx;
+    hipStream_t saved = nullptr;
+    bool active = false;
+    hipError_t begin(hdg_ctx c) {
+        ctx = c;
+        if (!c->cap_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return e;
+        saved = c->stream;
+        c->stream = c->cap_stream;
+        active = true;
+        return hipSuccess;
+    }
+    ~CaptureStreamScope() {
+        if (active) {
+            (void)hipStreamSynchronize(ctx->stream);
+            ctx->stream = saved;
+        }
+    }
 };
 
 // Returns a device buffer of at least `bytes` for `slot` (grows, never shrinks).

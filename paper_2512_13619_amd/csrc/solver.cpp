@@ -290,6 +290,8 @@ void hdg_solve_opts_default(hdg_solve_opts* o) {
 hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const float* K32, const int32_t* nbr,
                      const double* b, double* x, const hdg_solve_opts* o, hdg_solve_stats* stats) {
     const double t0 = now_s();
+    CaptureStreamScope cap;
+    if (o->use_graph) HDG_HIP_CHECK(ctx, cap.begin(ctx));
     std::memset(stats, 0, sizeof(*stats));
     const int nb = d->ncomp * d->npf, L = d->nlfe, S = 2 * L - 1, nf = d->nf;
     const size_t N = (size_t)nf * nb;
