@@ -80,6 +80,9 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
             T1 m[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) m[u] = __builtin_nontemporal_load(p + u * step);
+            // keep the U loads in flight together: without this the scheduler interleaves
+            // each 4-byte load with its wait and conversion, serialising the stream
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) a[u] += (double)m[u] * xs[k + u * G];
             p += U * step;
