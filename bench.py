@@ -54,6 +54,21 @@ def matvec_bytes(nbr_np, nb, wbytes):
     return nblocks * nb * nb * wbytes + nf * S * 4 + 2 * nf * nb * 8
 
 
+def measured_traffic(kind):
+    """Counter-measured HBM bytes per launch of the block matvec (profiles/ record), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "block_matvec_counters_elasticity24_p3.json")
+    try:
+        rec = json.load(open(rec_path))
+        src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+    except Exception:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    return rec[kind]["traffic_bytes"]
+
+
 def time_matvec(ctx, pl, precision, reps=100):
     import torch
     x = torch.randn(pl.x.numel(), dtype=torch.float64, device="cuda")
@@ -275,7 +290,8 @@ def main():
         "matvec_fp32_ms": t_mv32 * 1e3,
         "matvec_fp64_ms": t_mv64 * 1e3,
         "roofline": {"bound": "hbm", "achieved": gbs32, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": gbs32 / PEAK_HBM_GBS, "traffic": None,
+                     "frac": gbs32 / PEAK_HBM_GBS,
+                     "traffic": (measured_traffic("fp32_matvec") if (args.n, args.p) == (24, 3) else None),
                      "kernel": "k_face_op<float,float,256,false,0> (FP32 block matvec)",
                      "bytes_per_launch": b32},
     }
