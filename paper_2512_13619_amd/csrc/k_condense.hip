@@ -169,10 +169,11 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __
 
 // ---- blocked elimination of the first nu columns ----------------------------------------------
 // NBT: compile-time bound of the panel width (the triangular solve keeps one
-// column of U12 in registers).
-template <int NBT>
-__global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top,
-                                                double* __restrict__ bot, int* bad_elem, int e_off) {
+// column of U12 in registers). LBS threads share the LDS panel (512 for panels of
+// up to 32 columns, so eight waves hide the trailing update's memory latency).
+template <int NBT, int LBS>
+__global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top,
+                                                 double* __restrict__ bot, int* bad_elem, int e_off) {
     extern __shared__ double sm[];
     __shared__ int piv[64];
     __shared__ double pval;
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
         const int nbk = (nu - k0) < NB ? (nu - k0) : NB;
         const int nrow = R - k0;
         // 1. load the panel
-        for (int idx = threadIdx.x; idx < nrow * nbk; idx += BS) {
+        for (int idx = threadIdx.x; idx < nrow * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
             Pn[li * ldp + kk] = rowp(k0 + li)[k0 + kk];
         }
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
             double pv = pval;
             if (!(fabs(pv) > 0.0) || !isfinite(pv)) { singular = true; pv = 1.0; }
             if (p != kk) {
-                for (int c = threadIdx.x; c < nbk; c += BS) {
+                for (int c = threadIdx.x; c < nbk; c += LBS) {
                     const double t = Pn[kk * ldp + c];
                     Pn[kk * ldp + c] = Pn[p * ldp + c];
                     Pn[p * ldp + c] = t;
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
             }
             __syncthreads();
             const double inv = 1.0 / pv;
-            for (int li = kk + 1 + threadIdx.x; li < nrow; li += BS) {
+            for (int li = kk + 1 + threadIdx.x; li < nrow; li += LBS) {
                 const double mlt = Pn[li * ldp + kk] * inv;
                 Pn[li * ldp + kk] = mlt;
                 for (int c = kk + 1; c < nbk; ++c) Pn[li * ldp + c] -= mlt * Pn[kk * ldp + c];
@@ -233,14 +234,14 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
             __syncthreads();
         }
         // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final)
-        for (int idx = threadIdx.x; idx < nbk * nbk; idx += BS) {
+        for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
             rowp(k0 + li)[k0 + kk] = Pn[li * ldp + kk];
         }
         // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread per column)
         const int cbeg = k0 + nbk;
         const int ncol = C - cbeg;
-        for (int cl = threadIdx.x; cl < ncol; cl += BS) {
+        for (int cl = threadIdx.x; cl < ncol; cl += LBS) {
             const int col = cbeg + cl;
             for (int kk = 0; kk < nbk; ++kk) {
                 const int p = piv[kk];
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(BS) void k_cond_lu(CondDims cd, int NB, double* __r
         // 5. trailing update T22 -= L21 U12 (MFMA, 32x32 tiles per wave)
         const int nrow2 = R - cbeg;
         const int tr = (nrow2 + 31) / 32, tc = (ncol + 31) / 32;
-        for (int tile = wave; tile < tr * tc; tile += BS / 64) {
+        for (int tile = wave; tile < tr * tc; tile += LBS / 64) {
             const int r0 = (tile / tc) * 32, c0 = (tile % tc) * 32;
             double4_t acc[2][2];
 #pragma unroll
@@ -358,8 +359,8 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
     const int big = 0x7fffffff;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     const size_t lds = lu_lds_bytes(cd, NB);
-    const void* lu_fn = NB <= 16 ? (const void*)k_cond_lu<16> : NB <= 32 ? (const void*)k_cond_lu<32>
-                                                                          : (const void*)k_cond_lu<64>;
+    const void* lu_fn = NB <= 16 ? (const void*)k_cond_lu<16, 512> : NB <= 32 ? (const void*)k_cond_lu<32, 512>
+                                                                               : (const void*)k_cond_lu<64, 256>;
     if (lds > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
@@ -374,13 +375,13 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
                            in->ru + e0 * cd.nu, in->rt + e0 * cd.nt, W, local + e0 * cd.nu * cd.C, bot);
         HDG_LAUNCH_CHECK(ctx);
         if (NB <= 16)
-            hipLaunchKernelGGL(k_cond_lu<16>, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
+            hipLaunchKernelGGL((k_cond_lu<16, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB,
                                local + e0 * cd.nu * cd.C, bot, status, (int)e0);
         else if (NB <= 32)
-            hipLaunchKernelGGL(k_cond_lu<32>, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
+            hipLaunchKernelGGL((k_cond_lu<32, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB,
                                local + e0 * cd.nu * cd.C, bot, status, (int)e0);
         else
-            hipLaunchKernelGGL(k_cond_lu<64>, dim3((unsigned)n), dim3(BS), lds, ctx->stream, cd, NB,
+            hipLaunchKernelGGL((k_cond_lu<64, 256>), dim3((unsigned)n), dim3(256), lds, ctx->stream, cd, NB,
                                local + e0 * cd.nu * cd.C, bot, status, (int)e0);
         HDG_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_cond_copyout, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,

@@ -135,7 +135,10 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
 template <typename T1, typename T2, bool HAS_M2, int KIND>
 hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     int team;
-    const int want = 4 * a.nb;
+    // a block row (S1 > 1) has S1*nb columns: 4 column groups keep every thread busy; a
+    // block-diagonal product (S1 == 1) has only nb columns, so fewer groups give each
+    // thread a longer run of loads
+    const int want = (a.S1 > 1 ? 4 : 2) * a.nb;
     if (a.nb > 64 || want > 128) team = 256;
     else if (want > 64) team = 128;
     else if (want > 32) team = 64;

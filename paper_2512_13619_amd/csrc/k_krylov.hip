@@ -19,32 +19,36 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// part[i*nblk + b] = sum_{k in chunk b} V[i][k] w[k],  i < J
+// part[i*nblk + b] = sum_{k in chunk b} V[i][k] w[k],  i < J.
+// The block's slice of w is staged in LDS; each wave owns a subset of the vectors and
+// streams them with U loads in flight per lane, so one wave writes each partial.
+constexpr int CHUNK = 2048;        // entries per block (the partial layout depends on it)
+
+template <int U>
 __global__ __launch_bounds__(BS) void k_multidot(const double* __restrict__ V, size_t ldv, int J,
                                                  const double* __restrict__ w, size_t n,
                                                  double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
-    __shared__ double red[64][BS / 64];
-    const size_t chunk = (n + nblk - 1) / nblk;
-    const size_t k0 = (size_t)blockIdx.x * chunk;
-    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    __shared__ double ws[CHUNK];
+    const size_t k0 = (size_t)blockIdx.x * CHUNK;
+    const int len = (int)(k0 + CHUNK < n ? CHUNK : n - k0);
+    for (int k = threadIdx.x; k < len; k += BS) ws[k] = w[k0 + k];
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i0 = 0; i0 < J; i0 += 64) {
-        const int ni = (J - i0) < 64 ? (J - i0) : 64;
-        for (int ii = 0; ii < ni; ++ii) {
-            const double* v = V + (size_t)(i0 + ii) * ldv;
-            double acc = 0.0;
-            for (size_t k = k0 + threadIdx.x; k < k1; k += BS) acc += v[k] * w[k];
-            acc = wave_sum(acc);
-            if (lane == 0) red[ii][wave] = acc;
+    for (int i = wave; i < J; i += BS / 64) {
+        const double* v = V + (size_t)i * ldv + k0;
+        double acc = 0.0;
+        for (int k = lane; k < len; k += 64 * U) {
+            double m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) m[u] = (k + 64 * u < len) ? v[k + 64 * u] : 0.0;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k + 64 * u < len) acc += m[u] * ws[k + 64 * u];
         }
-        __syncthreads();
-        if (threadIdx.x < ni) {
-            double s = 0.0;
-            for (int q = 0; q < BS / 64; ++q) s += red[threadIdx.x][q];
-            part[(size_t)(i0 + threadIdx.x) * nblk + blockIdx.x] = s;
-        }
-        __syncthreads();
+        acc = wave_sum(acc);
+        if (lane == 0) part[(size_t)i * nblk + blockIdx.x] = acc;
     }
 }
 
@@ -64,7 +68,7 @@ __global__ void k_reduce(const double* __restrict__ part, int J, int nblk, doubl
     }
 }
 
-// w[k] += sign * sum_{i<J} V[i][k] h[i]
+// w[k] += sign * sum_{i<J} V[i][k] h[i]  (vectors in groups of 8 loads in flight)
 __global__ __launch_bounds__(BS) void k_multiaxpy(const double* __restrict__ V, size_t ldv, int J,
                                                   const double* __restrict__ h, double sign, double* w,
                                                   size_t n, const int* skip, const int* J_dev) {
@@ -73,7 +77,15 @@ __global__ __launch_bounds__(BS) void k_multiaxpy(const double* __restrict__ V, 
     if (k >= n) return;
     const int JJ = J_dev ? *J_dev : J;
     double acc = 0.0;
-    for (int i = 0; i < JJ; ++i) acc += V[(size_t)i * ldv + k] * h[i];
+    for (int i0 = 0; i0 < JJ; i0 += 8) {
+        double m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = (i0 + u < JJ) ? V[(size_t)(i0 + u) * ldv + k] : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u < JJ) acc += m[u] * h[i0 + u];
+    }
     w[k] += sign * acc;
 }
 
@@ -81,9 +93,8 @@ __global__ __launch_bounds__(BS) void k_sumsq(const double* __restrict__ w, size
                                               const int* skip) {
     if (skip && *skip) return;
     __shared__ double red[BS / 64];
-    const size_t chunk = (n + nblk - 1) / nblk;
-    const size_t k0 = (size_t)blockIdx.x * chunk;
-    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    const size_t k0 = (size_t)blockIdx.x * CHUNK;
+    const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
     double acc = 0.0;
     for (size_t k = k0 + threadIdx.x; k < k1; k += BS) acc += w[k] * w[k];
     acc = wave_sum(acc);
@@ -202,9 +213,8 @@ __global__ __launch_bounds__(BS) void k_axpy_dot(const double* __restrict__ V, s
                                                  double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
     __shared__ double red[JMAX][BS / 64];
-    const size_t chunk = (n + nblk - 1) / nblk;
-    const size_t k0 = (size_t)blockIdx.x * chunk;
-    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
+    const size_t k0 = (size_t)blockIdx.x * CHUNK;
+    const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
     double hh[JMAX], acc[JMAX];
 #pragma unroll
     for (int i = 0; i < JMAX; ++i) {
@@ -247,18 +257,20 @@ __global__ __launch_bounds__(BS) void k_axpy_sumsq(const double* __restrict__ V,
                                                    double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
     __shared__ double red[BS / 64];
-    const size_t chunk = (n + nblk - 1) / nblk;
-    const size_t k0 = (size_t)blockIdx.x * chunk;
-    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
-    double hh[JMAX];
-#pragma unroll
-    for (int i = 0; i < JMAX; ++i) hh[i] = i < J ? h2[i] : 0.0;
+    const size_t k0 = (size_t)blockIdx.x * CHUNK;
+    const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
     double acc = 0.0;
     for (size_t k = k0 + threadIdx.x; k < k1; k += BS) {
         double s = 0.0;
+        for (int i0 = 0; i0 < J; i0 += 8) {
+            double m[8];
 #pragma unroll
-        for (int i = 0; i < JMAX; ++i)
-            if (i < J) s += V[(size_t)i * ldv + k] * hh[i];
+            for (int u = 0; u < 8; ++u) m[u] = (i0 + u < J) ? V[(size_t)(i0 + u) * ldv + k] : 0.0;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < J) s += m[u] * h2[i0 + u];
+        }
         const double wn = w[k] - s;
         w[k] = wn;
         acc += wn * wn;
@@ -302,7 +314,7 @@ hdg_status vec_axpy_sumsq(hdg_ctx ctx, const double* V, size_t ldv, int J, const
 hdg_status vec_multidot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* w, size_t n,
                         double* part, int nblk, const int* skip) {
     if (J <= 0) return HDG_OK;
-    hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, w, n, part, nblk, skip);
+    hipLaunchKernelGGL(k_multidot<8>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, w, n, part, nblk, skip);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

@@ -192,7 +192,7 @@ hdg_status alloc_solve_ws(hdg_ctx ctx, size_t N, int m, int P, SolveWs* w) {
     if (!w->Z) return st;
     w->work = (double*)ws_get(ctx, WS_VEC, sizeof(double) * w->ld * 5, &st);
     if (!w->work) return st;
-    w->nblk = (int)std::min<size_t>(1024, std::max<size_t>(1, (N + 2047) / 2048));
+    w->nblk = krylov_nblk(N);
     w->part = (double*)ws_get(ctx, WS_PART, sizeof(double) * (size_t)w->nblk * (mv + 2), &st);
     if (!w->part) return st;
     w->ldh = mv + 1;

@@ -321,7 +321,8 @@ class HDGProblem:
         Rt_bnd = torch.einsum("elq,elqa,qj->elaj", dA, uhf - uD, psi)
         Rt = intr[..., None, None] * Rt_int + bndm[..., None, None] * Rt_bnd
         rt = (-Rt).reshape(E, L * M * PF)
-        return dict(Minv=Minv, Bd=Bd, Cd=Cd, D=Dm, E=Em, F=Fm, G=Gm, H=Hm, J=Jm, ru=ru, rt=rt)
+        out = dict(Minv=Minv, Bd=Bd, Cd=Cd, D=Dm, E=Em, F=Fm, G=Gm, H=Hm, J=Jm, ru=ru, rt=rt)
+        return {k: v.contiguous() for k, v in out.items()}
 
     def state_dofs(self, e0=0, e1=None):
         """Nodal linearisation state (u0 (E,M,npe), uhat0 (E,L,M,npf))."""
