@@ -6,7 +6,9 @@ A step is one pass of the whole hot path over the resident element blocks of the
   condensation -> face assembly -> FGMRES(50)+block-Jacobi to rtol 1e-8 -> recovery.
 The headline value is the mixed-precision step (FP32 matrix and block inverses in
 the Krylov cycles, FP64 residual/Arnoldi/Givens/update); the FP64 step, the solve
-times and the block-matvec bandwidth are reported next to it.
+times and the block-matvec and block-Jacobi bandwidths are reported next to it. The
+kernel rates come from HIP events that the library records on its own stream
+around every matvec, preconditioner and orthogonalisation of the timed solves.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -209,7 +211,8 @@ def main():
         ev[1].record(stream)
         pl.assemble()
         ev[2].record(stream)
-        st = pl.solve(restart=50, max_iters=20000, rtol=1e-8, prec="bj", orth="cgs2", precision=precision)
+        st = pl.solve(restart=50, max_iters=20000, rtol=1e-8, prec="bj", orth="cgs2", precision=precision,
+                      time_phases=True)
         ev[3].record(stream)
         pl.recover(blk["Minv"], blk["Bd"], blk["Cd"])
         ev[4].record(stream)
@@ -248,16 +251,26 @@ def main():
         dx = float(((x_mixed - pl.x).norm() / pl.x.norm()).item())
     else:
         dx = None
-    # block matvec bandwidth (live HIP-event timing on the library's stream)
+    # kernel rates inside the timed solves: the library records HIP events on its own stream
+    # around the preconditioner, the matvec and the orthogonalisation of every Arnoldi step
     nbr_np = pl.nbr.cpu().numpy()
     nb = d["ncomp"] * d["npf"]
-    t_mv32 = time_matvec(ctx, pl, "mixed")
-    t_mv64 = time_matvec(ctx, pl, "fp64")
+    N = d["nf"] * nb
     b32 = matvec_bytes(nbr_np, nb, 4)
     b64 = matvec_bytes(nbr_np, nb, 8)
-    gbs32 = b32 / t_mv32 / 1e9
-    gbs64 = b64 / t_mv64 / 1e9
-    log(f"matvec fp32 {t_mv32 * 1e3:.3f} ms {gbs32:.0f} GB/s, fp64 {t_mv64 * 1e3:.3f} ms {gbs64:.0f} GB/s")
+    bj32 = d["nf"] * nb * nb * 4 + 2 * N * 8
+    bj64 = d["nf"] * nb * nb * 8 + 2 * N * 8
+
+    def rates(stt, bmv, bbj):
+        n = max(stt["n_timed"], 1)
+        t_mv, t_bj = stt["t_matvec"] / n, stt["t_prec"] / n
+        return dict(n_timed=stt["n_timed"], matvec_ms=t_mv * 1e3, matvec_GBs=bmv / t_mv / 1e9,
+                    bj_apply_ms=t_bj * 1e3, bj_apply_GBs=bbj / t_bj / 1e9,
+                    t_matvec_s=stt["t_matvec"], t_prec_s=stt["t_prec"], t_orth_s=stt["t_orth"])
+    r32 = rates(st_mixed, b32, bj32)
+    r64 = rates(st64, b64, bj64) if st64 else None
+    log("in-solve rates mixed", r32)
+    log("in-solve rates fp64", r64)
     line = {
         "metric": METRIC,
         "value": t_mixed,
@@ -285,15 +298,14 @@ def main():
         "iters_fp64": st64["iters"] if st64 else None,
         "rel_resid_fp64": st64["rel_resid_true"] if st64 else None,
         "mixed_vs_fp64_solution_reldiff": dx,
-        "matvec_fp32_GBs": gbs32,
-        "matvec_fp64_GBs": gbs64,
-        "matvec_fp32_ms": t_mv32 * 1e3,
-        "matvec_fp64_ms": t_mv64 * 1e3,
-        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": gbs32 / PEAK_HBM_GBS,
+        "kernels_mixed": r32,
+        "kernels_fp64": r64,
+        "roofline": {"bound": "hbm", "achieved": r32["matvec_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": r32["matvec_GBs"] / PEAK_HBM_GBS,
                      "traffic": (measured_traffic("fp32_matvec") if (args.n, args.p) == (24, 3) else None),
                      "kernel": "k_face_op<float,float,256,false,0> (FP32 block matvec)",
-                     "bytes_per_launch": b32},
+                     "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
+                     "timing": "HIP events around each matvec launch of the timed mixed solves"},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, blk, pl, st_mixed["iters"])

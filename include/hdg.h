@@ -169,6 +169,10 @@ typedef struct {
     double* resid_hist_h;       /* host, optional: ||r|| at each cycle start and Givens estimates */
     int32_t resid_hist_len;
     int32_t use_graph;          /* 1: capture one restart cycle in a hipGraph and replay it */
+    int32_t time_phases;        /* 1: HIP events around the preconditioner, matvec and
+                                   orthogonalisation of every Arnoldi step (fills t_prec,
+                                   t_matvec, t_orth, n_timed; the cycle is then enqueued
+                                   directly even when use_graph = 1) */
 } hdg_solve_opts;
 
 typedef struct {
@@ -178,6 +182,10 @@ typedef struct {
     double  t_setup, t_total;   /* seconds (host clock around the stream work) */
     double  theta_re[64], theta_im[64];   /* Leja-ordered Ritz values (polynomial preconditioners) */
     int32_t hist_len;           /* entries written to resid_hist_h */
+    int32_t n_timed;            /* Arnoldi steps timed (time_phases = 1), else 0 */
+    double  t_prec, t_matvec, t_orth;     /* seconds of device time over the timed steps:
+                                   preconditioner, the step's one matvec, and orthogonalisation
+                                   + Givens + normalisation (HIP events on the solve's stream) */
 } hdg_solve_stats;
 
 void       hdg_solve_opts_default(hdg_solve_opts* opts_h);
@@ -241,7 +249,8 @@ hdg_status hdg_poly_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, 
  * hdg_gmres_solve_batch: one FGMRES per instance (own Arnoldi basis segment,
  *   Hessenberg, Givens rotations, tolerance relative to its own ||r_i||); finished
  *   instances are masked while the others continue; opts as for hdg_gmres_solve
- *   with prec NONE or BJ and orth CGS2 or CGS; stats_h has n_inst entries.
+ *   with prec NONE or BJ and orth CGS2 or CGS (time_phases is ignored and the
+ *   timing fields stay 0); stats_h has n_inst entries.
  *   Returns HDG_NOT_CONVERGED if any instance did not converge.
  */
 typedef struct hdg_batch_s* hdg_batch;

@@ -37,18 +37,52 @@ struct CondDims {
 // acc[bi][bj][q] holds row 16*bi + 4*q + lane/16, column 16*bj + lane%16 of a 32x32 tile
 // (v_mfma_f64_16x16x4f64: A[i][k] in lane i+16k, B[k][j] in lane j+16k, D[i][j] in lane
 // j+16*(i%4), register i/4).
+//
+// acc += A(32 x K) B(K x 32). k is taken in groups of 16: instruction s (0..3) of a
+// group gives lane (i, kq) the pair A[i][kb+4kq+s], B[kb+4kq+s][j], so the four
+// instructions together cover all 16 k of the group and each lane reads four
+// consecutive k of its A row. The next group's operands are loaded while the current
+// group's 16 MFMAs run (two register buffers). la/lb return 0 outside the matrices.
 template <class LA, class LB>
 __device__ __forceinline__ void mfma_32x32(const LA& la, const LB& lb, int K, double4_t (&acc)[2][2]) {
     const int lane = threadIdx.x & 63;
     const int i16 = lane & 15, kq = lane >> 4;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + kq;
-        const double a0 = la(i16, k), a1 = la(16 + i16, k);
-        const double b0 = lb(k, i16), b1 = lb(k, 16 + i16);
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    double a0[4][2], b0[4][2], a1[4][2], b1[4][2];
+    auto fetch = [&](double (&fa)[4][2], double (&fb)[4][2], int kb) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kb + 4 * kq + s;
+            fa[s][0] = la(i16, k);
+            fa[s][1] = la(16 + i16, k);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kb + 4 * kq + s;
+            fb[s][0] = lb(k, i16);
+            fb[s][1] = lb(k, 16 + i16);
+        }
+    };
+    auto mma = [&](const double (&fa)[4][2], const double (&fb)[4][2]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][0], fb[s][0], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][0], fb[s][1], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][1], fb[s][0], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s][1], fb[s][1], acc[1][1], 0, 0, 0);
+        }
+    };
+    // (loads past K are harmless: la/lb read a clamped address and return 0)
+    fetch(a0, b0, 0);
+    for (int kb = 0; kb < K; kb += 32) {
+        fetch(a1, b1, kb + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + 16 >= K) break;
+        fetch(a0, b0, kb + 32);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -76,14 +110,20 @@ __global__ __launch_bounds__(BS) void k_cond_w(CondDims cd, const double* __rest
         const int r0 = (tile / tc) * 32, c0 = (tile % tc) * 32;
         double4_t acc[2][2];
         acc_zero(acc);
+        // operand reads are unconditional (clamped to a valid address) and masked after,
+        // so a whole group of loads is issued without branches
         auto la = [&](int i, int k) -> double {
             const int r = r0 + i;
-            return (r < P && k < P) ? Mi[(size_t)r * P + k] : 0.0;
+            const bool ok = r < P && k < P;
+            const double v = Mi[ok ? (size_t)r * P + k : 0];
+            return ok ? v : 0.0;
         };
         auto lb = [&](int k, int j) -> double {
             const int c = c0 + j;
-            if (k >= P || c >= NW) return 0.0;
-            return c < P ? B[(size_t)k * P + c] : Cm[(size_t)k * LPF + (c - P)];
+            const bool ok = k < P && c < NW;
+            const double* src = c < P ? B + (size_t)k * P + c : Cm + (size_t)k * LPF + (c - P);
+            const double v = *(ok ? src : B);
+            return ok ? v : 0.0;
         };
         mfma_32x32(la, lb, P, acc);
 #pragma unroll
@@ -97,6 +137,14 @@ __global__ __launch_bounds__(BS) void k_cond_w(CondDims cd, const double* __rest
                     if (r < P && c < NW) Wo[(size_t)r * NW + c] = acc[bi][bj][q];
                 }
     }
+}
+
+// Column of T for column c of W (component m): u columns of m, then m's part of each
+// element-trace block l.
+__device__ __forceinline__ int qelim_col(int c, int m, int P, int PF, int M, int nu) {
+    if (c < P) return m * P + c;
+    const int cc = c - P, l = cc / PF, j = cc - l * PF;
+    return nu + (l * M + m) * PF + j;
 }
 
 // ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, component m) ----------------------------
@@ -127,13 +175,34 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __
         acc_zero(acc);
         auto la = [&](int i, int k) -> double {
             const int r = r0 + i;
-            if (r >= R || k >= KD) return 0.0;
-            return r < nu ? De[(size_t)r * nq + k] : Ge[(size_t)(r - nu) * nq + k];
+            const bool ok = r < R && k < KD;
+            const double* src = r < nu ? De + (size_t)r * nq + k : Ge + (size_t)(r - nu) * nq + k;
+            const double v = *(ok ? src : De);
+            return ok ? v : 0.0;
         };
         auto lb = [&](int k, int j) -> double {
             const int c = c0 + j;
-            return (k < KD && c < NW) ? We[(size_t)k * NW + c] : 0.0;
+            const bool ok = k < KD && c < NW;
+            const double v = We[ok ? (size_t)k * NW + c : 0];
+            return ok ? v : 0.0;
         };
+        // T0 entries of this tile, loaded before the product (in flight during it)
+        double t0[2][2][4];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                    const int c = c0 + 16 * bj + (lane & 15);
+                    const bool ok = r < R && c < NW;
+                    const int tcol = qelim_col(c, m, P, PF, M, nu);
+                    const double* src = r < nu ? (tcol < nu ? Ee + (size_t)r * nu + tcol : Fe + (size_t)r * nt + (tcol - nu))
+                                               : (tcol < nu ? He + (size_t)(r - nu) * nu + tcol
+                                                            : Je + (size_t)(r - nu) * nt + (tcol - nu));
+                    t0[bi][bj][q] = *(ok ? src : Ee);
+                }
         mfma_32x32(la, lb, KD, acc);
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -144,17 +213,8 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __
                     const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                     const int c = c0 + 16 * bj + (lane & 15);
                     if (r >= R || c >= NW) continue;
-                    int tcol;
-                    if (c < P) {
-                        tcol = m * P + c;
-                    } else {
-                        const int cc = c - P, l = cc / PF, j = cc - l * PF;
-                        tcol = nu + (l * M + m) * PF + j;
-                    }
-                    double t0;
-                    if (r < nu) t0 = tcol < nu ? Ee[(size_t)r * nu + tcol] : Fe[(size_t)r * nt + (tcol - nu)];
-                    else t0 = tcol < nu ? He[(size_t)(r - nu) * nu + tcol] : Je[(size_t)(r - nu) * nt + (tcol - nu)];
-                    const double v = t0 - acc[bi][bj][q];
+                    const int tcol = qelim_col(c, m, P, PF, M, nu);
+                    const double v = t0[bi][bj][q] - acc[bi][bj][q];
                     if (r < nu) Te[(size_t)r * C + tcol] = v;
                     else Be[(size_t)(r - nu) * C + tcol] = v;
                 }
@@ -171,13 +231,14 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __
 // NBT: compile-time bound of the panel width (the triangular solve keeps one
 // column of U12 in registers). LBS threads share the LDS panel (512 for panels of
 // up to 32 columns, so eight waves hide the trailing update's memory latency).
+// Dynamic LDS: the R x (NB+1) panel, then nu + 2*NBT ints for the row interchanges.
 template <int NBT, int LBS>
 __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top,
                                                  double* __restrict__ bot, int* bad_elem, int e_off) {
     extern __shared__ double sm[];
-    __shared__ int piv[64];
     __shared__ double pval;
     __shared__ int pidx;
+    __shared__ int ndisp;
     const long long e = blockIdx.x;
     const int nu = cd.nu, R = cd.R, C = cd.C;
     double* Te = top + (size_t)e * nu * C;
@@ -185,16 +246,32 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
     auto rowp = [&](int r) -> double* { return r < nu ? Te + (size_t)r * C : Be + (size_t)(r - nu) * C; };
     const int ldp = NB + 1;
     double* Pn = sm;                                   // R x ldp (panel; L21 stays here)
+    int* rsrc = (int*)(sm + (size_t)R * ldp);          // [nu]: row interchanges of the panel
+    int* dsrc = rsrc + nu;                             // [NBT]: displaced rows (source)
+    int* ddst = dsrc + NBT;                            // [NBT]: displaced rows (destination)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     bool singular = false;
     for (int k0 = 0; k0 < nu; k0 += NB) {
         const int nbk = (nu - k0) < NB ? (nu - k0) : NB;
         const int nrow = R - k0;
-        // 1. load the panel
-        for (int idx = threadIdx.x; idx < nrow * nbk; idx += LBS) {
-            const int li = idx / nbk, kk = idx - li * nbk;
-            Pn[li * ldp + kk] = rowp(k0 + li)[k0 + kk];
+        // 1. load the panel (four loads in flight per thread)
+        for (int base = threadIdx.x; base < nrow * nbk; base += 4 * LBS) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = base + u * LBS;
+                const int li = idx / nbk, kk = idx - li * nbk;
+                v[u] = idx < nrow * nbk ? rowp(k0 + li)[k0 + kk] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = base + u * LBS;
+                const int li = idx / nbk, kk = idx - li * nbk;
+                if (idx < nrow * nbk) Pn[li * ldp + kk] = v[u];
+            }
         }
+        for (int r = threadIdx.x; r < nu - k0; r += LBS) rsrc[r] = r;
+        if (threadIdx.x == 0) ndisp = 0;
         __syncthreads();
         // 2. factorise the panel (pivot rows restricted to the Ebar rows)
         for (int kk = 0; kk < nbk; ++kk) {
@@ -211,7 +288,13 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     const int oi = __shfl_xor(bi, off, 64);
                     if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
                 }
-                if (lane == 0) { pidx = bi; pval = Pn[bi * ldp + kk]; piv[kk] = bi; }
+                if (lane == 0) {
+                    pidx = bi;
+                    pval = Pn[bi * ldp + kk];
+                    const int t = rsrc[kk];
+                    rsrc[kk] = rsrc[bi];
+                    rsrc[bi] = t;
+                }
             }
             __syncthreads();
             const int p = pidx;
@@ -233,39 +316,49 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
             }
             __syncthreads();
         }
+        // rows at or below nbk whose content moved (at most nbk of them); the order of
+        // the list does not matter, each destination appears once
+        for (int r = nbk + threadIdx.x; r < nu - k0; r += LBS) {
+            if (rsrc[r] != r) {
+                const int q = atomicAdd(&ndisp, 1);
+                dsrc[q] = rsrc[r];
+                ddst[q] = r;
+            }
+        }
         // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final)
         for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
             rowp(k0 + li)[k0 + kk] = Pn[li * ldp + kk];
         }
-        // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread per column)
+        __syncthreads();
+        // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread
+        //    per column): every load of the column is issued before its first store
         const int cbeg = k0 + nbk;
         const int ncol = C - cbeg;
+        const int nd = ndisp;
         for (int cl = threadIdx.x; cl < ncol; cl += LBS) {
             const int col = cbeg + cl;
-            for (int kk = 0; kk < nbk; ++kk) {
-                const int p = piv[kk];
-                if (p != kk) {
-                    double* ra = rowp(k0 + kk);
-                    double* rb = rowp(k0 + p);
-                    const double t = ra[col];
-                    ra[col] = rb[col];
-                    rb[col] = t;
-                }
-            }
-            // forward substitution with the unit lower L11; U12 rows go straight back to T
-            // (this thread re-reads only entries it wrote itself)
-            double u[NBT];
+            double u[NBT], dv[NBT];
 #pragma unroll
-            for (int kk = 0; kk < NBT; ++kk) {
+            for (int t = 0; t < NBT; ++t) u[t] = t < nbk ? rowp(k0 + rsrc[t])[col] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NBT; ++q) dv[q] = q < nd ? rowp(k0 + dsrc[q])[col] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NBT; ++q)
+                if (q < nd) rowp(k0 + ddst[q])[col] = dv[q];
+            // forward substitution with the unit lower L11
+#pragma unroll
+            for (int kk = 1; kk < NBT; ++kk) {
                 if (kk < nbk) {
-                    double v = rowp(k0 + kk)[col];
+                    double v = u[kk];
 #pragma unroll
                     for (int q = 0; q < kk; ++q) v -= Pn[kk * ldp + q] * u[q];
                     u[kk] = v;
-                    rowp(k0 + kk)[col] = v;
                 }
             }
+#pragma unroll
+            for (int t = 0; t < NBT; ++t)
+                if (t < nbk) rowp(k0 + t)[col] = u[t];
         }
         __syncthreads();
         // 5. trailing update T22 -= L21 U12 (MFMA, 32x32 tiles per wave)
@@ -282,15 +375,21 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        acc[bi][bj][q] = (r < nrow2 && c < ncol) ? rowp(cbeg + r)[cbeg + c] : 0.0;
+                        const bool ok = r < nrow2 && c < ncol;
+                        const double v = rowp(cbeg + (ok ? r : 0))[ok ? cbeg + c : cbeg];
+                        acc[bi][bj][q] = ok ? v : 0.0;
                     }
             auto la = [&](int i, int k) -> double {
                 const int r = r0 + i;
-                return (r < nrow2 && k < nbk) ? -Pn[(nbk + r) * ldp + k] : 0.0;
+                const bool ok = r < nrow2 && k < nbk;
+                const double v = Pn[ok ? (nbk + r) * ldp + k : 0];
+                return ok ? -v : 0.0;
             };
             auto lb = [&](int k, int j) -> double {
                 const int c = c0 + j;
-                return (k < nbk && c < ncol) ? rowp(k0 + k)[cbeg + c] : 0.0;
+                const bool ok = k < nbk && c < ncol;
+                const double v = rowp(k0 + (ok ? k : 0))[ok ? cbeg + c : cbeg];
+                return ok ? v : 0.0;
             };
             mfma_32x32(la, lb, nbk, acc);
 #pragma unroll
@@ -321,7 +420,9 @@ __global__ __launch_bounds__(BS) void k_cond_copyout(CondDims cd, const double* 
     for (int i = threadIdx.x; i < nt; i += BS) rbar[(size_t)e * nt + i] = Be[(size_t)i * C + C - 1];
 }
 
-size_t lu_lds_bytes(const CondDims& cd, int NB) { return sizeof(double) * (size_t)cd.R * (NB + 1); }
+size_t lu_lds_bytes(const CondDims& cd, int NB) {
+    return sizeof(double) * (size_t)cd.R * (NB + 1) + sizeof(int) * ((size_t)cd.nu + 2 * 64);
+}
 
 }  // namespace
 

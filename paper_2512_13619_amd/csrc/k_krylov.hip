@@ -207,45 +207,65 @@ __global__ void k_backsolve(const GmresCtl* ctl, const double* H, int ldh, const
 
 // Fused second Gram-Schmidt pass, part 1: w <- w - V h1 and partial dots V^T w
 // (the new w) in one read of V. Same chunking as k_multidot, so k_reduce applies.
+//
+// A wave takes 64 consecutive entries (one per lane) and holds their JMAX basis values
+// only while it works on them: the products V[i][k] w[k] are summed over the lanes by a
+// reduce-scatter (log2(JMAX) halving steps of lane exchanges) that leaves the sum for
+// column (lane mod JMAX) in the lane, so each lane keeps one accumulator instead of JMAX.
 template <int JMAX>
 __global__ __launch_bounds__(BS) void k_axpy_dot(const double* __restrict__ V, size_t ldv, int J,
                                                  const double* __restrict__ h1, double* __restrict__ w, size_t n,
                                                  double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
-    __shared__ double red[JMAX][BS / 64];
+    __shared__ double hs[JMAX];
+    __shared__ double red[BS / 64][JMAX];
+    for (int i = threadIdx.x; i < JMAX; i += BS) hs[i] = i < J ? h1[i] : 0.0;
+    __syncthreads();
     const size_t k0 = (size_t)blockIdx.x * CHUNK;
     const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
-    double hh[JMAX], acc[JMAX];
-#pragma unroll
-    for (int i = 0; i < JMAX; ++i) {
-        hh[i] = i < J ? h1[i] : 0.0;
-        acc[i] = 0.0;
-    }
-    for (size_t k = k0 + threadIdx.x; k < k1; k += BS) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (size_t kb = k0 + (size_t)wave * 64; kb < k1; kb += BS) {
+        const size_t k = kb + lane;
+        const bool ok = k < k1;
+        const size_t kc = ok ? k : k0;
+        const double wk = w[kc];
+        // all JMAX loads in flight; columns at or past J read column 0 (valid memory) and
+        // drop out: hs is 0 there, and their dot products are never written
         double v[JMAX];
+#pragma unroll
+        for (int i = 0; i < JMAX; ++i) v[i] = V[(size_t)(i < J ? i : 0) * ldv + kc];
+        __builtin_amdgcn_sched_barrier(0);
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < JMAX; ++i) {
-            v[i] = i < J ? V[(size_t)i * ldv + k] : 0.0;
-            s += v[i] * hh[i];
-        }
-        const double wn = w[k] - s;
-        w[k] = wn;
+        for (int i = 0; i < JMAX; ++i) s += v[i] * hs[i];
+        const double wn = ok ? wk - s : 0.0;
+        if (ok) w[k] = wn;
 #pragma unroll
-        for (int i = 0; i < JMAX; ++i) acc[i] += v[i] * wn;
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int i = 0; i < JMAX; ++i) v[i] *= wn;
+        // reduce-scatter: after the step with mask m a lane holds half as many sums, each
+        // over twice as many lanes; the last one leaves column (lane mod JMAX) in v[0]
 #pragma unroll
-    for (int i = 0; i < JMAX; ++i) {
-        if (i < J) {
-            const double t = wave_sum(acc[i]);
-            if (lane == 0) red[i][wave] = t;
+        for (int S = JMAX; S > 1; S >>= 1) {
+            const int m = S >> 1;
+            const bool up = (lane & m) != 0;
+#pragma unroll
+            for (int t = 0; t < S / 2; ++t) {
+                const double keep = up ? v[t + S / 2] : v[t];
+                const double send = up ? v[t] : v[t + S / 2];
+                v[t] = keep + __shfl_xor(send, m, 64);
+            }
         }
+        acc += v[0];
     }
+    // lanes that share a column (lane mod JMAX) hold partial sums of it
+#pragma unroll
+    for (int m = 32; m >= JMAX; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane < JMAX) red[wave][lane] = acc;
     __syncthreads();
     if (threadIdx.x < J) {
         double t = 0.0;
-        for (int q = 0; q < BS / 64; ++q) t += red[threadIdx.x][q];
+        for (int q = 0; q < BS / 64; ++q) t += red[q][threadIdx.x];
         part[(size_t)threadIdx.x * nblk + blockIdx.x] = t;
     }
 }
@@ -289,7 +309,9 @@ __global__ __launch_bounds__(BS) void k_axpy_sumsq(const double* __restrict__ V,
 
 hdg_status vec_axpy_dot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h1, double* w, size_t n,
                         double* part, int nblk, const int* skip) {
-    if (J <= 16)
+    if (J <= 8)
+        hipLaunchKernelGGL(k_axpy_dot<8>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h1, w, n, part, nblk, skip);
+    else if (J <= 16)
         hipLaunchKernelGGL(k_axpy_dot<16>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h1, w, n, part, nblk, skip);
     else if (J <= 32)
         hipLaunchKernelGGL(k_axpy_dot<32>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h1, w, n, part, nblk, skip);

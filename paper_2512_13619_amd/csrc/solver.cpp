@@ -174,6 +174,21 @@ hdg_status prec_apply(hdg_ctx ctx, const Op& op, int prec, const PolyPlan& pl, c
     return poly_apply(ctx, op, pl, y, z, work, ld, skip);
 }
 
+// hipEvents owned for the duration of one solve (timing only)
+struct EventPool {
+    std::vector<hipEvent_t> e;
+    hdg_status create(int n) {
+        e.assign(n, nullptr);
+        for (auto& x : e)
+            if (hipEventCreate(&x) != hipSuccess) { x = nullptr; return HDG_ERR_HIP; }
+        return HDG_OK;
+    }
+    ~EventPool() {
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 struct SolveWs {
     double *V, *Z, *work, *part;
     GmresCtl* ctl;
@@ -290,8 +305,10 @@ void hdg_solve_opts_default(hdg_solve_opts* o) {
 hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const float* K32, const int32_t* nbr,
                      const double* b, double* x, const hdg_solve_opts* o, hdg_solve_stats* stats) {
     const double t0 = now_s();
+    const bool timed = o->time_phases != 0;
+    const bool use_graph = o->use_graph && !timed;
     CaptureStreamScope cap;
-    if (o->use_graph) HDG_HIP_CHECK(ctx, cap.begin(ctx));
+    if (use_graph) HDG_HIP_CHECK(ctx, cap.begin(ctx));
     std::memset(stats, 0, sizeof(*stats));
     const int nb = d->ncomp * d->npf, L = d->nlfe, S = 2 * L - 1, nf = d->nf;
     const size_t N = (size_t)nf * nb;
@@ -388,6 +405,17 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     hdg_status result = HDG_NOT_CONVERGED;
     std::vector<double> hbuf(m + 2);
     const int* skip = &w.ctl->done;
+    // phase timing: events at the start of the preconditioner, the matvec and the
+    // orthogonalisation of each Arnoldi step, and at the step's end
+    EventPool ev;
+    if (timed && (st = ev.create(4 * m)) != HDG_OK) {
+        ctx->err = "hipEventCreate failed";
+        return st;
+    }
+    auto mark = [&](int j, int k) -> hdg_status {
+        if (timed) HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[4 * j + k], ctx->stream));
+        return HDG_OK;
+    };
     // One restart cycle, entirely on the stream: FP64 residual, Arnoldi steps
     // (skipped on the device once converged), back substitution, x += Z y.
     auto enqueue_cycle = [&](int jmax) -> hdg_status {
@@ -405,8 +433,11 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             double* vj = w.V + (size_t)j * w.ld;
             double* zj = w.Z + (size_t)j * w.ld;
             double* wv = w.V + (size_t)(j + 1) * w.ld;
+            if ((s2 = mark(j, 0)) != HDG_OK) return s2;
             if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 1)) != HDG_OK) return s2;
             if ((s2 = op_matvec(ctx, op, zj, wv, skip)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 2)) != HDG_OK) return s2;
             if (o->orth == HDG_ORTH_CGS2 && j + 1 <= 64) {
                 // CGS2 with three reads of the basis: dots, (axpy + second dots), (axpy + norm)
                 double* col = w.H + (size_t)j * w.ldh;
@@ -422,6 +453,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             if ((s2 = krylov_givens(ctx, w.ctl, w.part, w.nblk, w.H, w.ldh, w.cs, w.sn, w.g, j, w.hist)) != HDG_OK)
                 return s2;
             if ((s2 = krylov_scale_by(ctx, wv, wv, N, w.H + (size_t)j * w.ldh + j + 1, skip)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 3)) != HDG_OK) return s2;
         }
         if ((s2 = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return s2;
         return vec_multiaxpy(ctx, w.Z, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
@@ -436,7 +468,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     };
     while (true) {
         const int jmax = std::max(0, std::min(m, o->max_iters - iters));
-        if (o->use_graph && jmax == m) {
+        if (use_graph && jmax == m) {
             if (!gexec) {
                 HDG_HIP_CHECK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
                 st = enqueue_cycle(jmax);
@@ -473,6 +505,23 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         }
         hist_push(hc.beta);
         for (int i = 0; i < hc.k; ++i) hist_push(hbuf[i]);
+        if (timed) {
+            // steps at or beyond hc.k returned at once on the device flag: not counted
+            for (int j = 0; j < hc.k && j < jmax; ++j) {
+                float a = 0.f, b2 = 0.f, c = 0.f;
+                if (hipEventElapsedTime(&a, ev.e[4 * j], ev.e[4 * j + 1]) != hipSuccess ||
+                    hipEventElapsedTime(&b2, ev.e[4 * j + 1], ev.e[4 * j + 2]) != hipSuccess ||
+                    hipEventElapsedTime(&c, ev.e[4 * j + 2], ev.e[4 * j + 3]) != hipSuccess) {
+                    drop_graph();
+                    ctx->err = "reading the phase timers failed";
+                    return HDG_ERR_HIP;
+                }
+                stats->t_prec += 1e-3 * a;
+                stats->t_matvec += 1e-3 * b2;
+                stats->t_orth += 1e-3 * c;
+                ++stats->n_timed;
+            }
+        }
         stats->rel_resid_true = bnorm > 0 ? hc.beta / bnorm : 0.0;
         if (hc.nonfinite) {
             ctx->err = "residual or Arnoldi data became NaN or Inf";

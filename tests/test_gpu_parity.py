@@ -256,6 +256,27 @@ def test_gmres_graph_replay_equals_direct(ctx, precision):
     assert torch.equal(xa, xc) and sc["iters"] == sa["iters"]
 
 
+@pytest.mark.parametrize("prec", ["bj", "bj_poly"])
+def test_gmres_phase_timing_changes_nothing(ctx, prec):
+    """Event timing of the Arnoldi phases leaves the iterates bitwise unchanged and covers
+    exactly the Arnoldi steps that ran."""
+    pb, out = case_data("c1")
+    say("phase timing", prec)
+    K, K32, nbr = _dev_matrix(out)
+    r = torch.as_tensor(out["r"]).cuda()
+    v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(r.numel())).cuda()
+    xa = torch.zeros_like(r)
+    xb = torch.zeros_like(r)
+    kw = dict(restart=10, max_iters=2000, rtol=1e-12, prec=prec, poly_degree=4, poly_v0=v0, precision="mixed")
+    sa = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xa, use_graph=True, **kw)
+    sb = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xb, use_graph=True, time_phases=True, **kw)
+    assert sa["converged"] and sb["converged"] and torch.equal(xa, xb)
+    assert sa["n_timed"] == 0 and sa["t_matvec"] == 0.0
+    assert sb["n_timed"] == sb["iters"] == sa["iters"]
+    assert sb["t_prec"] > 0 and sb["t_matvec"] > 0 and sb["t_orth"] > 0
+    assert sb["t_prec"] + sb["t_matvec"] + sb["t_orth"] <= sb["t_total"]
+
+
 def test_gmres_history_matches_oracle_fgmres(ctx):
     pb, out = case_data("c1")
     K, K32, nbr = _dev_matrix(out)
