@@ -4,8 +4,8 @@
 //     T = [[E F r_u], [H J r_t]] - [D; G] A^{-1} [B C 0]
 //       = [[Ebar Fbar r_u], [Hbar Jbar r_t]]                       (q eliminated, r_q = 0)
 // and then eliminate its first nu columns by Gaussian elimination with partial
-// pivoting restricted to the Ebar rows. Afterwards the bottom-right block is
-//     Kbar = Jbar - Hbar Ebar^{-1} Fbar   and the last column  rbar = r_t - Hbar Ebar^{-1} r_u,
+// pivoting restricted to the Ebar rows, which gives
+//     Kbar = Jbar - Hbar Ebar^{-1} Fbar   and   rbar = r_t - Hbar Ebar^{-1} r_u,
 // while the top rows hold [U | L^{-1}P Fbar | L^{-1}P r_u], which recovery uses.
 //
 // A^{-1} = I_{MD} (x) M^{-1} and B, C are component-diagonal (eq. w16), so
@@ -13,11 +13,16 @@
 //     sum_d [D;G][:, q(m,d,:)] (M^{-1} [B_d | C_d]):
 // one (nu+nt) x (D P_E) by (D P_E) x (P_E + N_lfe P_F) product per component,
 // with W = M^{-1}[B_d | C_d] formed first. All products run on the FP64 matrix
-// cores (v_mfma_f64_16x16x4f64, 32x32 tiles per wave). The elimination is
-// right-looking and blocked: the panel (NB columns, up to 64) is factorised in
-// LDS, the panel rows of the trailing columns are solved with L11 and written
-// back, and the trailing matrix is updated with MFMA from the LDS-resident L21
-// and the just-written U12 rows (L2-resident).
+// cores (v_mfma_f64_16x16x4f64). Three stages:
+//   1. q-elimination: LDS-staged 64x64 tiles (one block per element, component and
+//      tile), giving [[Ebar Fbar r_u], [Hbar Jbar r_t]];
+//   2. right-looking blocked elimination of the Ebar columns (panel of NB columns
+//      in LDS, pivot rows among the Ebar rows): the Ebar rows are updated over all
+//      trailing columns (they become [U | L^{-1}P Fbar | L^{-1}P r_u]); the trace
+//      rows only over the Ebar columns, which yields their multipliers
+//      L21 = Hbar U^{-1};
+//   3. Schur product Kbar = Jbar - L21 (L^{-1}P Fbar), rbar = r_t - L21 (L^{-1}P r_u):
+//      one product of depth nu in LDS-staged 64x64 tiles.
 //
 // Storage of T per element: the top nu rows live directly in the caller's
 // `local` buffer (row stride nu+nt+1), the bottom nt rows in a workspace.
@@ -93,6 +98,115 @@ __device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
         for (int b = 0; b < 2; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
 }
 
+// ---- LDS-staged 64x64 tile product -----------------------------------------------------------
+// acc += A(64 x K) B(K x 64) for the tile whose corner is (m0, n0): 256 threads, wave w owns
+// the 32x32 quadrant (rows 32*(w/2), columns 32*(w%2)) in the mfma_32x32 layout. K is
+// taken in chunks of 32 staged through LDS (double-buffered: the next chunk's global loads
+// are in flight while the current chunk's MFMAs run). A is stored k-major in LDS (row
+// stride 65 to spread the transposing writes over the banks), B as it is. Entries
+// outside the matrices read as 0.
+constexpr int GT = 64, GK = 32, GLDA = GT + 1, GLDB = GT;
+constexpr size_t GEMM_LDS = sizeof(double) * 2 * (GK * GLDA + GK * GLDB);
+
+// A row-major matrix whose rows [0, split) start at p0 and rows [split, rows) at p1
+// (same row stride ld).
+struct MatA {
+    const double* p0;
+    const double* p1;
+    int split, ld, rows, cols;
+};
+// A row-major matrix at p with row stride ld.
+struct MatB {
+    const double* p;
+    int ld, rows, cols;
+};
+
+__device__ __forceinline__ void gemm_tile64(const MatA& A, const MatB& B, int m0, int n0, double* lds,
+                                            double4_t (&acc)[2][2]) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int K = A.cols;
+    // staging roles: A rows m0 + (tid>>5) + 8u at column k0 + (tid&31); B rows
+    // k0 + (tid>>6) + 4u at column n0 + (tid&63)
+    const int ka = tid & 31, jb = tid & 63;
+    const double* arow[8];
+    bool aok[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = m0 + (tid >> 5) + 8 * u;
+        aok[u] = r < A.rows;
+        const int rr = aok[u] ? r : 0;
+        arow[u] = rr < A.split ? A.p0 + (size_t)rr * A.ld : A.p1 + (size_t)(rr - A.split) * A.ld;
+    }
+    const bool bok_c = n0 + jb < B.cols;
+    const double* bcol = B.p + (bok_c ? n0 + jb : 0);
+    // raw loads (clamped addresses); the masks are applied when the values go to LDS, so
+    // no load has to complete before the MFMAs of the current chunk are issued
+    double ra[8], rb[8];
+    int kst = 0;                       // k0 of the chunk held in ra/rb
+    auto gload = [&](int k0) {
+        kst = k0;
+        const int k = k0 + ka;
+        const int kc = k < K ? k : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ra[u] = arow[u][kc];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kb = k0 + (tid >> 6) + 4 * u;
+            rb[u] = bcol[(size_t)(kb < B.rows ? kb : 0) * B.ld];
+        }
+    };
+    auto lstore = [&](int b) {
+        double* As = lds + b * (GK * GLDA);
+        double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
+        const bool kok = kst + ka < K;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = (kok && aok[u]) ? ra[u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kb = kst + (tid >> 6) + 4 * u;
+            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (bok_c && kb < B.rows) ? rb[u] : 0.0;
+        }
+    };
+    const int nch = (K + GK - 1) / GK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int b = c & 1;
+        if (c + 1 < nch) gload((c + 1) * GK);
+        const double* As = lds + b * (GK * GLDA);
+        const double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
+        double a[8][2], bb[8][2];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int k = 4 * ks + kq;
+            a[ks][0] = As[k * GLDA + wr + i16];
+            a[ks][1] = As[k * GLDA + wr + 16 + i16];
+            bb[ks][0] = Bs[k * GLDB + wc + i16];
+            bb[ks][1] = Bs[k * GLDB + wc + 16 + i16];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][0], bb[ks][0], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][0], bb[ks][1], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bb[ks][0], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bb[ks][1], acc[1][1], 0, 0, 0);
+        }
+        if (c + 1 < nch) lstore(b ^ 1);
+        __syncthreads();
+    }
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD walks a
+// contiguous range of tiles (the tiles of one element then share that XCD's L2).
+__device__ __forceinline__ long long xcd_linear(long long nblk) {
+    const long long b = blockIdx.x;
+    const long long per = nblk / 8;
+    return (b % 8) * per + b / 8;
+}
+
 // ---- W = M^{-1} [B_d | C_d]  per (element, d):  (P x P) (P x NW) -----------------------
 __global__ __launch_bounds__(BS) void k_cond_w(CondDims cd, const double* __restrict__ Minv,
                                                const double* __restrict__ Bd, const double* __restrict__ Cd,
@@ -147,15 +261,25 @@ __device__ __forceinline__ int qelim_col(int c, int m, int P, int PF, int M, int
     return nu + (l * M + m) * PF + j;
 }
 
-// ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, component m) ----------------------------
-__global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __restrict__ Dm,
-                                                   const double* __restrict__ Em, const double* __restrict__ Fm,
-                                                   const double* __restrict__ Gm, const double* __restrict__ Hm,
-                                                   const double* __restrict__ Jm, const double* __restrict__ ru,
-                                                   const double* __restrict__ rt, const double* __restrict__ W,
-                                                   double* __restrict__ top, double* __restrict__ bot) {
-    const long long e = blockIdx.x;
-    const int m = blockIdx.y;
+// ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, component m, 64x64 tile) ------------------
+// One block per tile; tiles are numbered element-major, then component, row tile, column
+// tile. nblk is a multiple of 8 (trailing blocks exit).
+__global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
+                                                   const double* __restrict__ Dm, const double* __restrict__ Em,
+                                                   const double* __restrict__ Fm, const double* __restrict__ Gm,
+                                                   const double* __restrict__ Hm, const double* __restrict__ Jm,
+                                                   const double* __restrict__ ru, const double* __restrict__ rt,
+                                                   const double* __restrict__ W, double* __restrict__ top,
+                                                   double* __restrict__ bot) {
+    extern __shared__ double lds[];
+    const long long L = xcd_linear(gridDim.x);
+    if (L >= ntile) return;
+    const int per_e = cd.M * tm_n * tn_n;
+    const long long e = L / per_e;
+    int rem = (int)(L - e * per_e);
+    const int m = rem / (tm_n * tn_n);
+    rem -= m * tm_n * tn_n;
+    const int m0 = (rem / tn_n) * GT, n0 = (rem % tn_n) * GT;
     const int nu = cd.nu, nt = cd.nt, nq = cd.nq, R = cd.R, C = cd.C, NW = cd.NW, KD = cd.KD;
     const int P = cd.P, PF = cd.PF, M = cd.M;
     const double* De = Dm + (size_t)e * nu * nq + (size_t)m * KD;
@@ -167,60 +291,47 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, const double* __
     const double* Fe = Fm + (size_t)e * nu * nt;
     const double* He = Hm + (size_t)e * nt * nu;
     const double* Je = Jm + (size_t)e * nt * nt;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tr = (R + 31) / 32, tc = (NW + 31) / 32;
-    for (int tile = wave; tile < tr * tc; tile += BS / 64) {
-        const int r0 = (tile / tc) * 32, c0 = (tile % tc) * 32;
-        double4_t acc[2][2];
-        acc_zero(acc);
-        auto la = [&](int i, int k) -> double {
-            const int r = r0 + i;
-            const bool ok = r < R && k < KD;
-            const double* src = r < nu ? De + (size_t)r * nq + k : Ge + (size_t)(r - nu) * nq + k;
-            const double v = *(ok ? src : De);
-            return ok ? v : 0.0;
-        };
-        auto lb = [&](int k, int j) -> double {
-            const int c = c0 + j;
-            const bool ok = k < KD && c < NW;
-            const double v = We[ok ? (size_t)k * NW + c : 0];
-            return ok ? v : 0.0;
-        };
-        // T0 entries of this tile, loaded before the product (in flight during it)
-        double t0[2][2][4];
+    const MatA Am{De, Ge, nu, nq, R, KD};
+    const MatB Bm{We, NW, KD, NW};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = m0 + (wave >> 1) * 32, c0 = n0 + (wave & 1) * 32;
+    // T0 entries of this wave's quadrant, loaded before the product
+    double t0[2][2][4];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
-                    const int c = c0 + 16 * bj + (lane & 15);
-                    const bool ok = r < R && c < NW;
-                    const int tcol = qelim_col(c, m, P, PF, M, nu);
-                    const double* src = r < nu ? (tcol < nu ? Ee + (size_t)r * nu + tcol : Fe + (size_t)r * nt + (tcol - nu))
-                                               : (tcol < nu ? He + (size_t)(r - nu) * nu + tcol
-                                                            : Je + (size_t)(r - nu) * nt + (tcol - nu));
-                    t0[bi][bj][q] = *(ok ? src : Ee);
-                }
-        mfma_32x32(la, lb, KD, acc);
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                const int c = c0 + 16 * bj + (lane & 15);
+                const bool ok = r < R && c < NW;
+                const int tcol = qelim_col(c, m, P, PF, M, nu);
+                const double* src = r < nu ? (tcol < nu ? Ee + (size_t)r * nu + tcol : Fe + (size_t)r * nt + (tcol - nu))
+                                           : (tcol < nu ? He + (size_t)(r - nu) * nu + tcol
+                                                        : Je + (size_t)(r - nu) * nt + (tcol - nu));
+                t0[bi][bj][q] = *(ok ? src : Ee);
+            }
+    double4_t acc[2][2];
+    acc_zero(acc);
+    gemm_tile64(Am, Bm, m0, n0, lds, acc);
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
-                    const int c = c0 + 16 * bj + (lane & 15);
-                    if (r >= R || c >= NW) continue;
-                    const int tcol = qelim_col(c, m, P, PF, M, nu);
-                    const double v = t0[bi][bj][q] - acc[bi][bj][q];
-                    if (r < nu) Te[(size_t)r * C + tcol] = v;
-                    else Be[(size_t)(r - nu) * C + tcol] = v;
-                }
-    }
-    if (m == 0) {
-        for (int r = threadIdx.x; r < R; r += BS) {
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                const int c = c0 + 16 * bj + (lane & 15);
+                if (r >= R || c >= NW) continue;
+                const int tcol = qelim_col(c, m, P, PF, M, nu);
+                const double v = t0[bi][bj][q] - acc[bi][bj][q];
+                if (r < nu) Te[(size_t)r * C + tcol] = v;
+                else Be[(size_t)(r - nu) * C + tcol] = v;
+            }
+    // the right-hand-side column (once per element and row tile)
+    if (m == 0 && n0 == 0) {
+        for (int r = m0 + threadIdx.x; r < m0 + GT && r < R; r += BS) {
             if (r < nu) Te[(size_t)r * C + (C - 1)] = ru[(size_t)e * nu + r];
             else Be[(size_t)(r - nu) * C + (C - 1)] = rt[(size_t)e * nt + (r - nu)];
         }
@@ -325,10 +436,15 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                 ddst[q] = r;
             }
         }
-        // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final)
+        // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final), and the trace
+        //    rows' multipliers (L21 = Hbar U^{-1}, panel columns) for the Schur product
         for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
             rowp(k0 + li)[k0 + kk] = Pn[li * ldp + kk];
+        }
+        for (int idx = threadIdx.x; idx < cd.nt * nbk; idx += LBS) {
+            const int r = idx / nbk, kk = idx - r * nbk;
+            Be[(size_t)r * C + k0 + kk] = Pn[(nu - k0 + r) * ldp + kk];
         }
         __syncthreads();
         // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread
@@ -361,11 +477,26 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                 if (t < nbk) rowp(k0 + t)[col] = u[t];
         }
         __syncthreads();
-        // 5. trailing update T22 -= L21 U12 (MFMA, 32x32 tiles per wave)
-        const int nrow2 = R - cbeg;
-        const int tr = (nrow2 + 31) / 32, tc = (ncol + 31) / 32;
-        for (int tile = wave; tile < tr * tc; tile += LBS / 64) {
-            const int r0 = (tile / tc) * 32, c0 = (tile % tc) * 32;
+        // 5. trailing update (MFMA, 32x32 tiles per wave): the Ebar rows over every
+        //    trailing column, the trace rows over the remaining Ebar columns only (their
+        //    Schur update Jbar - L21 U12 is one product after the elimination)
+        const int na = nu - cbeg, nbc = nu - cbeg;
+        const int ta_c = (ncol + 31) / 32;
+        const int tA = ((na + 31) / 32) * ta_c;
+        const int tb_c = (nbc + 31) / 32;
+        const int tB = ((cd.nt + 31) / 32) * tb_c;
+        for (int tile = wave; tile < tA + tB; tile += LBS / 64) {
+            int rlo, rhi, clo, chi, r0, c0;
+            if (tile < tA) {
+                rlo = cbeg; rhi = nu; clo = cbeg; chi = C;
+                r0 = cbeg + (tile / ta_c) * 32;
+                c0 = cbeg + (tile % ta_c) * 32;
+            } else {
+                const int tt = tile - tA;
+                rlo = nu; rhi = R; clo = cbeg; chi = nu;
+                r0 = nu + (tt / tb_c) * 32;
+                c0 = cbeg + (tt % tb_c) * 32;
+            }
             double4_t acc[2][2];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
@@ -375,20 +506,20 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        const bool ok = r < nrow2 && c < ncol;
-                        const double v = rowp(cbeg + (ok ? r : 0))[ok ? cbeg + c : cbeg];
+                        const bool ok = r < rhi && c < chi;
+                        const double v = rowp(ok ? r : rlo)[ok ? c : clo];
                         acc[bi][bj][q] = ok ? v : 0.0;
                     }
             auto la = [&](int i, int k) -> double {
                 const int r = r0 + i;
-                const bool ok = r < nrow2 && k < nbk;
-                const double v = Pn[ok ? (nbk + r) * ldp + k : 0];
+                const bool ok = r < rhi && k < nbk;
+                const double v = Pn[ok ? (r - k0) * ldp + k : 0];
                 return ok ? -v : 0.0;
             };
             auto lb = [&](int k, int j) -> double {
                 const int c = c0 + j;
-                const bool ok = k < nbk && c < ncol;
-                const double v = rowp(k0 + (ok ? k : 0))[ok ? cbeg + c : cbeg];
+                const bool ok = k < nbk && c < chi;
+                const double v = rowp(k0 + (ok ? k : 0))[ok ? c : clo];
                 return ok ? v : 0.0;
             };
             mfma_32x32(la, lb, nbk, acc);
@@ -400,7 +531,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        if (r < nrow2 && c < ncol) rowp(cbeg + r)[cbeg + c] = acc[bi][bj][q];
+                        if (r < rhi && c < chi) rowp(r)[c] = acc[bi][bj][q];
                     }
         }
         __syncthreads();
@@ -408,16 +539,62 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
     if (singular && threadIdx.x == 0) atomicMin(bad_elem, e_off + (int)e);
 }
 
-__global__ __launch_bounds__(BS) void k_cond_copyout(CondDims cd, const double* __restrict__ bot,
-                                                     double* __restrict__ Kbar, double* __restrict__ rbar) {
-    const long long e = blockIdx.x;
-    const int nt = cd.nt, nu = cd.nu, C = cd.C;
+// ---- Kbar = Jbar - L21 U12, rbar = r_t - L21 (L^{-1} P r_u)   per (element, 64x64 tile) -----
+// L21 = the trace rows' multipliers (bottom rows, first nu columns), U12 = the Ebar rows'
+// trailing columns after the elimination (top rows, columns nu..): one product of depth nu.
+__global__ __launch_bounds__(BS) void k_cond_schur(CondDims cd, long long ntile, int tm_n, int tn_n,
+                                                   const double* __restrict__ top, const double* __restrict__ bot,
+                                                   double* __restrict__ Kbar, double* __restrict__ rbar) {
+    extern __shared__ double lds[];
+    const long long L = xcd_linear(gridDim.x);
+    if (L >= ntile) return;
+    const int per_e = tm_n * tn_n;
+    const long long e = L / per_e;
+    const int rem = (int)(L - e * per_e);
+    const int m0 = (rem / tn_n) * GT, n0 = (rem % tn_n) * GT;
+    const int nu = cd.nu, nt = cd.nt, C = cd.C;
+    const double* Te = top + (size_t)e * nu * C;
     const double* Be = bot + (size_t)e * nt * C;
-    for (int idx = threadIdx.x; idx < nt * nt; idx += BS) {
-        const int i = idx / nt, j = idx - i * nt;
-        Kbar[(size_t)e * nt * nt + idx] = Be[(size_t)i * C + nu + j];
+    const MatA Am{Be, Be, nt, C, nt, nu};
+    const MatB Bm{Te + nu, C, nu, nt};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = m0 + (wave >> 1) * 32, c0 = n0 + (wave & 1) * 32;
+    double j0[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                const int c = c0 + 16 * bj + (lane & 15);
+                const bool ok = r < nt && c < nt;
+                j0[bi][bj][q] = Be[ok ? (size_t)r * C + nu + c : 0];
+            }
+    double4_t acc[2][2];
+    acc_zero(acc);
+    gemm_tile64(Am, Bm, m0, n0, lds, acc);
+    double* Ke = Kbar + (size_t)e * nt * nt;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                const int c = c0 + 16 * bj + (lane & 15);
+                if (r < nt && c < nt) Ke[(size_t)r * nt + c] = j0[bi][bj][q] - acc[bi][bj][q];
+            }
+    // rbar for this row tile: four lanes per row, fixed-order combination
+    if (n0 == 0) {
+        const int r = m0 + (threadIdx.x >> 2), part = threadIdx.x & 3;
+        double sum = 0.0;
+        if (r < nt)
+            for (int k = part; k < nu; k += 4) sum += Be[(size_t)r * C + k] * Te[(size_t)k * C + C - 1];
+        sum += __shfl_xor(sum, 1, 64);
+        sum += __shfl_xor(sum, 2, 64);
+        if (r < nt && part == 0) rbar[(size_t)e * nt + r] = Be[(size_t)r * C + C - 1] - sum;
     }
-    for (int i = threadIdx.x; i < nt; i += BS) rbar[(size_t)e * nt + i] = Be[(size_t)i * C + C - 1];
 }
 
 size_t lu_lds_bytes(const CondDims& cd, int NB) {
@@ -464,17 +641,27 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
                                                                                : (const void*)k_cond_lu<64, 256>;
     if (lds > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_qelim, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)GEMM_LDS));
+    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)GEMM_LDS));
     for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
         const int64_t n = (ne - e0) < chunk ? (ne - e0) : chunk;
         const size_t P = cd.P, LPF = (size_t)cd.L * cd.PF;
         hipLaunchKernelGGL(k_cond_w, dim3((unsigned)n, cd.D), dim3(BS), 0, ctx->stream, cd, in->Minv + e0 * P * P,
                            in->Bd + e0 * cd.D * P * P, in->Cd + e0 * cd.D * P * LPF, W);
         HDG_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_cond_qelim, dim3((unsigned)n, cd.M), dim3(BS), 0, ctx->stream, cd,
-                           in->D + e0 * cd.nu * cd.nq, in->E + e0 * cd.nu * cd.nu, in->F + e0 * cd.nu * cd.nt,
-                           in->G + e0 * cd.nt * cd.nq, in->H + e0 * cd.nt * cd.nu, in->J + e0 * cd.nt * cd.nt,
-                           in->ru + e0 * cd.nu, in->rt + e0 * cd.nt, W, local + e0 * cd.nu * cd.C, bot);
-        HDG_LAUNCH_CHECK(ctx);
+        {
+            const int tm_n = div_up(cd.R, GT), tn_n = div_up(cd.NW, GT);
+            const long long ntile = (long long)n * cd.M * tm_n * tn_n;
+            const long long nblk = (ntile + 7) / 8 * 8;
+            hipLaunchKernelGGL(k_cond_qelim, dim3((unsigned)nblk), dim3(BS), GEMM_LDS, ctx->stream, cd, ntile, tm_n,
+                               tn_n, in->D + e0 * cd.nu * cd.nq, in->E + e0 * cd.nu * cd.nu,
+                               in->F + e0 * cd.nu * cd.nt, in->G + e0 * cd.nt * cd.nq, in->H + e0 * cd.nt * cd.nu,
+                               in->J + e0 * cd.nt * cd.nt, in->ru + e0 * cd.nu, in->rt + e0 * cd.nt, W,
+                               local + e0 * cd.nu * cd.C, bot);
+            HDG_LAUNCH_CHECK(ctx);
+        }
         if (NB <= 16)
             hipLaunchKernelGGL((k_cond_lu<16, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB,
                                local + e0 * cd.nu * cd.C, bot, status, (int)e0);
@@ -485,9 +672,14 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
             hipLaunchKernelGGL((k_cond_lu<64, 256>), dim3((unsigned)n), dim3(256), lds, ctx->stream, cd, NB,
                                local + e0 * cd.nu * cd.C, bot, status, (int)e0);
         HDG_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_cond_copyout, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,
-                           Kbar + e0 * cd.nt * cd.nt, rbar + e0 * cd.nt);
-        HDG_LAUNCH_CHECK(ctx);
+        {
+            const int tm_n = div_up(cd.nt, GT);
+            const long long ntile = (long long)n * tm_n * tm_n;
+            const long long nblk = (ntile + 7) / 8 * 8;
+            hipLaunchKernelGGL(k_cond_schur, dim3((unsigned)nblk), dim3(BS), GEMM_LDS, ctx->stream, cd, ntile, tm_n,
+                               tm_n, local + e0 * cd.nu * cd.C, bot, Kbar + e0 * cd.nt * cd.nt, rbar + e0 * cd.nt);
+            HDG_LAUNCH_CHECK(ctx);
+        }
     }
     int bad = big;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));

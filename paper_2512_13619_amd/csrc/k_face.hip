@@ -5,21 +5,30 @@
 //
 // Mapping (gfx950, wave64): a "team" of TEAM threads owns one face. The face's
 // blocks are stored column-major, K[f][s][col][row], so the face row of blocks
-// is an nb x (S nb) column-major matrix streamed contiguously from HBM. Thread t
-// of the team owns row (t mod nb) and column group (t div nb); with G = TEAM/nb
-// groups the team reads G*nb consecutive matrix entries per step, each thread
-// accumulating into its fixed row. The extended x (S nb values gathered through
-// nbr) sits in LDS; the G partial sums of each row are combined in a fixed order,
-// so results are bitwise reproducible. Empty slots (boundary faces) are trailing
-// and are never read.
+// is an nb x (S nb) column-major matrix streamed contiguously from HBM. Each
+// thread owns VEC consecutive rows (one 16-byte load of 4 floats or 2 doubles when
+// nb allows it) and a column group; with G column groups the team reads G whole
+// columns, i.e. one contiguous run of G*nb entries, per step. The extended x (S nb
+// values gathered through nbr) sits in LDS; the G partial sums of each row are
+// combined in a fixed order, so results are bitwise reproducible. Empty slots
+// (boundary faces) are trailing and are never read.
 #include "hdg_internal.hpp"
 
 namespace {
 
+// VEC consecutive entries of T as one load
+template <typename T, int VEC>
+struct VecOf {
+    typedef T type __attribute__((ext_vector_type(VEC)));
+};
 template <typename T>
-__device__ __forceinline__ double ld_stream(const T* p) {
-    return (double)__builtin_nontemporal_load(p);
-}
+struct VecOf<T, 1> {
+    typedef T type;
+};
+template <typename V>
+__device__ __forceinline__ double lane_of(const V& v, int i) { return (double)v[i]; }
+__device__ __forceinline__ double lane_of(float v, int) { return (double)v; }
+__device__ __forceinline__ double lane_of(double v, int) { return v; }
 
 struct FaceArgs {
     const void* M1;
@@ -33,9 +42,10 @@ struct FaceArgs {
 
 // KIND only separates kernel symbols for profiling: 0 = block row product
 // (matvec / fused step), 1 = block-diagonal product (block-Jacobi apply).
-template <typename T1, typename T2, int TEAM, bool HAS_M2, int KIND>
+template <typename T1, typename T2, int TEAM, bool HAS_M2, int KIND, int VEC>
 __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
     constexpr int FPB = 256 / TEAM;        // faces per block
+    typedef typename VecOf<T1, VEC>::type V1;
     extern __shared__ double smem[];
     if (A.skip && *A.skip) return;
     const int nb = A.nb, S = A.S1;
@@ -45,8 +55,9 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
     const bool valid = f < A.nf;
     const int L = S * nb;
     double* xs = smem + team * L;
-    double* red = smem + FPB * L;            // 256
-    double* uf = red + 256 + team * nb;      // nb per team (second stage input)
+    double* red = smem + FPB * L;                   // 256*VEC: one partial sum per (thread, row)
+    double* redt = red + (size_t)team * TEAM * VEC; // this team's part, indexed group*nb + row
+    double* uf = red + 256 * VEC + team * nb;       // nb per team (second stage input)
 
     // number of leading non-empty slots (empty slots only ever trail)
     int Seff = S;
@@ -62,59 +73,68 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
     }
     __syncthreads();
 
-    const int G = TEAM / nb;
-    const int grp = t / nb;
-    const int row = t - grp * nb;
-    double acc = 0.0;
+    const int nbv = nb / VEC;          // threads per column
+    const int G = TEAM / nbv;          // column groups
+    const int grp = t / nbv;
+    const int r0 = (t - grp * nbv) * VEC;
+    double acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
     if (valid && grp < G) {
         const T1* Mf = static_cast<const T1*>(A.M1) + (size_t)f * S * nb * nb;
-        const T1* p = Mf + (size_t)grp * nb + row;
-        const size_t step = (size_t)G * nb;
-        // U independent streaming loads in flight per thread (more for 4-byte entries)
-        constexpr int U = sizeof(T1) == 4 ? 8 : 4;
-        double a[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = 0.0;
+        const V1* p = reinterpret_cast<const V1*>(Mf + (size_t)grp * nb + r0);
+        const size_t step = (size_t)G * nbv;        // in units of V1
+        // U independent streaming loads in flight per thread (more for 4-byte loads)
+        constexpr int U = (VEC == 1 && sizeof(T1) == 4) ? 8 : 4;
         int k = grp;
         for (; k + (U - 1) * G < ncols; k += U * G) {
-            T1 m[U];
+            V1 m[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) m[u] = __builtin_nontemporal_load(p + u * step);
             // keep the U loads in flight together: without this the scheduler interleaves
-            // each 4-byte load with its wait and conversion, serialising the stream
+            // each load with its wait and conversion, serialising the stream
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[u] += (double)m[u] * xs[k + u * G];
+            for (int u = 0; u < U; ++u) {
+                const double xv = xs[k + u * G];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += lane_of(m[u], v) * xv;
+            }
             p += U * step;
         }
         for (; k < ncols; k += G) {
-            a[0] += ld_stream(p) * xs[k];
+            const V1 m = __builtin_nontemporal_load(p);
+            const double xv = xs[k];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += lane_of(m, v) * xv;
             p += step;
         }
+        // index grp*nb + row, row = r0 + v
 #pragma unroll
-        for (int u = 1; u < U; ++u) a[0] += a[u];
-        acc = a[0];
+        for (int v = 0; v < VEC; ++v) redt[(size_t)t * VEC + v] = acc[v];
     }
-    red[threadIdx.x] = acc;
     __syncthreads();
     double u = 0.0;
     if (valid && t < nb) {
-        for (int g2 = 0; g2 < G; ++g2) u += red[team * TEAM + g2 * nb + t];
+        for (int g2 = 0; g2 < G; ++g2) u += redt[g2 * nb + t];
     }
     if (HAS_M2) {
+        // second product (one thread per row and column group, scalar loads)
+        const int G2 = TEAM / nb;
+        const int grp2 = t / nb;
+        const int row2 = t - grp2 * nb;
         if (valid && t < nb) uf[t] = u;
         __syncthreads();
-        acc = 0.0;
-        if (valid && grp < G) {
+        double acc2 = 0.0;
+        if (valid && grp2 < G2) {
             const T2* Bf = static_cast<const T2*>(A.M2) + (size_t)f * nb * nb;
-            for (int k = grp; k < nb; k += G) acc += (double)Bf[(size_t)k * nb + row] * uf[k];
+            for (int k = grp2; k < nb; k += G2) acc2 += (double)Bf[(size_t)k * nb + row2] * uf[k];
         }
-        __syncthreads();
-        red[threadIdx.x] = acc;
+        redt[t] = acc2;
         __syncthreads();
         u = 0.0;
         if (valid && t < nb) {
-            for (int g2 = 0; g2 < G; ++g2) u += red[team * TEAM + g2 * nb + t];
+            for (int g2 = 0; g2 < G2; ++g2) u += redt[g2 * nb + t];
         }
     }
     if (valid && t < nb) {
@@ -134,27 +154,44 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
 
 template <typename T1, typename T2, bool HAS_M2, int KIND>
 hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
+    // 16-byte loads (4 floats or 2 doubles per thread) when nb and the matrix pointer
+    // allow them, else 8-byte float pairs, else one entry per load
+    int vec = 1;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(a.M1);
+    for (int cand = (int)(16 / sizeof(T1)); cand > 1; cand /= 2)
+        if (a.nb % cand == 0 && addr % (cand * sizeof(T1)) == 0) { vec = cand; break; }
+    // columns in flight per team: a block row (S1 > 1) has S1*nb columns, a block-diagonal
+    // product (S1 == 1) only nb, so it takes fewer groups and longer runs per thread
+    const int groups = (a.S1 > 1 ? 4 : 2) * (vec > 1 ? 4 : 1);
+    const int want = groups * (a.nb / vec);
     int team;
-    // a block row (S1 > 1) has S1*nb columns: 4 column groups keep every thread busy; a
-    // block-diagonal product (S1 == 1) has only nb columns, so fewer groups give each
-    // thread a longer run of loads
-    const int want = (a.S1 > 1 ? 4 : 2) * a.nb;
     if (a.nb > 64 || want > 128) team = 256;
     else if (want > 64) team = 128;
     else if (want > 32) team = 64;
     else if (want > 16) team = 32;
     else team = 16;
+    if (team < 128) vec = 1;           // vector loads only for the wide teams
+    if (team < a.nb / vec) team = 256;
     const int fpb = 256 / team;
-    const size_t lds = sizeof(double) * ((size_t)fpb * a.S1 * a.nb + 256 + (size_t)fpb * a.nb);
+    const size_t lds = sizeof(double) * ((size_t)fpb * a.S1 * a.nb + 256 * (size_t)vec + (size_t)fpb * a.nb);
     const int grid = div_up(a.nf, fpb);
     if (grid == 0) return HDG_OK;
-    switch (team) {
-        case 256: hipLaunchKernelGGL((k_face_op<T1, T2, 256, HAS_M2, KIND>), dim3(grid), dim3(256), lds, ctx->stream, a); break;
-        case 128: hipLaunchKernelGGL((k_face_op<T1, T2, 128, HAS_M2, KIND>), dim3(grid), dim3(256), lds, ctx->stream, a); break;
-        case 64:  hipLaunchKernelGGL((k_face_op<T1, T2, 64, HAS_M2, KIND>), dim3(grid), dim3(256), lds, ctx->stream, a); break;
-        case 32:  hipLaunchKernelGGL((k_face_op<T1, T2, 32, HAS_M2, KIND>), dim3(grid), dim3(256), lds, ctx->stream, a); break;
-        default:  hipLaunchKernelGGL((k_face_op<T1, T2, 16, HAS_M2, KIND>), dim3(grid), dim3(256), lds, ctx->stream, a); break;
+#define HDG_FACE_LAUNCH(TM, VC) \
+    hipLaunchKernelGGL((k_face_op<T1, T2, TM, HAS_M2, KIND, VC>), dim3(grid), dim3(256), lds, ctx->stream, a)
+    if (vec == 4) {
+        if (team == 256) HDG_FACE_LAUNCH(256, 4); else HDG_FACE_LAUNCH(128, 4);
+    } else if (vec == 2) {
+        if (team == 256) HDG_FACE_LAUNCH(256, 2); else HDG_FACE_LAUNCH(128, 2);
+    } else {
+        switch (team) {
+            case 256: HDG_FACE_LAUNCH(256, 1); break;
+            case 128: HDG_FACE_LAUNCH(128, 1); break;
+            case 64:  HDG_FACE_LAUNCH(64, 1); break;
+            case 32:  HDG_FACE_LAUNCH(32, 1); break;
+            default:  HDG_FACE_LAUNCH(16, 1); break;
+        }
     }
+#undef HDG_FACE_LAUNCH
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
