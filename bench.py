@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
 METRIC = "time-to-1e-8 solve + block-matvec HBM GB/s, mixed-precision vs FP64, 1 GPU"
 
 
@@ -54,6 +55,17 @@ def matvec_bytes(nbr_np, nb, wbytes):
     nf, S = nbr_np.shape
     nblocks = int((nbr_np >= 0).sum())
     return nblocks * nb * nb * wbytes + nf * S * 4 + 2 * nf * nb * 8
+
+
+def condense_flops(d):
+    """Algorithmic FP64 flops of condensing one element: W = M^-1 [B_d | C_d] (each d), the
+    q-elimination product per component, LU of Ebar, the two triangular solves with the nt+1
+    right-hand sides [Fbar | r_u], and the Schur product Hbar (Ebar^-1 [Fbar | r_u])."""
+    M, D, P, PF, L = d["ncomp"], d["dim"], d["npe"], d["npf"], d["nlfe"]
+    nu, nt = M * P, L * M * PF
+    R, NW = nu + nt, P + L * PF
+    return (2 * D * P * P * NW + 2 * M * R * D * P * NW + 2 * nu ** 3 / 3 + 2 * nu * nu * (nt + 1)
+            + 2 * nt * nu * (nt + 1))
 
 
 def measured_traffic(kind):
@@ -157,6 +169,8 @@ def main():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-condense", type=int, default=0,
+                    help="condense the resident elements this many times (for MFMA counters), then exit")
     ap.add_argument("--profile-matvec", type=int, default=0,
                     help="build the workload's matrix, run this many FP32 and FP64 block matvecs and a 1 GiB "
                          "device copy (counter calibration), then exit")
@@ -182,6 +196,18 @@ def main():
     ctx = hdg.Context(0)
     pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
     stream = torch.cuda.current_stream()
+    if args.profile_condense > 0:
+        for _ in range(args.profile_condense):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            pl.condense(blk)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            t = ev0.elapsed_time(ev1) / 1e3
+            fl = condense_flops(d) * d["ne"]
+            print(json.dumps({"profile": "condensation", "s": t, "TFLOPs": fl / t / 1e12,
+                              "flops": fl}), flush=True)
+        return
     if args.profile_matvec > 0:
         pl.condense(blk)
         pl.assemble()
@@ -298,6 +324,8 @@ def main():
         "iters_fp64": st64["iters"] if st64 else None,
         "rel_resid_fp64": st64["rel_resid_true"] if st64 else None,
         "mixed_vs_fp64_solution_reldiff": dx,
+        "condense_TFLOPs": condense_flops(d) * d["ne"] / ph_mixed["condense"] / 1e12,
+        "condense_frac_fp64_peak": condense_flops(d) * d["ne"] / ph_mixed["condense"] / 1e12 / PEAK_FP64_TFLOPS,
         "kernels_mixed": r32,
         "kernels_fp64": r64,
         "roofline": {"bound": "hbm", "achieved": r32["matvec_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
