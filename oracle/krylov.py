@@ -113,6 +113,105 @@ def fgmres(matvec, b, prec=None, x0=None, restart=50, rtol=1e-10, atol=0.0, max_
         x = x + Z[:k].T @ y
 
 
+def gmres_dcgs2(matvec, b, prec=None, x0=None, restart=50, rtol=1e-10, atol=0.0, max_iters=1000, hist=None):
+    """Right-preconditioned GMRES(m) (Section 3.1; x = x0 + M^{-1} V y, for a fixed linear
+    preconditioner) whose Arnoldi process uses delayed classical Gram-Schmidt with
+    reorthogonalisation (DCGS2: Swirydowicz, Langou, Ananthan, Yang, Thomas, Numer. Linear
+    Algebra Appl. 28 (2021) e2343). Same iterates as CGS2 Arnoldi in exact arithmetic.
+
+    Step j applies the operator B = K M^{-1} to the not yet reorthogonalised vector
+    vt_j (one CGS pass, unnormalised) and takes all inner products in one sweep:
+        a = V_{j-1}^T vt_j, alpha = vt_j^T vt_j, c = V_{j-1}^T wt, gamma = vt_j^T wt  (wt = B vt_j).
+    Then  rho = sqrt(alpha - a^T a),  v_j = (vt_j - V_{j-1} a) / rho  (the delayed second pass),
+    column j-1 of the Hessenberg matrix gains H[:j, j-1] += a and H[j, j-1] = rho, and with
+    t = H[:j+1, :j] a (so that B v_j = (wt - V_j t) / rho) the new column and vector are
+        h = ([c; (gamma - a^T c) / rho] - t) / rho,
+        vt_{j+1} = wt / rho - V_j (t / rho + h).
+    Column j-1 is thus final one step late, and so is the Givens residual estimate; a cycle
+    that runs all m steps ends with one more reorthogonalisation sweep for vt_m.
+    Returns (x, info) like fgmres."""
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.copy()
+    prec = prec if prec is not None else (lambda v: v)
+    bnorm = np.linalg.norm(b)
+    target = max(rtol * bnorm, atol)
+    its = 0
+    cycles = 0
+    while True:
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+        if hist is not None:
+            hist.append(beta)
+        if beta <= target or its >= max_iters:
+            return x, dict(iters=its, cycles=cycles, converged=beta <= target, resid=beta / bnorm)
+        cycles += 1
+        m = min(restart, max_iters - its)
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        R = np.zeros((m + 1, m))          # H with the Givens rotations applied
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+
+        def finish_column(col):
+            """Apply the previous rotations and a new one to Hessenberg column col."""
+            R[:col + 2, col] = H[:col + 2, col]
+            for i in range(col):
+                t = cs[i] * R[i, col] + sn[i] * R[i + 1, col]
+                R[i + 1, col] = -sn[i] * R[i, col] + cs[i] * R[i + 1, col]
+                R[i, col] = t
+            cs[col], sn[col] = _givens(R[col, col], R[col + 1, col])
+            R[col, col] = cs[col] * R[col, col] + sn[col] * R[col + 1, col]
+            R[col + 1, col] = 0.0
+            g[col + 1] = -sn[col] * g[col]
+            g[col] = cs[col] * g[col]
+
+        def reorth(j):
+            """Delayed second pass for vt_j: returns a, rho and fixes column j-1."""
+            a = V[:j] @ V[j]
+            rho = np.sqrt(V[j] @ V[j] - a @ a)
+            if j > 0:
+                H[:j, j - 1] += a
+                H[j, j - 1] = rho
+            return a, rho
+
+        k = 0
+        done = False
+        for j in range(m):
+            wt = matvec(prec(V[j]))
+            a, rho = reorth(j)
+            if j > 0:
+                finish_column(j - 1)
+                its += 1
+                k = j
+                if hist is not None:
+                    hist.append(abs(g[j]))
+                if abs(g[j]) <= target or its >= max_iters:
+                    done = True
+                    break
+            c = V[:j] @ wt
+            gamma = V[j] @ wt
+            t = H[:j + 1, :j] @ a
+            vj = (V[j] - V[:j].T @ a) / rho
+            h = (np.append(c, (gamma - a @ c) / rho) - t) / rho
+            V[j] = vj
+            V[j + 1] = wt / rho - V[:j + 1].T @ (t / rho + h)
+            H[:j + 1, j] = h
+        if not done:
+            reorth(m)
+            finish_column(m - 1)
+            its += 1
+            k = m
+            if hist is not None:
+                hist.append(abs(g[m]))
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - R[i, i + 1:k] @ y[i + 1:k]) / R[i, i]
+        x = x + prec(V[:k].T @ y)
+
+
 def gmres_left(matvec, b, prec, restart=50, rtol=1e-6, max_iters=1000, orth="cgs"):
     """Left-preconditioned GMRES(m) as the paper states it (Section 3.1):
     GMRES on P^{-1} K x = P^{-1} b, stopping on the preconditioned residual."""

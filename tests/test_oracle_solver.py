@@ -146,3 +146,65 @@ def test_leja_keeps_pairs_adjacent_and_starts_at_max_modulus():
     for k, t in enumerate(o):
         if t.imag > 0:
             assert o[k + 1] == np.conj(t)
+
+
+def _krylov_min_residual(B, r0, k):
+    """min over y of ||r0 - B K y|| with K an orthonormal basis of span{r0, B r0, ..., B^{k-1} r0}
+    (explicit Krylov vectors, orthonormalised by a QR factorisation, then least squares)."""
+    vecs = [r0]
+    for _ in range(k - 1):
+        vecs.append(B @ vecs[-1])
+    Q, _ = np.linalg.qr(np.array(vecs).T)
+    y, *_ = np.linalg.lstsq(B @ Q, r0, rcond=None)
+    return np.linalg.norm(r0 - B @ Q @ y)
+
+
+def _block_system(seed, nf=12, nb=5, off=0.3):
+    rng = np.random.default_rng(seed)
+    N = nf * nb
+    A = rng.standard_normal((N, N)) * off + np.diag(2.0 + rng.random(N))
+    Binv = np.zeros((nf, nb, nb))
+    for f in range(nf):
+        blk = A[f * nb:(f + 1) * nb, f * nb:(f + 1) * nb]
+        Binv[f] = np.linalg.inv(blk).T
+    return A, Binv, rng.standard_normal(N)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_gmres_dcgs2_is_minimal_residual(k):
+    """After k steps, right-preconditioned GMRES attains the least-squares minimum of
+    ||b - K M^{-1} u|| over the Krylov space of K M^{-1} (brute force)."""
+    A, Binv, b = _block_system(3)
+    prec = lambda v: krylov.bj_apply(Binv, v)
+    B = A @ np.array([prec(e) for e in np.eye(A.shape[0])]).T
+    hist = []
+    x, info = krylov.gmres_dcgs2(lambda v: A @ v, b, prec=prec, restart=50, rtol=0.0, max_iters=k, hist=hist)
+    assert info["iters"] == k
+    ref = _krylov_min_residual(B, b, k)
+    assert abs(np.linalg.norm(b - A @ x) - ref) <= 1e-10 * np.linalg.norm(b)
+    assert abs(hist[k] - ref) <= 1e-10 * np.linalg.norm(b)       # Givens estimate
+
+
+def test_gmres_dcgs2_matches_cgs2_fgmres_iterates():
+    """Delayed reorthogonalisation changes no iterate (exact arithmetic): the residual
+    histories of DCGS2-GMRES and CGS2-FGMRES agree step by step over several restarts."""
+    A, Binv, b = _block_system(4, nf=30, nb=4, off=0.1)
+    prec = lambda v: krylov.bj_apply(Binv, v)
+    h1, h2 = [], []
+    x1, i1 = krylov.fgmres(lambda v: A @ v, b, prec=prec, restart=7, rtol=1e-11, max_iters=400, hist=h1)
+    x2, i2 = krylov.gmres_dcgs2(lambda v: A @ v, b, prec=prec, restart=7, rtol=1e-11, max_iters=400, hist=h2)
+    assert i1["converged"] and i2["converged"] and i1["iters"] == i2["iters"] and i1["cycles"] == i2["cycles"]
+    assert len(h1) == len(h2)
+    bn = np.linalg.norm(b)
+    assert max(abs(p - q) for p, q in zip(h1, h2)) <= 1e-9 * bn
+    assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
+
+
+def test_gmres_dcgs2_bj_matches_direct_on_c1():
+    pb = configs.c1()
+    out = oracle_pipeline(pb)
+    Binv = krylov.bj_inverses(out["K"])
+    x, info = krylov.gmres_dcgs2(lambda v: out["A"] @ v, out["r"], prec=lambda v: krylov.bj_apply(Binv, v),
+                                 restart=20, rtol=1e-12)
+    assert info["converged"] and info["cycles"] >= 2
+    assert np.linalg.norm(x - out["x"]) <= 1e-10 * np.linalg.norm(out["x"])
