@@ -148,13 +148,21 @@ hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
  *   cycle of length poly_degree on B started at poly_v0, Leja order, Section 4.7),
  *   HDG_PREC_BJ_CHEB (Chebyshev acceleration of degree poly_degree on B over a real
  *   interval estimated from the same Ritz values).
+ * orth: Arnoldi orthogonalisation (Section 4.4). HDG_ORTH_CGS2 (default), HDG_ORTH_CGS
+ *   and HDG_ORTH_MGS run the flexible form above (x += Z y, z_j = M^{-1} v_j kept).
+ *   HDG_ORTH_DCGS2 runs right-preconditioned GMRES with the preconditioner fixed
+ *   (x += M^{-1} V y, no Z) and delayed classical Gram-Schmidt with
+ *   reorthogonalisation: two sweeps over the basis per step instead of three, the
+ *   same iterates as CGS2 in exact arithmetic; each column of the Hessenberg matrix
+ *   (and the residual estimate) is completed one step late, so a converged cycle
+ *   spends one operator application that it does not use.
  * poly_v0: device vector [N_dof], the random Arnoldi start (required for the
  *   polynomial preconditioners; the caller draws it so both sides of a parity
  *   test use the same vector).
  * x: on entry the initial guess, on exit the solution.
  * Returns HDG_NOT_CONVERGED (positive) when max_iters is reached. */
 enum { HDG_PREC_NONE = 0, HDG_PREC_BJ = 1, HDG_PREC_BJ_POLY = 2, HDG_PREC_BJ_CHEB = 3 };
-enum { HDG_ORTH_CGS2 = 0, HDG_ORTH_CGS = 1, HDG_ORTH_MGS = 2 };
+enum { HDG_ORTH_CGS2 = 0, HDG_ORTH_CGS = 1, HDG_ORTH_MGS = 2, HDG_ORTH_DCGS2 = 3 };
 enum { HDG_FP64 = 0, HDG_MIXED = 1 };
 
 typedef struct {

@@ -179,7 +179,7 @@ hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims, const double* K64,
     if (o->max_iters < 0) return set_err(ctx, HDG_ERR_ARG, "max_iters must be >= 0");
     if (!(o->rtol >= 0.0) || !(o->atol >= 0.0)) return set_err(ctx, HDG_ERR_ARG, "rtol/atol must be >= 0");
     if (o->prec < HDG_PREC_NONE || o->prec > HDG_PREC_BJ_CHEB) return set_err(ctx, HDG_ERR_ARG, "unknown prec");
-    if (o->orth < HDG_ORTH_CGS2 || o->orth > HDG_ORTH_MGS) return set_err(ctx, HDG_ERR_ARG, "unknown orth");
+    if (o->orth < HDG_ORTH_CGS2 || o->orth > HDG_ORTH_DCGS2) return set_err(ctx, HDG_ERR_ARG, "unknown orth");
     if (o->precision != HDG_FP64 && o->precision != HDG_MIXED)
         return set_err(ctx, HDG_ERR_ARG, "precision must be HDG_FP64 or HDG_MIXED");
     if (o->precision == HDG_MIXED && !K32) return set_err(ctx, HDG_ERR_ARG, "mixed precision needs K32");

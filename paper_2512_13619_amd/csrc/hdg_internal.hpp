@@ -115,6 +115,10 @@ hdg_status vec_multiaxpy(hdg_ctx ctx, const double* V, size_t ldv, int J, const 
                          double* w, size_t n, const int* skip, const int* J_dev = nullptr);
 hdg_status vec_sumsq_partial(hdg_ctx ctx, const double* w, size_t n, double* part, int nblk, const int* skip);
 // Fused CGS2 second pass (J <= 64): w -= V h1 with partial dots V^T w; w -= V h2 with partial ||w||^2.
+hdg_status vec_multidot2(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* x1, const double* x2,
+                         size_t n, double* part, int nblk, const int* skip);
+hdg_status vec_dcgs2_update(hdg_ctx ctx, const double* V, size_t ldv, int j, double* vj, double* wt,
+                            const double* coef, int ldc, size_t n, const int* skip);
 hdg_status vec_axpy_dot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h1, double* w, size_t n,
                         double* part, int nblk, const int* skip);
 hdg_status vec_axpy_sumsq(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h2, double* w, size_t n,
@@ -141,6 +145,8 @@ hdg_status krylov_givens(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nbl
                          double* cs, double* sn, double* g, int j, double* hist);
 hdg_status krylov_backsolve(hdg_ctx ctx, const GmresCtl* ctl, const double* H, int ldh, const double* g,
                             double* y);
+hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* d, int j, int finish, double* Hu, double* H,
+                             int ldh, double* cs, double* sn, double* g, double* coef, int ldc, double* hist);
 hdg_status krylov_store_norm(hdg_ctx ctx, const double* part, int nblk, double* dst);
 
 // ---------------------------------------------------------------------------

@@ -305,6 +305,171 @@ __global__ __launch_bounds__(BS) void k_axpy_sumsq(const double* __restrict__ V,
     }
 }
 
+// ---- delayed CGS2 (DCGS2) Arnoldi -------------------------------------------------------------
+// One sweep of inner products per step: columns 0..J-1 of V against one or two staged
+// vectors x1, x2 (the not yet reorthogonalised vt_j and wt = B vt_j). Rows [0, J) of part
+// hold the partial dots with x1, rows [J, 2J) those with x2.
+template <int NRHS>
+__global__ __launch_bounds__(BS) void k_multidot2(const double* __restrict__ V, size_t ldv, int J,
+                                                  const double* __restrict__ x1, const double* __restrict__ x2,
+                                                  size_t n, double* __restrict__ part, int nblk, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double xs[NRHS][CHUNK];
+    const size_t k0 = (size_t)blockIdx.x * CHUNK;
+    const int len = (int)(k0 + CHUNK < n ? CHUNK : n - k0);
+    for (int k = threadIdx.x; k < len; k += BS) {
+        xs[0][k] = x1[k0 + k];
+        if (NRHS == 2) xs[NRHS - 1][k] = x2[k0 + k];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int U = 8;
+    for (int i = wave; i < J; i += BS / 64) {
+        const double* v = V + (size_t)i * ldv + k0;
+        double acc1 = 0.0, acc2 = 0.0;
+        for (int k = lane; k < len; k += 64 * U) {
+            double m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) m[u] = (k + 64 * u < len) ? v[k + 64 * u] : 0.0;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k + 64 * u < len) {
+                    acc1 += m[u] * xs[0][k + 64 * u];
+                    if (NRHS == 2) acc2 += m[u] * xs[NRHS - 1][k + 64 * u];
+                }
+        }
+        acc1 = wave_sum(acc1);
+        if (NRHS == 2) acc2 = wave_sum(acc2);
+        if (lane == 0) {
+            part[(size_t)i * nblk + blockIdx.x] = acc1;
+            if (NRHS == 2) part[(size_t)(J + i) * nblk + blockIdx.x] = acc2;
+        }
+    }
+}
+
+// Step j of the delayed CGS2 Arnoldi process, one block of 64 threads. d holds the sweep's
+// inner products: d[i] = V_i . vt_j (i <= j; i < j is the delayed projection a, i = j is
+// alpha) and d[J + i] = V_i . wt (c, gamma), J = j + 1. rho = sqrt(alpha - a.a) normalises
+// the reorthogonalised v_j; column j-1 of the unrotated Hessenberg Hu gains a and rho and
+// is then rotated into H (Givens, residual estimate). Unless finish, the new column
+//     h = ([c; (gamma - a.c)/rho] - t)/rho,  t = Hu[:j+1, :j] a,
+// goes to Hu, and coef receives what the update sweep needs: a (j values) at coef[0..],
+// b = t/rho + h (j+1 values) at coef[ldc..], 1/rho at coef[2 ldc].
+__global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j, int finish, double* Hu,
+                             double* H, int ldh, double* cs, double* sn, double* g, double* coef, int ldc,
+                             double* hist) {
+    if (ctl->done) return;
+    __shared__ double ds[2 * 201];      // restart lengths up to 200
+    __shared__ double tsh[201];
+    __shared__ double sh_rho;
+    __shared__ int sh_stop;
+    const int lane = threadIdx.x;
+    const int J = j + 1;
+    for (int i = lane; i < (finish ? J : 2 * J); i += 64) ds[i] = d[i];
+    __syncthreads();
+    double aa = 0.0, ac = 0.0;
+    for (int i = lane; i < j; i += 64) {
+        aa += ds[i] * ds[i];
+        if (!finish) ac += ds[i] * ds[J + i];
+    }
+    aa = wave_sum(aa);
+    ac = wave_sum(ac);
+    if (lane == 0) {
+        const double r2 = ds[j] - aa;
+        const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+        sh_rho = rho;
+        int stop = 0;
+        if (j > 0) {
+            // delayed pass for column j-1, then its Givens rotation
+            double* hu = Hu + (size_t)(j - 1) * ldh;
+            double* col = H + (size_t)(j - 1) * ldh;
+            for (int i = 0; i < j; ++i) hu[i] += ds[i];
+            hu[j] = rho;
+            for (int i = 0; i <= j; ++i) col[i] = hu[i];
+            const int c0 = j - 1;
+            for (int i = 0; i < c0; ++i) {
+                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const double hjj = col[c0], hn = col[c0 + 1];
+            double c = 1.0, sg = 0.0;
+            if (hn != 0.0) {
+                const double r = hypot(hjj, hn);
+                c = hjj / r;
+                sg = hn / r;
+            }
+            cs[c0] = c;
+            sn[c0] = sg;
+            col[c0] = c * hjj + sg * hn;
+            col[c0 + 1] = 0.0;
+            const double gj = g[c0];
+            g[c0 + 1] = -sg * gj;
+            g[c0] = c * gj;
+            const double est = fabs(g[c0 + 1]);
+            ctl->est = est;
+            ctl->k = j;
+            if (hist) hist[c0] = est;
+            if (!isfinite(est) || !isfinite(col[c0])) ctl->nonfinite = 1;
+            if (est <= ctl->target || !isfinite(est)) stop = 1;
+        }
+        if (!(rho > 0.0) || !isfinite(rho)) stop = 1;   // breakdown: the space is invariant
+        if (finish) stop = 1;
+        if (stop) ctl->done = 1;
+        sh_stop = stop;
+    }
+    __syncthreads();
+    if (sh_stop) return;
+    const double rho = sh_rho, irho = 1.0 / rho;
+    // t = Hu[:j+1, :j] a (column j-1 was just completed)
+    for (int i = lane; i <= j; i += 64) {
+        double t = 0.0;
+        for (int q = 0; q < j; ++q) t += Hu[(size_t)q * ldh + i] * ds[q];
+        tsh[i] = t;
+    }
+    __syncthreads();
+    for (int i = lane; i <= j; i += 64) {
+        const double ci = i < j ? ds[J + i] : (ds[J + j] - ac) * irho;
+        const double h = (ci - tsh[i]) * irho;
+        Hu[(size_t)j * ldh + i] = h;
+        coef[ldc + i] = tsh[i] * irho + h;
+        if (i < j) coef[i] = ds[i];
+    }
+    if (lane == 0) coef[2 * ldc] = irho;
+}
+
+// The update sweep of step j, one read of V_0..V_{j-1}:
+//     v_j = (vt_j - V_{<j} a) / rho           (written over vt_j),
+//     vt_{j+1} = wt / rho - V_{<j} b_{<j} - v_j b_j   (written over wt).
+__global__ __launch_bounds__(BS) void k_dcgs2_update(const double* __restrict__ V, size_t ldv, int j,
+                                                     double* vj, double* wt, const double* __restrict__ coef,
+                                                     int ldc, size_t n, const int* skip) {
+    if (skip && *skip) return;
+    const size_t k = (size_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    const double* a = coef;
+    const double* b = coef + ldc;
+    const double irho = coef[2 * ldc];
+    double s1 = 0.0, s2 = 0.0;
+    const double vt = vj[k], w = wt[k];
+    for (int i0 = 0; i0 < j; i0 += 8) {
+        double m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = V[(size_t)(i0 + u < j ? i0 + u : 0) * ldv + k];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u < j) {
+                s1 += m[u] * a[i0 + u];
+                s2 += m[u] * b[i0 + u];
+            }
+    }
+    const double v = (vt - s1) * irho;
+    vj[k] = v;
+    wt[k] = w * irho - s2 - v * b[j];
+}
+
 }  // namespace
 
 hdg_status vec_axpy_dot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* h1, double* w, size_t n,
@@ -329,6 +494,35 @@ hdg_status vec_axpy_sumsq(hdg_ctx ctx, const double* V, size_t ldv, int J, const
         hipLaunchKernelGGL(k_axpy_sumsq<32>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h2, w, n, part, nblk, skip);
     else
         hipLaunchKernelGGL(k_axpy_sumsq<64>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, h2, w, n, part, nblk, skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_multidot2(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* x1, const double* x2,
+                         size_t n, double* part, int nblk, const int* skip) {
+    if (J <= 0) return HDG_OK;
+    if (x2)
+        hipLaunchKernelGGL(k_multidot2<2>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, x1, x2, n, part, nblk,
+                           skip);
+    else
+        hipLaunchKernelGGL(k_multidot2<1>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, x1, x2, n, part, nblk,
+                           skip);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* d, int j, int finish, double* Hu, double* H,
+                             int ldh, double* cs, double* sn, double* g, double* coef, int ldc, double* hist) {
+    hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(64), 0, ctx->stream, ctl, d, j, finish, Hu, H, ldh, cs, sn, g,
+                       coef, ldc, hist);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status vec_dcgs2_update(hdg_ctx ctx, const double* V, size_t ldv, int j, double* vj, double* wt,
+                            const double* coef, int ldc, size_t n, const int* skip) {
+    hipLaunchKernelGGL(k_dcgs2_update, dim3(div_up((long long)n, BS)), dim3(BS), 0, ctx->stream, V, ldv, j, vj, wt,
+                       coef, ldc, n, skip);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

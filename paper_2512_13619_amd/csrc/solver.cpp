@@ -193,25 +193,29 @@ struct SolveWs {
     double *V, *Z, *work, *part;
     GmresCtl* ctl;
     double *H, *cs, *sn, *g, *y, *h2, *hist, *bnorm;
+    double *Hu, *dd, *coef;     // delayed CGS2: unrotated Hessenberg, sweep results, update coefficients
     size_t ld;
     int nblk, ldh;
 };
 
-hdg_status alloc_solve_ws(hdg_ctx ctx, size_t N, int m, int P, SolveWs* w) {
+// zcols: columns of Z (m for the flexible form; the delayed-CGS2 form keeps no Z and
+// uses two columns as temporaries)
+hdg_status alloc_solve_ws(hdg_ctx ctx, size_t N, int m, int P, int zcols, SolveWs* w) {
     hdg_status st;
     w->ld = (N + 63) / 64 * 64;
     const int mv = std::max(m, P);
     w->V = (double*)ws_get(ctx, WS_KRYLOV_V, sizeof(double) * w->ld * (size_t)(mv + 1), &st);
     if (!w->V) return st;
-    w->Z = (double*)ws_get(ctx, WS_KRYLOV_Z, sizeof(double) * w->ld * (size_t)m, &st);
+    w->Z = (double*)ws_get(ctx, WS_KRYLOV_Z, sizeof(double) * w->ld * (size_t)zcols, &st);
     if (!w->Z) return st;
     w->work = (double*)ws_get(ctx, WS_VEC, sizeof(double) * w->ld * 5, &st);
     if (!w->work) return st;
     w->nblk = krylov_nblk(N);
-    w->part = (double*)ws_get(ctx, WS_PART, sizeof(double) * (size_t)w->nblk * (mv + 2), &st);
+    w->part = (double*)ws_get(ctx, WS_PART, sizeof(double) * (size_t)w->nblk * (2 * mv + 4), &st);
     if (!w->part) return st;
     w->ldh = mv + 1;
-    const size_t nctl = 8 + (size_t)w->ldh * mv + 6 * (size_t)(mv + 2);
+    const size_t nctl = 8 + 2 * (size_t)w->ldh * mv + 6 * (size_t)(mv + 2) + 2 * (size_t)(mv + 2) +
+                        3 * (size_t)w->ldh + 1;
     char* base = (char*)ws_get(ctx, WS_CTL, sizeof(double) * nctl + sizeof(GmresCtl), &st);
     if (!base) return st;
     w->ctl = (GmresCtl*)base;
@@ -223,6 +227,9 @@ hdg_status alloc_solve_ws(hdg_ctx ctx, size_t N, int m, int P, SolveWs* w) {
     w->y = p; p += mv + 2;
     w->h2 = p; p += mv + 2;
     w->hist = p; p += mv + 2;
+    w->Hu = p; p += (size_t)w->ldh * mv;
+    w->dd = p; p += 2 * (size_t)(mv + 2);
+    w->coef = p; p += 3 * (size_t)w->ldh + 1;
     w->bnorm = p;
     return HDG_OK;
 }
@@ -318,7 +325,8 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     const int P = poly ? o->poly_degree : 0;
     hdg_status st;
     SolveWs w;
-    if ((st = alloc_solve_ws(ctx, N, m, P, &w)) != HDG_OK) return st;
+    const bool dcgs2 = o->orth == HDG_ORTH_DCGS2;
+    if ((st = alloc_solve_ws(ctx, N, m, P, dcgs2 ? 2 : m, &w)) != HDG_OK) return st;
     Op op;
     op.nf = nf; op.nb = nb; op.S = S; op.L = L; op.N = N; op.nbr = nbr;
     op.K = mixed ? (const void*)K32 : (const void*)K64;
@@ -416,6 +424,43 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         if (timed) HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[4 * j + k], ctx->stream));
         return HDG_OK;
     };
+    // Delayed-CGS2 steps of one cycle (right preconditioning with a fixed preconditioner,
+    // no Z): step j applies B = K M^{-1} to vt_j, one inner-product sweep, the coefficient
+    // kernel (delayed pass for vt_j, column j-1 and its Givens rotation, new column), one
+    // update sweep; a final sweep closes column jmax-1; then x += M^{-1} V y.
+    auto enqueue_dcgs2_steps = [&](int jmax) -> hdg_status {
+        hdg_status s2;
+        double* zt = w.Z;
+        double* tv = w.Z + w.ld;
+        for (int j = 0; j < jmax; ++j) {
+            double* vj = w.V + (size_t)j * w.ld;
+            double* wv = w.V + (size_t)(j + 1) * w.ld;
+            if ((s2 = mark(j, 0)) != HDG_OK) return s2;
+            if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 1)) != HDG_OK) return s2;
+            if ((s2 = op_matvec(ctx, op, zt, wv, skip)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 2)) != HDG_OK) return s2;
+            if ((s2 = vec_multidot2(ctx, w.V, w.ld, j + 1, vj, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+            if ((s2 = vec_reduce(ctx, w.part, 2 * (j + 1), w.nblk, w.dd, nullptr, skip)) != HDG_OK) return s2;
+            if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.dd, j, 0, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef, w.ldh,
+                                        w.hist)) != HDG_OK)
+                return s2;
+            if ((s2 = vec_dcgs2_update(ctx, w.V, w.ld, j, vj, wv, w.coef, w.ldh, N, skip)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 3)) != HDG_OK) return s2;
+        }
+        double* vm = w.V + (size_t)jmax * w.ld;
+        if ((s2 = vec_multidot2(ctx, w.V, w.ld, jmax + 1, vm, nullptr, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+        if ((s2 = vec_reduce(ctx, w.part, jmax + 1, w.nblk, w.dd, nullptr, skip)) != HDG_OK) return s2;
+        if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.dd, jmax, 1, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef, w.ldh,
+                                    w.hist)) != HDG_OK)
+            return s2;
+        if ((s2 = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return s2;
+        if (o->prec == HDG_PREC_NONE) return vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
+        if ((s2 = vec_lincomb(ctx, N, tv, 0.0, nullptr, 0.0, nullptr, nullptr)) != HDG_OK) return s2;
+        if ((s2 = vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, tv, N, nullptr, &w.ctl->k)) != HDG_OK) return s2;
+        if ((s2 = prec_apply(ctx, op, o->prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
+        return vec_lincomb(ctx, N, x, 1.0, x, 1.0, zt, nullptr);
+    };
     // One restart cycle, entirely on the stream: FP64 residual, Arnoldi steps
     // (skipped on the device once converged), back substitution, x += Z y.
     auto enqueue_cycle = [&](int jmax) -> hdg_status {
@@ -429,6 +474,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         if ((s2 = vec_sumsq_partial(ctx, w.V, N, w.part, w.nblk, nullptr)) != HDG_OK) return s2;
         if ((s2 = krylov_cycle_init(ctx, w.ctl, w.part, w.nblk, w.g, jmax, target)) != HDG_OK) return s2;
         if ((s2 = krylov_scale_by(ctx, w.V, w.V, N, &w.ctl->beta, skip)) != HDG_OK) return s2;
+        if (dcgs2) return enqueue_dcgs2_steps(jmax);
         for (int j = 0; j < jmax; ++j) {
             double* vj = w.V + (size_t)j * w.ld;
             double* zj = w.Z + (size_t)j * w.ld;
@@ -507,7 +553,8 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         for (int i = 0; i < hc.k; ++i) hist_push(hbuf[i]);
         if (timed) {
             // steps at or beyond hc.k returned at once on the device flag: not counted
-            for (int j = 0; j < hc.k && j < jmax; ++j) {
+            const int nsteps = (dcgs2 && hc.k > 0 && hc.k < jmax) ? hc.k + 1 : hc.k;
+            for (int j = 0; j < nsteps && j < jmax; ++j) {
                 float a = 0.f, b2 = 0.f, c = 0.f;
                 if (hipEventElapsedTime(&a, ev.e[4 * j], ev.e[4 * j + 1]) != hipSuccess ||
                     hipEventElapsedTime(&b2, ev.e[4 * j + 1], ev.e[4 * j + 2]) != hipSuccess ||
@@ -553,7 +600,7 @@ hdg_status poly_apply_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, con
     const size_t N = (size_t)nf * nb;
     hdg_status st;
     SolveWs w;
-    if ((st = alloc_solve_ws(ctx, N, 1, 1, &w)) != HDG_OK) return st;
+    if ((st = alloc_solve_ws(ctx, N, 1, 1, 1, &w)) != HDG_OK) return st;
     Op op;
     const bool mixed = precision == HDG_MIXED;
     op.nf = nf; op.nb = nb; op.S = S; op.L = L; op.N = N; op.nbr = nbr;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
 HDG_OK, HDG_NOT_CONVERGED = 0, 1
 PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3}
-ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2}
+ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2, "dcgs2": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol declared in include/hdg.h
