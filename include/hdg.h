@@ -181,6 +181,13 @@ typedef struct {
                                    orthogonalisation of every Arnoldi step (fills t_prec,
                                    t_matvec, t_orth, n_timed; the cycle is then enqueued
                                    directly even when use_graph = 1) */
+    int32_t fold_prec;          /* 1 (with HDG_ORTH_DCGS2 and a preconditioner): form the
+                                   right-preconditioned blocks K[f][s] P_g^{-1} (g = nbr(f,s))
+                                   once per solve in a workspace, FP32 on the mixed path, so a
+                                   step applies one block row product instead of block-Jacobi +
+                                   product (polynomial preconditioners become polynomials in
+                                   K M^{-1}); x += M^{-1}(...) once per cycle. Same iterates in
+                                   exact arithmetic; ignored otherwise. */
 } hdg_solve_opts;
 
 typedef struct {

@@ -24,6 +24,7 @@ enum WsSlot {
     WS_VEC,            // work vectors for the preconditioners
     WS_PART,           // reduction partials
     WS_CTL,            // GMRES device control block + Hessenberg/Givens state
+    WS_KFOLD,          // right-preconditioned operator blocks K M^{-1}
     WS_NSLOTS
 };
 
@@ -151,6 +152,9 @@ hdg_status krylov_store_norm(hdg_ctx ctx, const double* part, int nblk, double* 
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi batched inverse (Gauss-Jordan with partial pivoting).
+// Kf[f][s] = K[f][s] Binv[nbr(f,s)] (the right-preconditioned block row), FP64 products.
+hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const int32_t* nbr, const double* B64,
+                   void* out, bool out_fp32);
 hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, double* B64, float* B32,
                      int* bad_face);
 

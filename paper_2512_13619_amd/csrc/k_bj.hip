@@ -79,7 +79,69 @@ __global__ __launch_bounds__(BS) void k_bj_invert(int nf, int nb, int S, const d
     }
 }
 
+// Right-preconditioned operator blocks (Section 3.2 with M = blockdiag(K_ff)):
+//     Kf[f][s] = K[f][s] * Binv[nbr(f,s)]
+// so that (K M^{-1}) x needs one block row product and no separate block-Jacobi pass.
+// One wave per (face, slot), 16x16 output tiles of v_mfma_f64_16x16x4f64 over the block
+// padded to a multiple of 16; FP64 products, rounded to T on output. Empty slots are skipped.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_fold_bj(int nf, int nb, int S, const double* __restrict__ K,
+                                                const int32_t* __restrict__ nbr, const double* __restrict__ Binv,
+                                                T* __restrict__ out) {
+    const long long pair = (long long)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (pair >= (long long)nf * S) return;
+    const int g = nbr[pair];
+    if (g < 0) return;
+    const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const size_t bsz = (size_t)nb * nb;
+    const double* A = K + (size_t)pair * bsz;       // A(row, k) = A[k*nb + row]
+    const double* B = Binv + (size_t)g * bsz;       // B(k, col) = B[col*nb + k]
+    T* C = out + (size_t)pair * bsz;                // C(row, col) at C[col*nb + row]
+    const int nt = (nb + 15) / 16;
+    for (int ti = 0; ti < nt; ++ti)
+        for (int tj = 0; tj < nt; ++tj) {
+            double4_t acc = {0.0, 0.0, 0.0, 0.0};
+            const int row = ti * 16 + i16, col = tj * 16 + i16;
+            for (int k0 = 0; k0 < nb; k0 += 16) {
+                double a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = k0 + 4 * u + kq;
+                    const bool oka = row < nb && k < nb, okb = col < nb && k < nb;
+                    const double va = A[oka ? (size_t)k * nb + row : 0];
+                    const double vb = B[okb ? (size_t)col * nb + k : 0];
+                    a[u] = oka ? va : 0.0;
+                    b[u] = okb ? vb : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = ti * 16 + 4 * q + (lane >> 4);
+                const int c = tj * 16 + (lane & 15);
+                if (r < nb && c < nb) C[(size_t)c * nb + r] = (T)acc[q];
+            }
+        }
+}
+
 }  // namespace
+
+hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const int32_t* nbr, const double* B64,
+                   void* out, bool out_fp32) {
+    const long long pairs = (long long)nf * S;
+    if (pairs == 0) return HDG_OK;
+    const int grid = div_up(pairs, BS / 64);
+    if (out_fp32)
+        hipLaunchKernelGGL(k_fold_bj<float>, dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64,
+                           (float*)out);
+    else
+        hipLaunchKernelGGL(k_fold_bj<double>, dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64,
+                           (double*)out);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
 
 hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, double* B64, float* B32,
                      int* bad_face) {

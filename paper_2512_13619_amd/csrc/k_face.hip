@@ -152,6 +152,24 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
     }
 }
 
+// M1 = identity: u = x, the epilogue only (one thread per entry).
+__global__ __launch_bounds__(256) void k_face_identity(FaceArgs A, size_t n) {
+    if (A.skip && *A.skip) return;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    const double u = A.x[idx];
+    double v[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        v[o] = A.epi.s[o] * u;
+        if (A.epi.X[o]) v[o] += A.epi.a[o] * A.epi.X[o][idx];
+        if (A.epi.Y[o]) v[o] += A.epi.b[o] * A.epi.Y[o][idx];
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o)
+        if (A.epi.out[o]) A.epi.out[o][idx] = v[o];
+}
+
 template <typename T1, typename T2, bool HAS_M2, int KIND>
 hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     // 16-byte loads (4 floats or 2 doubles per thread) when nb and the matrix pointer
@@ -216,6 +234,18 @@ hdg_status face_op(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1
     a.nb = nb;
     a.S1 = S1;
     a.nlfe = nlfe;
+    if (M1 == nullptr) {
+        // identity operator (a preconditioner folded into the operator blocks)
+        if (M2 != nullptr || nbr1 != nullptr) {
+            ctx->err = "face operator: identity M1 takes neither a second matrix nor neighbours";
+            return HDG_ERR_ARG;
+        }
+        const size_t n = (size_t)nf * nb;
+        if (n == 0) return HDG_OK;
+        hipLaunchKernelGGL(k_face_identity, dim3((unsigned)div_up((long long)n, 256)), dim3(256), 0, ctx->stream, a, n);
+        HDG_LAUNCH_CHECK(ctx);
+        return HDG_OK;
+    }
     if (M2 == nullptr) {
         if (nbr1 == nullptr)
             return m1_fp32 ? launch_team<float, float, false, 1>(ctx, a) : launch_team<double, double, false, 1>(ctx, a);

@@ -360,6 +360,20 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         op64.Binv = B64;
         op64.b32 = false;
     }
+    // operator of the Arnoldi steps: K, or the folded K M^{-1} blocks
+    const bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE;
+    Op opi = op;
+    if (fold) {
+        const size_t nblk_el = (size_t)nf * S * nb * nb;
+        void* Kf = ws_get(ctx, WS_KFOLD, nblk_el * (mixed ? sizeof(float) : sizeof(double)), &st);
+        if (!Kf) return st;
+        if ((st = fold_bj(ctx, nf, nb, S, K64, nbr, op64.Binv ? (const double*)op64.Binv : nullptr, Kf, mixed)) !=
+            HDG_OK)
+            return st;
+        opi.K = Kf;
+        opi.k32 = mixed;
+        opi.Binv = nullptr;
+    }
     // ||b||
     if ((st = vec_sumsq_partial(ctx, b, N, w.part, w.nblk, nullptr)) != HDG_OK) return st;
     if ((st = krylov_store_norm(ctx, w.part, w.nblk, w.bnorm)) != HDG_OK) return st;
@@ -436,9 +450,11 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             double* vj = w.V + (size_t)j * w.ld;
             double* wv = w.V + (size_t)(j + 1) * w.ld;
             if ((s2 = mark(j, 0)) != HDG_OK) return s2;
-            if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
+            const double* src = zt;
+            if (fold && o->prec == HDG_PREC_BJ) src = vj;    // folded: nothing left to apply
+            else if ((s2 = prec_apply(ctx, opi, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 1)) != HDG_OK) return s2;
-            if ((s2 = op_matvec(ctx, op, zt, wv, skip)) != HDG_OK) return s2;
+            if ((s2 = op_matvec(ctx, opi, src, wv, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 2)) != HDG_OK) return s2;
             if ((s2 = vec_multidot2(ctx, w.V, w.ld, j + 1, vj, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
             if ((s2 = vec_reduce(ctx, w.part, 2 * (j + 1), w.nblk, w.dd, nullptr, skip)) != HDG_OK) return s2;
@@ -458,8 +474,22 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         if (o->prec == HDG_PREC_NONE) return vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
         if ((s2 = vec_lincomb(ctx, N, tv, 0.0, nullptr, 0.0, nullptr, nullptr)) != HDG_OK) return s2;
         if ((s2 = vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, tv, N, nullptr, &w.ctl->k)) != HDG_OK) return s2;
-        if ((s2 = prec_apply(ctx, op, o->prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
-        return vec_lincomb(ctx, N, x, 1.0, x, 1.0, zt, nullptr);
+        if (!fold) {
+            if ((s2 = prec_apply(ctx, op, o->prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
+            return vec_lincomb(ctx, N, x, 1.0, x, 1.0, zt, nullptr);
+        }
+        // folded: x += M^{-1} q(K M^{-1}) (V y), q = 1 for block-Jacobi, the polynomial otherwise
+        const double* u = tv;
+        if (o->prec != HDG_PREC_BJ) {
+            if ((s2 = prec_apply(ctx, opi, o->prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
+            u = zt;
+        }
+        FaceEpilogue e = epi0();
+        e.out[0] = x;
+        e.s[0] = 1.0;
+        e.X[0] = x;
+        e.a[0] = 1.0;
+        return op_bj(ctx, op64, u, e, nullptr);
     };
     // One restart cycle, entirely on the stream: FP64 residual, Arnoldi steps
     // (skipped on the device once converged), back substitution, x += Z y.

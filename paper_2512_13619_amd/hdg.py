@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
                 ("atol", ctypes.c_double), ("prec", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
                 ("poly_v0", ctypes.c_void_p), ("orth", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("time_phases", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("time_phases", ctypes.c_int32), ("fold_prec", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -239,7 +239,7 @@ class Context:
     # (3)
     def gmres_solve(self, dims, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0,
                     prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0,
-                    use_graph=False, time_phases=False):
+                    use_graph=False, time_phases=False, fold_prec=False):
         import torch
         d = make_dims(dims)
         nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
@@ -252,6 +252,7 @@ class Context:
         o.poly_v0 = _ptr(poly_v0, torch.float64, N, "poly_v0", allow_none=True)
         o.use_graph = 1 if use_graph else 0
         o.time_phases = 1 if time_phases else 0
+        o.fold_prec = 1 if fold_prec else 0
         hist = np.zeros(max(hist_len, 1))
         if hist_len > 0:
             o.resid_hist_h = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -52,7 +52,7 @@ REDUCED = {
 }
 
 
-@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+@pytest.mark.parametrize("orth", ["cgs2", "dcgs2", "dcgs2+fold"])
 @pytest.mark.parametrize("name", list(REDUCED))
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_reduced_workload_solution(ctx, name, precision, orth):
@@ -67,7 +67,7 @@ def test_reduced_workload_solution(ctx, name, precision, orth):
     pl.assemble()
     v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(pl.x.numel())).cuda()
     st = pl.solve(restart=50, max_iters=5000, rtol=1e-13, prec=prec, poly_degree=P, poly_v0=v0,
-                  precision=precision, use_graph=True, orth=orth)
+                  precision=precision, use_graph=True, orth=orth.split("+")[0], fold_prec=orth.endswith("fold"))
     pl.recover(blk["Minv"], blk["Bd"], blk["Cd"])
     torch.cuda.synchronize()
     ex = relerr(pl.x.cpu().numpy(), out["x"])
@@ -138,7 +138,7 @@ def test_full_size_sampled(ctx, name):
     pl.assemble()
     v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(pl.x.numel())).cuda()
     st = pl.solve(restart=50, max_iters=20000, rtol=1e-8, prec=prec, poly_degree=10, poly_v0=v0,
-                  precision=precision, use_graph=True, orth="dcgs2")
+                  precision=precision, use_graph=True, orth="dcgs2", fold_prec=True)
     say("  solve", st["iters"], st["rel_resid_true"], st["t_total"])
     assert st["converged"] and st["rel_resid_true"] <= 1e-8
     pl.recover(keep["Minv"], keep["Bd"], keep["Cd"])

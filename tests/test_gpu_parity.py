@@ -70,6 +70,16 @@ def to_dev(blk):
     return {k: torch.as_tensor(v).to("cuda").contiguous() for k, v in blk.items()}
 
 
+def orth_kw(orth):
+    """'dcgs2+fold': delayed CGS2 with the block-Jacobi inverses folded into the operator blocks."""
+    if orth == "dcgs2+fold":
+        return dict(orth="dcgs2", fold_prec=True)
+    return dict(orth=orth)
+
+
+ORTHS = ["cgs2", "dcgs2", "dcgs2+fold"]
+
+
 def relerr(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
@@ -213,7 +223,7 @@ def test_poly_apply_matches_product_form(ctx, name):
     assert relerr(z.cpu().numpy(), ref) < 1e-9, relerr(z.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+@pytest.mark.parametrize("orth", ORTHS)
 @pytest.mark.parametrize("precision,prec", [("fp64", "bj"), ("mixed", "bj"), ("fp64", "bj_poly"),
                                             ("mixed", "bj_poly"), ("fp64", "none"), ("fp64", "bj_cheb")])
 def test_gmres_solution_c1(ctx, precision, prec, orth):
@@ -224,7 +234,7 @@ def test_gmres_solution_c1(ctx, precision, prec, orth):
     x = torch.zeros_like(r)
     v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(r.numel())).cuda()
     st = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=50, max_iters=2000, rtol=1e-13, prec=prec,
-                         poly_v0=v0, precision=precision, poly_degree=10, orth=orth)
+                         poly_v0=v0, precision=precision, poly_degree=10, **orth_kw(orth))
     assert st["converged"], st
     tol = 1e-10 if precision == "fp64" else 1e-8
     ex = relerr(x.cpu().numpy(), out["x"])
@@ -234,7 +244,7 @@ def test_gmres_solution_c1(ctx, precision, prec, orth):
     assert true <= 1e-13 * 1.01
 
 
-@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+@pytest.mark.parametrize("orth", ORTHS)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_gmres_graph_replay_equals_direct(ctx, precision, orth):
     """A captured-and-replayed cycle gives bitwise the same iterates as direct launches."""
@@ -245,20 +255,20 @@ def test_gmres_graph_replay_equals_direct(ctx, precision, orth):
     xa = torch.zeros_like(r)
     xb = torch.zeros_like(r)
     sa = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xa, restart=10, max_iters=2000, rtol=1e-12,
-                         precision=precision, use_graph=False, orth=orth)
+                         precision=precision, use_graph=False, **orth_kw(orth))
     sb = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xb, restart=10, max_iters=2000, rtol=1e-12,
-                         precision=precision, use_graph=True, orth=orth)
+                         precision=precision, use_graph=True, **orth_kw(orth))
     assert sa["converged"] and sb["converged"] and sa["iters"] == sb["iters"] and sb["cycles"] > 2
     assert torch.equal(xa, xb)
     # eager work between replays, then a second graph solve
     xc = torch.zeros_like(r)
     r2 = (r * 1.0).contiguous()
     sc = ctx.gmres_solve(pb.dims(), K, K32, nbr, r2, xc, restart=10, max_iters=2000, rtol=1e-12,
-                         precision=precision, use_graph=True, orth=orth)
+                         precision=precision, use_graph=True, **orth_kw(orth))
     assert torch.equal(xa, xc) and sc["iters"] == sa["iters"]
 
 
-@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+@pytest.mark.parametrize("orth", ORTHS)
 @pytest.mark.parametrize("prec", ["bj", "bj_poly"])
 def test_gmres_phase_timing_changes_nothing(ctx, prec, orth):
     """Event timing of the Arnoldi phases leaves the iterates bitwise unchanged and covers
@@ -272,26 +282,27 @@ def test_gmres_phase_timing_changes_nothing(ctx, prec, orth):
     xa = torch.zeros_like(r)
     xb = torch.zeros_like(r)
     kw = dict(restart=10, max_iters=2000, rtol=1e-12, prec=prec, poly_degree=4, poly_v0=v0, precision="mixed",
-              orth=orth)
+              **orth_kw(orth))
     sa = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xa, use_graph=True, **kw)
     sb = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, xb, use_graph=True, time_phases=True, **kw)
     assert sa["converged"] and sb["converged"] and torch.equal(xa, xb)
     assert sa["n_timed"] == 0 and sa["t_matvec"] == 0.0
     assert sb["iters"] == sa["iters"]
-    extra = 1 if orth == "dcgs2" and sb["iters"] % 10 != 0 else 0
+    extra = 1 if orth.startswith("dcgs2") and sb["iters"] % 10 != 0 else 0
     assert sb["n_timed"] == sb["iters"] + extra
-    assert sb["t_prec"] > 0 and sb["t_matvec"] > 0 and sb["t_orth"] > 0
+    assert sb["t_matvec"] > 0 and sb["t_orth"] > 0
+    assert sb["t_prec"] > 0 or (orth == "dcgs2+fold" and prec == "bj")
     assert sb["t_prec"] + sb["t_matvec"] + sb["t_orth"] <= sb["t_total"]
 
 
-@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+@pytest.mark.parametrize("orth", ORTHS)
 def test_gmres_history_matches_oracle_fgmres(ctx, orth):
     pb, out = case_data("c1")
     K, K32, nbr = _dev_matrix(out)
     r = torch.as_tensor(out["r"]).cuda()
     x = torch.zeros_like(r)
     st = ctx.gmres_solve(pb.dims(), K, None, nbr, r, x, restart=50, max_iters=500, rtol=1e-12, prec="bj",
-                         hist_len=600, orth=orth)
+                         hist_len=600, **orth_kw(orth))
     Binv = krylov.bj_inverses(out["K"])
     hist = []
     solver = krylov.fgmres if orth == "cgs2" else krylov.gmres_dcgs2
