@@ -84,7 +84,10 @@ __global__ __launch_bounds__(BS) void k_bj_invert(int nf, int nb, int S, const d
 // so that (K M^{-1}) x needs one block row product and no separate block-Jacobi pass.
 // One wave per (face, slot), 16x16 output tiles of v_mfma_f64_16x16x4f64 over the block
 // padded to a multiple of 16; FP64 products, rounded to T on output. Empty slots are skipped.
-template <typename T>
+// k is taken in groups of 16 with instruction s giving lane (i, kq) the pair
+// A(i, kb+4kq+s), B(kb+4kq+s, j): the sum over a group covers its 16 k, and each lane reads
+// four consecutive k of the column-major B. A tile's loads are all issued before its MFMAs.
+template <typename T, int KG>
 __global__ __launch_bounds__(BS) void k_fold_bj(int nf, int nb, int S, const double* __restrict__ K,
                                                 const int32_t* __restrict__ nbr, const double* __restrict__ Binv,
                                                 T* __restrict__ out) {
@@ -101,22 +104,28 @@ __global__ __launch_bounds__(BS) void k_fold_bj(int nf, int nb, int S, const dou
     const int nt = (nb + 15) / 16;
     for (int ti = 0; ti < nt; ++ti)
         for (int tj = 0; tj < nt; ++tj) {
-            double4_t acc = {0.0, 0.0, 0.0, 0.0};
             const int row = ti * 16 + i16, col = tj * 16 + i16;
-            for (int k0 = 0; k0 < nb; k0 += 16) {
-                double a[4], b[4];
+            double a[KG][4], b[KG][4];
+#pragma unroll
+            for (int gi = 0; gi < KG; ++gi)
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int k = k0 + 4 * u + kq;
+                    const int k = gi * 16 + 4 * kq + u;
                     const bool oka = row < nb && k < nb, okb = col < nb && k < nb;
-                    const double va = A[oka ? (size_t)k * nb + row : 0];
-                    const double vb = B[okb ? (size_t)col * nb + k : 0];
-                    a[u] = oka ? va : 0.0;
-                    b[u] = okb ? vb : 0.0;
+                    a[gi][u] = A[oka ? (size_t)k * nb + row : 0];
+                    b[gi][u] = B[okb ? (size_t)col * nb + k : 0];
                 }
+            __builtin_amdgcn_sched_barrier(0);      // all loads in flight before the first use
+            double4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
-            }
+            for (int gi = 0; gi < KG; ++gi)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = gi * 16 + 4 * kq + u;
+                    const double av = (row < nb && k < nb) ? a[gi][u] : 0.0;   // padding
+                    const double bv = (col < nb && k < nb) ? b[gi][u] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = ti * 16 + 4 * q + (lane >> 4);
@@ -133,12 +142,22 @@ hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const 
     const long long pairs = (long long)nf * S;
     if (pairs == 0) return HDG_OK;
     const int grid = div_up(pairs, BS / 64);
-    if (out_fp32)
-        hipLaunchKernelGGL(k_fold_bj<float>, dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64,
-                           (float*)out);
-    else
-        hipLaunchKernelGGL(k_fold_bj<double>, dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64,
-                           (double*)out);
+    if (nb > 256) {
+        ctx->err = "fold_bj: face block edge above 256";
+        return HDG_ERR_SHAPE;
+    }
+#define HDG_FOLD(T, KG) \
+    hipLaunchKernelGGL((k_fold_bj<T, KG>), dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64, (T*)out)
+    // KG groups of 16 k cover the (padded) block edge
+    const int kg = (nb + 15) / 16;
+    if (out_fp32) {
+        if (kg <= 1) HDG_FOLD(float, 1); else if (kg <= 2) HDG_FOLD(float, 2); else if (kg <= 3) HDG_FOLD(float, 3);
+        else if (kg <= 4) HDG_FOLD(float, 4); else if (kg <= 8) HDG_FOLD(float, 8); else HDG_FOLD(float, 16);
+    } else {
+        if (kg <= 1) HDG_FOLD(double, 1); else if (kg <= 2) HDG_FOLD(double, 2); else if (kg <= 3) HDG_FOLD(double, 3);
+        else if (kg <= 4) HDG_FOLD(double, 4); else if (kg <= 8) HDG_FOLD(double, 8); else HDG_FOLD(double, 16);
+    }
+#undef HDG_FOLD
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

@@ -362,11 +362,21 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
     if (ctl->done) return;
     __shared__ double ds[2 * 201];      // restart lengths up to 200
     __shared__ double tsh[201];
+    __shared__ double hcol[202];        // column j-1 of Hu (rows 0..j)
+    __shared__ double css[201], sns[201];
     __shared__ double sh_rho;
     __shared__ int sh_stop;
     const int lane = threadIdx.x;
     const int J = j + 1;
+    // everything the serial part needs, loaded by all lanes at once
     for (int i = lane; i < (finish ? J : 2 * J); i += 64) ds[i] = d[i];
+    if (j > 0) {
+        for (int i = lane; i < j; i += 64) {
+            hcol[i] = Hu[(size_t)(j - 1) * ldh + i];
+            css[i] = cs[i];
+            sns[i] = sn[i];
+        }
+    }
     __syncthreads();
     double aa = 0.0, ac = 0.0;
     for (int i = lane; i < j; i += 64) {
@@ -375,25 +385,34 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
     }
     aa = wave_sum(aa);
     ac = wave_sum(ac);
+    // delayed pass for column j-1: Hu[:j, j-1] += a, Hu[j, j-1] = rho
+    const double r2 = ds[j] - aa;
+    const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+    if (j > 0) {
+        for (int i = lane; i < j; i += 64) {
+            hcol[i] += ds[i];
+            Hu[(size_t)(j - 1) * ldh + i] = hcol[i];
+        }
+        if (lane == 0) {
+            hcol[j] = rho;
+            Hu[(size_t)(j - 1) * ldh + j] = rho;
+        }
+    }
+    __syncthreads();
     if (lane == 0) {
-        const double r2 = ds[j] - aa;
-        const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
-        sh_rho = rho;
         int stop = 0;
         if (j > 0) {
-            // delayed pass for column j-1, then its Givens rotation
-            double* hu = Hu + (size_t)(j - 1) * ldh;
-            double* col = H + (size_t)(j - 1) * ldh;
-            for (int i = 0; i < j; ++i) hu[i] += ds[i];
-            hu[j] = rho;
-            for (int i = 0; i <= j; ++i) col[i] = hu[i];
+            // Givens: previous rotations, a new one, the residual estimate (column j-1)
             const int c0 = j - 1;
+            double* col = H + (size_t)c0 * ldh;
+            double hprev = hcol[0];
             for (int i = 0; i < c0; ++i) {
-                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                const double hn = hcol[i + 1];
+                const double t = css[i] * hprev + sns[i] * hn;
                 col[i] = t;
+                hprev = -sns[i] * hprev + css[i] * hn;
             }
-            const double hjj = col[c0], hn = col[c0 + 1];
+            const double hjj = hprev, hn = hcol[c0 + 1];
             double c = 1.0, sg = 0.0;
             if (hn != 0.0) {
                 const double r = hypot(hjj, hn);
@@ -417,15 +436,27 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
         if (!(rho > 0.0) || !isfinite(rho)) stop = 1;   // breakdown: the space is invariant
         if (finish) stop = 1;
         if (stop) ctl->done = 1;
+        sh_rho = rho;
         sh_stop = stop;
     }
     __syncthreads();
     if (sh_stop) return;
-    const double rho = sh_rho, irho = 1.0 / rho;
-    // t = Hu[:j+1, :j] a (column j-1 was just completed)
+    const double irho = 1.0 / sh_rho;
+    // t = Hu[:j+1, :j] a over the Hessenberg pattern (row i has entries in columns q >= i-1
+    // only; nothing below the subdiagonal is ever read): column j-1 from LDS, the others
+    // read eight at a time
     for (int i = lane; i <= j; i += 64) {
         double t = 0.0;
-        for (int q = 0; q < j; ++q) t += Hu[(size_t)q * ldh + i] * ds[q];
+        const int qe = j - 1;
+        for (int q0 = i > 0 ? i - 1 : 0; q0 < qe; q0 += 8) {
+            double m[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m[u] = Hu[(size_t)(q0 + u < qe ? q0 + u : q0) * ldh + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u < qe) t += m[u] * ds[q0 + u];
+        }
+        if (j > 0 && i <= j) t += hcol[i] * ds[j - 1];
         tsh[i] = t;
     }
     __syncthreads();
@@ -442,32 +473,54 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
 // The update sweep of step j, one read of V_0..V_{j-1}:
 //     v_j = (vt_j - V_{<j} a) / rho           (written over vt_j),
 //     vt_{j+1} = wt / rho - V_{<j} b_{<j} - v_j b_j   (written over wt).
+// Two consecutive entries per thread (16-byte loads), eight columns in flight.
 __global__ __launch_bounds__(BS) void k_dcgs2_update(const double* __restrict__ V, size_t ldv, int j,
                                                      double* vj, double* wt, const double* __restrict__ coef,
                                                      int ldc, size_t n, const int* skip) {
     if (skip && *skip) return;
-    const size_t k = (size_t)blockIdx.x * BS + threadIdx.x;
+    const size_t k = 2 * ((size_t)blockIdx.x * BS + threadIdx.x);
     if (k >= n) return;
     const double* a = coef;
     const double* b = coef + ldc;
     const double irho = coef[2 * ldc];
-    double s1 = 0.0, s2 = 0.0;
-    const double vt = vj[k], w = wt[k];
+    if (k + 1 >= n) {      // odd tail entry
+        double s1 = 0.0, s2 = 0.0;
+        for (int i = 0; i < j; ++i) {
+            const double m = V[(size_t)i * ldv + k];
+            s1 += m * a[i];
+            s2 += m * b[i];
+        }
+        const double v = (vj[k] - s1) * irho;
+        vj[k] = v;
+        wt[k] = wt[k] * irho - s2 - v * b[j];
+        return;
+    }
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 vt = *reinterpret_cast<const d2*>(vj + k);
+    const d2 w = *reinterpret_cast<const d2*>(wt + k);
+    double s1x = 0.0, s1y = 0.0, s2x = 0.0, s2y = 0.0;
     for (int i0 = 0; i0 < j; i0 += 8) {
-        double m[8];
+        d2 m[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) m[u] = V[(size_t)(i0 + u < j ? i0 + u : 0) * ldv + k];
+        for (int u = 0; u < 8; ++u)
+            m[u] = *reinterpret_cast<const d2*>(V + (size_t)(i0 + u < j ? i0 + u : 0) * ldv + k);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (i0 + u < j) {
-                s1 += m[u] * a[i0 + u];
-                s2 += m[u] * b[i0 + u];
+                s1x += m[u].x * a[i0 + u];
+                s1y += m[u].y * a[i0 + u];
+                s2x += m[u].x * b[i0 + u];
+                s2y += m[u].y * b[i0 + u];
             }
     }
-    const double v = (vt - s1) * irho;
-    vj[k] = v;
-    wt[k] = w * irho - s2 - v * b[j];
+    d2 v, o;
+    v.x = (vt.x - s1x) * irho;
+    v.y = (vt.y - s1y) * irho;
+    o.x = w.x * irho - s2x - v.x * b[j];
+    o.y = w.y * irho - s2y - v.y * b[j];
+    *reinterpret_cast<d2*>(vj + k) = v;
+    *reinterpret_cast<d2*>(wt + k) = o;
 }
 
 }  // namespace
@@ -521,8 +574,10 @@ hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* d, int j,
 
 hdg_status vec_dcgs2_update(hdg_ctx ctx, const double* V, size_t ldv, int j, double* vj, double* wt,
                             const double* coef, int ldc, size_t n, const int* skip) {
-    hipLaunchKernelGGL(k_dcgs2_update, dim3(div_up((long long)n, BS)), dim3(BS), 0, ctx->stream, V, ldv, j, vj, wt,
-                       coef, ldc, n, skip);
+    // two entries per thread: vj, wt and the columns of V must be 16-byte aligned (the basis
+    // columns start at multiples of ldv, a multiple of 64 doubles)
+    hipLaunchKernelGGL(k_dcgs2_update, dim3(div_up((long long)(n + 1) / 2, BS)), dim3(BS), 0, ctx->stream, V, ldv, j,
+                       vj, wt, coef, ldc, n, skip);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
