@@ -30,6 +30,47 @@ def bj_apply(Binv, y):
     return np.einsum("fcr,fc->fr", Binv, Y).reshape(-1)
 
 
+def asm_matrices(Kbar, K, f2e, e2f, dims):
+    """Additive Schwarz subdomain matrices, one per element (Section 4.6): start from the
+    element Schur complement Kbar^e (nt x nt, row-major, blocks of nb = M P_F per local face)
+    and replace the diagonal block of every local face l by the sum of both neighbours'
+    diagonal blocks, Kbar^{e1}_{l1 l1} + Kbar^{e2}_{l2 l2} (on a boundary face only e1
+    contributes). Faces in their canonical orientation (no permutation). Returns P [ne][nt][nt]."""
+    M, PF, L = dims["ncomp"], dims["npf"], dims["nlfe"]
+    nb = M * PF
+    P = np.array(Kbar, dtype=np.float64, copy=True)
+    for f in range(f2e.shape[0]):
+        e1, l1, e2, l2 = (int(v) for v in f2e[f])
+        if e2 < 0:
+            continue
+        s1 = slice(l1 * nb, (l1 + 1) * nb)
+        s2 = slice(l2 * nb, (l2 + 1) * nb)
+        enriched = Kbar[e1][s1, s1] + Kbar[e2][s2, s2]
+        P[e1][s1, s1] = enriched
+        P[e2][s2, s2] = enriched
+    return P
+
+
+def asm_inverses(P):
+    return np.array([np.linalg.inv(Pe) for Pe in P])
+
+
+def asm_apply(Pinv, e2f, y, dims):
+    """z = sum_e R_e^T (P^e)^{-1} R_e y (Section 3.3 / 4.6): gather the element's face slices
+    of y, apply the element inverse, add the result back onto the faces."""
+    M, PF, L = dims["ncomp"], dims["npf"], dims["nlfe"]
+    nb = M * PF
+    nf = y.size // nb
+    Y = y.reshape(nf, nb)
+    Z = np.zeros_like(Y)
+    for e in range(Pinv.shape[0]):
+        ye = np.concatenate([Y[int(e2f[e, l])] for l in range(L)])
+        ze = Pinv[e] @ ye
+        for l in range(L):
+            Z[int(e2f[e, l])] += ze[l * nb:(l + 1) * nb]
+    return Z.reshape(-1)
+
+
 def _orth(V, w, j, method):
     """Orthogonalise w against V[:j+1]; returns coefficients h (j+1,) and w."""
     if method == "mgs":

@@ -208,3 +208,53 @@ def test_gmres_dcgs2_bj_matches_direct_on_c1():
                                  restart=20, rtol=1e-12)
     assert info["converged"] and info["cycles"] >= 2
     assert np.linalg.norm(x - out["x"]) <= 1e-10 * np.linalg.norm(out["x"])
+
+
+def _face_dofs(f, nb):
+    return np.arange(f * nb, (f + 1) * nb)
+
+
+@pytest.mark.parametrize("make", [lambda: configs.c1(n=3), lambda: configs.c2(n=2, p=1),
+                                  lambda: configs.c5(n=1, p=1)])
+def test_asm_subdomain_matrix_is_restricted_global_matrix(make):
+    """The enriched element matrix equals R_e K R_e^T: the assembled global matrix restricted
+    to the faces of the element (Section 3.3 defines K_l that way)."""
+    pb = make()
+    out = oracle_pipeline(pb)
+    d = pb.dims()
+    nb = d["ncomp"] * d["npf"]
+    P = krylov.asm_matrices(out["Kbar"], out["K"], pb.mesh.f2e, pb.mesh.e2f, d)
+    A = out["A"].tocsr()
+    for e in range(pb.mesh.ne):
+        idx = np.concatenate([_face_dofs(int(f), nb) for f in pb.mesh.e2f[e]])
+        Re = A[idx][:, idx].toarray()
+        assert np.allclose(P[e], Re, rtol=0, atol=1e-12 * np.abs(Re).max())
+
+
+def test_asm_single_element_is_exact_inverse():
+    """One element: every face belongs to it, so ASM is the exact inverse of K."""
+    pb = configs.c1(n=1)
+    out = oracle_pipeline(pb)
+    d = pb.dims()
+    Pinv = krylov.asm_inverses(krylov.asm_matrices(out["Kbar"], out["K"], pb.mesh.f2e, pb.mesh.e2f, d))
+    y = np.random.default_rng(3).standard_normal(out["r"].size)
+    z = krylov.asm_apply(Pinv, pb.mesh.e2f, y, d)
+    assert np.allclose(out["A"] @ z, y, atol=1e-11 * np.abs(y).max())
+
+
+def test_asm_converges_faster_than_bj():
+    """ASM-preconditioned FGMRES needs fewer iterations than block-Jacobi on the Poisson
+    workload (the paper's observation, Section 5), and both reach the direct solution."""
+    pb = configs.c1()
+    out = oracle_pipeline(pb)
+    d = pb.dims()
+    Pinv = krylov.asm_inverses(krylov.asm_matrices(out["Kbar"], out["K"], pb.mesh.f2e, pb.mesh.e2f, d))
+    A = out["A"]
+    x1, i_asm = krylov.fgmres(lambda v: A @ v, out["r"], prec=lambda v: krylov.asm_apply(Pinv, pb.mesh.e2f, v, d),
+                              restart=50, rtol=1e-11)
+    Binv = krylov.bj_inverses(out["K"])
+    x2, i_bj = krylov.fgmres(lambda v: A @ v, out["r"], prec=lambda v: krylov.bj_apply(Binv, v),
+                             restart=50, rtol=1e-11)
+    assert i_asm["converged"] and i_bj["converged"] and i_asm["iters"] < i_bj["iters"]
+    for x in (x1, x2):
+        assert np.linalg.norm(x - out["x"]) <= 1e-9 * np.linalg.norm(out["x"])
