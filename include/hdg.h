@@ -147,7 +147,9 @@ hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
  *   z = p(B) M^{-1} y, B = M^{-1} K, harmonic Ritz values from one MGS Arnoldi
  *   cycle of length poly_degree on B started at poly_v0, Leja order, Section 4.7),
  *   HDG_PREC_BJ_CHEB (Chebyshev acceleration of degree poly_degree on B over a real
- *   interval estimated from the same Ritz values).
+ *   interval estimated from the same Ritz values); HDG_PREC_ASM, HDG_PREC_ASM_POLY and
+ *   HDG_PREC_ASM_CHEB are the same with M^{-1} the element-patch additive Schwarz
+ *   operator (Sections 3.3, 4.6), whose inverses hdg_asm_setup forms (asm_* options).
  * orth: Arnoldi orthogonalisation (Section 4.4). HDG_ORTH_CGS2 (default), HDG_ORTH_CGS
  *   and HDG_ORTH_MGS run the flexible form above (x += Z y, z_j = M^{-1} v_j kept).
  *   HDG_ORTH_DCGS2 runs right-preconditioned GMRES with the preconditioner fixed
@@ -161,7 +163,8 @@ hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
  *   test use the same vector).
  * x: on entry the initial guess, on exit the solution.
  * Returns HDG_NOT_CONVERGED (positive) when max_iters is reached. */
-enum { HDG_PREC_NONE = 0, HDG_PREC_BJ = 1, HDG_PREC_BJ_POLY = 2, HDG_PREC_BJ_CHEB = 3 };
+enum { HDG_PREC_NONE = 0, HDG_PREC_BJ = 1, HDG_PREC_BJ_POLY = 2, HDG_PREC_BJ_CHEB = 3,
+       HDG_PREC_ASM = 4, HDG_PREC_ASM_POLY = 5, HDG_PREC_ASM_CHEB = 6 };
 enum { HDG_ORTH_CGS2 = 0, HDG_ORTH_CGS = 1, HDG_ORTH_MGS = 2, HDG_ORTH_DCGS2 = 3 };
 enum { HDG_FP64 = 0, HDG_MIXED = 1 };
 
@@ -188,6 +191,10 @@ typedef struct {
                                    product (polynomial preconditioners become polynomials in
                                    K M^{-1}); x += M^{-1}(...) once per cycle. Same iterates in
                                    exact arithmetic; ignored otherwise. */
+    const double* asm_inv64;    /* device, additive Schwarz inverses from hdg_asm_setup: FP64 */
+    const float* asm_inv32;     /*   and FP32 (needed with HDG_MIXED) */
+    const int32_t* asm_f2e;     /* device f2e and e2f as for hdg_assemble_blocks */
+    const int32_t* asm_e2f;
 } hdg_solve_opts;
 
 typedef struct {
@@ -222,6 +229,27 @@ hdg_status hdg_recover_local(hdg_ctx ctx, const hdg_dims* dims, const double* lo
 
 /* (5) Newton update state += alpha * delta over n entries -- Section 2.3, Section 4.4. */
 hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double* delta, double* state);
+
+/* (6) Additive Schwarz preconditioner with one element per subdomain -- Section 3.3
+ * (definition), Section 4.6 (element matrices and their enrichment).
+ *
+ * hdg_asm_setup forms, for every element e, P^e = Kbar^e with the diagonal block of each
+ * local face l replaced by the assembled K[f][0] of its face f = e2f[e][l] (for an
+ * interior face the sum of both neighbours' diagonal blocks; P^e = R_e K R_e^T), and
+ * writes its inverse as the block rows of the element's local faces:
+ *   inv [ne][N_lfe][N_lfe][nb][nb], inv[e][l][l'][col][row] = (P^e)^{-1}(l nb + row, l' nb + col)
+ * in FP64 (inv64) and/or FP32 (inv32; either may be NULL, not both). Kbar as from
+ * hdg_condense, K64 as from hdg_assemble_blocks (canonical face orientation: assembled with
+ * perm = NULL), e2f as for hdg_assemble_blocks. Workspace about 4 GiB (element chunks).
+ * HDG_ERR_SINGULAR names the first element whose P^e has a zero pivot.
+ * hdg_asm_apply (test hook): z = sum_e R_e^T (P^e)^{-1} R_e y with inv64 (HDG_FP64) or
+ * inv32 (HDG_MIXED); f2e and e2f as for hdg_assemble_blocks; y and z must not alias.
+ * Pass inv64/inv32/f2e/e2f to hdg_gmres_solve through the asm_* options with prec
+ * HDG_PREC_ASM, HDG_PREC_ASM_POLY or HDG_PREC_ASM_CHEB. */
+hdg_status hdg_asm_setup(hdg_ctx ctx, const hdg_dims* dims, const double* Kbar, const double* K64,
+                         const int32_t* e2f, double* inv64, float* inv32);
+hdg_status hdg_asm_apply(hdg_ctx ctx, const hdg_dims* dims, const double* inv64, const float* inv32,
+                         int32_t precision, const int32_t* f2e, const int32_t* e2f, const double* y, double* z);
 
 /* ---------------------------------------------------------------------------
  * Building blocks exposed for tests and benchmarks (same kernels as the solver).

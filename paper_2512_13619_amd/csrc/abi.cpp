@@ -178,12 +178,19 @@ hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims, const double* K64,
     if (o->restart < 1 || o->restart > 200) return set_err(ctx, HDG_ERR_ARG, "restart must be in [1, 200]");
     if (o->max_iters < 0) return set_err(ctx, HDG_ERR_ARG, "max_iters must be >= 0");
     if (!(o->rtol >= 0.0) || !(o->atol >= 0.0)) return set_err(ctx, HDG_ERR_ARG, "rtol/atol must be >= 0");
-    if (o->prec < HDG_PREC_NONE || o->prec > HDG_PREC_BJ_CHEB) return set_err(ctx, HDG_ERR_ARG, "unknown prec");
+    if (o->prec < HDG_PREC_NONE || o->prec > HDG_PREC_ASM_CHEB) return set_err(ctx, HDG_ERR_ARG, "unknown prec");
     if (o->orth < HDG_ORTH_CGS2 || o->orth > HDG_ORTH_DCGS2) return set_err(ctx, HDG_ERR_ARG, "unknown orth");
     if (o->precision != HDG_FP64 && o->precision != HDG_MIXED)
         return set_err(ctx, HDG_ERR_ARG, "precision must be HDG_FP64 or HDG_MIXED");
     if (o->precision == HDG_MIXED && !K32) return set_err(ctx, HDG_ERR_ARG, "mixed precision needs K32");
-    const bool poly = o->prec == HDG_PREC_BJ_POLY || o->prec == HDG_PREC_BJ_CHEB;
+    const bool poly = o->prec == HDG_PREC_BJ_POLY || o->prec == HDG_PREC_BJ_CHEB || o->prec == HDG_PREC_ASM_POLY ||
+                      o->prec == HDG_PREC_ASM_CHEB;
+    const bool schwarz = o->prec == HDG_PREC_ASM || o->prec == HDG_PREC_ASM_POLY || o->prec == HDG_PREC_ASM_CHEB;
+    if (schwarz) {
+        if (!o->asm_f2e || !o->asm_e2f || !o->asm_inv64 || (o->precision == HDG_MIXED && !o->asm_inv32))
+            return set_err(ctx, HDG_ERR_ARG, "additive Schwarz needs asm_inv64 (and asm_inv32 when mixed), asm_f2e and asm_e2f");
+        if (dims->ne <= 0) return set_err(ctx, HDG_ERR_SHAPE, "additive Schwarz needs dims->ne > 0");
+    }
     if (poly && (o->poly_degree < 1 || o->poly_degree > 64))
         return set_err(ctx, HDG_ERR_ARG, "poly_degree must be in [1, 64]");
     if (poly && !o->poly_v0) return set_err(ctx, HDG_ERR_ARG, "polynomial preconditioner needs poly_v0");
@@ -268,6 +275,34 @@ hdg_status hdg_bj_apply(hdg_ctx ctx, const hdg_dims* dims, const double* Binv64,
         return set_err(ctx, HDG_ERR_ARG, "hdg_bj_apply: NULL pointer");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
     return op_apply_run(ctx, dims, m32 ? (const void*)Binv32 : (const void*)Binv64, m32, nullptr, 1, y, z);
+    GUARD_END
+}
+
+hdg_status hdg_asm_setup(hdg_ctx ctx, const hdg_dims* dims, const double* Kbar, const double* K64,
+                         const int32_t* e2f, double* inv64, float* inv32) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    if (dims->ne == 0) return HDG_OK;
+    if (!Kbar || !K64 || !e2f || (!inv64 && !inv32)) return set_err(ctx, HDG_ERR_ARG, "hdg_asm_setup: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return asm_setup_run(ctx, dims, Kbar, K64, e2f, inv64, inv32);
+    GUARD_END
+}
+
+hdg_status hdg_asm_apply(hdg_ctx ctx, const hdg_dims* dims, const double* inv64, const float* inv32,
+                         int32_t precision, const int32_t* f2e, const int32_t* e2f, const double* y, double* z) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    const bool m32 = precision == HDG_MIXED;
+    if ((m32 ? (const void*)inv32 : (const void*)inv64) == nullptr || !f2e || !e2f || !y || !z || y == z)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_asm_apply: NULL or aliased pointer");
+    if (dims->ne <= 0) return set_err(ctx, HDG_ERR_SHAPE, "hdg_asm_apply: dims->ne must be > 0");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return asm_apply_run(ctx, dims, m32 ? (const void*)inv32 : (const void*)inv64, m32, f2e, e2f, y, z);
     GUARD_END
 }
 

@@ -25,6 +25,7 @@ enum WsSlot {
     WS_PART,           // reduction partials
     WS_CTL,            // GMRES device control block + Hessenberg/Givens state
     WS_KFOLD,          // right-preconditioned operator blocks K M^{-1}
+    WS_ASM,            // additive Schwarz: unit neighbour table, unit results, a work vector
     WS_NSLOTS
 };
 
@@ -152,6 +153,17 @@ hdg_status krylov_store_norm(hdg_ctx ctx, const double* part, int nblk, double* 
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi batched inverse (Gauss-Jordan with partial pivoting).
+// Additive Schwarz (Section 4.6): subdomain inverses inv[e][l][l'][col][row] (FP64 and/or
+// FP32), the unit neighbour table, and z = sum_e R_e^T (P^e)^{-1} R_e y with the epilogue
+// applied per face entry (zu: ne*L*nb scratch).
+hdg_status asm_setup_run(hdg_ctx ctx, const hdg_dims* d, const double* Kbar, const double* K64, const int32_t* e2f,
+                         double* inv64, float* inv32);
+hdg_status asm_unit_nbr(hdg_ctx ctx, int64_t ne, int L, const int32_t* e2f, int32_t* unbr);
+hdg_status asm_apply_run(hdg_ctx ctx, const hdg_dims* d, const void* inv, bool inv32, const int32_t* f2e,
+                         const int32_t* e2f, const double* y, double* z);
+hdg_status asm_apply_op(hdg_ctx ctx, int nf, int nb, int L, int64_t ne, const void* inv, bool inv32,
+                        const int32_t* unbr, const int32_t* f2e, double* zu, const double* y, const FaceEpilogue& epi,
+                        const int* skip);
 // Kf[f][s] = K[f][s] Binv[nbr(f,s)] (the right-preconditioned block row), FP64 products.
 hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const int32_t* nbr, const double* B64,
                    void* out, bool out_fp32);

@@ -601,6 +601,109 @@ size_t lu_lds_bytes(const CondDims& cd, int NB) {
     return sizeof(double) * (size_t)cd.R * (NB + 1) + sizeof(int) * ((size_t)cd.nu + 2 * 64);
 }
 
+// Panel width of the elimination: all nu columns when nu <= 64 and the panel fits in LDS,
+// else 32, 16 or 8 columns; 0 when even 8 does not fit.
+int pick_panel(const CondDims& cd) {
+    const size_t lds_cap = 150 * 1024;
+    const int cands[4] = {cd.nu, 32, 16, 8};
+    for (int k = 0; k < 4; ++k) {
+        const int nb = cands[k] < cd.nu ? cands[k] : cd.nu;
+        if (nb <= 64 && lu_lds_bytes(cd, nb) <= lds_cap) return nb;
+    }
+    return 0;
+}
+
+hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
+    const size_t lds = lu_lds_bytes(cd, NB);
+    const void* lu_fn = NB <= 16 ? (const void*)k_cond_lu<16, 512> : NB <= 32 ? (const void*)k_cond_lu<32, 512>
+                                                                               : (const void*)k_cond_lu<64, 256>;
+    if (lds > 64 * 1024)
+        HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_qelim, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)GEMM_LDS));
+    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)GEMM_LDS));
+    return HDG_OK;
+}
+
+// Stages 2 and 3 on n elements whose matrices T are in place (top rows at `top`, row stride
+// cd.C, trace rows at `bot`): elimination of the first nu columns, then the Schur product
+// into Kout [n][nt][nt] and rout [n][nt]. A zero pivot records e_off + element in status.
+hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t n, double* top, double* bot,
+                               double* Kout, double* rout, int* status, int64_t e_off) {
+    const size_t lds = lu_lds_bytes(cd, NB);
+    if (NB <= 16)
+        hipLaunchKernelGGL((k_cond_lu<16, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB, top, bot,
+                           status, (int)e_off);
+    else if (NB <= 32)
+        hipLaunchKernelGGL((k_cond_lu<32, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB, top, bot,
+                           status, (int)e_off);
+    else
+        hipLaunchKernelGGL((k_cond_lu<64, 256>), dim3((unsigned)n), dim3(256), lds, ctx->stream, cd, NB, top, bot,
+                           status, (int)e_off);
+    HDG_LAUNCH_CHECK(ctx);
+    const int tm_n = div_up(cd.nt, GT);
+    const long long ntile = (long long)n * tm_n * tm_n;
+    const long long nblk = (ntile + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_cond_schur, dim3((unsigned)nblk), dim3(BS), GEMM_LDS, ctx->stream, cd, ntile, tm_n, tm_n,
+                       top, bot, Kout, rout);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+// ---- additive Schwarz subdomain inverses (Section 4.6) -----------------------------------------
+// T = [[P, I, 0], [I, 0, 0]] with P the element's enriched Schur complement: eliminating the
+// first nt columns leaves -P^{-1} where the Schur complement would be.
+//   P = Kbar^e, except that the diagonal block of each local face l is the assembled K_ff of
+//   its face f = e2f[e][l] (= Kbar^{e1}_{l1 l1} + Kbar^{e2}_{l2 l2}; one term on a boundary).
+__global__ __launch_bounds__(BS) void k_asm_fill(int nb, int L, const double* __restrict__ Kbar,
+                                                 const double* __restrict__ K64, int S, const int32_t* __restrict__ e2f,
+                                                 double* __restrict__ top, double* __restrict__ bot) {
+    const long long e = blockIdx.x;
+    const int nt = L * nb, C = 2 * nt + 1;
+    const double* Ke = Kbar + (size_t)e * nt * nt;
+    double* Te = top + (size_t)e * nt * C;
+    double* Be = bot + (size_t)e * nt * C;
+    for (int idx = threadIdx.x; idx < nt * C; idx += BS) {
+        const int r = idx / C, c = idx - r * C;
+        double v = 0.0, w = 0.0;
+        if (c < nt) {
+            const int lr = r / nb, lc = c / nb;
+            if (lr == lc) {
+                const long long f = e2f[e * L + lr];
+                v = K64[((size_t)f * S) * nb * nb + (size_t)(c - lc * nb) * nb + (r - lr * nb)];
+            } else {
+                v = Ke[(size_t)r * nt + c];
+            }
+            w = (c == r) ? 1.0 : 0.0;
+        } else if (c < 2 * nt) {
+            v = (c - nt == r) ? 1.0 : 0.0;
+        }
+        Te[idx] = v;
+        Be[idx] = w;
+    }
+}
+
+// inv[e][l][l'][col][row] = P^{-1}(l nb + row, l' nb + col) = -Kout[e][l nb + row][l' nb + col]
+// (the block row of unit (e, l), blocks column-major, as the face operator streams them).
+__global__ __launch_bounds__(BS) void k_asm_store(int nb, int L, const double* __restrict__ Kout,
+                                                  double* __restrict__ inv64, float* __restrict__ inv32) {
+    const long long e = blockIdx.x;
+    const int nt = L * nb;
+    const size_t base = (size_t)e * nt * nt;
+    for (int idx = threadIdx.x; idx < nt * nt; idx += BS) {
+        // idx enumerates the output order: l, l', col, row
+        int rem = idx;
+        const int row = rem % nb; rem /= nb;
+        const int col = rem % nb; rem /= nb;
+        const int lp = rem % L; rem /= L;
+        const int l = rem;
+        const double v = -Kout[base + (size_t)(l * nb + row) * nt + (lp * nb + col)];
+        if (inv64) inv64[base + idx] = v;
+        if (inv32) inv32[base + idx] = (float)v;
+    }
+}
+
 }  // namespace
 
 hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_elem_blocks* in, double* Kbar,
@@ -610,14 +713,7 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
     cd.nu = cd.M * cd.P; cd.nq = cd.M * cd.D * cd.P; cd.nt = cd.L * cd.M * cd.PF;
     cd.R = cd.nu + cd.nt; cd.C = cd.R + 1; cd.NW = cd.P + cd.L * cd.PF; cd.KD = cd.D * cd.P;
     if (ne <= 0) return HDG_OK;
-    // panel width: the whole Ebar when it fits in LDS, else 32 or 16 columns
-    const size_t lds_cap = 150 * 1024;
-    int NB = 0;
-    const int cands[4] = {cd.nu, 32, 16, 8};
-    for (int k = 0; k < 4; ++k) {
-        const int nb = cands[k] < cd.nu ? cands[k] : cd.nu;
-        if (nb <= 64 && lu_lds_bytes(cd, nb) <= lds_cap) { NB = nb; break; }
-    }
+    const int NB = pick_panel(cd);
     if (NB == 0) {
         ctx->err = "condensation: element too large for the LDS-blocked elimination";
         return HDG_ERR_SHAPE;
@@ -636,15 +732,7 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
     if (!status) return st;
     const int big = 0x7fffffff;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-    const size_t lds = lu_lds_bytes(cd, NB);
-    const void* lu_fn = NB <= 16 ? (const void*)k_cond_lu<16, 512> : NB <= 32 ? (const void*)k_cond_lu<32, 512>
-                                                                               : (const void*)k_cond_lu<64, 256>;
-    if (lds > 64 * 1024)
-        HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_qelim, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)GEMM_LDS));
-    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)GEMM_LDS));
+    if ((st = set_kernel_lds(ctx, cd, NB)) != HDG_OK) return st;
     for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
         const int64_t n = (ne - e0) < chunk ? (ne - e0) : chunk;
         const size_t P = cd.P, LPF = (size_t)cd.L * cd.PF;
@@ -662,30 +750,68 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
                                local + e0 * cd.nu * cd.C, bot);
             HDG_LAUNCH_CHECK(ctx);
         }
-        if (NB <= 16)
-            hipLaunchKernelGGL((k_cond_lu<16, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB,
-                               local + e0 * cd.nu * cd.C, bot, status, (int)e0);
-        else if (NB <= 32)
-            hipLaunchKernelGGL((k_cond_lu<32, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB,
-                               local + e0 * cd.nu * cd.C, bot, status, (int)e0);
-        else
-            hipLaunchKernelGGL((k_cond_lu<64, 256>), dim3((unsigned)n), dim3(256), lds, ctx->stream, cd, NB,
-                               local + e0 * cd.nu * cd.C, bot, status, (int)e0);
-        HDG_LAUNCH_CHECK(ctx);
-        {
-            const int tm_n = div_up(cd.nt, GT);
-            const long long ntile = (long long)n * tm_n * tm_n;
-            const long long nblk = (ntile + 7) / 8 * 8;
-            hipLaunchKernelGGL(k_cond_schur, dim3((unsigned)nblk), dim3(BS), GEMM_LDS, ctx->stream, cd, ntile, tm_n,
-                               tm_n, local + e0 * cd.nu * cd.C, bot, Kbar + e0 * cd.nt * cd.nt, rbar + e0 * cd.nt);
-            HDG_LAUNCH_CHECK(ctx);
-        }
+        if ((st = eliminate_and_schur(ctx, cd, NB, n, local + e0 * cd.nu * cd.C, bot, Kbar + e0 * cd.nt * cd.nt,
+                                      rbar + e0 * cd.nt, status, e0)) != HDG_OK)
+            return st;
     }
     int bad = big;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     if (bad != big) {
         ctx->err = "condensation: zero or non-finite pivot in Ebar of element " + std::to_string(bad);
+        return HDG_ERR_SINGULAR;
+    }
+    return HDG_OK;
+}
+
+hdg_status asm_setup_run(hdg_ctx ctx, const hdg_dims* d, const double* Kbar, const double* K64, const int32_t* e2f,
+                         double* inv64, float* inv32) {
+    const int nb = d->ncomp * d->npf, L = d->nlfe, S = 2 * L - 1;
+    const int64_t ne = d->ne;
+    CondDims cd{};
+    cd.nu = L * nb;
+    cd.nt = L * nb;
+    cd.R = 2 * cd.nt;
+    cd.C = cd.R + 1;
+    if (ne <= 0) return HDG_OK;
+    const int NB = pick_panel(cd);
+    if (NB == 0) {
+        ctx->err = "additive Schwarz: element trace block too large for the LDS-blocked elimination";
+        return HDG_ERR_SHAPE;
+    }
+    const size_t per_elem = sizeof(double) * ((size_t)2 * cd.nt * cd.C + (size_t)cd.nt * cd.nt + cd.nt);
+    int64_t chunk = (int64_t)((size_t)4 << 30) / (int64_t)per_elem;
+    if (chunk < 1) chunk = 1;
+    if (chunk > ne) chunk = ne;
+    hdg_status st;
+    // workspace: top rows, trace rows, -P^{-1} and the (zero) right-hand-side output
+    double* top = (double*)ws_get(ctx, WS_T_BOTTOM, per_elem * (size_t)chunk, &st);
+    if (!top) return st;
+    double* bot = top + (size_t)chunk * cd.nt * cd.C;
+    double* Kout = bot + (size_t)chunk * cd.nt * cd.C;
+    double* rout = Kout + (size_t)chunk * cd.nt * cd.nt;
+    int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
+    if (!status) return st;
+    const int big = 0x7fffffff;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    if ((st = set_kernel_lds(ctx, cd, NB)) != HDG_OK) return st;
+    const size_t nt2 = (size_t)cd.nt * cd.nt;
+    for (int64_t e0 = 0; e0 < ne; e0 += chunk) {
+        const int64_t n = (ne - e0) < chunk ? (ne - e0) : chunk;
+        hipLaunchKernelGGL(k_asm_fill, dim3((unsigned)n), dim3(BS), 0, ctx->stream, nb, L, Kbar + e0 * nt2, K64, S,
+                           e2f + e0 * L, top, bot);
+        HDG_LAUNCH_CHECK(ctx);
+        if ((st = eliminate_and_schur(ctx, cd, NB, n, top, bot, Kout, rout, status, e0)) != HDG_OK) return st;
+        hipLaunchKernelGGL(k_asm_store, dim3((unsigned)n), dim3(BS), 0, ctx->stream, nb, L, Kout,
+                           inv64 ? inv64 + e0 * nt2 : nullptr, inv32 ? inv32 + e0 * nt2 : nullptr);
+        HDG_LAUNCH_CHECK(ctx);
+    }
+    int bad = big;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad != big) {
+        ctx->err = "additive Schwarz: zero or non-finite pivot in the subdomain matrix of element " +
+                   std::to_string(bad);
         return HDG_ERR_SINGULAR;
     }
     return HDG_OK;

@@ -170,6 +170,41 @@ __global__ __launch_bounds__(256) void k_face_identity(FaceArgs A, size_t n) {
         if (A.epi.out[o]) A.epi.out[o][idx] = v[o];
 }
 
+// Additive Schwarz prolongation (Section 4.6): face f sums the results of its one or two
+// elements' units (e1, l1) and (e2, l2), zu[(e*L + l)*nb + t], then applies the epilogue.
+// Face-parallel, no atomics: bitwise reproducible.
+__global__ __launch_bounds__(256) void k_asm_gather(int nf, int nb, int L, const int32_t* __restrict__ f2e,
+                                                    const double* __restrict__ zu, FaceArgs A) {
+    if (A.skip && *A.skip) return;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)nf * nb) return;
+    const size_t f = idx / nb;
+    const int t = (int)(idx - f * nb);
+    const int e1 = f2e[4 * f], l1 = f2e[4 * f + 1], e2 = f2e[4 * f + 2], l2 = f2e[4 * f + 3];
+    double u = zu[((size_t)e1 * L + l1) * nb + t];
+    if (e2 >= 0) u += zu[((size_t)e2 * L + l2) * nb + t];
+    double v[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        v[o] = A.epi.s[o] * u;
+        if (A.epi.X[o]) v[o] += A.epi.a[o] * A.epi.X[o][idx];
+        if (A.epi.Y[o]) v[o] += A.epi.b[o] * A.epi.Y[o][idx];
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o)
+        if (A.epi.out[o]) A.epi.out[o][idx] = v[o];
+}
+
+// Neighbour table of the element units: unit (e, l) takes block l' from face e2f[e][l'].
+__global__ __launch_bounds__(256) void k_asm_unit_nbr(long long ne, int L, const int32_t* __restrict__ e2f,
+                                                      int32_t* __restrict__ unbr) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= ne * L * L) return;
+    const long long e = idx / ((long long)L * L);
+    const int lp = (int)(idx % L);
+    unbr[idx] = e2f[e * L + lp];
+}
+
 template <typename T1, typename T2, bool HAS_M2, int KIND>
 hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     // 16-byte loads (4 floats or 2 doubles per thread) when nb and the matrix pointer
@@ -255,4 +290,48 @@ hdg_status face_op(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1
     if (!m1_fp32 && !m2_fp32) return launch_team<double, double, true, 0>(ctx, a);
     if (m1_fp32) return launch_team<float, double, true, 0>(ctx, a);
     return launch_team<double, float, true, 0>(ctx, a);
+}
+
+hdg_status asm_unit_nbr(hdg_ctx ctx, int64_t ne, int L, const int32_t* e2f, int32_t* unbr) {
+    const long long n = (long long)ne * L * L;
+    if (n == 0) return HDG_OK;
+    hipLaunchKernelGGL(k_asm_unit_nbr, dim3((unsigned)div_up(n, 256)), dim3(256), 0, ctx->stream, (long long)ne, L, e2f,
+                       unbr);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
+
+hdg_status asm_apply_op(hdg_ctx ctx, int nf, int nb, int L, int64_t ne, const void* inv, bool inv32,
+                        const int32_t* unbr, const int32_t* f2e, double* zu, const double* y, const FaceEpilogue& epi,
+                        const int* skip) {
+    // restriction + element solves: unit (e, l) = block row l of (P^e)^{-1} against y on e's faces
+    FaceEpilogue e0;
+    for (int o = 0; o < 3; ++o) {
+        e0.out[o] = nullptr;
+        e0.X[o] = nullptr;
+        e0.Y[o] = nullptr;
+        e0.s[o] = e0.a[o] = e0.b[o] = 0.0;
+    }
+    e0.out[0] = zu;
+    e0.s[0] = 1.0;
+    hdg_status st = face_op(ctx, (int)(ne * L), nb, L, L, inv, inv32, unbr, nullptr, false, y, e0, skip);
+    if (st != HDG_OK) return st;
+    // prolongation: sum over the face's elements
+    FaceArgs a;
+    a.M1 = nullptr;
+    a.nbr1 = nullptr;
+    a.M2 = nullptr;
+    a.x = nullptr;
+    a.epi = epi;
+    a.skip = skip;
+    a.nf = nf;
+    a.nb = nb;
+    a.S1 = 1;
+    a.nlfe = L;
+    const size_t n = (size_t)nf * nb;
+    if (n == 0) return HDG_OK;
+    hipLaunchKernelGGL(k_asm_gather, dim3((unsigned)div_up((long long)n, 256)), dim3(256), 0, ctx->stream, nf, nb, L,
+                       f2e, zu, a);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
 }

@@ -36,6 +36,10 @@
 
 namespace {
 
+// Preconditioner M^{-1} inside an operator: identity (block-Jacobi folded into K), block-Jacobi,
+// or element-patch additive Schwarz.
+enum { PK_IDENTITY = 0, PK_BJ = 1, PK_ASM = 2 };
+
 struct Op {
     int nf, nb, S, L;
     size_t N;
@@ -44,6 +48,15 @@ struct Op {
     const void* Binv;     // block-Jacobi inverses (64 or 32)
     bool b32;
     const int32_t* nbr;
+    int pk = PK_BJ;
+    // additive Schwarz
+    const void* asm_inv = nullptr;
+    bool asm32 = false;
+    const int32_t* unbr = nullptr;
+    const int32_t* f2e = nullptr;
+    double* zu = nullptr;
+    double* tmp = nullptr;
+    int64_t ne = 0;
 };
 
 FaceEpilogue epi0() {
@@ -65,12 +78,24 @@ hdg_status op_matvec(hdg_ctx ctx, const Op& op, const double* x, double* y, cons
     return face_op(ctx, op.nf, op.nb, op.S, op.L, op.K, op.k32, op.nbr, nullptr, false, x, e, skip);
 }
 
+// out = epilogue(M^{-1} y)
 hdg_status op_bj(hdg_ctx ctx, const Op& op, const double* y, const FaceEpilogue& e, const int* skip) {
-    return face_op(ctx, op.nf, op.nb, 1, op.L, op.Binv, op.b32, nullptr, nullptr, false, y, e, skip);
+    if (op.pk == PK_ASM)
+        return asm_apply_op(ctx, op.nf, op.nb, op.L, op.ne, op.asm_inv, op.asm32, op.unbr, op.f2e, op.zu, y, e, skip);
+    const void* M = op.pk == PK_BJ ? op.Binv : nullptr;      // nullptr: identity
+    return face_op(ctx, op.nf, op.nb, 1, op.L, M, op.b32, nullptr, nullptr, false, y, e, skip);
 }
 
+// out = epilogue(M^{-1} K x): one fused kernel for block-Jacobi (and the identity), the
+// product then the Schwarz operator otherwise
 hdg_status op_B(hdg_ctx ctx, const Op& op, const double* x, const FaceEpilogue& e, const int* skip) {
-    return face_op(ctx, op.nf, op.nb, op.S, op.L, op.K, op.k32, op.nbr, op.Binv, op.b32, x, e, skip);
+    if (op.pk == PK_ASM) {
+        hdg_status st = op_matvec(ctx, op, x, op.tmp, skip);
+        if (st != HDG_OK) return st;
+        return op_bj(ctx, op, op.tmp, e, skip);
+    }
+    const void* M2 = op.pk == PK_BJ ? op.Binv : nullptr;
+    return face_op(ctx, op.nf, op.nb, op.S, op.L, op.K, op.k32, op.nbr, M2, op.b32, x, e, skip);
 }
 
 struct PolyPlan {
@@ -165,7 +190,7 @@ hdg_status poly_apply(hdg_ctx ctx, const Op& op, const PolyPlan& pl, const doubl
 hdg_status prec_apply(hdg_ctx ctx, const Op& op, int prec, const PolyPlan& pl, const double* y, double* z,
                       double* work, size_t ld, const int* skip) {
     if (prec == HDG_PREC_NONE) return vec_lincomb(ctx, op.N, z, 1.0, y, 0.0, nullptr, skip);
-    if (prec == HDG_PREC_BJ) {
+    if (prec == HDG_PREC_BJ || prec == HDG_PREC_ASM) {
         FaceEpilogue e = epi0();
         e.out[0] = z;
         e.s[0] = 1.0;
@@ -321,7 +346,9 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     const size_t N = (size_t)nf * nb;
     const bool mixed = o->precision == HDG_MIXED;
     const int m = o->restart;
-    const bool poly = o->prec == HDG_PREC_BJ_POLY || o->prec == HDG_PREC_BJ_CHEB;
+    const bool poly = o->prec == HDG_PREC_BJ_POLY || o->prec == HDG_PREC_BJ_CHEB || o->prec == HDG_PREC_ASM_POLY ||
+                      o->prec == HDG_PREC_ASM_CHEB;
+    const bool schwarz = o->prec == HDG_PREC_ASM || o->prec == HDG_PREC_ASM_POLY || o->prec == HDG_PREC_ASM_CHEB;
     const int P = poly ? o->poly_degree : 0;
     hdg_status st;
     SolveWs w;
@@ -336,7 +363,28 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     Op op64 = op;
     op64.K = K64;
     op64.k32 = false;
-    if (o->prec != HDG_PREC_NONE) {
+    if (schwarz) {
+        // element-patch additive Schwarz: unit neighbour table, unit results, work vector
+        const int64_t ne = d->ne;
+        const size_t nunit = (size_t)ne * L;
+        const size_t bytes = sizeof(int32_t) * nunit * L + sizeof(double) * (nunit * nb + N) + 256;
+        char* base = (char*)ws_get(ctx, WS_ASM, bytes, &st);
+        if (!base) return st;
+        double* zu = (double*)base;
+        double* tmp = zu + nunit * nb;
+        int32_t* unbr = (int32_t*)(tmp + N);
+        if ((st = asm_unit_nbr(ctx, ne, L, o->asm_e2f, unbr)) != HDG_OK) return st;
+        op.pk = op64.pk = PK_ASM;
+        op.asm_inv = mixed ? (const void*)o->asm_inv32 : (const void*)o->asm_inv64;
+        op.asm32 = mixed;
+        op64.asm_inv = o->asm_inv64;
+        op64.asm32 = false;
+        op.unbr = op64.unbr = unbr;
+        op.f2e = op64.f2e = o->asm_f2e;
+        op.zu = op64.zu = zu;
+        op.tmp = op64.tmp = tmp;
+        op.ne = op64.ne = ne;
+    } else if (o->prec != HDG_PREC_NONE) {
         double* B64 = (double*)ws_get(ctx, WS_BINV64, sizeof(double) * (size_t)nf * nb * nb, &st);
         if (!B64) return st;
         float* B32 = nullptr;
@@ -361,7 +409,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         op64.b32 = false;
     }
     // operator of the Arnoldi steps: K, or the folded K M^{-1} blocks
-    const bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE;
+    const bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE && !schwarz;
     Op opi = op;
     if (fold) {
         const size_t nblk_el = (size_t)nf * S * nb * nb;
@@ -373,6 +421,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         opi.K = Kf;
         opi.k32 = mixed;
         opi.Binv = nullptr;
+        opi.pk = PK_IDENTITY;
     }
     // ||b||
     if ((st = vec_sumsq_partial(ctx, b, N, w.part, w.nblk, nullptr)) != HDG_OK) return st;
@@ -387,7 +436,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     const double target = std::max(o->rtol * bnorm, o->atol);
     // polynomial preconditioner setup
     PolyPlan plan;
-    plan.kind = o->prec;
+    plan.kind = (o->prec == HDG_PREC_BJ_CHEB || o->prec == HDG_PREC_ASM_CHEB) ? HDG_PREC_BJ_CHEB : HDG_PREC_BJ_POLY;
     if (poly) {
         std::vector<double> Hh;
         int pe = 0;
@@ -652,4 +701,22 @@ hdg_status op_apply_run(hdg_ctx ctx, const hdg_dims* d, const void* M1, bool m1_
     e.out[0] = y;
     e.s[0] = 1.0;
     return face_op(ctx, d->nf, d->ncomp * d->npf, S1, d->nlfe, M1, m1_32, nbr, nullptr, false, x, e, nullptr);
+}
+
+// Test hook: z = sum_e R_e^T (P^e)^{-1} R_e y.
+hdg_status asm_apply_run(hdg_ctx ctx, const hdg_dims* d, const void* inv, bool inv32, const int32_t* f2e,
+                         const int32_t* e2f, const double* y, double* z) {
+    const int nb = d->ncomp * d->npf, L = d->nlfe, nf = d->nf;
+    const int64_t ne = d->ne;
+    const size_t nunit = (size_t)ne * L;
+    hdg_status st;
+    char* base = (char*)ws_get(ctx, WS_ASM, sizeof(int32_t) * nunit * L + sizeof(double) * nunit * nb + 256, &st);
+    if (!base) return st;
+    double* zu = (double*)base;
+    int32_t* unbr = (int32_t*)(zu + nunit * nb);
+    if ((st = asm_unit_nbr(ctx, ne, L, e2f, unbr)) != HDG_OK) return st;
+    FaceEpilogue e = epi0();
+    e.out[0] = z;
+    e.s[0] = 1.0;
+    return asm_apply_op(ctx, nf, nb, L, ne, inv, inv32, unbr, f2e, zu, y, e, nullptr);
 }

@@ -14,15 +14,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
 HDG_OK, HDG_NOT_CONVERGED = 0, 1
-PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3}
+PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3, "asm": 4, "asm_poly": 5, "asm_cheb": 6}
 ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2, "dcgs2": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol declared in include/hdg.h
 SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
            "hdg_local_size", "hdg_condense", "hdg_assemble_blocks", "hdg_solve_opts_default", "hdg_gmres_solve",
-           "hdg_recover_local", "hdg_newton_update", "hdg_matvec", "hdg_bj_setup", "hdg_bj_apply",
-           "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
+           "hdg_recover_local", "hdg_newton_update", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
+           "hdg_bj_apply", "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch"]
 
@@ -49,7 +49,9 @@ class SolveOpts(ctypes.Structure):
                 ("atol", ctypes.c_double), ("prec", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
                 ("poly_v0", ctypes.c_void_p), ("orth", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("time_phases", ctypes.c_int32), ("fold_prec", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("time_phases", ctypes.c_int32), ("fold_prec", ctypes.c_int32),
+                ("asm_inv64", ctypes.c_void_p), ("asm_inv32", ctypes.c_void_p), ("asm_f2e", ctypes.c_void_p),
+                ("asm_e2f", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -93,6 +95,8 @@ def load():
     lib.hdg_matvec.argtypes = [vp, pd, vp, vp, vp, i32, vp, vp]
     lib.hdg_bj_setup.argtypes = [vp, pd, vp, vp, vp]
     lib.hdg_bj_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp]
+    lib.hdg_asm_setup.argtypes = [vp, pd, vp, vp, vp, vp, vp]
+    lib.hdg_asm_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp, vp, vp]
     lib.hdg_poly_apply.argtypes = [vp, pd, vp, vp, vp, vp, vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                    vp, vp]
     pdbl = ctypes.POINTER(dbl)
@@ -239,7 +243,7 @@ class Context:
     # (3)
     def gmres_solve(self, dims, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0,
                     prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0,
-                    use_graph=False, time_phases=False, fold_prec=False):
+                    use_graph=False, time_phases=False, fold_prec=False, asm=None):
         import torch
         d = make_dims(dims)
         nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
@@ -253,6 +257,12 @@ class Context:
         o.use_graph = 1 if use_graph else 0
         o.time_phases = 1 if time_phases else 0
         o.fold_prec = 1 if fold_prec else 0
+        if asm is not None:      # dict(inv64=..., inv32=..., f2e=..., e2f=...) from asm_setup
+            nt2 = int(dims["ne"]) * (L * nb) ** 2
+            o.asm_inv64 = _ptr(asm["inv64"], torch.float64, nt2, "asm_inv64")
+            o.asm_inv32 = _ptr(asm.get("inv32"), torch.float32, nt2, "asm_inv32", allow_none=True)
+            o.asm_f2e = _ptr(asm["f2e"], torch.int32, nf * 4, "asm_f2e")
+            o.asm_e2f = _ptr(asm["e2f"], torch.int32, int(dims["ne"]) * L, "asm_e2f")
         hist = np.zeros(max(hist_len, 1))
         if hist_len > 0:
             o.resid_hist_h = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -317,6 +327,30 @@ class Context:
         return self._check(self.lib.hdg_bj_apply(
             self.h, ctypes.byref(d), _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64", allow_none=True),
             _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision],
+            _ptr(y, torch.float64, nf * nb, "y"), _ptr(z, torch.float64, nf * nb, "z")))
+
+    def asm_setup(self, dims, Kbar, K64, e2f, inv64, inv32=None):
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        nt = L * nb
+        return self._check(self.lib.hdg_asm_setup(
+            self.h, ctypes.byref(d), _ptr(Kbar, torch.float64, ne * nt * nt, "Kbar"),
+            _ptr(K64, torch.float64, nf * S * nb * nb, "K64"), _ptr(e2f, torch.int32, ne * L, "e2f"),
+            _ptr(inv64, torch.float64, ne * nt * nt, "inv64", allow_none=True),
+            _ptr(inv32, torch.float32, ne * nt * nt, "inv32", allow_none=True)))
+
+    def asm_apply(self, dims, inv64, inv32, f2e, e2f, y, z, precision="fp64"):
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "npf", "nlfe"))
+        nb = M * PF
+        nt = L * nb
+        return self._check(self.lib.hdg_asm_apply(
+            self.h, ctypes.byref(d), _ptr(inv64, torch.float64, ne * nt * nt, "inv64", allow_none=True),
+            _ptr(inv32, torch.float32, ne * nt * nt, "inv32", allow_none=True), PRECISION[precision],
+            _ptr(f2e, torch.int32, nf * 4, "f2e"), _ptr(e2f, torch.int32, ne * L, "e2f"),
             _ptr(y, torch.float64, nf * nb, "y"), _ptr(z, torch.float64, nf * nb, "z")))
 
     def poly_apply(self, dims, K64, K32, nbr, Binv64, Binv32, theta, y, z, precision="fp64"):

@@ -42,8 +42,19 @@ class Pipeline:
         self.ctx.assemble(self.dims, self.f2e, self.e2f, self.perm, self.Kbar, self.rbar, self.K64, self.K32,
                           self.nbr, self.r)
 
+    def asm_setup(self, fp32=True):
+        """Additive Schwarz inverses of the element patches (needs Kbar and K64)."""
+        d = self.dims
+        n = d["ne"] * self.nt * self.nt
+        self.asm_inv64 = torch.empty(n, dtype=torch.float64, device=self.device)
+        self.asm_inv32 = torch.empty(n, dtype=torch.float32, device=self.device) if fp32 else None
+        self.ctx.asm_setup(d, self.Kbar, self.K64, self.e2f, self.asm_inv64, self.asm_inv32)
+        return dict(inv64=self.asm_inv64, inv32=self.asm_inv32, f2e=self.f2e, e2f=self.e2f)
+
     def solve(self, **kw):
         self.x.zero_()
+        if str(kw.get("prec", "")).startswith("asm") and "asm" not in kw:
+            kw["asm"] = dict(inv64=self.asm_inv64, inv32=self.asm_inv32, f2e=self.f2e, e2f=self.e2f)
         return self.ctx.gmres_solve(self.dims, self.K64, self.K32, self.nbr, self.r, self.x, **kw)
 
     def recover(self, Minv, Bd, Cd):

@@ -78,6 +78,30 @@ def test_reduced_workload_solution(ctx, name, precision, orth):
     assert ex < tol and eu < tol, (ex, eu)
 
 
+@pytest.mark.parametrize("prec", ["asm", "asm_poly"])
+@pytest.mark.parametrize("name", ["c2_elasticity_3cube_p3", "c5_ns_tet_2cube_p2"])
+def test_reduced_workload_asm(ctx, name, prec):
+    """The reduced workloads with the additive Schwarz preconditioners (mixed precision,
+    delayed CGS2): solution against the oracle's direct solve."""
+    from paper_2512_13619_amd.pipeline import Pipeline
+    make, _, P = REDUCED[name]
+    pb = make()
+    say("reduced asm", name, prec, pb.dims())
+    out = oracle_pipeline(pb)
+    pl = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    blk = {k: torch.as_tensor(v).cuda().contiguous() for k, v in out["blk"].items()}
+    pl.condense(blk)
+    pl.assemble()
+    pl.asm_setup()
+    v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(pl.x.numel())).cuda()
+    st = pl.solve(restart=50, max_iters=5000, rtol=1e-13, prec=prec, poly_degree=P, poly_v0=v0,
+                  precision="mixed", orth="dcgs2")
+    torch.cuda.synchronize()
+    ex = relerr(pl.x.cpu().numpy(), out["x"])
+    say("  iters", st["iters"], "err x", ex)
+    assert st["converged"] and ex < 1e-8, (st, ex)
+
+
 # ---------------------------------------------------------------------------------------------
 FULL = {
     "c2": (lambda: configs.c2(device="cuda"), "bj", "mixed"),
