@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--also", default="",
+                    help="comma-separated preconditioners (asm, asm_poly, bj_poly, ...) to time in one extra "
+                         "mixed-precision step each after the headline")
     ap.add_argument("--no-fold", action="store_true",
                     help="apply block-Jacobi separately in every step instead of folding it into the blocks")
     ap.add_argument("--orth", default="dcgs2", choices=["cgs2", "dcgs2", "cgs", "mgs"],
@@ -236,23 +239,30 @@ def main():
                           "copy_bytes_each_way": src.numel() * 8}), flush=True)
         return
 
-    def step(precision):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(d["nf"] * d["ncomp"] * d["npf"])).cuda()
+
+    def step(precision, prec="bj"):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         ev[0].record(stream)
         pl.condense(blk)
         ev[1].record(stream)
         pl.assemble()
         ev[2].record(stream)
-        st = pl.solve(restart=50, max_iters=20000, rtol=1e-8, prec="bj", orth=args.orth, precision=precision,
-                      time_phases=True, fold_prec=not args.no_fold)
+        if prec.startswith("asm"):        # additive Schwarz subdomain inverses
+            pl.asm_setup(fp32=precision == "mixed")
         ev[3].record(stream)
-        pl.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+        st = pl.solve(restart=50, max_iters=20000, rtol=1e-8, prec=prec, orth=args.orth, precision=precision,
+                      time_phases=True, fold_prec=not args.no_fold, poly_degree=10, poly_v0=v0)
         ev[4].record(stream)
+        pl.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+        ev[5].record(stream)
         torch.cuda.synchronize()
         ph = dict(condense=ev[0].elapsed_time(ev[1]) / 1e3, assemble=ev[1].elapsed_time(ev[2]) / 1e3,
-                  solve=ev[2].elapsed_time(ev[3]) / 1e3, recover=ev[3].elapsed_time(ev[4]) / 1e3)
+                  solve=ev[3].elapsed_time(ev[4]) / 1e3, recover=ev[4].elapsed_time(ev[5]) / 1e3)
+        if prec.startswith("asm"):
+            ph["asm_setup"] = ev[2].elapsed_time(ev[3]) / 1e3
         if not st["converged"]:
-            raise RuntimeError(f"{precision} solve did not converge: {st}")
+            raise RuntimeError(f"{precision} {prec} solve did not converge: {st}")
         return st, ph
 
     for _ in range(args.warmup):
@@ -368,6 +378,21 @@ def main():
                      "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
                      "timing": "HIP events around each matvec launch of the timed mixed solves"},
     }
+    extra = []
+    for prec in [p for p in args.also.split(",") if p]:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st_x, ph_x = step("mixed", prec)
+        t_x = time.perf_counter() - ts
+        extra.append(dict(prec=prec, step_s=t_x, phases_s=ph_x, iters=st_x["iters"],
+                          rel_resid=st_x["rel_resid_true"], t_matvec_s=st_x["t_matvec"], t_prec_s=st_x["t_prec"],
+                          t_orth_s=st_x["t_orth"]))
+        log("extra", extra[-1])
+        if prec.startswith("asm"):
+            pl.asm_inv64 = pl.asm_inv32 = None
+            torch.cuda.empty_cache()
+    if extra:
+        line["other_preconditioners_mixed"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, blk, pl, st_mixed["iters"])
     print(json.dumps(line), flush=True)
