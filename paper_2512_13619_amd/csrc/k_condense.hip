@@ -338,6 +338,38 @@ __global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, long long ntile,
     }
 }
 
+// Largest v over the wave (ties: smallest i), returned in every lane. Within each row of
+// 16 lanes the partners come through DPP (xor 1, xor 2, half-row and row mirrors, no LDS
+// round trip); the four row results are then read as uniform values.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false);
+    const double ov = __hiloint2double(ohi, olo);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+    argmax_dpp_step<0xB1>(v, i);   // quad_perm [1,0,3,2]
+    argmax_dpp_step<0x4E>(v, i);   // quad_perm [2,3,0,1]
+    argmax_dpp_step<0x141>(v, i);  // row_half_mirror
+    argmax_dpp_step<0x140>(v, i);  // row_mirror
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const double ov = __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r), __builtin_amdgcn_readlane(lo, 16 * r));
+        const int oi = __builtin_amdgcn_readlane(i, 16 * r);
+        if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+    }
+    // row 0's lanes started from their own row value; make every lane agree on the result
+    const double v0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 0));
+    i = __builtin_amdgcn_readlane(i, 0);
+    v = v0;
+}
+
 // ---- blocked elimination of the first nu columns ----------------------------------------------
 // NBT: compile-time bound of the panel width (the triangular solve keeps one
 // column of U12 in registers). LBS threads share the LDS panel (512 for panels of
@@ -393,12 +425,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     const double v = fabs(Pn[li * ldp + kk]);
                     if (v > best || (v == best && li < bi)) { best = v; bi = li; }
                 }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ob = __shfl_xor(best, off, 64);
-                    const int oi = __shfl_xor(bi, off, 64);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
+                wave_argmax(best, bi);
                 if (lane == 0) {
                     pidx = bi;
                     pval = Pn[bi * ldp + kk];
@@ -448,20 +475,26 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
         }
         __syncthreads();
         // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread
-        //    per column): every load of the column is issued before its first store
+        //    per column)
         const int cbeg = k0 + nbk;
         const int ncol = C - cbeg;
         const int nd = ndisp;
+        // all rows involved are Ebar rows (top part); the pivot rows' offsets from row k0
+        // are read from LDS once, before any global load (reads past the valid entries stay
+        // inside the LDS allocation and are replaced by row 0)
+        int rs[NBT];
+#pragma unroll
+        for (int t = 0; t < NBT; ++t) rs[t] = rsrc[t];
+#pragma unroll
+        for (int t = 0; t < NBT; ++t) rs[t] = (t < nbk ? rs[t] : 0) * C;
         for (int cl = threadIdx.x; cl < ncol; cl += LBS) {
-            const int col = cbeg + cl;
-            double u[NBT], dv[NBT];
+            double* Tc = Te + (size_t)k0 * C + cbeg + cl;   // this column, from row k0 on
+            double u[NBT];
 #pragma unroll
-            for (int t = 0; t < NBT; ++t) u[t] = t < nbk ? rowp(k0 + rsrc[t])[col] : 0.0;
-#pragma unroll
-            for (int q = 0; q < NBT; ++q) dv[q] = q < nd ? rowp(k0 + dsrc[q])[col] : 0.0;
-#pragma unroll
-            for (int q = 0; q < NBT; ++q)
-                if (q < nd) rowp(k0 + ddst[q])[col] = dv[q];
+            for (int t = 0; t < NBT; ++t) u[t] = Tc[rs[t]];
+            // displaced rows: sources lie among the first nbk rows, destinations below them,
+            // and the pivot rows are already loaded, so the moves may go one at a time
+            for (int q = 0; q < nd; ++q) Tc[(size_t)ddst[q] * C] = Tc[(size_t)dsrc[q] * C];
             // forward substitution with the unit lower L11
 #pragma unroll
             for (int kk = 1; kk < NBT; ++kk) {
@@ -474,7 +507,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
             }
 #pragma unroll
             for (int t = 0; t < NBT; ++t)
-                if (t < nbk) rowp(k0 + t)[col] = u[t];
+                if (t < nbk) Tc[(size_t)t * C] = u[t];
         }
         __syncthreads();
         // 5. trailing update (MFMA, 32x32 tiles per wave): the Ebar rows over every
