@@ -101,8 +101,8 @@ __device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
 // ---- LDS-staged 64x64 tile product -----------------------------------------------------------
 // acc += A(64 x K) B(K x 64) for the tile whose corner is (m0, n0): 256 threads, wave w owns
 // the 32x32 quadrant (rows 32*(w/2), columns 32*(w%2)) in the mfma_32x32 layout. K is
-// taken in chunks of 32 staged through LDS (double-buffered: the next chunk's global loads
-// are in flight while the current chunk's MFMAs run). A is stored k-major in LDS (row
+// taken in chunks of 32 staged through LDS (double-buffered; a chunk's global loads are
+// issued two chunks ahead). A is stored k-major in LDS (row
 // stride 65 to spread the transposing writes over the banks), B as it is. Entries
 // outside the matrices read as 0.
 constexpr int GT = 64, GK = 32, GLDA = GT + 1, GLDB = GT;
@@ -142,40 +142,36 @@ __device__ __forceinline__ void gemm_tile64(const MatA& A, const MatB& B, int m0
     const bool bok_c = n0 + jb < B.cols;
     const double* bcol = B.p + (bok_c ? n0 + jb : 0);
     // raw loads (clamped addresses); the masks are applied when the values go to LDS, so
-    // no load has to complete before the MFMAs of the current chunk are issued
-    double ra[8], rb[8];
-    int kst = 0;                       // k0 of the chunk held in ra/rb
-    auto gload = [&](int k0) {
-        kst = k0;
+    // no load has to complete before the MFMAs of the current chunk are issued. Two
+    // register sets: a chunk's loads are issued two chunks before its MFMAs, so their
+    // latency is covered by a whole chunk of MFMAs.
+    double ra[2][8], rb[2][8];
+    int kst[2] = {0, 0};               // k0 of the chunk held in set s
+    auto gload = [&](int s, int k0) {
+        kst[s] = k0;
         const int k = k0 + ka;
         const int kc = k < K ? k : 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ra[u] = arow[u][kc];
+        for (int u = 0; u < 8; ++u) ra[s][u] = arow[u][kc];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int kb = k0 + (tid >> 6) + 4 * u;
-            rb[u] = bcol[(size_t)(kb < B.rows ? kb : 0) * B.ld];
+            rb[s][u] = bcol[(size_t)(kb < B.rows ? kb : 0) * B.ld];
         }
     };
-    auto lstore = [&](int b) {
+    auto lstore = [&](int s, int b) {
         double* As = lds + b * (GK * GLDA);
         double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
-        const bool kok = kst + ka < K;
+        const bool kok = kst[s] + ka < K;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = (kok && aok[u]) ? ra[u] : 0.0;
+        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = (kok && aok[u]) ? ra[s][u] : 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int kb = kst + (tid >> 6) + 4 * u;
-            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (bok_c && kb < B.rows) ? rb[u] : 0.0;
+            const int kb = kst[s] + (tid >> 6) + 4 * u;
+            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (bok_c && kb < B.rows) ? rb[s][u] : 0.0;
         }
     };
-    const int nch = (K + GK - 1) / GK;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
-        const int b = c & 1;
-        if (c + 1 < nch) gload((c + 1) * GK);
+    auto compute = [&](int b) {
         const double* As = lds + b * (GK * GLDA);
         const double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
         double a[8][2], bb[8][2];
@@ -194,7 +190,22 @@ __device__ __forceinline__ void gemm_tile64(const MatA& A, const MatB& B, int m0
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bb[ks][0], acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bb[ks][1], acc[1][1], 0, 0, 0);
         }
-        if (c + 1 < nch) lstore(b ^ 1);
+    };
+    const int nch = (K + GK - 1) / GK;
+    gload(0, 0);
+    if (nch > 1) gload(1, GK);
+    lstore(0, 0);
+    __syncthreads();
+    // even chunks in LDS buffer 0 (their loads in set 0), odd ones in buffer 1 (set 1)
+    for (int c = 0; c < nch; c += 2) {
+        if (c + 2 < nch) gload(0, (c + 2) * GK);
+        compute(0);
+        if (c + 1 < nch) lstore(1, 1);
+        __syncthreads();
+        if (c + 1 >= nch) break;
+        if (c + 3 < nch) gload(1, (c + 3) * GK);
+        compute(1);
+        if (c + 2 < nch) lstore(0, 0);
         __syncthreads();
     }
 }
@@ -264,7 +275,7 @@ __device__ __forceinline__ int qelim_col(int c, int m, int P, int PF, int M, int
 // ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, component m, 64x64 tile) ------------------
 // One block per tile; tiles are numbered element-major, then component, row tile, column
 // tile. nblk is a multiple of 8 (trailing blocks exit).
-__global__ __launch_bounds__(BS) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
+__global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
                                                    const double* __restrict__ Dm, const double* __restrict__ Em,
                                                    const double* __restrict__ Fm, const double* __restrict__ Gm,
                                                    const double* __restrict__ Hm, const double* __restrict__ Jm,
@@ -575,7 +586,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
 // ---- Kbar = Jbar - L21 U12, rbar = r_t - L21 (L^{-1} P r_u)   per (element, 64x64 tile) -----
 // L21 = the trace rows' multipliers (bottom rows, first nu columns), U12 = the Ebar rows'
 // trailing columns after the elimination (top rows, columns nu..): one product of depth nu.
-__global__ __launch_bounds__(BS) void k_cond_schur(CondDims cd, long long ntile, int tm_n, int tn_n,
+__global__ __launch_bounds__(BS, 2) void k_cond_schur(CondDims cd, long long ntile, int tm_n, int tn_n,
                                                    const double* __restrict__ top, const double* __restrict__ bot,
                                                    double* __restrict__ Kbar, double* __restrict__ rbar) {
     extern __shared__ double lds[];
