@@ -147,8 +147,9 @@ hdg_status krylov_givens(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nbl
                          double* cs, double* sn, double* g, int j, double* hist);
 hdg_status krylov_backsolve(hdg_ctx ctx, const GmresCtl* ctl, const double* H, int ldh, const double* g,
                             double* y);
-hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* d, int j, int finish, double* Hu, double* H,
-                             int ldh, double* cs, double* sn, double* g, double* coef, int ldc, double* hist);
+hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, int j, int finish, double* Hu,
+                             double* H, int ldh, double* cs, double* sn, double* g, double* coef, int ldc,
+                             double* hist);
 hdg_status krylov_store_norm(hdg_ctx ctx, const double* part, int nblk, double* dst);
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // The block's slice of w is staged in LDS; each wave owns a subset of the vectors and
 // streams them with U loads in flight per lane, so one wave writes each partial.
 constexpr int CHUNK = 2048;        // entries per block (the partial layout depends on it)
+constexpr int COEF_BS = 1024;      // threads of the delayed-CGS2 coefficient kernel
 
 template <int U>
 __global__ __launch_bounds__(BS) void k_multidot(const double* __restrict__ V, size_t ldv, int J,
@@ -348,17 +349,18 @@ __global__ __launch_bounds__(BS) void k_multidot2(const double* __restrict__ V, 
     }
 }
 
-// Step j of the delayed CGS2 Arnoldi process, one block of 64 threads. d holds the sweep's
-// inner products: d[i] = V_i . vt_j (i <= j; i < j is the delayed projection a, i = j is
-// alpha) and d[J + i] = V_i . wt (c, gamma), J = j + 1. rho = sqrt(alpha - a.a) normalises
+// Step j of the delayed CGS2 Arnoldi process, one block. It first adds up the sweep's block
+// partials (part[i*nblk + b]) into the inner products d: d[i] = V_i . vt_j (i <= j; i < j is
+// the delayed projection a, i = j is alpha) and d[J + i] = V_i . wt (c, gamma), J = j + 1. rho = sqrt(alpha - a.a) normalises
 // the reorthogonalised v_j; column j-1 of the unrotated Hessenberg Hu gains a and rho and
 // is then rotated into H (Givens, residual estimate). Unless finish, the new column
 //     h = ([c; (gamma - a.c)/rho] - t)/rho,  t = Hu[:j+1, :j] a,
 // goes to Hu, and coef receives what the update sweep needs: a (j values) at coef[0..],
 // b = t/rho + h (j+1 values) at coef[ldc..], 1/rho at coef[2 ldc].
-__global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j, int finish, double* Hu,
-                             double* H, int ldh, double* cs, double* sn, double* g, double* coef, int ldc,
-                             double* hist) {
+__global__ __launch_bounds__(COEF_BS) void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ part, int nblk,
+                                                        int j, int finish, double* Hu, double* H, int ldh,
+                                                        double* cs, double* sn, double* g, double* coef, int ldc,
+                                                        double* hist) {
     if (ctl->done) return;
     __shared__ double ds[2 * 201];      // restart lengths up to 200
     __shared__ double tsh[201];
@@ -366,11 +368,28 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
     __shared__ double css[201], sns[201];
     __shared__ double sh_rho;
     __shared__ int sh_stop;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int J = j + 1;
-    // everything the serial part needs, loaded by all lanes at once
-    for (int i = lane; i < (finish ? J : 2 * J); i += 64) ds[i] = d[i];
-    if (j > 0) {
+    // the block partials of the inner-product sweep, one wave per sum (each lane adds its
+    // blocks in increasing order, eight loads in flight), and everything the serial part needs
+    const int nout = finish ? J : 2 * J;
+    for (int i = wave; i < nout; i += COEF_BS / 64) {
+        const double* pi = part + (size_t)i * nblk;
+        double sacc = 0.0;
+        for (int b0 = 0; b0 < nblk; b0 += 8 * 64) {
+            double m[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + 64 * u + lane;
+                m[u] = pi[b < nblk ? b : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sacc += b0 + 64 * u + lane < nblk ? m[u] : 0.0;
+        }
+        sacc = wave_sum(sacc);
+        if (lane == 0) ds[i] = sacc;
+    }
+    if (j > 0 && wave == 0) {
         for (int i = lane; i < j; i += 64) {
             hcol[i] = Hu[(size_t)(j - 1) * ldh + i];
             css[i] = cs[i];
@@ -378,28 +397,31 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
         }
     }
     __syncthreads();
-    double aa = 0.0, ac = 0.0;
-    for (int i = lane; i < j; i += 64) {
-        aa += ds[i] * ds[i];
-        if (!finish) ac += ds[i] * ds[J + i];
-    }
-    aa = wave_sum(aa);
-    ac = wave_sum(ac);
-    // delayed pass for column j-1: Hu[:j, j-1] += a, Hu[j, j-1] = rho
-    const double r2 = ds[j] - aa;
-    const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
-    if (j > 0) {
+    double rho = 0.0, ac = 0.0;
+    if (wave == 0) {
+        double aa = 0.0;
         for (int i = lane; i < j; i += 64) {
-            hcol[i] += ds[i];
-            Hu[(size_t)(j - 1) * ldh + i] = hcol[i];
+            aa += ds[i] * ds[i];
+            if (!finish) ac += ds[i] * ds[J + i];
         }
-        if (lane == 0) {
-            hcol[j] = rho;
-            Hu[(size_t)(j - 1) * ldh + j] = rho;
+        aa = wave_sum(aa);
+        ac = wave_sum(ac);
+        // delayed pass for column j-1: Hu[:j, j-1] += a, Hu[j, j-1] = rho
+        const double r2 = ds[j] - aa;
+        rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+        if (j > 0) {
+            for (int i = lane; i < j; i += 64) {
+                hcol[i] += ds[i];
+                Hu[(size_t)(j - 1) * ldh + i] = hcol[i];
+            }
+            if (lane == 0) {
+                hcol[j] = rho;
+                Hu[(size_t)(j - 1) * ldh + j] = rho;
+            }
         }
     }
     __syncthreads();
-    if (lane == 0) {
+    if (tid == 0) {
         int stop = 0;
         if (j > 0) {
             // Givens: previous rotations, a new one, the residual estimate (column j-1)
@@ -441,6 +463,7 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
     }
     __syncthreads();
     if (sh_stop) return;
+    if (wave != 0) return;     // the rest is one wave's work (no barriers below)
     const double irho = 1.0 / sh_rho;
     // t = Hu[:j+1, :j] a over the Hessenberg pattern (row i has entries in columns q >= i-1
     // only; nothing below the subdiagonal is ever read): column j-1 from LDS, the others
@@ -459,7 +482,7 @@ __global__ void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ d, int j,
         if (j > 0 && i <= j) t += hcol[i] * ds[j - 1];
         tsh[i] = t;
     }
-    __syncthreads();
+    // (each lane reads back only the tsh entries it wrote)
     for (int i = lane; i <= j; i += 64) {
         const double ci = i < j ? ds[J + i] : (ds[J + j] - ac) * irho;
         const double h = (ci - tsh[i]) * irho;
@@ -564,10 +587,11 @@ hdg_status vec_multidot2(hdg_ctx ctx, const double* V, size_t ldv, int J, const 
     return HDG_OK;
 }
 
-hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* d, int j, int finish, double* Hu, double* H,
-                             int ldh, double* cs, double* sn, double* g, double* coef, int ldc, double* hist) {
-    hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(64), 0, ctx->stream, ctl, d, j, finish, Hu, H, ldh, cs, sn, g,
-                       coef, ldc, hist);
+hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, int j, int finish, double* Hu,
+                             double* H, int ldh, double* cs, double* sn, double* g, double* coef, int ldc,
+                             double* hist) {
+    hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(COEF_BS), 0, ctx->stream, ctl, part, nblk, j, finish, Hu, H, ldh,
+                       cs, sn, g, coef, ldc, hist);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

@@ -218,7 +218,7 @@ struct SolveWs {
     double *V, *Z, *work, *part;
     GmresCtl* ctl;
     double *H, *cs, *sn, *g, *y, *h2, *hist, *bnorm;
-    double *Hu, *dd, *coef;     // delayed CGS2: unrotated Hessenberg, sweep results, update coefficients
+    double *Hu, *coef;          // delayed CGS2: unrotated Hessenberg, update coefficients
     size_t ld;
     int nblk, ldh;
 };
@@ -239,8 +239,7 @@ hdg_status alloc_solve_ws(hdg_ctx ctx, size_t N, int m, int P, int zcols, SolveW
     w->part = (double*)ws_get(ctx, WS_PART, sizeof(double) * (size_t)w->nblk * (2 * mv + 4), &st);
     if (!w->part) return st;
     w->ldh = mv + 1;
-    const size_t nctl = 8 + 2 * (size_t)w->ldh * mv + 6 * (size_t)(mv + 2) + 2 * (size_t)(mv + 2) +
-                        3 * (size_t)w->ldh + 1;
+    const size_t nctl = 8 + 2 * (size_t)w->ldh * mv + 6 * (size_t)(mv + 2) + 3 * (size_t)w->ldh + 1;
     char* base = (char*)ws_get(ctx, WS_CTL, sizeof(double) * nctl + sizeof(GmresCtl), &st);
     if (!base) return st;
     w->ctl = (GmresCtl*)base;
@@ -253,7 +252,6 @@ hdg_status alloc_solve_ws(hdg_ctx ctx, size_t N, int m, int P, int zcols, SolveW
     w->h2 = p; p += mv + 2;
     w->hist = p; p += mv + 2;
     w->Hu = p; p += (size_t)w->ldh * mv;
-    w->dd = p; p += 2 * (size_t)(mv + 2);
     w->coef = p; p += 3 * (size_t)w->ldh + 1;
     w->bnorm = p;
     return HDG_OK;
@@ -506,18 +504,16 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             if ((s2 = op_matvec(ctx, opi, src, wv, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 2)) != HDG_OK) return s2;
             if ((s2 = vec_multidot2(ctx, w.V, w.ld, j + 1, vj, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
-            if ((s2 = vec_reduce(ctx, w.part, 2 * (j + 1), w.nblk, w.dd, nullptr, skip)) != HDG_OK) return s2;
-            if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.dd, j, 0, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef, w.ldh,
-                                        w.hist)) != HDG_OK)
+            if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.part, w.nblk, j, 0, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef,
+                                        w.ldh, w.hist)) != HDG_OK)
                 return s2;
             if ((s2 = vec_dcgs2_update(ctx, w.V, w.ld, j, vj, wv, w.coef, w.ldh, N, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 3)) != HDG_OK) return s2;
         }
         double* vm = w.V + (size_t)jmax * w.ld;
         if ((s2 = vec_multidot2(ctx, w.V, w.ld, jmax + 1, vm, nullptr, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
-        if ((s2 = vec_reduce(ctx, w.part, jmax + 1, w.nblk, w.dd, nullptr, skip)) != HDG_OK) return s2;
-        if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.dd, jmax, 1, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef, w.ldh,
-                                    w.hist)) != HDG_OK)
+        if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.part, w.nblk, jmax, 1, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef,
+                                    w.ldh, w.hist)) != HDG_OK)
             return s2;
         if ((s2 = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return s2;
         if (o->prec == HDG_PREC_NONE) return vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
