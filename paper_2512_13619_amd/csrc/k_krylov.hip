@@ -360,8 +360,9 @@ __global__ __launch_bounds__(BS) void k_multidot2(const double* __restrict__ V, 
 __global__ __launch_bounds__(COEF_BS) void k_dcgs2_coef(GmresCtl* ctl, const double* __restrict__ part, int nblk,
                                                         int j, int finish, double* Hu, double* H, int ldh,
                                                         double* cs, double* sn, double* g, double* coef, int ldc,
-                                                        double* hist) {
+                                                        double* hist, int hs_ld) {
     if (ctl->done) return;
+    extern __shared__ double hstage[];  // (j-1) x hs_ld when hs_ld > 0
     __shared__ double ds[2 * 201];      // restart lengths up to 200
     __shared__ double tsh[201];
     __shared__ double hcol[202];        // column j-1 of Hu (rows 0..j)
@@ -376,18 +377,25 @@ __global__ __launch_bounds__(COEF_BS) void k_dcgs2_coef(GmresCtl* ctl, const dou
     for (int i = wave; i < nout; i += COEF_BS / 64) {
         const double* pi = part + (size_t)i * nblk;
         double sacc = 0.0;
-        for (int b0 = 0; b0 < nblk; b0 += 8 * 64) {
-            double m[8];
+        for (int b0 = 0; b0 < nblk; b0 += 16 * 64) {
+            double m[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int b = b0 + 64 * u + lane;
                 m[u] = pi[b < nblk ? b : 0];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) sacc += b0 + 64 * u + lane < nblk ? m[u] : 0.0;
+            for (int u = 0; u < 16; ++u) sacc += b0 + 64 * u + lane < nblk ? m[u] : 0.0;
         }
         sacc = wave_sum(sacc);
         if (lane == 0) ds[i] = sacc;
+    }
+    // columns 0..j-2 of Hu (rows 0..j) staged in LDS when they fit (hs_ld = j+1, else 0)
+    if (hs_ld > 0) {
+        for (int idx = tid; idx < (j - 1) * hs_ld; idx += COEF_BS) {
+            const int q = idx / hs_ld;
+            hstage[idx] = Hu[(size_t)q * ldh + (idx - q * hs_ld)];
+        }
     }
     if (j > 0 && wave == 0) {
         for (int i = lane; i < j; i += 64) {
@@ -473,8 +481,13 @@ __global__ __launch_bounds__(COEF_BS) void k_dcgs2_coef(GmresCtl* ctl, const dou
         const int qe = j - 1;
         for (int q0 = i > 0 ? i - 1 : 0; q0 < qe; q0 += 8) {
             double m[8];
+            if (hs_ld > 0) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) m[u] = Hu[(size_t)(q0 + u < qe ? q0 + u : q0) * ldh + i];
+                for (int u = 0; u < 8; ++u) m[u] = hstage[(q0 + u < qe ? q0 + u : q0) * hs_ld + i];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m[u] = Hu[(size_t)(q0 + u < qe ? q0 + u : q0) * ldh + i];
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (q0 + u < qe) t += m[u] * ds[q0 + u];
@@ -590,8 +603,11 @@ hdg_status vec_multidot2(hdg_ctx ctx, const double* V, size_t ldv, int J, const 
 hdg_status krylov_dcgs2_coef(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nblk, int j, int finish, double* Hu,
                              double* H, int ldh, double* cs, double* sn, double* g, double* coef, int ldc,
                              double* hist) {
-    hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(COEF_BS), 0, ctx->stream, ctl, part, nblk, j, finish, Hu, H, ldh,
-                       cs, sn, g, coef, ldc, hist);
+    // the columns of Hu the new column's product reads go through LDS when they fit in 48 KiB
+    const int hs_ld = (j >= 2 && (size_t)(j - 1) * (j + 1) * sizeof(double) <= 48 * 1024) ? j + 1 : 0;
+    const size_t lds = hs_ld ? (size_t)(j - 1) * hs_ld * sizeof(double) : 0;
+    hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(COEF_BS), lds, ctx->stream, ctl, part, nblk, j, finish, Hu, H, ldh,
+                       cs, sn, g, coef, ldc, hist, hs_ld);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
