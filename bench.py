@@ -374,7 +374,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r32["matvec_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": r32["matvec_GBs"] / PEAK_HBM_GBS,
                      "traffic": (measured_traffic("fp32_matvec") if (args.n, args.p) == (24, 3) else None),
-                     "kernel": "k_face_op<float,float,256,false,0> (FP32 block matvec)",
+                     "kernel": "k_face_op<float,float,256,false,0,4> (FP32 block matvec)",
                      "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
                      "timing": "HIP events around each matvec launch of the timed mixed solves"},
     }
