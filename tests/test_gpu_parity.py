@@ -313,6 +313,69 @@ def test_gmres_history_matches_oracle_fgmres(ctx, orth):
     assert np.allclose(st["hist"][:n], hist[:n], rtol=1e-6)
 
 
+@pytest.mark.parametrize("orth", ORTHS)
+def test_gmres_long_cycle_matches_oracle(ctx, orth):
+    """One restart cycle longer than 64 steps (beyond the fused CGS2 sweeps) and than 78
+    (beyond the LDS staging of the Hessenberg columns in the delayed-CGS2 kernel): c1 without
+    a preconditioner needs about 110 steps; restart 200 is the largest the library takes."""
+    pb, out = case_data("c1")
+    say("long cycle", orth)
+    K, K32, nbr = _dev_matrix(out)
+    r = torch.as_tensor(out["r"]).cuda()
+    x = torch.zeros_like(r)
+    st = ctx.gmres_solve(pb.dims(), K, None, nbr, r, x, restart=200, max_iters=1000, rtol=1e-12, prec="none",
+                         hist_len=300, **orth_kw(orth))
+    hist = []
+    solver = krylov.fgmres if orth == "cgs2" else krylov.gmres_dcgs2
+    _, info = solver(lambda v: out["A"] @ v, out["r"], restart=200, rtol=1e-12, max_iters=1000, hist=hist)
+    assert st["converged"] and st["cycles"] == 1 and st["iters"] > 80, st
+    assert abs(st["iters"] - info["iters"]) <= 1
+    n = min(80, len(hist), len(st["hist"]))
+    assert np.allclose(st["hist"][:n], hist[:n], rtol=1e-6)
+    assert relerr(x.cpu().numpy(), out["x"]) < 1e-10
+
+
+@pytest.mark.parametrize("orth", ORTHS)
+def test_gmres_zero_rhs(ctx, orth):
+    """b = 0 with x0 = 0: converged before the first step, x untouched."""
+    pb, out = case_data("c1")
+    K, K32, nbr = _dev_matrix(out)
+    r = torch.zeros(out["r"].shape[0], dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(r)
+    st = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=20, max_iters=100, rtol=1e-10, prec="bj",
+                         precision="mixed", **orth_kw(orth))
+    assert st["converged"] and st["iters"] == 0, st
+    assert torch.count_nonzero(x).item() == 0
+
+
+def test_condense_empty_and_ragged_chunks(ctx):
+    """Condensing an element range of length 0 touches nothing; condensing a ragged split of
+    the elements (chunks of 3, 1 and the rest) equals condensing them all at once."""
+    pb, out = case_data("elast_hex_p1")
+    d = pb.dims()
+    ne = d["ne"]
+    M, D, P, PF, L = d["ncomp"], d["dim"], d["npe"], d["npf"], d["nlfe"]
+    nu, nt = M * P, L * M * PF
+    blk = to_dev(out["blk"])
+    Kall = torch.empty(ne, nt, nt, dtype=torch.float64, device="cuda")
+    rall = torch.empty(ne, nt, dtype=torch.float64, device="cuda")
+    lall = torch.empty(ne, nu * (nu + nt + 1), dtype=torch.float64, device="cuda")
+    ctx.condense(d, blk, Kall, rall, lall)
+    Kc = torch.full_like(Kall, 7.0)
+    rc = torch.full_like(rall, 7.0)
+    lc = torch.full_like(lall, 7.0)
+    ctx.condense(d, {k: v[:0] for k, v in blk.items()}, Kc[:0], rc[:0], lc[:0], ne_chunk=0)
+    torch.cuda.synchronize()
+    assert bool((Kc == 7.0).all()) and bool((rc == 7.0).all()) and bool((lc == 7.0).all())
+    e0 = 0
+    for n in (3, 1, ne - 4):
+        sl = slice(e0, e0 + n)
+        ctx.condense(d, {k: v[sl].contiguous() for k, v in blk.items()}, Kc[sl], rc[sl], lc[sl], ne_chunk=n)
+        e0 += n
+    torch.cuda.synchronize()
+    assert torch.equal(Kc, Kall) and torch.equal(rc, rall) and torch.equal(lc, lall)
+
+
 @pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2"])
 def test_pipeline_end_to_end(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
