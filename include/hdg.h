@@ -104,6 +104,33 @@ size_t     hdg_local_size(const hdg_dims* dims);   /* doubles per element of `lo
 hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
                         const hdg_elem_blocks* in, double* Kbar, double* rbar, double* local);
 
+/* (1b) Stage reuse -- Section 2.2 (the stages of a DIRK scheme solve systems with the
+ *     same matrix and new right-hand sides, so matrices and preconditioners carry over)
+ *     with the condensed right-hand side of Section 4.1 eq. w19 / Section 4.2 eq. w22.
+ *
+ * hdg_condense_keep: hdg_condense that also keeps what a later right-hand side needs:
+ *   L21  [ne][nt][nu]  the trace rows' multipliers Hbar U^{-1};
+ *   ipiv [ne][nu]      row interchanges of the elimination: at step k the rows at
+ *                      (element-local) positions k and ipiv[k] >= k were exchanged;
+ *   local additionally holds the unit lower L below the diagonal of its first nu
+ *         columns, each panel's columns in that panel's row order (the elimination runs
+ *         in panels of 32 columns, or of all nu columns when nu <= 64, 16 or 8 when the
+ *         element is too large for LDS; the interchanges of later panels are not applied
+ *         to earlier columns of L).
+ *   All outputs are caller-owned device buffers; the same errors as hdg_condense.
+ * hdg_condense_rhs: for new right-hand sides ru [ne][nu], rt [ne][nt] of the same element
+ *   matrices: c = L^{-1} P ru (panel by panel: the panel's interchanges, its unit lower
+ *   triangle, its multipliers below it) replaces the last column of `local`, and
+ *   rbar = rt - L21 c. `local`, L21 and ipiv must come from hdg_condense_keep on the same
+ *   dims (the panel width is derived from dims as it was there). Enqueued only, no
+ *   synchronisation; no pivots are re-checked. */
+hdg_status hdg_condense_keep(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
+                             const hdg_elem_blocks* in, double* Kbar, double* rbar, double* local,
+                             double* L21, int32_t* ipiv);
+hdg_status hdg_condense_rhs(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, double* local,
+                            const double* L21, const int32_t* ipiv, const double* ru, const double* rt,
+                            double* rbar);
+
 /* ---------------------------------------------------------------------------
  * (2) Face-block assembly -- Section 2.4, Section 4.2.
  *
@@ -125,6 +152,10 @@ hdg_status hdg_assemble_blocks(hdg_ctx ctx, const hdg_dims* dims,
                                const int32_t* f2e, const int32_t* e2f, const int32_t* perm,
                                const double* Kbar, const double* rbar,
                                double* K64, float* K32, int32_t* nbr, double* r);
+/* hdg_assemble_rhs: r alone (the same sums as hdg_assemble_blocks) for a new rbar, e.g. a
+ * later DIRK stage whose matrix is unchanged (Section 2.2). One wave per face, no atomics. */
+hdg_status hdg_assemble_rhs(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const int32_t* perm,
+                            const double* rbar, double* r);
 
 /* ---------------------------------------------------------------------------
  * (3) Preconditioned restarted FGMRES on K x = r -- Sections 3.1-3.4, 4.3-4.7.
@@ -195,6 +226,12 @@ typedef struct {
     const float* asm_inv32;     /*   and FP32 (needed with HDG_MIXED) */
     const int32_t* asm_f2e;     /* device f2e and e2f as for hdg_assemble_blocks */
     const int32_t* asm_e2f;
+    int32_t reuse_setup;        /* 1 (block-Jacobi family only): keep the block inverses, and the
+                                   folded blocks if the earlier solve formed them, from the last
+                                   solve on this context with the same K64, nbr, dims and precision
+                                   (the matrix must not have changed since: Section 2.2's reuse
+                                   across DIRK stages); HDG_ERR_ARG if the context holds none.
+                                   Ignored for HDG_PREC_NONE and the additive Schwarz family. */
 } hdg_solve_opts;
 
 typedef struct {

@@ -19,6 +19,7 @@ void* ws_get(hdg_ctx ctx, WsSlot slot, size_t bytes, hdg_status* st) {
     *st = HDG_OK;
     if (bytes == 0) bytes = 64;
     if (ctx->ws_bytes[slot] >= bytes) return ctx->ws[slot];
+    if (slot == WS_BINV64 || slot == WS_BINV32 || slot == WS_KFOLD) ctx->bj_key.valid = false;
     if (ctx->ws[slot]) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipFree(ctx->ws[slot]);
@@ -124,6 +125,7 @@ hdg_status hdg_release_workspace(hdg_ctx ctx) {
         ctx->ws[s] = nullptr;
         ctx->ws_bytes[s] = 0;
     }
+    ctx->bj_key = BjSetupKey{};
     return HDG_OK;
 }
 
@@ -149,6 +151,53 @@ hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, con
         return set_err(ctx, HDG_ERR_SHAPE, "hdg_condense: nu above 4096");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
     return condense_run(ctx, dims, ne_chunk, in, Kbar, rbar, local);
+    GUARD_END
+}
+
+hdg_status hdg_condense_keep(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, const hdg_elem_blocks* in,
+                             double* Kbar, double* rbar, double* local, double* L21, int32_t* ipiv) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, false);
+    if (st != HDG_OK) return st;
+    if (ne_chunk < 0) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk must be >= 0");
+    if (ne_chunk == 0) return HDG_OK;
+    if (ne_chunk > 0x7fffffff) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk too large");
+    if (!in || !in->Minv || !in->Bd || !in->Cd || !in->D || !in->E || !in->F || !in->G || !in->H || !in->J ||
+        !in->ru || !in->rt || !Kbar || !rbar || !local || !L21 || !ipiv)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_condense_keep: NULL input or output pointer");
+    if ((size_t)dims->ncomp * dims->npe > 4096)
+        return set_err(ctx, HDG_ERR_SHAPE, "hdg_condense_keep: nu above 4096");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return condense_run(ctx, dims, ne_chunk, in, Kbar, rbar, local, L21, ipiv);
+    GUARD_END
+}
+
+hdg_status hdg_condense_rhs(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, double* local, const double* L21,
+                            const int32_t* ipiv, const double* ru, const double* rt, double* rbar) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, false);
+    if (st != HDG_OK) return st;
+    if (ne_chunk < 0) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk must be >= 0");
+    if (ne_chunk == 0) return HDG_OK;
+    if (ne_chunk > 0x7fffffff) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk too large");
+    if (!local || !L21 || !ipiv || !ru || !rt || !rbar)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_condense_rhs: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return condense_rhs_run(ctx, dims, ne_chunk, local, L21, ipiv, ru, rt, rbar);
+    GUARD_END
+}
+
+hdg_status hdg_assemble_rhs(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const int32_t* perm,
+                            const double* rbar, double* r) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, true, true);
+    if (st != HDG_OK) return st;
+    if (!f2e || !rbar || !r) return set_err(ctx, HDG_ERR_ARG, "hdg_assemble_rhs: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return assemble_rhs_run(ctx, dims, f2e, perm, rbar, r);
     GUARD_END
 }
 

@@ -306,6 +306,7 @@ hdg_status hdg_gmres_solve_batch(hdg_ctx ctx, hdg_batch b, const double* K64, co
     float* B32 = nullptr;
     if (o->prec == HDG_PREC_BJ) {
         const int64_t nbinv = b->offs[A_BINV][ni];
+        ctx->bj_key.valid = false;   // the batch's inverses go to the same workspace
         B64 = (double*)ws_get(ctx, WS_BINV64, sizeof(double) * nbinv, &st);
         if (!B64) return st;
         if (mixed) {

@@ -29,6 +29,14 @@ enum WsSlot {
     WS_NSLOTS
 };
 
+// What the block-Jacobi workspace (WS_BINV64/32 and, with fold, WS_KFOLD) holds after a
+// solve, so that a later solve on the same matrix may reuse it.
+struct BjSetupKey {
+    bool valid = false, fold = false, mixed = false;
+    const void *K64 = nullptr, *K32 = nullptr, *nbr = nullptr;
+    int nf = 0, nb = 0, S = 0;
+};
+
 struct hdg_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -36,6 +44,7 @@ struct hdg_ctx_s {
     std::string err;
     void* ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
+    BjSetupKey bj_key;
 };
 
 // Runs the enclosing scope on the context's private capture stream: the caller's
@@ -173,7 +182,11 @@ hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, doub
 
 // Condensation, assembly, recovery launchers.
 hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_elem_blocks* in,
-                        double* Kbar, double* rbar, double* local);
+                        double* Kbar, double* rbar, double* local, double* L21 = nullptr, int32_t* ipiv = nullptr);
+hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* local, const double* L21,
+                            const int32_t* ipiv, const double* ru, const double* rt, double* rbar);
+hdg_status assemble_rhs_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* perm,
+                            const double* rbar, double* r);
 hdg_status assemble_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* e2f,
                         const int32_t* perm, const double* Kbar, const double* rbar, double* K64,
                         float* K32, int32_t* nbr, double* r);

@@ -92,7 +92,40 @@ __global__ __launch_bounds__(BS) void k_assemble(int nf, int M, int PF, int L, c
     }
 }
 
+// The right-hand side alone: r_f = rbar^{e1}_{l1} + rbar^{e2}_{l2} (the same sums as above),
+// one wave per face.
+__global__ __launch_bounds__(BS) void k_assemble_rhs(int nf, int M, int PF, int L, const int32_t* __restrict__ f2e,
+                                                     const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ rbar, double* __restrict__ r) {
+    const int nb = M * PF, nt = L * nb;
+    const long long f = (long long)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (f >= nf) return;
+    const int lane = threadIdx.x & 63;
+    const int e1 = f2e[4 * f + 0], l1 = f2e[4 * f + 1];
+    const int e2 = f2e[4 * f + 2], l2 = f2e[4 * f + 3];
+    for (int rr = lane; rr < nb; rr += 64) {
+        const int m = rr / PF, j = rr - m * PF;
+        const int j1 = perm ? perm[((size_t)e1 * L + l1) * PF + j] : j;
+        double v = rbar[(size_t)e1 * nt + (l1 * M + m) * PF + j1];
+        if (e2 >= 0) {
+            const int j2 = perm ? perm[((size_t)e2 * L + l2) * PF + j] : j;
+            v += rbar[(size_t)e2 * nt + (l2 * M + m) * PF + j2];
+        }
+        r[f * nb + rr] = v;
+    }
+}
+
 }  // namespace
+
+hdg_status assemble_rhs_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* perm,
+                            const double* rbar, double* r) {
+    if (d->nf == 0) return HDG_OK;
+    const long long grid = ((long long)d->nf + BS / 64 - 1) / (BS / 64);
+    hipLaunchKernelGGL(k_assemble_rhs, dim3((unsigned)grid), dim3(BS), 0, ctx->stream, d->nf, d->ncomp, d->npf,
+                       d->nlfe, f2e, perm, rbar, r);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}
 
 hdg_status assemble_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* e2f,
                         const int32_t* perm, const double* Kbar, const double* rbar, double* K64, float* K32,

@@ -381,6 +381,12 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
     v = v0;
 }
 
+// v from lane l (l uniform), as a uniform value
+__device__ __forceinline__ double lane_value(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 // ---- blocked elimination of the first nu columns ----------------------------------------------
 // NBT: compile-time bound of the panel width (the triangular solve keeps one
 // column of U12 in registers). LBS threads share the LDS panel (512 for panels of
@@ -388,7 +394,8 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // Dynamic LDS: the R x (NB+1) panel, then nu + 2*NBT ints for the row interchanges.
 template <int NBT, int LBS>
 __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top,
-                                                 double* __restrict__ bot, int* bad_elem, int e_off) {
+                                                 double* __restrict__ bot, int* bad_elem, int e_off,
+                                                 int32_t* __restrict__ ipiv_out, int keep) {
     extern __shared__ double sm[];
     __shared__ double pval;
     __shared__ int pidx;
@@ -440,6 +447,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                 if (lane == 0) {
                     pidx = bi;
                     pval = Pn[bi * ldp + kk];
+                    if (ipiv_out) ipiv_out[(size_t)e * nu + k0 + kk] = k0 + bi;
                     const int t = rsrc[kk];
                     rsrc[kk] = rsrc[bi];
                     rsrc[bi] = t;
@@ -479,6 +487,14 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
         for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
             rowp(k0 + li)[k0 + kk] = Pn[li * ldp + kk];
+        }
+        if (keep) {
+            // the Ebar rows' multipliers below the panel as well (unit lower L, in this
+            // panel's row order; later interchanges move only the trailing columns)
+            for (int idx = threadIdx.x; idx < (nu - k0 - nbk) * nbk; idx += LBS) {
+                const int li = nbk + idx / nbk, kk = idx - (li - nbk) * nbk;
+                Te[(size_t)(k0 + li) * C + k0 + kk] = Pn[li * ldp + kk];
+            }
         }
         for (int idx = threadIdx.x; idx < cd.nt * nbk; idx += LBS) {
             const int r = idx / nbk, kk = idx - r * nbk;
@@ -641,6 +657,97 @@ __global__ __launch_bounds__(BS, 2) void k_cond_schur(CondDims cd, long long nti
     }
 }
 
+// The trace rows' multipliers L21 = Hbar U^{-1} (first nu columns of the trace rows), per
+// element, out of the elimination workspace into a caller buffer [n][nt][nu].
+__global__ __launch_bounds__(BS) void k_copy_l21(CondDims cd, const double* __restrict__ bot,
+                                                 double* __restrict__ L21) {
+    const long long e = blockIdx.x;
+    const int nu = cd.nu, nt = cd.nt, C = cd.C;
+    for (int idx = threadIdx.x; idx < nt * nu; idx += BS) {
+        const int t = idx / nu, r = idx - t * nu;
+        L21[(size_t)e * nt * nu + idx] = bot[((size_t)e * nt + t) * C + r];
+    }
+}
+
+// Right-hand side of the condensation for a new (r_u, r_t) with the factors a previous
+// elimination of the same element matrices left (the stages of a DIRK step solve systems
+// with the same matrix and new right-hand sides, Section 2.2):
+//     c = L^{-1} P r_u   panel by panel as the elimination went (the panel's interchanges,
+//                         its unit lower triangle, then its multipliers below it),
+//     rbar = r_t - L21 c.
+// c replaces the last column of `local` (recovery reads it). One block per element, y in LDS.
+__global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __restrict__ local,
+                                                 const double* __restrict__ L21, const int32_t* __restrict__ ipiv,
+                                                 const double* __restrict__ ru, const double* __restrict__ rt,
+                                                 double* __restrict__ rbar) {
+    extern __shared__ double y[];          // nu
+    __shared__ int sp[64];
+    const long long e = blockIdx.x;
+    const int nu = cd.nu, nt = cd.nt, C = cd.C;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* Te = local + (size_t)e * nu * C;
+    const int32_t* pv = ipiv + (size_t)e * nu;
+    for (int i = threadIdx.x; i < nu; i += BS) y[i] = ru[(size_t)e * nu + i];
+    __syncthreads();
+    for (int k0 = 0; k0 < nu; k0 += NB) {
+        const int nbk = (nu - k0) < NB ? (nu - k0) : NB;
+        if (wave == 0) {
+            if (lane < nbk) sp[lane] = pv[k0 + lane];
+            if (lane == 0) {
+                for (int t = 0; t < nbk; ++t) {
+                    const int kk = k0 + t, p = sp[t];
+                    if (p != kk) {
+                        const double a = y[kk];
+                        y[kk] = y[p];
+                        y[p] = a;
+                    }
+                }
+            }
+            // the panel's unit lower triangle: lane t holds y[k0+t]
+            double yt = lane < nbk ? y[k0 + lane] : 0.0;
+            for (int kk = 0; kk + 1 < nbk; ++kk) {
+                const bool below = lane > kk && lane < nbk;
+                const double l = Te[(size_t)(k0 + (below ? lane : kk)) * C + k0 + kk];
+                const double ykk = lane_value(yt, kk);
+                yt -= below ? l * ykk : 0.0;
+            }
+            if (lane < nbk) y[k0 + lane] = yt;
+        }
+        __syncthreads();
+        // rows below the panel
+        for (int i = k0 + nbk + threadIdx.x; i < nu; i += BS) {
+            const double* li = Te + (size_t)i * C + k0;
+            double acc = 0.0;
+            for (int kk = 0; kk < nbk; ++kk) acc += li[kk] * y[k0 + kk];
+            y[i] -= acc;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nu; i += BS) Te[(size_t)i * C + C - 1] = y[i];
+    // rbar = r_t - L21 c, four rows per wave at a time
+    for (int t0 = 4 * wave; t0 < nt; t0 += 4 * (BS / 64)) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r0 = 0; r0 < nu; r0 += 64) {
+            const int r = r0 + lane;
+            const bool ok = r < nu;
+            const double yv = y[ok ? r : 0];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = t0 + q < nt ? t0 + q : nt - 1;
+                const double a = L21[((size_t)e * nt + t) * nu + (ok ? r : 0)];
+                acc[q] += ok ? a * yv : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double v = acc[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && t0 + q < nt) rbar[(size_t)e * nt + t0 + q] = rt[(size_t)e * nt + t0 + q] - v;
+        }
+    }
+}
+
 size_t lu_lds_bytes(const CondDims& cd, int NB) {
     return sizeof(double) * (size_t)cd.R * (NB + 1) + sizeof(int) * ((size_t)cd.nu + 2 * 64);
 }
@@ -673,18 +780,21 @@ hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
 // Stages 2 and 3 on n elements whose matrices T are in place (top rows at `top`, row stride
 // cd.C, trace rows at `bot`): elimination of the first nu columns, then the Schur product
 // into Kout [n][nt][nt] and rout [n][nt]. A zero pivot records e_off + element in status.
+// ipiv (optional, [n][nu]) receives the row interchanges; keep = 1 also leaves the Ebar
+// multipliers below the diagonal of the top rows.
 hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t n, double* top, double* bot,
-                               double* Kout, double* rout, int* status, int64_t e_off) {
+                               double* Kout, double* rout, int* status, int64_t e_off, int32_t* ipiv = nullptr,
+                               int keep = 0) {
     const size_t lds = lu_lds_bytes(cd, NB);
     if (NB <= 16)
         hipLaunchKernelGGL((k_cond_lu<16, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB, top, bot,
-                           status, (int)e_off);
+                           status, (int)e_off, ipiv, keep);
     else if (NB <= 32)
         hipLaunchKernelGGL((k_cond_lu<32, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB, top, bot,
-                           status, (int)e_off);
+                           status, (int)e_off, ipiv, keep);
     else
         hipLaunchKernelGGL((k_cond_lu<64, 256>), dim3((unsigned)n), dim3(256), lds, ctx->stream, cd, NB, top, bot,
-                           status, (int)e_off);
+                           status, (int)e_off, ipiv, keep);
     HDG_LAUNCH_CHECK(ctx);
     const int tm_n = div_up(cd.nt, GT);
     const long long ntile = (long long)n * tm_n * tm_n;
@@ -751,7 +861,7 @@ __global__ __launch_bounds__(BS) void k_asm_store(int nb, int L, const double* _
 }  // namespace
 
 hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_elem_blocks* in, double* Kbar,
-                        double* rbar, double* local) {
+                        double* rbar, double* local, double* L21, int32_t* ipiv) {
     CondDims cd;
     cd.M = d->ncomp; cd.D = d->dim; cd.P = d->npe; cd.PF = d->npf; cd.L = d->nlfe;
     cd.nu = cd.M * cd.P; cd.nq = cd.M * cd.D * cd.P; cd.nt = cd.L * cd.M * cd.PF;
@@ -794,9 +904,16 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
                                local + e0 * cd.nu * cd.C, bot);
             HDG_LAUNCH_CHECK(ctx);
         }
+        const bool keep = L21 != nullptr;
         if ((st = eliminate_and_schur(ctx, cd, NB, n, local + e0 * cd.nu * cd.C, bot, Kbar + e0 * cd.nt * cd.nt,
-                                      rbar + e0 * cd.nt, status, e0)) != HDG_OK)
+                                      rbar + e0 * cd.nt, status, e0, keep ? ipiv + e0 * cd.nu : nullptr,
+                                      keep ? 1 : 0)) != HDG_OK)
             return st;
+        if (keep) {
+            hipLaunchKernelGGL(k_copy_l21, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,
+                               L21 + e0 * cd.nt * cd.nu);
+            HDG_LAUNCH_CHECK(ctx);
+        }
     }
     int bad = big;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -858,5 +975,23 @@ hdg_status asm_setup_run(hdg_ctx ctx, const hdg_dims* d, const double* Kbar, con
                    std::to_string(bad);
         return HDG_ERR_SINGULAR;
     }
+    return HDG_OK;
+}
+
+hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* local, const double* L21,
+                            const int32_t* ipiv, const double* ru, const double* rt, double* rbar) {
+    CondDims cd;
+    cd.M = d->ncomp; cd.D = d->dim; cd.P = d->npe; cd.PF = d->npf; cd.L = d->nlfe;
+    cd.nu = cd.M * cd.P; cd.nq = cd.M * cd.D * cd.P; cd.nt = cd.L * cd.M * cd.PF;
+    cd.R = cd.nu + cd.nt; cd.C = cd.R + 1; cd.NW = cd.P + cd.L * cd.PF; cd.KD = cd.D * cd.P;
+    if (ne <= 0) return HDG_OK;
+    const int NB = pick_panel(cd);     // the panel width the elimination used
+    if (NB == 0) {
+        ctx->err = "condensation: element too large for the LDS-blocked elimination";
+        return HDG_ERR_SHAPE;
+    }
+    hipLaunchKernelGGL(k_cond_rhs, dim3((unsigned)ne), dim3(BS), sizeof(double) * cd.nu, ctx->stream, cd, NB, local,
+                       L21, ipiv, ru, rt, rbar);
+    HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

@@ -390,17 +390,37 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             B32 = (float*)ws_get(ctx, WS_BINV32, sizeof(float) * (size_t)nf * nb * nb, &st);
             if (!B32) return st;
         }
-        int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
-        if (!status) return st;
-        const int big = 0x7fffffff;
-        HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-        if ((st = bj_invert(ctx, nf, nb, S, K64, B64, B32, status)) != HDG_OK) return st;
-        int bad = big;
-        HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-        if (bad != big) {
-            ctx->err = "block-Jacobi: zero or non-finite pivot in the diagonal block of face " + std::to_string(bad);
-            return HDG_ERR_SINGULAR;
+        BjSetupKey want;
+        want.valid = true;
+        want.mixed = mixed;
+        want.K64 = K64;
+        want.nbr = nbr;
+        want.nf = nf;
+        want.nb = nb;
+        want.S = S;
+        const BjSetupKey& have = ctx->bj_key;
+        if (o->reuse_setup) {
+            // the inverses (and folded blocks) of an earlier solve on the same matrix
+            if (!(have.valid && have.mixed == mixed && have.K64 == K64 && have.nbr == nbr && have.nf == nf &&
+                  have.nb == nb && have.S == S)) {
+                ctx->err = "reuse_setup: this context holds no block-Jacobi setup of this matrix and precision";
+                return HDG_ERR_ARG;
+            }
+        } else {
+            ctx->bj_key.valid = false;
+            int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
+            if (!status) return st;
+            const int big = 0x7fffffff;
+            HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+            if ((st = bj_invert(ctx, nf, nb, S, K64, B64, B32, status)) != HDG_OK) return st;
+            int bad = big;
+            HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+            if (bad != big) {
+                ctx->err = "block-Jacobi: zero or non-finite pivot in the diagonal block of face " + std::to_string(bad);
+                return HDG_ERR_SINGULAR;
+            }
+            ctx->bj_key = want;
         }
         op.Binv = mixed ? (const void*)B32 : (const void*)B64;
         op64.Binv = B64;
@@ -411,11 +431,23 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     Op opi = op;
     if (fold) {
         const size_t nblk_el = (size_t)nf * S * nb * nb;
+        const bool had_fold = o->reuse_setup && ctx->bj_key.valid && ctx->bj_key.fold;
         void* Kf = ws_get(ctx, WS_KFOLD, nblk_el * (mixed ? sizeof(float) : sizeof(double)), &st);
         if (!Kf) return st;
-        if ((st = fold_bj(ctx, nf, nb, S, K64, nbr, op64.Binv ? (const double*)op64.Binv : nullptr, Kf, mixed)) !=
-            HDG_OK)
-            return st;
+        if (!(had_fold && ctx->bj_key.valid)) {
+            if ((st = fold_bj(ctx, nf, nb, S, K64, nbr, op64.Binv ? (const double*)op64.Binv : nullptr, Kf,
+                              mixed)) != HDG_OK)
+                return st;
+            // the inverses are those of this matrix either way (computed or checked above)
+            ctx->bj_key.valid = true;
+            ctx->bj_key.mixed = mixed;
+            ctx->bj_key.K64 = K64;
+            ctx->bj_key.nbr = nbr;
+            ctx->bj_key.nf = nf;
+            ctx->bj_key.nb = nb;
+            ctx->bj_key.S = S;
+            ctx->bj_key.fold = true;
+        }
         opi.K = Kf;
         opi.k32 = mixed;
         opi.Binv = nullptr;

@@ -20,7 +20,8 @@ PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol declared in include/hdg.h
 SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
-           "hdg_local_size", "hdg_condense", "hdg_assemble_blocks", "hdg_solve_opts_default", "hdg_gmres_solve",
+           "hdg_local_size", "hdg_condense", "hdg_condense_keep", "hdg_condense_rhs", "hdg_assemble_blocks",
+           "hdg_assemble_rhs", "hdg_solve_opts_default", "hdg_gmres_solve",
            "hdg_recover_local", "hdg_newton_update", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
            "hdg_bj_apply", "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
@@ -51,7 +52,7 @@ class SolveOpts(ctypes.Structure):
                 ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("time_phases", ctypes.c_int32), ("fold_prec", ctypes.c_int32),
                 ("asm_inv64", ctypes.c_void_p), ("asm_inv32", ctypes.c_void_p), ("asm_f2e", ctypes.c_void_p),
-                ("asm_e2f", ctypes.c_void_p)]
+                ("asm_e2f", ctypes.c_void_p), ("reuse_setup", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -86,6 +87,9 @@ def load():
     lib.hdg_local_size.restype = ctypes.c_size_t
     lib.hdg_condense.argtypes = [vp, pd, i64, ctypes.POINTER(ElemBlocks), vp, vp, vp]
     lib.hdg_assemble_blocks.argtypes = [vp, pd, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_condense_keep.argtypes = [vp, pd, i64, ctypes.POINTER(ElemBlocks), vp, vp, vp, vp, vp]
+    lib.hdg_condense_rhs.argtypes = [vp, pd, i64, vp, vp, vp, vp, vp, vp]
+    lib.hdg_assemble_rhs.argtypes = [vp, pd, vp, vp, vp, vp]
     lib.hdg_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
     lib.hdg_solve_opts_default.restype = None
     lib.hdg_gmres_solve.argtypes = [vp, pd, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
@@ -226,6 +230,44 @@ class Context:
                                                  _ptr(Kbar, f64, ne * nt * nt, "Kbar"), _ptr(rbar, f64, ne * nt, "rbar"),
                                                  _ptr(local, f64, ne * nu * (nu + nt + 1), "local")))
 
+    def condense_keep(self, dims, blk, Kbar, rbar, local, L21, ipiv, ne_chunk=None):
+        import torch
+        d = make_dims(dims)
+        ne = int(dims["ne"]) if ne_chunk is None else int(ne_chunk)
+        M, D, P, PF, L = (int(dims[k]) for k in ("ncomp", "dim", "npe", "npf", "nlfe"))
+        nu, nq, nt = M * P, M * D * P, L * M * PF
+        f64 = torch.float64
+        sizes = dict(Minv=P * P, Bd=D * P * P, Cd=D * P * L * PF, D=nu * nq, E=nu * nu, F=nu * nt, G=nt * nq,
+                     H=nt * nu, J=nt * nt, ru=nu, rt=nt)
+        names = [f[0] for f in ElemBlocks._fields_]
+        eb = ElemBlocks(*[_ptr(blk[k], f64, ne * sizes[k], k) for k in names])
+        return self._check(self.lib.hdg_condense_keep(
+            self.h, ctypes.byref(d), ne, ctypes.byref(eb), _ptr(Kbar, f64, ne * nt * nt, "Kbar"),
+            _ptr(rbar, f64, ne * nt, "rbar"), _ptr(local, f64, ne * nu * (nu + nt + 1), "local"),
+            _ptr(L21, f64, ne * nt * nu, "L21"), _ptr(ipiv, torch.int32, ne * nu, "ipiv")))
+
+    def condense_rhs(self, dims, local, L21, ipiv, ru, rt, rbar, ne_chunk=None):
+        import torch
+        d = make_dims(dims)
+        ne = int(dims["ne"]) if ne_chunk is None else int(ne_chunk)
+        M, P, PF, L = (int(dims[k]) for k in ("ncomp", "npe", "npf", "nlfe"))
+        nu, nt = M * P, L * M * PF
+        f64 = torch.float64
+        return self._check(self.lib.hdg_condense_rhs(
+            self.h, ctypes.byref(d), ne, _ptr(local, f64, ne * nu * (nu + nt + 1), "local"),
+            _ptr(L21, f64, ne * nt * nu, "L21"), _ptr(ipiv, torch.int32, ne * nu, "ipiv"),
+            _ptr(ru, f64, ne * nu, "ru"), _ptr(rt, f64, ne * nt, "rt"), _ptr(rbar, f64, ne * nt, "rbar")))
+
+    def assemble_rhs(self, dims, f2e, perm, rbar, r):
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "npf", "nlfe"))
+        nb, nt = M * PF, L * M * PF
+        return self._check(self.lib.hdg_assemble_rhs(
+            self.h, ctypes.byref(d), _ptr(f2e, torch.int32, nf * 4, "f2e"),
+            _ptr(perm, torch.int32, ne * L * PF, "perm", allow_none=True),
+            _ptr(rbar, torch.float64, ne * nt, "rbar"), _ptr(r, torch.float64, nf * nb, "r")))
+
     # (2)
     def assemble(self, dims, f2e, e2f, perm, Kbar, rbar, K64, K32, nbr, r):
         import torch
@@ -243,7 +285,7 @@ class Context:
     # (3)
     def gmres_solve(self, dims, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0,
                     prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0,
-                    use_graph=False, time_phases=False, fold_prec=False, asm=None):
+                    use_graph=False, time_phases=False, fold_prec=False, asm=None, reuse_setup=False):
         import torch
         d = make_dims(dims)
         nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
@@ -257,6 +299,7 @@ class Context:
         o.use_graph = 1 if use_graph else 0
         o.time_phases = 1 if time_phases else 0
         o.fold_prec = 1 if fold_prec else 0
+        o.reuse_setup = 1 if reuse_setup else 0
         if asm is not None:      # dict(inv64=..., inv32=..., f2e=..., e2f=...) from asm_setup
             nt2 = int(dims["ne"]) * (L * nb) ** 2
             o.asm_inv64 = _ptr(asm["inv64"], torch.float64, nt2, "asm_inv64")

@@ -33,10 +33,27 @@ class Pipeline:
         self.du = z(ne, self.nu)
         self.dq = z(ne, self.nq)
 
-    def condense(self, blk, e0=0, e1=None):
-        """Condense elements [e0, e1) from device blocks that cover exactly that range."""
+    def condense(self, blk, e0=0, e1=None, keep=False):
+        """Condense elements [e0, e1) from device blocks that cover exactly that range. keep=True
+        also retains the factors a later right-hand side needs (condense_rhs)."""
         e1 = self.dims["ne"] if e1 is None else e1
-        self.ctx.condense(self.dims, blk, self.Kbar[e0:e1], self.rbar[e0:e1], self.local[e0:e1], ne_chunk=e1 - e0)
+        if not keep:
+            self.ctx.condense(self.dims, blk, self.Kbar[e0:e1], self.rbar[e0:e1], self.local[e0:e1],
+                              ne_chunk=e1 - e0)
+            return
+        if getattr(self, "L21", None) is None:
+            ne = self.dims["ne"]
+            self.L21 = torch.zeros(ne, self.nt, self.nu, dtype=torch.float64, device=self.device)
+            self.ipiv = torch.zeros(ne, self.nu, dtype=torch.int32, device=self.device)
+        self.ctx.condense_keep(self.dims, blk, self.Kbar[e0:e1], self.rbar[e0:e1], self.local[e0:e1],
+                               self.L21[e0:e1], self.ipiv[e0:e1], ne_chunk=e1 - e0)
+
+    def condense_rhs(self, ru, rt):
+        """New element right-hand sides with the kept factors (the matrices unchanged)."""
+        self.ctx.condense_rhs(self.dims, self.local, self.L21, self.ipiv, ru, rt, self.rbar)
+
+    def assemble_rhs(self):
+        self.ctx.assemble_rhs(self.dims, self.f2e, self.perm, self.rbar, self.r)
 
     def assemble(self):
         self.ctx.assemble(self.dims, self.f2e, self.e2f, self.perm, self.Kbar, self.rbar, self.K64, self.K32,

@@ -1,0 +1,145 @@
+"""GPU parity of the stage-reuse entry points (Section 2.2: the stages of a DIRK scheme solve
+systems with the same matrix and new right-hand sides): hdg_condense_keep, hdg_condense_rhs,
+hdg_assemble_rhs and hdg_solve_opts.reuse_setup, against the FP64 oracle run on the element
+blocks with the new right-hand sides, and against the library's own first-stage path.
+
+Tolerances as in test_gpu_parity: condensed right-hand sides to 1e-11 relative, solutions and
+recovered unknowns to 1e-10 (FP64) / 1e-8 (mixed); what must not change at all (the matrix
+outputs of hdg_condense_keep, a solve with reused setup) is compared bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import oracle_pipeline
+from test_gpu_parity import case_data, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2512_13619_amd import hdg
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return hdg.Context(0)
+
+
+def new_rhs(out, seed):
+    """The same element matrices with seeded new right-hand sides (the next stage)."""
+    rng = np.random.default_rng(seed)
+    blk = {k: v.copy() for k, v in out["blk"].items()}
+    blk["ru"] = rng.standard_normal(blk["ru"].shape)
+    blk["rt"] = rng.standard_normal(blk["rt"].shape)
+    return blk
+
+
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4"])
+def test_condense_keep_leaves_the_condensation_unchanged(ctx, name):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, out = case_data(name)
+    say("keep", name)
+    blk = to_dev(out["blk"])
+    pa = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    pb_ = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    pa.condense(blk)
+    pb_.condense(blk, keep=True)
+    torch.cuda.synchronize()
+    assert torch.equal(pa.Kbar, pb_.Kbar) and torch.equal(pa.rbar, pb_.rbar)
+    nu = pa.nu
+    upper = torch.triu(torch.ones(nu, nu, dtype=torch.bool, device="cuda"))
+    la, lb = pa.local, pb_.local
+    assert torch.equal(la[:, :, nu:], lb[:, :, nu:])
+    assert torch.equal(la[:, :, :nu][:, upper], lb[:, :, :nu][:, upper])
+    ip = pb_.ipiv.cpu().numpy()
+    assert ((ip >= np.arange(nu)[None, :]) & (ip < nu)).all()
+
+
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4"])
+def test_condense_rhs_matches_oracle(ctx, name):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    import oracle
+    pb, out = case_data(name)
+    say("rhs", name)
+    pl = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    pl.condense(to_dev(out["blk"]), keep=True)
+    blk2 = new_rhs(out, 21)
+    _, rb2 = oracle.condense.condense(blk2, pb.dims())
+    pl.condense_rhs(torch.as_tensor(blk2["ru"]).cuda(), torch.as_tensor(blk2["rt"]).cuda())
+    torch.cuda.synchronize()
+    er = relerr(pl.rbar.cpu().numpy(), rb2)
+    say("rhs error", er)
+    assert er < 1e-11, er
+    # the same as condensing the new blocks from scratch (up to rounding order)
+    pf = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    pf.condense(to_dev(blk2))
+    torch.cuda.synchronize()
+    assert relerr(pl.rbar.cpu().numpy(), pf.rbar.cpu().numpy()) < 1e-12
+    assert relerr(pl.local[:, :, -1].cpu().numpy(), pf.local[:, :, -1].cpu().numpy()) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p1"])
+def test_second_stage_end_to_end(ctx, name, precision):
+    """Stage 1: condense (keeping the factors), assemble, solve, recover. Stage 2 with new
+    right-hand sides: condense_rhs, assemble_rhs, solve reusing the block-Jacobi setup and
+    the folded blocks, recover -- against the oracle's whole pipeline on the new blocks."""
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, out = case_data(name)
+    say("stages", name, precision)
+    pl = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    blk = to_dev(out["blk"])
+    pl.condense(blk, keep=True)
+    pl.assemble()
+    kw = dict(restart=50, max_iters=5000, rtol=1e-13, prec="bj", orth="dcgs2", fold_prec=True,
+              precision=precision)
+    st1 = pl.solve(**kw)
+    assert st1["converged"]
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    assert relerr(pl.x.cpu().numpy(), out["x"]) < tol
+    blk2 = new_rhs(out, 22)
+    out2 = oracle_pipeline(pb, blk=blk2)
+    pl.condense_rhs(torch.as_tensor(blk2["ru"]).cuda(), torch.as_tensor(blk2["rt"]).cuda())
+    pl.assemble_rhs()
+    torch.cuda.synchronize()
+    assert relerr(pl.r.cpu().numpy(), out2["r"]) < 1e-11
+    st2 = pl.solve(reuse_setup=True, **kw)
+    assert st2["converged"]
+    x_reuse = pl.x.clone()
+    ex = relerr(x_reuse.cpu().numpy(), out2["x"])
+    pl.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+    torch.cuda.synchronize()
+    eu = relerr(pl.du.cpu().numpy(), out2["du"])
+    eq = relerr(pl.dq.cpu().numpy(), out2["dq"])
+    say("stage 2 errors", st2["iters"], ex, eu, eq)
+    assert ex < tol and eu < tol and eq < tol, (ex, eu, eq)
+    # reusing the setup changes nothing: a solve that recomputes it gives the same iterates
+    st3 = pl.solve(**kw)
+    assert st3["iters"] == st2["iters"] and torch.equal(pl.x, x_reuse)
+
+
+def test_reuse_setup_needs_a_matching_setup(ctx):
+    from paper_2512_13619_amd import hdg
+    pb, out = case_data("c1")
+    K = torch.as_tensor(out["K"]).cuda().contiguous()
+    nbr = torch.as_tensor(out["nbr"].astype(np.int32)).cuda().contiguous()
+    r = torch.as_tensor(out["r"]).cuda()
+    x = torch.zeros_like(r)
+    fresh = hdg.Context(0)
+    with pytest.raises(hdg.HdgError) as ei:
+        fresh.gmres_solve(pb.dims(), K, None, nbr, r, x, prec="bj", reuse_setup=True)
+    assert ei.value.status == -1
+    st = fresh.gmres_solve(pb.dims(), K, None, nbr, r, x, prec="bj", rtol=1e-12)
+    assert st["converged"]
+    K2 = K.clone()        # another matrix (another buffer): no reuse
+    with pytest.raises(hdg.HdgError) as ei:
+        fresh.gmres_solve(pb.dims(), K2, None, nbr, r, x, prec="bj", reuse_setup=True)
+    assert ei.value.status == -1
+    x.zero_()
+    st = fresh.gmres_solve(pb.dims(), K, None, nbr, r, x, prec="bj", rtol=1e-12, reuse_setup=True)
+    assert st["converged"] and relerr(x.cpu().numpy(), out["x"]) < 1e-10
