@@ -420,7 +420,8 @@ def main():
                      "traffic": (measured_traffic("fp32_matvec") if (args.n, args.p) == (24, 3) else None),
                      "kernel": "k_face_op<float,float,256,false,0,4> (FP32 block matvec)",
                      "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
-                     "timing": "HIP events around each matvec launch of the timed mixed solves"},
+                     "timing": "HIP events recorded at the start and end of each matvec kernel of the timed mixed "
+                               "solves (hipExtLaunchKernelGGL on the library's stream)"},
     }
     extra = []
     for prec in [p for p in args.also.split(",") if p]:

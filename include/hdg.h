@@ -243,7 +243,8 @@ typedef struct {
     int32_t hist_len;           /* entries written to resid_hist_h */
     int32_t n_timed;            /* Arnoldi steps timed (time_phases = 1), else 0 */
     double  t_prec, t_matvec, t_orth;     /* seconds of device time over the timed steps:
-                                   preconditioner, the step's one matvec, and orthogonalisation
+                                   preconditioner, the step's one matvec (events recorded at the
+                                   block-matvec kernel's own start and end), and orthogonalisation
                                    + Givens + normalisation (HIP events on the solve's stream) */
 } hdg_solve_stats;
 

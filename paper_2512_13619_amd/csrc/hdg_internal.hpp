@@ -45,6 +45,10 @@ struct hdg_ctx_s {
     void* ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
     BjSetupKey bj_key;
+    // when set, the next face-operator kernel is launched with these events recorded at its
+    // start and end (hipExtLaunchKernelGGL), then both are cleared: the solver's phase timing
+    // of the block matvec
+    hipEvent_t ext_start = nullptr, ext_stop = nullptr;
 };
 
 // Runs the enclosing scope on the context's private capture stream: the caller's

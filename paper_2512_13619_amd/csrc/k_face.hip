@@ -12,6 +12,8 @@
 // values gathered through nbr) sits in LDS; the G partial sums of each row are
 // combined in a fixed order, so results are bitwise reproducible. Empty slots
 // (boundary faces) are trailing and are never read.
+#include <hip/hip_ext.h>
+
 #include "hdg_internal.hpp"
 
 namespace {
@@ -229,8 +231,17 @@ hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     const size_t lds = sizeof(double) * ((size_t)fpb * a.S1 * a.nb + 256 * (size_t)vec + (size_t)fpb * a.nb);
     const int grid = div_up(a.nf, fpb);
     if (grid == 0) return HDG_OK;
-#define HDG_FACE_LAUNCH(TM, VC) \
-    hipLaunchKernelGGL((k_face_op<T1, T2, TM, HAS_M2, KIND, VC>), dim3(grid), dim3(256), lds, ctx->stream, a)
+#define HDG_FACE_LAUNCH(TM, VC)                                                                                 \
+    do {                                                                                                        \
+        if (ctx->ext_start) {                                                                                   \
+            hipExtLaunchKernelGGL((k_face_op<T1, T2, TM, HAS_M2, KIND, VC>), dim3(grid), dim3(256), lds,        \
+                                  ctx->stream, ctx->ext_start, ctx->ext_stop, 0, a);                            \
+            ctx->ext_start = ctx->ext_stop = nullptr;                                                           \
+        } else {                                                                                                \
+            hipLaunchKernelGGL((k_face_op<T1, T2, TM, HAS_M2, KIND, VC>), dim3(grid), dim3(256), lds,           \
+                               ctx->stream, a);                                                                 \
+        }                                                                                                       \
+    } while (0)
     if (vec == 4) {
         if (team == 256) HDG_FACE_LAUNCH(256, 4); else HDG_FACE_LAUNCH(128, 4);
     } else if (vec == 2) {

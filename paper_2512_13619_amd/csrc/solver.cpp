@@ -509,13 +509,27 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     // phase timing: events at the start of the preconditioner, the matvec and the
     // orthogonalisation of each Arnoldi step, and at the step's end
     EventPool ev;
-    if (timed && (st = ev.create(4 * m)) != HDG_OK) {
+    if (timed && (st = ev.create(6 * m)) != HDG_OK) {
         ctx->err = "hipEventCreate failed";
         return st;
     }
     auto mark = [&](int j, int k) -> hdg_status {
-        if (timed) HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[4 * j + k], ctx->stream));
+        if (timed) HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[6 * j + k], ctx->stream));
         return HDG_OK;
+    };
+    // the step's block matvec, timed by events recorded at the kernel's own start and end
+    auto timed_matvec = [&](int j, const Op& o2, const double* xin, double* yout) -> hdg_status {
+        if (timed) {
+            ctx->ext_start = ev.e[6 * j + 4];
+            ctx->ext_stop = ev.e[6 * j + 5];
+        }
+        hdg_status s3 = op_matvec(ctx, o2, xin, yout, skip);
+        if (timed && ctx->ext_start) {      // no kernel took them (nothing to launch)
+            ctx->ext_start = ctx->ext_stop = nullptr;
+            HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[6 * j + 4], ctx->stream));
+            HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[6 * j + 5], ctx->stream));
+        }
+        return s3;
     };
     // Delayed-CGS2 steps of one cycle (right preconditioning with a fixed preconditioner,
     // no Z): step j applies B = K M^{-1} to vt_j, one inner-product sweep, the coefficient
@@ -533,7 +547,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             if (fold && o->prec == HDG_PREC_BJ) src = vj;    // folded: nothing left to apply
             else if ((s2 = prec_apply(ctx, opi, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 1)) != HDG_OK) return s2;
-            if ((s2 = op_matvec(ctx, opi, src, wv, skip)) != HDG_OK) return s2;
+            if ((s2 = timed_matvec(j, opi, src, wv)) != HDG_OK) return s2;
             if ((s2 = mark(j, 2)) != HDG_OK) return s2;
             if ((s2 = vec_multidot2(ctx, w.V, w.ld, j + 1, vj, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
             if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.part, w.nblk, j, 0, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef,
@@ -589,7 +603,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             if ((s2 = mark(j, 0)) != HDG_OK) return s2;
             if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 1)) != HDG_OK) return s2;
-            if ((s2 = op_matvec(ctx, op, zj, wv, skip)) != HDG_OK) return s2;
+            if ((s2 = timed_matvec(j, op, zj, wv)) != HDG_OK) return s2;
             if ((s2 = mark(j, 2)) != HDG_OK) return s2;
             if (o->orth == HDG_ORTH_CGS2 && j + 1 <= 64) {
                 // CGS2 with three reads of the basis: dots, (axpy + second dots), (axpy + norm)
@@ -663,9 +677,9 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             const int nsteps = (dcgs2 && hc.k > 0 && hc.k < jmax) ? hc.k + 1 : hc.k;
             for (int j = 0; j < nsteps && j < jmax; ++j) {
                 float a = 0.f, b2 = 0.f, c = 0.f;
-                if (hipEventElapsedTime(&a, ev.e[4 * j], ev.e[4 * j + 1]) != hipSuccess ||
-                    hipEventElapsedTime(&b2, ev.e[4 * j + 1], ev.e[4 * j + 2]) != hipSuccess ||
-                    hipEventElapsedTime(&c, ev.e[4 * j + 2], ev.e[4 * j + 3]) != hipSuccess) {
+                if (hipEventElapsedTime(&a, ev.e[6 * j], ev.e[6 * j + 1]) != hipSuccess ||
+                    hipEventElapsedTime(&b2, ev.e[6 * j + 4], ev.e[6 * j + 5]) != hipSuccess ||
+                    hipEventElapsedTime(&c, ev.e[6 * j + 2], ev.e[6 * j + 3]) != hipSuccess) {
                     drop_graph();
                     ctx->err = "reading the phase timers failed";
                     return HDG_ERR_HIP;
