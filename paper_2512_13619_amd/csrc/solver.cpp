@@ -307,9 +307,11 @@ hdg_status arnoldi_setup(hdg_ctx ctx, const Op& op, const SolveWs& w, const doub
     int pe = P;
     for (int j = 0; j < P; ++j)
         if (!(Hc[(size_t)j * w.ldh + j + 1] > 0.0)) { pe = j + 1; break; }
+    // only rows 0..j+1 of column j are ever written on the device; the rest of
+    // the Hessenberg matrix is zero by definition, not whatever the workspace holds
     Hh.assign((size_t)(pe + 1) * pe, 0.0);
-    for (int i = 0; i <= pe; ++i)
-        for (int j = 0; j < pe; ++j) Hh[(size_t)i * pe + j] = Hc[(size_t)j * w.ldh + i];
+    for (int j = 0; j < pe; ++j)
+        for (int i = 0; i <= j + 1; ++i) Hh[(size_t)i * pe + j] = Hc[(size_t)j * w.ldh + i];
     *Peff = pe;
     return HDG_OK;
 }

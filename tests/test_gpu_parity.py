@@ -244,6 +244,33 @@ def test_gmres_solution_c1(ctx, precision, prec, orth):
     assert true <= 1e-13 * 1.01
 
 
+@pytest.mark.parametrize("prec", ["bj_poly", "bj_cheb"])
+def test_poly_setup_ignores_stale_hessenberg_entries(prec):
+    """The polynomial setup's Hessenberg matrix is zero below the subdiagonal whatever the kept
+    workspace holds: a context whose earlier solves (restart 50, then restart 4) left other values
+    where the new layout's zero entries lie gives the same Ritz values and iterates as a fresh one."""
+    from paper_2512_13619_amd import hdg
+    pb, out = case_data("c1")
+    say("stale hessenberg", prec)
+    K, K32, nbr = _dev_matrix(out)
+    r = torch.as_tensor(out["r"]).cuda()
+    v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(r.numel())).cuda()
+    used = hdg.Context(0)
+    for m in (50, 4):
+        x = torch.zeros_like(r)
+        used.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=m, max_iters=40, rtol=1e-13, prec="bj")
+    res = []
+    for c in (used, hdg.Context(0)):
+        x = torch.zeros_like(r)
+        st = c.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=7, max_iters=2000, rtol=1e-12, prec=prec,
+                           poly_v0=v0, poly_degree=6)
+        assert st["converged"], st
+        res.append((st["theta"], x.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert relerr(res[0][1], out["x"]) < 1e-9
+
+
 @pytest.mark.parametrize("orth", ORTHS)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_gmres_graph_replay_equals_direct(ctx, precision, orth):
