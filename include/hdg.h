@@ -214,7 +214,10 @@ typedef struct {
     int32_t time_phases;        /* 1: HIP events around the preconditioner, matvec and
                                    orthogonalisation of every Arnoldi step (fills t_prec,
                                    t_matvec, t_orth, n_timed; the cycle is then enqueued
-                                   directly even when use_graph = 1) */
+                                   directly even when use_graph = 1). Where a phase starts or
+                                   ends with a face-operator or delayed-CGS2 sweep kernel, the
+                                   launch itself records the event at the kernel's start or end
+                                   (hipExtLaunchKernelGGL); elsewhere a plain event record. */
     int32_t fold_prec;          /* 1 (with HDG_ORTH_DCGS2 and a preconditioner): form the
                                    right-preconditioned blocks K[f][s] P_g^{-1} (g = nbr(f,s))
                                    once per solve in a workspace, FP32 on the mixed path, so a
@@ -243,9 +246,10 @@ typedef struct {
     int32_t hist_len;           /* entries written to resid_hist_h */
     int32_t n_timed;            /* Arnoldi steps timed (time_phases = 1), else 0 */
     double  t_prec, t_matvec, t_orth;     /* seconds of device time over the timed steps:
-                                   preconditioner, the step's one matvec (events recorded at the
-                                   block-matvec kernel's own start and end), and orthogonalisation
-                                   + Givens + normalisation (HIP events on the solve's stream) */
+                                   preconditioner (0 with block-Jacobi folded into the blocks:
+                                   no separate apply), the step's one matvec (events recorded at
+                                   the block-matvec kernel's own start and end), and
+                                   orthogonalisation + Givens + normalisation */
 } hdg_solve_stats;
 
 void       hdg_solve_opts_default(hdg_solve_opts* opts_h);

@@ -45,11 +45,17 @@ struct hdg_ctx_s {
     void* ws[WS_NSLOTS] = {};
     size_t ws_bytes[WS_NSLOTS] = {};
     BjSetupKey bj_key;
-    // when set, the next face-operator kernel is launched with these events recorded at its
-    // start and end (hipExtLaunchKernelGGL), then both are cleared: the solver's phase timing
-    // of the block matvec
+    // phase timing: the next instrumented kernel launch (face operator, delayed-CGS2 sweeps)
+    // records ext_start at its start and ext_stop at its end (hipExtLaunchKernelGGL) if they
+    // are set, and clears them
     hipEvent_t ext_start = nullptr, ext_stop = nullptr;
 };
+
+inline void take_ext_events(hdg_ctx ctx, hipEvent_t* start, hipEvent_t* stop) {
+    *start = ctx->ext_start;
+    *stop = ctx->ext_stop;
+    ctx->ext_start = ctx->ext_stop = nullptr;
+}
 
 // Runs the enclosing scope on the context's private capture stream: the caller's
 // stream (possibly the legacy null stream, which cannot be captured) is drained

@@ -231,16 +231,16 @@ hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     const size_t lds = sizeof(double) * ((size_t)fpb * a.S1 * a.nb + 256 * (size_t)vec + (size_t)fpb * a.nb);
     const int grid = div_up(a.nf, fpb);
     if (grid == 0) return HDG_OK;
+    hipEvent_t ev_start, ev_stop;
+    take_ext_events(ctx, &ev_start, &ev_stop);
 #define HDG_FACE_LAUNCH(TM, VC)                                                                                 \
     do {                                                                                                        \
-        if (ctx->ext_start) {                                                                                   \
+        if (ev_start || ev_stop)                                                                                \
             hipExtLaunchKernelGGL((k_face_op<T1, T2, TM, HAS_M2, KIND, VC>), dim3(grid), dim3(256), lds,        \
-                                  ctx->stream, ctx->ext_start, ctx->ext_stop, 0, a);                            \
-            ctx->ext_start = ctx->ext_stop = nullptr;                                                           \
-        } else {                                                                                                \
+                                  ctx->stream, ev_start, ev_stop, 0, a);                                        \
+        else                                                                                                    \
             hipLaunchKernelGGL((k_face_op<T1, T2, TM, HAS_M2, KIND, VC>), dim3(grid), dim3(256), lds,           \
                                ctx->stream, a);                                                                 \
-        }                                                                                                       \
     } while (0)
     if (vec == 4) {
         if (team == 256) HDG_FACE_LAUNCH(256, 4); else HDG_FACE_LAUNCH(128, 4);

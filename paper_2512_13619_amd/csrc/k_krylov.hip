@@ -7,6 +7,8 @@
 // so every run gives bitwise identical results.
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "hdg_internal.hpp"
 
 namespace {
@@ -590,12 +592,22 @@ hdg_status vec_axpy_sumsq(hdg_ctx ctx, const double* V, size_t ldv, int J, const
 hdg_status vec_multidot2(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* x1, const double* x2,
                          size_t n, double* part, int nblk, const int* skip) {
     if (J <= 0) return HDG_OK;
-    if (x2)
+    hipEvent_t es, ee;
+    take_ext_events(ctx, &es, &ee);
+    if (es || ee) {
+        if (x2)
+            hipExtLaunchKernelGGL(k_multidot2<2>, dim3(nblk), dim3(BS), 0, ctx->stream, es, ee, 0, V, ldv, J, x1, x2,
+                                  n, part, nblk, skip);
+        else
+            hipExtLaunchKernelGGL(k_multidot2<1>, dim3(nblk), dim3(BS), 0, ctx->stream, es, ee, 0, V, ldv, J, x1, x2,
+                                  n, part, nblk, skip);
+    } else if (x2) {
         hipLaunchKernelGGL(k_multidot2<2>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, x1, x2, n, part, nblk,
                            skip);
-    else
+    } else {
         hipLaunchKernelGGL(k_multidot2<1>, dim3(nblk), dim3(BS), 0, ctx->stream, V, ldv, J, x1, x2, n, part, nblk,
                            skip);
+    }
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
@@ -616,8 +628,14 @@ hdg_status vec_dcgs2_update(hdg_ctx ctx, const double* V, size_t ldv, int j, dou
                             const double* coef, int ldc, size_t n, const int* skip) {
     // two entries per thread: vj, wt and the columns of V must be 16-byte aligned (the basis
     // columns start at multiples of ldv, a multiple of 64 doubles)
-    hipLaunchKernelGGL(k_dcgs2_update, dim3(div_up((long long)(n + 1) / 2, BS)), dim3(BS), 0, ctx->stream, V, ldv, j,
-                       vj, wt, coef, ldc, n, skip);
+    hipEvent_t es, ee;
+    take_ext_events(ctx, &es, &ee);
+    const dim3 grid(div_up((long long)(n + 1) / 2, BS));
+    if (es || ee)
+        hipExtLaunchKernelGGL(k_dcgs2_update, grid, dim3(BS), 0, ctx->stream, es, ee, 0, V, ldv, j, vj, wt, coef, ldc,
+                              n, skip);
+    else
+        hipLaunchKernelGGL(k_dcgs2_update, grid, dim3(BS), 0, ctx->stream, V, ldv, j, vj, wt, coef, ldc, n, skip);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

@@ -519,20 +519,32 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         if (timed) HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[6 * j + k], ctx->stream));
         return HDG_OK;
     };
-    // the step's block matvec, timed by events recorded at the kernel's own start and end
-    auto timed_matvec = [&](int j, const Op& o2, const double* xin, double* yout) -> hdg_status {
+    // Events of step j: 0/1 preconditioner, 2/3 matvec, 4/5 orthogonalisation. Where a phase
+    // starts or ends with an instrumented kernel the event is recorded at that kernel's own
+    // start or end (no separate marker); arm() hands them to the next such launch and
+    // settle() records any that no launch took.
+    auto arm = [&](hipEvent_t s0, hipEvent_t s1) {
         if (timed) {
-            ctx->ext_start = ev.e[6 * j + 4];
-            ctx->ext_stop = ev.e[6 * j + 5];
+            ctx->ext_start = s0;
+            ctx->ext_stop = s1;
         }
-        hdg_status s3 = op_matvec(ctx, o2, xin, yout, skip);
-        if (timed && ctx->ext_start) {      // no kernel took them (nothing to launch)
-            ctx->ext_start = ctx->ext_stop = nullptr;
-            HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[6 * j + 4], ctx->stream));
-            HDG_HIP_CHECK(ctx, hipEventRecord(ev.e[6 * j + 5], ctx->stream));
-        }
-        return s3;
     };
+    auto settle = [&]() -> hdg_status {
+        if (!timed) return HDG_OK;
+        hipEvent_t s0, s1;
+        take_ext_events(ctx, &s0, &s1);
+        if (s0) HDG_HIP_CHECK(ctx, hipEventRecord(s0, ctx->stream));
+        if (s1) HDG_HIP_CHECK(ctx, hipEventRecord(s1, ctx->stream));
+        return HDG_OK;
+    };
+    auto timed_matvec = [&](int j, const Op& o2, const double* xin, double* yout) -> hdg_status {
+        arm(timed ? ev.e[6 * j + 2] : nullptr, timed ? ev.e[6 * j + 3] : nullptr);
+        hdg_status s3 = op_matvec(ctx, o2, xin, yout, skip);
+        hdg_status s4 = settle();
+        return s3 != HDG_OK ? s3 : s4;
+    };
+    // the preconditioner is timed only where a step applies one (not with block-Jacobi folded)
+    const bool prec_timed = !(fold && o->prec == HDG_PREC_BJ);
     // Delayed-CGS2 steps of one cycle (right preconditioning with a fixed preconditioner,
     // no Z): step j applies B = K M^{-1} to vt_j, one inner-product sweep, the coefficient
     // kernel (delayed pass for vt_j, column j-1 and its Givens rotation, new column), one
@@ -544,19 +556,27 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         for (int j = 0; j < jmax; ++j) {
             double* vj = w.V + (size_t)j * w.ld;
             double* wv = w.V + (size_t)(j + 1) * w.ld;
-            if ((s2 = mark(j, 0)) != HDG_OK) return s2;
             const double* src = zt;
-            if (fold && o->prec == HDG_PREC_BJ) src = vj;    // folded: nothing left to apply
-            else if ((s2 = prec_apply(ctx, opi, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
-            if ((s2 = mark(j, 1)) != HDG_OK) return s2;
+            if (fold && o->prec == HDG_PREC_BJ) {
+                src = vj;    // folded: nothing left to apply
+            } else {
+                // block-Jacobi is one face-operator kernel; a polynomial takes a marker at its end
+                const bool one_kernel = opi.pk != PK_ASM && o->prec == HDG_PREC_BJ;
+                arm(timed ? ev.e[6 * j] : nullptr, timed && one_kernel ? ev.e[6 * j + 1] : nullptr);
+                if ((s2 = prec_apply(ctx, opi, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
+                if ((s2 = settle()) != HDG_OK) return s2;
+                if (!one_kernel && (s2 = mark(j, 1)) != HDG_OK) return s2;
+            }
             if ((s2 = timed_matvec(j, opi, src, wv)) != HDG_OK) return s2;
-            if ((s2 = mark(j, 2)) != HDG_OK) return s2;
+            arm(timed ? ev.e[6 * j + 4] : nullptr, nullptr);
             if ((s2 = vec_multidot2(ctx, w.V, w.ld, j + 1, vj, wv, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
+            if ((s2 = settle()) != HDG_OK) return s2;
             if ((s2 = krylov_dcgs2_coef(ctx, w.ctl, w.part, w.nblk, j, 0, w.Hu, w.H, w.ldh, w.cs, w.sn, w.g, w.coef,
                                         w.ldh, w.hist)) != HDG_OK)
                 return s2;
+            arm(nullptr, timed ? ev.e[6 * j + 5] : nullptr);
             if ((s2 = vec_dcgs2_update(ctx, w.V, w.ld, j, vj, wv, w.coef, w.ldh, N, skip)) != HDG_OK) return s2;
-            if ((s2 = mark(j, 3)) != HDG_OK) return s2;
+            if ((s2 = settle()) != HDG_OK) return s2;
         }
         double* vm = w.V + (size_t)jmax * w.ld;
         if ((s2 = vec_multidot2(ctx, w.V, w.ld, jmax + 1, vm, nullptr, N, w.part, w.nblk, skip)) != HDG_OK) return s2;
@@ -606,7 +626,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 1)) != HDG_OK) return s2;
             if ((s2 = timed_matvec(j, op, zj, wv)) != HDG_OK) return s2;
-            if ((s2 = mark(j, 2)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 4)) != HDG_OK) return s2;
             if (o->orth == HDG_ORTH_CGS2 && j + 1 <= 64) {
                 // CGS2 with three reads of the basis: dots, (axpy + second dots), (axpy + norm)
                 double* col = w.H + (size_t)j * w.ldh;
@@ -622,7 +642,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             if ((s2 = krylov_givens(ctx, w.ctl, w.part, w.nblk, w.H, w.ldh, w.cs, w.sn, w.g, j, w.hist)) != HDG_OK)
                 return s2;
             if ((s2 = krylov_scale_by(ctx, wv, wv, N, w.H + (size_t)j * w.ldh + j + 1, skip)) != HDG_OK) return s2;
-            if ((s2 = mark(j, 3)) != HDG_OK) return s2;
+            if ((s2 = mark(j, 5)) != HDG_OK) return s2;
         }
         if ((s2 = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return s2;
         return vec_multiaxpy(ctx, w.Z, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
@@ -679,9 +699,10 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             const int nsteps = (dcgs2 && hc.k > 0 && hc.k < jmax) ? hc.k + 1 : hc.k;
             for (int j = 0; j < nsteps && j < jmax; ++j) {
                 float a = 0.f, b2 = 0.f, c = 0.f;
-                if (hipEventElapsedTime(&a, ev.e[6 * j], ev.e[6 * j + 1]) != hipSuccess ||
-                    hipEventElapsedTime(&b2, ev.e[6 * j + 4], ev.e[6 * j + 5]) != hipSuccess ||
-                    hipEventElapsedTime(&c, ev.e[6 * j + 2], ev.e[6 * j + 3]) != hipSuccess) {
+                const bool pt = !dcgs2 || prec_timed;
+                if ((pt && hipEventElapsedTime(&a, ev.e[6 * j], ev.e[6 * j + 1]) != hipSuccess) ||
+                    hipEventElapsedTime(&b2, ev.e[6 * j + 2], ev.e[6 * j + 3]) != hipSuccess ||
+                    hipEventElapsedTime(&c, ev.e[6 * j + 4], ev.e[6 * j + 5]) != hipSuccess) {
                     drop_graph();
                     ctx->err = "reading the phase timers failed";
                     return HDG_ERR_HIP;
