@@ -10,9 +10,12 @@ computes, written from the paper:
                (Section 3.1, Section 4.4), block-Jacobi (Sections 3.2, 4.5)
   poly.py      polynomial preconditioner: Arnoldi, harmonic Ritz values, Leja
                order, product-form apply (Sections 3.4, 4.7); Chebyshev smoother
+  elements.py  element residuals and Jacobian blocks of scalar convection-diffusion
+               models from the weak form (Sections 2.2, 4.1)
+  newton.py    damped Newton with step halving on the residual norm (Section 4.3)
 
 Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may import
 this package. It shares no code with the GPU library (paper_2512_13619_amd);
 the two meet only at the seeded inputs produced by `workloads`.
 """
-from . import condense, assemble, krylov, poly  # noqa: F401
+from . import condense, assemble, krylov, poly, elements, newton  # noqa: F401

@@ -324,6 +324,28 @@ class HDGProblem:
         out = dict(Minv=Minv, Bd=Bd, Cd=Cd, D=Dm, E=Em, F=Fm, G=Gm, H=Hm, J=Jm, ru=ru, rt=rt)
         return {k: v.contiguous() for k, v in out.items()}
 
+    def newton_inputs(self):
+        """Inputs of the element residual/Jacobian generation for scalar convection-diffusion
+        models (Poisson, Burgers): the mesh's quadrature geometry, the reference tables, the
+        source and Dirichlet data at quadrature points, the model coefficients and the initial
+        state (nodal u per element, canonical face values uhat per face). Float64 tensors on
+        the problem's device; bnd is int32."""
+        assert self.M == 1 and hasattr(self.phys, "conv_diff")
+        ne, L = self.mesh.ne, self.nlfe
+        g = self.geometry(0, ne)
+        u0, uh_el = self._state(0, ne, g)
+        f2e = torch.as_tensor(self.mesh.f2e, device=self.device).long()
+        uhat0 = uh_el[f2e[:, 0], f2e[:, 1], 0].contiguous()              # (nf, npf)
+        cd = self.phys.conv_diff()
+        return dict(
+            wdet=g["wdet"].contiguous(), dphix=g["dphix"].contiguous(), phi=self.phi.contiguous(),
+            phif=g["phif"].contiguous(), psi=self.psi.contiguous(), ndA=g["ndA"].contiguous(),
+            dA=g["dA"].contiguous(), src=self.phys.source(g["xq"])[..., 0].contiguous(),
+            uD=self.phys.dirichlet(g["xf"])[..., 0].contiguous(),
+            bnd=self.bnd.to(torch.int32).contiguous(), nqv=int(self.wv.shape[0]), nqf=int(self.wf.shape[0]),
+            nu=float(cd["nu"]), tau=float(self.phys.tau), beta=list(cd["beta"]), gamma=list(cd["gamma"]),
+            u0=u0[:, 0].contiguous(), uhat0=uhat0)
+
     def state_dofs(self, e0=0, e1=None):
         """Nodal linearisation state (u0 (E,M,npe), uhat0 (E,L,M,npf))."""
         if e1 is None:

@@ -57,6 +57,10 @@ class Poisson(Physics):
     def flux(self, u, q):
         return -q
 
+    def conv_diff(self):
+        """F = beta u^2/2 + gamma u - nu q with these coefficients (see Burgers)."""
+        return dict(nu=1.0, beta=[0.0] * self.D, gamma=[0.0] * self.D)
+
     def source(self, x):
         if self._forcing is not None:
             return self._forcing(x)
@@ -167,6 +171,10 @@ class Burgers(Physics):
         fx = 0.5 * u[..., 0] ** 2 - self.nu * q[..., 0, 0]
         fy = u[..., 0] - self.nu * q[..., 0, 1]
         return torch.stack([fx, fy], dim=-1)[..., None, :]
+
+    def conv_diff(self):
+        """Scalar convection-diffusion form F_x = beta_x u^2/2 + gamma_x u - nu q_x."""
+        return dict(nu=self.nu, beta=[1.0, 0.0], gamma=[0.0, 1.0])
 
     def source(self, x):
         if self._forcing is None:
