@@ -272,6 +272,60 @@ hdg_status hdg_recover_local(hdg_ctx ctx, const hdg_dims* dims, const double* lo
 /* (5) Newton update state += alpha * delta over n entries -- Section 2.3, Section 4.4. */
 hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double* delta, double* state);
 
+/* (5b) Element residuals and Jacobian blocks on the device -- Section 4.1 (the element
+ *     matrices as products of reference basis tables with per-point weights, Jacobian
+ *     determinants and flux derivatives), Section 2.2 (weak form, numerical flux), and the
+ *     residual evaluation of Section 4.3's damped Newton iteration.
+ *
+ * Scalar convection-diffusion models (ncomp = 1):
+ *   F(u, q) = beta u^2/2 + gamma u - nu q  (a dim-vector), source s(x),
+ *   fhat = F(uhat, q).n + tau (u - uhat),  Dirichlet data u_D on boundary faces.
+ * Poisson is beta = gamma = 0, nu = 1; 2D viscous Burgers is beta = (1,0), gamma = (0,1).
+ * Steady residual rows, with the trace rows negated on interior faces:
+ *   R_u[i]   = -(F, grad phi_i) + <fhat, phi_i> - (s, phi_i)
+ *   R_t[l,j] = -<fhat, psi_j>_l  (interior face),  <uhat - u_D, psi_j>_l  (boundary face)
+ *
+ * Geometry of the mesh's quadrature (device, float64 unless stated; all caller-owned):
+ *   wdet  [ne][nqv]            volume weights times |det J|
+ *   dphix [ne][nqv][npe][dim]  physical gradients of the element basis
+ *   phi   [nqv][npe]           element basis at the volume points (reference)
+ *   phif  [ne][nlfe][nqf][npe] element basis at the points of each local face
+ *   psi   [nqf][npf]           face basis at the face points, canonical face order
+ *   ndA   [ne][nlfe][nqf][dim] outward normal times face weight;  dA [ne][nlfe][nqf]
+ *   src   [ne][nqv] source;  uD [ne][nlfe][nqf] Dirichlet data;  bnd [ne][nlfe] int32,
+ *   1 on boundary faces. */
+typedef struct {
+    int32_t nqv, nqf;
+    const double *wdet, *dphix, *phi, *phif, *psi, *ndA, *dA, *src, *uD;
+    const int32_t* bnd;
+} hdg_elem_geom;
+
+typedef struct {
+    double nu, tau, beta[3], gamma[3];
+} hdg_conv_diff;
+
+/* Device outputs in the layouts hdg_condense reads, plus q [ne][dim][npe] (may be NULL). */
+typedef struct {
+    double *Minv, *Bd, *Cd, *D, *E, *F, *G, *H, *J, *ru, *rt, *q;
+} hdg_elem_arrays;
+
+/* hdg_element_blocks: at the state u [ne][npe] (nodal) and uhat [nf][npf] (face values,
+ *   canonical order; element e's face l is uhat[e2f[e][l]]), with q derived from the
+ *   q-equation (M q_d + B_d u + C_d uhat = 0, eq. w16, so r_q = 0), writes ru = -R_u,
+ *   rt = -R_t and, unless residual_only, Minv, Bd, Cd, D, E, F, G, H, J (the derivatives of
+ *   R_u and R_t with respect to q, u, uhat). Outputs not written may be NULL. One workgroup
+ *   per element with its data in LDS: HDG_ERR_SHAPE if the element needs more than 64 KiB;
+ *   HDG_ERR_ARG for ncomp != 1. HDG_ERR_SINGULAR names the first element whose mass matrix
+ *   has a non-positive pivot (synchronises to read it).
+ * hdg_residual_norm: ||R|| = sqrt(sum_e ||R_u^e||^2 + sum_f ||R_f||^2) from ru and rt as
+ *   written above, R_f being face f's trace rows summed over its elements (perm = NULL
+ *   assembly); result in *norm_h. Uses a context workspace; synchronises. */
+hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* geom,
+                              const hdg_conv_diff* model, const int32_t* e2f, const double* u,
+                              const double* uhat, int32_t residual_only, const hdg_elem_arrays* out);
+hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
+                             const double* rt, double* norm_h);
+
 /* (6) Additive Schwarz preconditioner with one element per subdomain -- Section 3.3
  * (definition), Section 4.6 (element matrices and their enrichment).
  *

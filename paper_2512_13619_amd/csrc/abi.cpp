@@ -1,5 +1,6 @@
 // C ABI entry points of libhdg.so: argument validation on the host, then the
 // launchers. No C++ exception crosses this boundary.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -272,6 +273,73 @@ hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double*
     if (!delta || !state) return set_err(ctx, HDG_ERR_ARG, "hdg_newton_update: NULL pointer");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
     return axpy_run(ctx, n, alpha, delta, state);
+    GUARD_END
+}
+
+hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* g, const hdg_conv_diff* m,
+                              const int32_t* e2f, const double* u, const double* uhat, int32_t residual_only,
+                              const hdg_elem_arrays* out) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, false);
+    if (st != HDG_OK) return st;
+    if (!g || !m || !out) return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: NULL argument struct");
+    if (dims->ncomp != 1) return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: scalar models only (ncomp = 1)");
+    if (g->nqv < 1 || g->nqf < 1) return set_err(ctx, HDG_ERR_SHAPE, "hdg_element_blocks: nqv and nqf must be >= 1");
+    if (dims->ne == 0) return HDG_OK;
+    if (!g->wdet || !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD ||
+        !g->bnd || !e2f || !u || !uhat || !out->ru || !out->rt)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: NULL pointer");
+    if (!residual_only && (!out->Minv || !out->Bd || !out->Cd || !out->D || !out->E || !out->F || !out->G ||
+                           !out->H || !out->J))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: NULL matrix output (residual_only = 0)");
+    if (element_blocks_lds_bytes(dims, g->nqv, g->nqf) > 65536)
+        return set_err(ctx, HDG_ERR_SHAPE, "hdg_element_blocks: element data exceed 64 KiB of LDS");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
+    if (!status) return st;
+    const int big = 0x7fffffff;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    if ((st = element_blocks_run(ctx, dims, g, m, e2f, u, uhat, residual_only, out, status)) != HDG_OK) return st;
+    int bad = big;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad != big) {
+        ctx->err = "hdg_element_blocks: non-positive mass-matrix pivot in element " + std::to_string(bad);
+        return HDG_ERR_SINGULAR;
+    }
+    return HDG_OK;
+    GUARD_END
+}
+
+hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
+                             const double* rt, double* norm_h) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, true, true);
+    if (st != HDG_OK) return st;
+    if (!f2e || !ru || !rt || !norm_h) return set_err(ctx, HDG_ERR_ARG, "hdg_residual_norm: NULL pointer");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const size_t nu_all = (size_t)dims->ne * dims->ncomp * dims->npe;
+    const size_t nface = (size_t)dims->nf * dims->ncomp * dims->npf;
+    const int nb_u = krylov_nblk(nu_all), nb_f = krylov_nblk(nface);
+    const size_t nfa = (nface + 63) / 64 * 64;
+    double* base = (double*)ws_get(ctx, WS_NEWTON, sizeof(double) * (nfa + nb_u + nb_f + 2), &st);
+    if (!base) return st;
+    double* rf = base;
+    double* part_u = base + nfa;
+    double* part_f = part_u + nb_u;
+    double* nrm = part_f + nb_f;
+    if ((st = assemble_rhs_run(ctx, dims, f2e, nullptr, rt, rf)) != HDG_OK) return st;
+    if ((st = vec_sumsq_partial(ctx, ru, nu_all, part_u, nb_u, nullptr)) != HDG_OK) return st;
+    if ((st = krylov_store_norm(ctx, part_u, nb_u, nrm)) != HDG_OK) return st;
+    if ((st = vec_sumsq_partial(ctx, rf, nface, part_f, nb_f, nullptr)) != HDG_OK) return st;
+    if ((st = krylov_store_norm(ctx, part_f, nb_f, nrm + 1)) != HDG_OK) return st;
+    double h[2] = {0.0, 0.0};
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    *norm_h = std::sqrt(h[0] * h[0] + h[1] * h[1]);
+    return HDG_OK;
     GUARD_END
 }
 

@@ -26,6 +26,7 @@ enum WsSlot {
     WS_CTL,            // GMRES device control block + Hessenberg/Givens state
     WS_KFOLD,          // right-preconditioned operator blocks K M^{-1}
     WS_ASM,            // additive Schwarz: unit neighbour table, unit results, a work vector
+    WS_NEWTON,         // residual norm: assembled trace residual and reduction partials
     WS_NSLOTS
 };
 
@@ -204,6 +205,13 @@ hdg_status recover_run(hdg_ctx ctx, const hdg_dims* d, const double* local, cons
                        const double* Bd, const double* Cd, const int32_t* e2f, const int32_t* perm,
                        const double* xhat, double* du, double* dq);
 hdg_status axpy_run(hdg_ctx ctx, int64_t n, double alpha, const double* x, double* y);
+
+// Element residuals / Jacobian blocks (k_element.hip). `bad` receives the first element
+// whose mass matrix has a non-positive pivot (atomicMin; initialise it to INT_MAX).
+size_t element_blocks_lds_bytes(const hdg_dims* d, int nqv, int nqf);
+hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geom* g, const hdg_conv_diff* m,
+                              const int32_t* e2f, const double* u, const double* uhat, int residual_only,
+                              const hdg_elem_arrays* out, int* bad);
 
 // Host-side eigenvalues / harmonic Ritz values (ritz.cpp).
 int hessenberg_eigvals(int n, double* H, int ld, double* wr, double* wi);

@@ -1,0 +1,335 @@
+// Element residuals and Jacobian blocks on the device (Section 4.1, Section 4.3's residual
+// evaluation) for scalar convection-diffusion models
+//   F(u, q) = beta u^2/2 + gamma u - nu q,   fhat = F(uhat, q).n + tau (u - uhat),
+// which cover Poisson (beta = gamma = 0, nu = 1) and viscous Burgers. Each element is one
+// workgroup: its quadrature geometry and state are staged in LDS, the state is evaluated at
+// the quadrature points (the Phi/Psi products of Section 4.1 as per-point sums), the flux
+// and its derivatives are formed per point, and every output entry is one sum over the
+// volume or face points. q is derived from the q-equation (M q_d + B_d u + C_d uhat = 0),
+// so r_q = 0.
+//
+// Residual rows (steady, the sign of the trace rows as everywhere in the library):
+//   R_u[i]   = -(F, grad phi_i) + <fhat, phi_i> - (s, phi_i)
+//   R_t[l,j] = -<fhat, psi_j>_l (interior face), <uhat - u_D, psi_j>_l (Dirichlet face)
+// and ru = -R_u, rt = -R_t; D..J are their derivatives with respect to q, u and uhat.
+#include "hdg_internal.hpp"
+
+namespace {
+
+constexpr int EBS = 256;
+
+struct ElemArgs {
+    hdg_elem_geom g;
+    hdg_conv_diff m;
+    const int32_t* e2f;
+    const double* u;       // [ne][P]
+    const double* uhat;    // [nf][PF]
+    hdg_elem_arrays out;
+    int* bad;              // first element with a non-positive mass pivot
+    int ne, P, PF, L, D, residual_only;
+};
+
+// LDS offsets (in doubles) of the element's staged arrays
+struct ElemLds {
+    int phi, dphi, wdet, phif, psi, ndA, dA, src, uD, u, uh, M, t, q, uq, qq, uf, qf, uhf, wF, wFu, fhat, Z, total;
+};
+
+__host__ __device__ inline ElemLds elem_lds(int P, int PF, int L, int D, int Qv, int Qf) {
+    ElemLds o;
+    int p = 0;
+    o.phi = p;  p += Qv * P;
+    o.dphi = p; p += Qv * P * D;
+    o.wdet = p; p += Qv;
+    o.phif = p; p += L * Qf * P;
+    o.psi = p;  p += Qf * PF;
+    o.ndA = p;  p += L * Qf * D;
+    o.dA = p;   p += L * Qf;
+    o.src = p;  p += Qv;
+    o.uD = p;   p += L * Qf;
+    o.u = p;    p += P;
+    o.uh = p;   p += L * PF;
+    o.M = p;    p += P * P;
+    o.t = p;    p += D * P;
+    o.q = p;    p += D * P;
+    o.uq = p;   p += Qv;
+    o.qq = p;   p += Qv * D;
+    o.uf = p;   p += L * Qf;
+    o.qf = p;   p += L * Qf * D;
+    o.uhf = p;  p += L * Qf;
+    o.wF = p;   p += Qv * D;
+    o.wFu = p;  p += Qv * D;
+    o.fhat = p; p += L * Qf;
+    o.Z = p;    p += L * Qf;
+    o.total = p;
+    return o;
+}
+
+__global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
+    extern __shared__ double sm[];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int P = a.P, PF = a.PF, L = a.L, D = a.D, Qv = a.g.nqv, Qf = a.g.nqf;
+    const int nt = L * PF;
+    const ElemLds o = elem_lds(P, PF, L, D, Qv, Qf);
+    double *phi = sm + o.phi, *dphi = sm + o.dphi, *wdet = sm + o.wdet, *phif = sm + o.phif, *psi = sm + o.psi;
+    double *ndA = sm + o.ndA, *dA = sm + o.dA, *src = sm + o.src, *uD = sm + o.uD, *u = sm + o.u, *uh = sm + o.uh;
+    double *Mm = sm + o.M, *t = sm + o.t, *q = sm + o.q, *uq = sm + o.uq, *qq = sm + o.qq, *uf = sm + o.uf;
+    double *qf = sm + o.qf, *uhf = sm + o.uhf, *wF = sm + o.wF, *wFu = sm + o.wFu, *fhat = sm + o.fhat, *Z = sm + o.Z;
+    const size_t E = (size_t)e;
+
+    // 1. stage geometry, reference tables and state
+    for (int k = tid; k < Qv * P; k += EBS) phi[k] = a.g.phi[k];
+    for (int k = tid; k < Qv * P * D; k += EBS) dphi[k] = a.g.dphix[E * Qv * P * D + k];
+    for (int k = tid; k < Qv; k += EBS) {
+        wdet[k] = a.g.wdet[E * Qv + k];
+        src[k] = a.g.src[E * Qv + k];
+    }
+    for (int k = tid; k < L * Qf * P; k += EBS) phif[k] = a.g.phif[E * L * Qf * P + k];
+    for (int k = tid; k < Qf * PF; k += EBS) psi[k] = a.g.psi[k];
+    for (int k = tid; k < L * Qf * D; k += EBS) ndA[k] = a.g.ndA[E * L * Qf * D + k];
+    for (int k = tid; k < L * Qf; k += EBS) {
+        dA[k] = a.g.dA[E * L * Qf + k];
+        uD[k] = a.g.uD[E * L * Qf + k];
+    }
+    for (int k = tid; k < P; k += EBS) u[k] = a.u[E * P + k];
+    for (int k = tid; k < nt; k += EBS) {
+        const int l = k / PF, j = k - l * PF;
+        uh[k] = a.uhat[(size_t)a.e2f[E * L + l] * PF + j];
+    }
+    __syncthreads();
+
+    // 2. mass matrix and its inverse (Gauss-Jordan in place; M is SPD, no interchanges)
+    for (int k = tid; k < P * P; k += EBS) {
+        const int i = k / P, j = k - i * P;
+        double s = 0.0;
+        for (int x = 0; x < Qv; ++x) s += wdet[x] * phi[x * P + i] * phi[x * P + j];
+        Mm[k] = s;
+    }
+    __syncthreads();
+    for (int k = 0; k < P; ++k) {
+        const double piv = Mm[k * P + k];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (tid == 0) atomicMin(a.bad, e);
+            return;    // uniform across the workgroup: every thread read the same pivot
+        }
+        const double rp = 1.0 / piv;
+        // row k scaled (entry k becomes 1/piv), other rows updated with the old column k
+        for (int idx = tid; idx < P * P; idx += EBS) {
+            const int i = idx / P, j = idx - i * P;
+            if (i == k) continue;
+            const double f = Mm[i * P + k] * rp;
+            if (j == k) continue;
+            Mm[idx] -= f * Mm[k * P + j];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < P; idx += EBS) {
+            if (idx != k) {
+                Mm[idx * P + k] = -Mm[idx * P + k] * rp;
+                Mm[k * P + idx] *= rp;
+            }
+        }
+        if (tid == 0) Mm[k * P + k] = rp;
+        __syncthreads();
+    }
+
+    // 3. u and uhat at the quadrature points
+    for (int k = tid; k < Qv; k += EBS) {
+        double s = 0.0;
+        for (int i = 0; i < P; ++i) s += phi[k * P + i] * u[i];
+        uq[k] = s;
+    }
+    for (int k = tid; k < L * Qf; k += EBS) {
+        const int l = k / Qf, x = k - l * Qf;
+        double s = 0.0, h = 0.0;
+        for (int i = 0; i < P; ++i) s += phif[k * P + i] * u[i];
+        for (int j = 0; j < PF; ++j) h += psi[x * PF + j] * uh[l * PF + j];
+        uf[k] = s;
+        uhf[k] = h;
+    }
+    __syncthreads();
+
+    // 4. q = -M^{-1} (B_d u + C_d uhat), with B_d u and C_d uhat summed over the points
+    for (int k = tid; k < D * P; k += EBS) {
+        const int d = k / P, i = k - d * P;
+        double s = 0.0;
+        for (int x = 0; x < Qv; ++x) s += wdet[x] * dphi[(x * P + i) * D + d] * uq[x];
+        for (int lx = 0; lx < L * Qf; ++lx) s -= ndA[lx * D + d] * phif[lx * P + i] * uhf[lx];
+        t[k] = s;
+    }
+    __syncthreads();
+    for (int k = tid; k < D * P; k += EBS) {
+        const int d = k / P, i = k - d * P;
+        double s = 0.0;
+        for (int j = 0; j < P; ++j) s += Mm[i * P + j] * t[d * P + j];
+        q[k] = -s;
+        if (a.out.q) a.out.q[E * D * P + k] = -s;
+    }
+    __syncthreads();
+
+    // 5. q at the points, then the flux and its derivatives per point
+    for (int k = tid; k < Qv * D; k += EBS) {
+        const int x = k / D, d = k - x * D;
+        double s = 0.0;
+        for (int i = 0; i < P; ++i) s += phi[x * P + i] * q[d * P + i];
+        qq[k] = s;
+    }
+    for (int k = tid; k < L * Qf * D; k += EBS) {
+        const int lx = k / D, d = k - lx * D;
+        double s = 0.0;
+        for (int i = 0; i < P; ++i) s += phif[lx * P + i] * q[d * P + i];
+        qf[k] = s;
+    }
+    __syncthreads();
+    const double nu = a.m.nu, tau = a.m.tau;
+    for (int k = tid; k < Qv * D; k += EBS) {
+        const int x = k / D, d = k - x * D;
+        const double v = uq[x];
+        wF[k] = wdet[x] * (a.m.beta[d] * 0.5 * v * v + a.m.gamma[d] * v - nu * qq[k]);
+        wFu[k] = wdet[x] * (a.m.beta[d] * v + a.m.gamma[d]);
+    }
+    for (int lx = tid; lx < L * Qf; lx += EBS) {
+        const double v = uhf[lx];
+        double fn = 0.0, zn = 0.0;
+        for (int d = 0; d < D; ++d) {
+            const double n = ndA[lx * D + d];
+            fn += (a.m.beta[d] * 0.5 * v * v + a.m.gamma[d] * v - nu * qf[lx * D + d]) * n;
+            zn += (a.m.beta[d] * v + a.m.gamma[d]) * n;
+        }
+        fhat[lx] = fn + tau * (uf[lx] - v) * dA[lx];
+        Z[lx] = zn - tau * dA[lx];    // d fhat / d uhat per unit trace value
+    }
+    __syncthreads();
+
+    // 6. right-hand sides ru = -R_u, rt = -R_t
+    for (int i = tid; i < P; i += EBS) {
+        double s = 0.0;
+        for (int x = 0; x < Qv; ++x) {
+            double g = 0.0;
+            for (int d = 0; d < D; ++d) g += wF[x * D + d] * dphi[(x * P + i) * D + d];
+            s += g + wdet[x] * src[x] * phi[x * P + i];
+        }
+        for (int lx = 0; lx < L * Qf; ++lx) s -= fhat[lx] * phif[lx * P + i];
+        a.out.ru[E * P + i] = s;
+    }
+    for (int k = tid; k < nt; k += EBS) {
+        const int l = k / PF, j = k - l * PF;
+        const bool bd = a.g.bnd[E * L + l] != 0;
+        double s = 0.0;
+        for (int x = 0; x < Qf; ++x) {
+            const int lx = l * Qf + x;
+            s += (bd ? -dA[lx] * (uhf[lx] - uD[lx]) : fhat[lx]) * psi[x * PF + j];
+        }
+        a.out.rt[E * nt + k] = s;
+    }
+    if (a.residual_only) return;
+
+    // 7. matrices
+    for (int k = tid; k < P * P; k += EBS) a.out.Minv[E * P * P + k] = Mm[k];
+    for (int k = tid; k < D * P * P; k += EBS) {            // Bd[d][i][j]
+        const int d = k / (P * P), r = k - d * P * P, i = r / P, j = r - i * P;
+        double s = 0.0;
+        for (int x = 0; x < Qv; ++x) s += wdet[x] * dphi[(x * P + i) * D + d] * phi[x * P + j];
+        a.out.Bd[E * D * P * P + k] = s;
+    }
+    for (int k = tid; k < D * P * nt; k += EBS) {           // Cd[d][i][(l,j)]
+        const int d = k / (P * nt), r = k - d * P * nt, i = r / nt, c = r - i * nt, l = c / PF, j = c - l * PF;
+        double s = 0.0;
+        for (int x = 0; x < Qf; ++x) {
+            const int lx = l * Qf + x;
+            s -= ndA[lx * D + d] * phif[lx * P + i] * psi[x * PF + j];
+        }
+        a.out.Cd[E * D * P * nt + k] = s;
+    }
+    for (int k = tid; k < P * D * P; k += EBS) {            // D[i][(d,j)]
+        const int i = k / (D * P), c = k - i * D * P, d = c / P, j = c - d * P;
+        double s = 0.0;
+        for (int x = 0; x < Qv; ++x) s += nu * wdet[x] * dphi[(x * P + i) * D + d] * phi[x * P + j];
+        for (int lx = 0; lx < L * Qf; ++lx) s -= nu * ndA[lx * D + d] * phif[lx * P + i] * phif[lx * P + j];
+        a.out.D[E * P * D * P + k] = s;
+    }
+    for (int k = tid; k < P * P; k += EBS) {                // E[i][j]
+        const int i = k / P, j = k - i * P;
+        double s = 0.0;
+        for (int x = 0; x < Qv; ++x) {
+            double g = 0.0;
+            for (int d = 0; d < D; ++d) g += wFu[x * D + d] * dphi[(x * P + i) * D + d];
+            s -= g * phi[x * P + j];
+        }
+        for (int lx = 0; lx < L * Qf; ++lx) s += tau * dA[lx] * phif[lx * P + i] * phif[lx * P + j];
+        a.out.E[E * P * P + k] = s;
+    }
+    for (int k = tid; k < P * nt; k += EBS) {               // F[i][(l,j)]
+        const int i = k / nt, c = k - i * nt, l = c / PF, j = c - l * PF;
+        double s = 0.0;
+        for (int x = 0; x < Qf; ++x) {
+            const int lx = l * Qf + x;
+            s += Z[lx] * phif[lx * P + i] * psi[x * PF + j];
+        }
+        a.out.F[E * P * nt + k] = s;
+    }
+    for (int k = tid; k < nt * D * P; k += EBS) {           // G[(l,j)][(d,i)]
+        const int r = k / (D * P), c = k - r * D * P, l = r / PF, j = r - l * PF, d = c / P, i = c - d * P;
+        double s = 0.0;
+        if (a.g.bnd[E * L + l] == 0) {
+            for (int x = 0; x < Qf; ++x) {
+                const int lx = l * Qf + x;
+                s += nu * ndA[lx * D + d] * psi[x * PF + j] * phif[lx * P + i];
+            }
+        }
+        a.out.G[E * nt * D * P + k] = s;
+    }
+    for (int k = tid; k < nt * P; k += EBS) {               // H[(l,j)][i]
+        const int r = k / P, i = k - r * P, l = r / PF, j = r - l * PF;
+        double s = 0.0;
+        if (a.g.bnd[E * L + l] == 0) {
+            for (int x = 0; x < Qf; ++x) {
+                const int lx = l * Qf + x;
+                s -= tau * dA[lx] * psi[x * PF + j] * phif[lx * P + i];
+            }
+        }
+        a.out.H[E * nt * P + k] = s;
+    }
+    for (int k = tid; k < nt * nt; k += EBS) {              // J[(l,j)][(l',j')], block diagonal in l
+        const int r = k / nt, c = k - r * nt, l = r / PF, j = r - l * PF, l2 = c / PF, j2 = c - l2 * PF;
+        double s = 0.0;
+        if (l == l2) {
+            const bool bd = a.g.bnd[E * L + l] != 0;
+            for (int x = 0; x < Qf; ++x) {
+                const int lx = l * Qf + x;
+                s += (bd ? dA[lx] : -Z[lx]) * psi[x * PF + j] * psi[x * PF + j2];
+            }
+        }
+        a.out.J[E * nt * nt + k] = s;
+    }
+}
+
+}  // namespace
+
+size_t element_blocks_lds_bytes(const hdg_dims* d, int nqv, int nqf) {
+    const ElemLds o = elem_lds(d->npe, d->npf, d->nlfe, d->dim, nqv, nqf);
+    return sizeof(double) * (size_t)o.total;
+}
+
+hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geom* g, const hdg_conv_diff* m,
+                              const int32_t* e2f, const double* u, const double* uhat, int residual_only,
+                              const hdg_elem_arrays* out, int* bad) {
+    if (d->ne == 0) return HDG_OK;
+    ElemArgs a;
+    a.g = *g;
+    a.m = *m;
+    a.e2f = e2f;
+    a.u = u;
+    a.uhat = uhat;
+    a.out = *out;
+    a.bad = bad;
+    a.ne = d->ne;
+    a.P = d->npe;
+    a.PF = d->npf;
+    a.L = d->nlfe;
+    a.D = d->dim;
+    a.residual_only = residual_only;
+    const size_t lds = element_blocks_lds_bytes(d, g->nqv, g->nqf);
+    hipLaunchKernelGGL(k_element_blocks, dim3(d->ne), dim3(EBS), lds, ctx->stream, a);
+    HDG_LAUNCH_CHECK(ctx);
+    return HDG_OK;
+}

@@ -22,7 +22,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
            "hdg_local_size", "hdg_condense", "hdg_condense_keep", "hdg_condense_rhs", "hdg_assemble_blocks",
            "hdg_assemble_rhs", "hdg_solve_opts_default", "hdg_gmres_solve",
-           "hdg_recover_local", "hdg_newton_update", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
+           "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
            "hdg_bj_apply", "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch"]
@@ -43,6 +43,20 @@ class Dims(ctypes.Structure):
 
 class ElemBlocks(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt")]
+
+
+class ElemGeom(ctypes.Structure):
+    _fields_ = [("nqv", ctypes.c_int32), ("nqf", ctypes.c_int32)] + \
+        [(n, ctypes.c_void_p) for n in ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")]
+
+
+class ConvDiff(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("tau", ctypes.c_double), ("beta", ctypes.c_double * 3),
+                ("gamma", ctypes.c_double * 3)]
+
+
+class ElemArrays(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "q")]
 
 
 class SolveOpts(ctypes.Structure):
@@ -96,6 +110,9 @@ def load():
                                     ctypes.POINTER(SolveStats)]
     lib.hdg_recover_local.argtypes = [vp, pd, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_newton_update.argtypes = [vp, i64, dbl, vp, vp]
+    lib.hdg_element_blocks.argtypes = [vp, pd, ctypes.POINTER(ElemGeom), ctypes.POINTER(ConvDiff), vp, vp, vp, i32,
+                                       ctypes.POINTER(ElemArrays)]
+    lib.hdg_residual_norm.argtypes = [vp, pd, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.hdg_matvec.argtypes = [vp, pd, vp, vp, vp, i32, vp, vp]
     lib.hdg_bj_setup.argtypes = [vp, pd, vp, vp, vp]
     lib.hdg_bj_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp]
@@ -341,6 +358,42 @@ class Context:
         n = state.numel()
         return self._check(self.lib.hdg_newton_update(self.h, n, float(alpha), _ptr(delta, torch.float64, n, "delta"),
                                                       _ptr(state, torch.float64, n, "state")))
+
+    def element_blocks(self, dims, geom, model, e2f, u, uhat, out, residual_only=False):
+        """Element residuals (and Jacobian blocks unless residual_only) at the state (u, uhat):
+        geom holds the quadrature geometry (wdet, dphix, phi, phif, psi, ndA, dA, src, uD, bnd,
+        nqv, nqf), model the coefficients (nu, tau, beta, gamma), out the device outputs."""
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, D, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe"))
+        Qv, Qf = int(geom["nqv"]), int(geom["nqf"])
+        f64 = torch.float64
+        gsz = dict(wdet=ne * Qv, dphix=ne * Qv * P * D, phi=Qv * P, phif=ne * L * Qf * P, psi=Qf * PF,
+                   ndA=ne * L * Qf * D, dA=ne * L * Qf, src=ne * Qv, uD=ne * L * Qf)
+        g = ElemGeom(Qv, Qf, *[_ptr(geom[k], f64, gsz[k], k) for k in gsz],
+                     _ptr(geom["bnd"], torch.int32, ne * L, "bnd"))
+        beta = list(model["beta"]) + [0.0] * (3 - len(model["beta"]))
+        gamma = list(model["gamma"]) + [0.0] * (3 - len(model["gamma"]))
+        m = ConvDiff(float(model["nu"]), float(model["tau"]), (ctypes.c_double * 3)(*beta),
+                     (ctypes.c_double * 3)(*gamma))
+        nu, nq, nt = M * P, M * D * P, L * M * PF
+        osz = dict(Minv=P * P, Bd=D * P * P, Cd=D * P * nt, D=nu * nq, E=nu * nu, F=nu * nt, G=nt * nq,
+                   H=nt * nu, J=nt * nt, ru=nu, rt=nt, q=nq)
+        o = ElemArrays(*[_ptr(out.get(k), f64, ne * osz[k], k, allow_none=True) for k in osz])
+        return self._check(self.lib.hdg_element_blocks(
+            self.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(m), _ptr(e2f, torch.int32, ne * L, "e2f"),
+            _ptr(u, f64, ne * P, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"), int(bool(residual_only)),
+            ctypes.byref(o)))
+
+    def residual_norm(self, dims, f2e, ru, rt):
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "npe", "npf", "nlfe"))
+        out = ctypes.c_double(0.0)
+        self._check(self.lib.hdg_residual_norm(
+            self.h, ctypes.byref(d), _ptr(f2e, torch.int32, nf * 4, "f2e"), _ptr(ru, torch.float64, ne * M * P, "ru"),
+            _ptr(rt, torch.float64, ne * L * M * PF, "rt"), ctypes.byref(out)))
+        return out.value
 
     # building blocks
     def matvec(self, dims, K64, K32, nbr, x, y, precision="fp64"):

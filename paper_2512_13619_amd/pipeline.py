@@ -76,3 +76,54 @@ class Pipeline:
 
     def recover(self, Minv, Bd, Cd):
         self.ctx.recover(self.dims, self.local, Minv, Bd, Cd, self.e2f, self.perm, self.x, self.du, self.dq)
+
+    def element_arrays(self):
+        """Device buffers for the element blocks of a scalar model (hdg_element_blocks)."""
+        d = self.dims
+        ne, D, P = d["ne"], d["dim"], d["npe"]
+        z = lambda n: torch.zeros(ne * n, dtype=torch.float64, device=self.device)
+        nu, nq, nt = self.nu, self.nq, self.nt
+        return dict(Minv=z(P * P), Bd=z(D * P * P), Cd=z(D * P * nt), D=z(nu * nq), E=z(nu * nu), F=z(nu * nt),
+                    G=z(nt * nq), H=z(nt * nu), J=z(nt * nt), ru=z(nu), rt=z(nt), q=z(nq))
+
+    def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, **solve_kw):
+        """Damped Newton iteration (Section 4.3) on a scalar convection-diffusion model.
+
+        u [ne*npe] and uhat [nf*npf] (device, float64) hold the state and are updated in place.
+        Each step: element blocks at the state, condensation, assembly, preconditioned GMRES,
+        recovery, then alpha = 1, 1/2, 1/4, ... until the residual norm decreases (or alpha
+        reaches min_alpha); stops once the norm is at most max(tol * initial norm, atol).
+        solve_kw go to the linear solves (restart, rtol, prec, ...). Returns one
+        dict(norm, alpha, iters) per step and a last entry with the final norm. Sequencing
+        only: evaluation, solve and updates run in libhdg.so."""
+        d = self.dims
+        blk = self.element_arrays()
+        self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk)
+        nrm = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
+        n0 = nrm
+        hist = []
+        for _ in range(max_steps):
+            if nrm <= max(tol * n0, atol):
+                break
+            self.condense(blk)
+            self.assemble()
+            if str(solve_kw.get("prec", "")).startswith("asm"):
+                # additive Schwarz patches of this linearisation
+                self.asm_setup(fp32=solve_kw.get("precision", "fp64") == "mixed")
+            st = self.solve(**solve_kw)
+            self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+            alpha, applied = 1.0, 0.0
+            while True:
+                self.ctx.newton_update(alpha - applied, self.du, u)
+                self.ctx.newton_update(alpha - applied, self.x, uhat)
+                applied = alpha
+                # the trial state's blocks: kept as the next step's linearisation if accepted
+                self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk)
+                trial = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
+                if trial < nrm or alpha <= min_alpha:
+                    break
+                alpha *= 0.5
+            hist.append(dict(norm=nrm, alpha=alpha, iters=st["iters"]))
+            nrm = trial
+        hist.append(dict(norm=nrm, alpha=0.0, iters=0))
+        return hist

@@ -1,0 +1,150 @@
+"""Device element residuals/Jacobian blocks and the damped Newton loop against the oracle
+(Section 4.1, Section 4.3): hdg_element_blocks, hdg_residual_norm, Pipeline.newton."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.elements as OE
+import oracle.newton as ON
+from workloads import mesh as Mh
+from workloads import physics as Ph
+from workloads.blocks import HDGProblem
+
+from test_gpu_parity import relerr, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2512_13619_amd import hdg
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return hdg.Context(0)
+
+
+def _forcing(x):
+    return (torch.sin(np.pi * x[..., 0]) * torch.sin(2 * np.pi * x[..., 1]))[..., None]
+
+
+CASES = {
+    "burgers_tri_p3": lambda: HDGProblem(Mh.structured_tris(3, 0.0, 4), 3, Ph.Burgers(nu=0.05)),
+    "burgers_quad_p2": lambda: HDGProblem(Mh.structured_quads(3, 0.1, 4), 2, Ph.Burgers(nu=0.01, forcing=_forcing)),
+    "burgers_quad_p4": lambda: HDGProblem(Mh.structured_quads(4, 0.05, 6), 4, Ph.Burgers(nu=0.02, forcing=_forcing)),
+    "poisson_tri_p2": lambda: HDGProblem(Mh.structured_tris(3, 0.1, 5), 2, Ph.Poisson(2, 1.0, forcing=_forcing)),
+}
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        pb = CASES[name]()
+        inp = pb.newton_inputs()
+        _cache[name] = (pb, inp, {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in inp.items()})
+    return _cache[name]
+
+
+def _model(inp):
+    return dict(nu=inp["nu"], tau=inp["tau"], beta=inp["beta"], gamma=inp["gamma"])
+
+
+def _geom_dev(inp):
+    g = {k: inp[k].cuda().contiguous() for k in ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD",
+                                                  "bnd")}
+    g["nqv"], g["nqf"] = inp["nqv"], inp["nqf"]
+    return g
+
+
+def _random_state(pb, inp_np, seed):
+    rng = np.random.default_rng(seed)
+    u = inp_np["u0"] + 0.3 * rng.standard_normal(inp_np["u0"].shape)
+    uh = inp_np["uhat0"] + 0.3 * rng.standard_normal(inp_np["uhat0"].shape)
+    return u, uh
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_element_blocks_match_oracle(ctx, name):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case(name)
+    d = pb.dims()
+    say("element blocks", name, d)
+    u, uh = _random_state(pb, inp_np, 1)
+    ref = OE.element_blocks(inp_np, _model(inp_np), u, uh, pb.mesh.e2f)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    out = pl.element_arrays()
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, torch.as_tensor(u).cuda().flatten(),
+                       torch.as_tensor(uh).cuda().flatten(), out)
+    torch.cuda.synchronize()
+    for k in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "q"):
+        got = out[k].cpu().numpy().reshape(ref[k].shape)
+        err = relerr(got, ref[k])
+        assert err < 1e-12, (k, err)
+
+
+def test_residual_only_and_norm(ctx):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case("burgers_tri_p3")
+    d = pb.dims()
+    u, uh = _random_state(pb, inp_np, 2)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    full = pl.element_arrays()
+    ud, uhd = torch.as_tensor(u).cuda().flatten(), torch.as_tensor(uh).cuda().flatten()
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, ud, uhd, full)
+    res = {"ru": torch.full_like(full["ru"], np.nan), "rt": torch.full_like(full["rt"], np.nan)}
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, ud, uhd, res, residual_only=True)
+    torch.cuda.synchronize()
+    assert torch.equal(res["ru"], full["ru"]) and torch.equal(res["rt"], full["rt"])
+    nrm = ctx.residual_norm(d, pl.f2e, res["ru"], res["rt"])
+    ref = OE.element_blocks(inp_np, _model(inp_np), u, uh, pb.mesh.e2f)
+    want = ON._norm_from_blocks(ref, pb.mesh.e2f, pb.mesh.f2e, d)
+    assert abs(nrm - want) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("name,prec", [("burgers_quad_p2", "bj"), ("burgers_tri_p3", "asm"),
+                                       ("poisson_tri_p2", "bj")])
+def test_newton_matches_oracle(ctx, name, prec):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case(name)
+    d = pb.dims()
+    say("newton", name, prec)
+    m = _model(inp_np)
+    u_ref, uh_ref, hist_ref = ON.damped_newton(inp_np, m, inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f, pb.mesh.f2e,
+                                               d, rtol=1e-11)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    u = inp["u0"].cuda().flatten().clone()
+    uh = inp["uhat0"].cuda().flatten().clone()
+    g = _geom_dev(inp)
+    hist = pl.newton(g, _model(inp), u, uh, tol=1e-11, restart=50, max_iters=2000, rtol=1e-13, prec=prec)
+    say("  steps", [(f"{h['norm']:.3e}", h["alpha"], h["iters"]) for h in hist])
+    assert len(hist) == len(hist_ref)
+    assert [h["alpha"] for h in hist] == [h["alpha"] for h in hist_ref]
+    for a, b in zip(hist, hist_ref):
+        assert abs(a["norm"] - b["norm"]) <= 1e-7 * hist_ref[0]["norm"]
+    assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-9
+    assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-9
+
+
+def test_element_blocks_rejects_bad_input(ctx):
+    from paper_2512_13619_amd import hdg
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case("poisson_tri_p2")
+    d = dict(pb.dims())
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    out = pl.element_arrays()
+    u = inp["u0"].cuda().flatten()
+    uh = inp["uhat0"].cuda().flatten()
+    g = _geom_dev(inp)
+    with pytest.raises(hdg.HdgError):           # matrices requested but missing
+        ctx.element_blocks(d, g, _model(inp), pl.e2f, u, uh, {"ru": out["ru"], "rt": out["rt"]})
+    ne, P, D, L = d["ne"], d["npe"], d["dim"], d["nlfe"]
+    Qv = 4000                                   # one element's LDS above 64 KiB: rejected on the host
+    big = dict(g, nqv=Qv, wdet=torch.zeros(ne * Qv, dtype=torch.float64, device="cuda"),
+               dphix=torch.zeros(ne * Qv * P * D, dtype=torch.float64, device="cuda"),
+               phi=torch.zeros(Qv * P, dtype=torch.float64, device="cuda"),
+               src=torch.zeros(ne * Qv, dtype=torch.float64, device="cuda"))
+    with pytest.raises(hdg.HdgError) as ei:
+        ctx.element_blocks(d, big, _model(inp), pl.e2f, u, uh, out)
+    assert "LDS" in str(ei.value)
+    # no elements: nothing to do
+    per_elem = ("wdet", "dphix", "phif", "ndA", "dA", "src", "uD", "bnd")
+    g0 = {k: (v[:0] if k in per_elem else v) for k, v in g.items()}
+    ctx.element_blocks(dict(d, ne=0), g0, _model(inp), pl.e2f[:0], u[:0], uh, {k: v[:0] for k, v in out.items()})
