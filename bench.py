@@ -202,6 +202,78 @@ def second_stage(args, pl, blk, d, stream):
     return out
 
 
+def element_bytes(d, nqv, nqf, residual_only):
+    """Algorithmic HBM bytes per element of hdg_element_blocks (scalar model): the element's
+    geometry and state read once, every output written once (reference tables not counted)."""
+    P, PF, L, D = d["npe"], d["npf"], d["nlfe"], d["dim"]
+    nt = L * PF
+    rd = nqv * (1 + P * D + 1) + L * nqf * (P + D + 2) + P + nt + 2 * L * 4 / 8
+    wr = P + nt + D * P
+    if not residual_only:
+        wr += P * P + D * P * P + D * P * nt + P * D * P + P * P + P * nt + nt * D * P + nt * P + nt * nt
+    return 8 * (rd + wr)
+
+
+def newton_bench(args):
+    """Damped Newton on 2D viscous Burgers (nu = 0.01, smooth forcing) on n x n jittered quads of
+    degree p: the element-block kernel timed alone, then the whole Newton loop (element blocks,
+    condensation, assembly, GMRES(50) with block-Jacobi folded into the blocks and delayed CGS2
+    to 1e-10, recovery, step halving) to a residual reduction of 1e-10."""
+    import numpy as np
+    import torch
+    from paper_2512_13619_amd import hdg
+    from paper_2512_13619_amd.pipeline import Pipeline
+    from workloads import mesh as Mh
+    from workloads import physics as Ph
+    from workloads.blocks import HDGProblem
+
+    def forcing(x):
+        return (torch.sin(np.pi * x[..., 0]) * torch.sin(2 * np.pi * x[..., 1]))[..., None]
+    n, p = args.newton, args.p
+    pb = HDGProblem(Mh.structured_quads(n, 0.05, 6), p, Ph.Burgers(nu=0.01, forcing=forcing), device="cuda")
+    d = pb.dims()
+    inp = pb.newton_inputs()
+    geom = {k: inp[k].contiguous() for k in ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")}
+    geom["nqv"], geom["nqf"] = inp["nqv"], inp["nqf"]
+    model = dict(nu=inp["nu"], tau=inp["tau"], beta=inp["beta"], gamma=inp["gamma"])
+    ctx = hdg.Context(0)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f, keep_fp32=False)
+    blk = pl.element_arrays()
+    u = inp["u0"].flatten().clone()
+    uh = inp["uhat0"].flatten().clone()
+    stream = torch.cuda.current_stream()
+    rates = {}
+    for ro in (False, True):
+        ctx.element_blocks(d, geom, model, pl.e2f, u, uh, blk, residual_only=ro)
+        reps = 20
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            ctx.element_blocks(d, geom, model, pl.e2f, u, uh, blk, residual_only=ro)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) / 1e3 / reps
+        by = element_bytes(d, geom["nqv"], geom["nqf"], ro) * d["ne"]
+        rates["residual_only" if ro else "blocks"] = dict(ms=t * 1e3, bytes=by, GBs=by / t / 1e9)
+    runs = {}
+    for graph in (False, True):
+        u.copy_(inp["u0"].flatten())
+        uh.copy_(inp["uhat0"].flatten())
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        hist = pl.newton(geom, model, u, uh, tol=1e-10, restart=50, max_iters=20000, rtol=1e-10, prec="bj",
+                         orth="dcgs2", fold_prec=True, use_graph=graph)
+        torch.cuda.synchronize()
+        runs["graph" if graph else "direct"] = time.perf_counter() - ts
+    t_newton = min(runs.values())
+    print(json.dumps({"profile": "newton", "workload": f"2D viscous Burgers nu=0.01, {n}x{n} quads jitter 0.05, "
+                      f"p={p}", "dims": d, "nqv": geom["nqv"], "nqf": geom["nqf"], "element_kernel": rates,
+                      "newton_s": t_newton, "newton_s_by_launch": runs, "steps": len(hist) - 1,
+                      "history": [dict(norm=h["norm"], alpha=h["alpha"], iters=h["iters"]) for h in hist]}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +299,9 @@ def main():
     ap.add_argument("--profile-matvec", type=int, default=0,
                     help="build the workload's matrix, run this many FP32 and FP64 block matvecs and a 1 GiB "
                          "device copy (counter calibration), then exit")
+    ap.add_argument("--newton", type=int, default=0,
+                    help="instead of the headline: damped Newton on 2D viscous Burgers with this many quads per "
+                         "direction at degree --p (element-kernel rates and the Newton loop), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the hot path is "
@@ -239,6 +314,9 @@ def main():
     from workloads import configs
 
     torch.cuda.set_device(0)
+    if args.newton > 0:
+        newton_bench(args)
+        return
     t0 = time.perf_counter()
     pb = configs.c2(n=args.n, p=args.p, device="cuda")
     d = pb.dims()

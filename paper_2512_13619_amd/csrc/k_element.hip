@@ -17,6 +17,7 @@
 namespace {
 
 constexpr int EBS = 256;
+constexpr int TJ = 4;      // output columns per work item in the (i, j) sums
 
 struct ElemArgs {
     hdg_elem_geom g;
@@ -99,11 +100,19 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
     __syncthreads();
 
     // 2. mass matrix and its inverse (Gauss-Jordan in place; M is SPD, no interchanges)
-    for (int k = tid; k < P * P; k += EBS) {
-        const int i = k / P, j = k - i * P;
-        double s = 0.0;
-        for (int x = 0; x < Qv; ++x) s += wdet[x] * phi[x * P + i] * phi[x * P + j];
-        Mm[k] = s;
+    const int nJT = (P + TJ - 1) / TJ;    // column tiles of TJ entries: one row i per work item
+    for (int it = tid; it < P * nJT; it += EBS) {
+        const int i = it / nJT, j0 = (it - i * nJT) * TJ;
+        double acc[TJ] = {};
+        for (int x = 0; x < Qv; ++x) {
+            const double wi = wdet[x] * phi[x * P + i];
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj)
+                if (j0 + jj < P) acc[jj] += wi * phi[x * P + j0 + jj];
+        }
+#pragma unroll
+        for (int jj = 0; jj < TJ; ++jj)
+            if (j0 + jj < P) Mm[i * P + j0 + jj] = acc[jj];
     }
     __syncthreads();
     for (int k = 0; k < P; ++k) {
@@ -223,71 +232,72 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
     }
     if (a.residual_only) return;
 
-    // 7. matrices
+    // 7. matrices. With dF/dq = -nu I: the volume part of D is nu B_d, and G on an interior
+    // face is -nu C_d^T; the (i, j) sums over volume and face points share one pass with
+    // the row's per-point values held in registers.
     for (int k = tid; k < P * P; k += EBS) a.out.Minv[E * P * P + k] = Mm[k];
-    for (int k = tid; k < D * P * P; k += EBS) {            // Bd[d][i][j]
-        const int d = k / (P * P), r = k - d * P * P, i = r / P, j = r - i * P;
-        double s = 0.0;
-        for (int x = 0; x < Qv; ++x) s += wdet[x] * dphi[(x * P + i) * D + d] * phi[x * P + j];
-        a.out.Bd[E * D * P * P + k] = s;
-    }
-    for (int k = tid; k < D * P * nt; k += EBS) {           // Cd[d][i][(l,j)]
-        const int d = k / (P * nt), r = k - d * P * nt, i = r / nt, c = r - i * nt, l = c / PF, j = c - l * PF;
-        double s = 0.0;
-        for (int x = 0; x < Qf; ++x) {
-            const int lx = l * Qf + x;
-            s -= ndA[lx * D + d] * phif[lx * P + i] * psi[x * PF + j];
-        }
-        a.out.Cd[E * D * P * nt + k] = s;
-    }
-    for (int k = tid; k < P * D * P; k += EBS) {            // D[i][(d,j)]
-        const int i = k / (D * P), c = k - i * D * P, d = c / P, j = c - d * P;
-        double s = 0.0;
-        for (int x = 0; x < Qv; ++x) s += nu * wdet[x] * dphi[(x * P + i) * D + d] * phi[x * P + j];
-        for (int lx = 0; lx < L * Qf; ++lx) s -= nu * ndA[lx * D + d] * phif[lx * P + i] * phif[lx * P + j];
-        a.out.D[E * P * D * P + k] = s;
-    }
-    for (int k = tid; k < P * P; k += EBS) {                // E[i][j]
-        const int i = k / P, j = k - i * P;
-        double s = 0.0;
+    for (int it = tid; it < P * nJT; it += EBS) {        // Bd, D, E
+        const int i = it / nJT, j0 = (it - i * nJT) * TJ;
+        double bd[3][TJ] = {}, sf[3][TJ] = {}, ev[TJ] = {}, ef[TJ] = {};
         for (int x = 0; x < Qv; ++x) {
-            double g = 0.0;
-            for (int d = 0; d < D; ++d) g += wFu[x * D + d] * dphi[(x * P + i) * D + d];
-            s -= g * phi[x * P + j];
+            double wd[3], g = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double dp = d < D ? dphi[(x * P + i) * D + d] : 0.0;
+                wd[d] = wdet[x] * dp;
+                g += d < D ? wFu[x * D + d] * dp : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) {
+                const double pj = j0 + jj < P ? phi[x * P + j0 + jj] : 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) bd[d][jj] += wd[d] * pj;
+                ev[jj] -= g * pj;
+            }
         }
-        for (int lx = 0; lx < L * Qf; ++lx) s += tau * dA[lx] * phif[lx * P + i] * phif[lx * P + j];
-        a.out.E[E * P * P + k] = s;
+        for (int lx = 0; lx < L * Qf; ++lx) {
+            const double pi = phif[lx * P + i];
+            double nd[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) nd[d] = d < D ? ndA[lx * D + d] * pi : 0.0;
+            const double da = dA[lx] * pi;
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) {
+                const double pj = j0 + jj < P ? phif[lx * P + j0 + jj] : 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sf[d][jj] += nd[d] * pj;
+                ef[jj] += da * pj;
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < TJ; ++jj) {
+            const int j = j0 + jj;
+            if (j >= P) continue;
+            for (int d = 0; d < D; ++d) {
+                a.out.Bd[E * D * P * P + (size_t)(d * P + i) * P + j] = bd[d][jj];
+                a.out.D[E * P * D * P + (size_t)i * D * P + d * P + j] = nu * (bd[d][jj] - sf[d][jj]);
+            }
+            a.out.E[E * P * P + (size_t)i * P + j] = ev[jj] + tau * ef[jj];
+        }
     }
-    for (int k = tid; k < P * nt; k += EBS) {               // F[i][(l,j)]
-        const int i = k / nt, c = k - i * nt, l = c / PF, j = c - l * PF;
-        double s = 0.0;
+    for (int it = tid; it < P * nt; it += EBS) {          // Cd, F, G, H for one (i, l, j)
+        const int i = it / nt, c = it - i * nt, l = c / PF, j = c - l * PF;
+        double cd[3] = {}, f = 0.0, h = 0.0;
         for (int x = 0; x < Qf; ++x) {
             const int lx = l * Qf + x;
-            s += Z[lx] * phif[lx * P + i] * psi[x * PF + j];
+            const double w = phif[lx * P + i] * psi[x * PF + j];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cd[d] -= d < D ? ndA[lx * D + d] * w : 0.0;
+            f += Z[lx] * w;
+            h += dA[lx] * w;
         }
-        a.out.F[E * P * nt + k] = s;
-    }
-    for (int k = tid; k < nt * D * P; k += EBS) {           // G[(l,j)][(d,i)]
-        const int r = k / (D * P), c = k - r * D * P, l = r / PF, j = r - l * PF, d = c / P, i = c - d * P;
-        double s = 0.0;
-        if (a.g.bnd[E * L + l] == 0) {
-            for (int x = 0; x < Qf; ++x) {
-                const int lx = l * Qf + x;
-                s += nu * ndA[lx * D + d] * psi[x * PF + j] * phif[lx * P + i];
-            }
+        const bool interior = a.g.bnd[E * L + l] == 0;
+        for (int d = 0; d < D; ++d) {
+            a.out.Cd[E * D * P * nt + (size_t)(d * P + i) * nt + c] = cd[d];
+            a.out.G[E * nt * D * P + (size_t)c * D * P + d * P + i] = interior ? -nu * cd[d] : 0.0;
         }
-        a.out.G[E * nt * D * P + k] = s;
-    }
-    for (int k = tid; k < nt * P; k += EBS) {               // H[(l,j)][i]
-        const int r = k / P, i = k - r * P, l = r / PF, j = r - l * PF;
-        double s = 0.0;
-        if (a.g.bnd[E * L + l] == 0) {
-            for (int x = 0; x < Qf; ++x) {
-                const int lx = l * Qf + x;
-                s -= tau * dA[lx] * psi[x * PF + j] * phif[lx * P + i];
-            }
-        }
-        a.out.H[E * nt * P + k] = s;
+        a.out.F[E * P * nt + (size_t)i * nt + c] = f;
+        a.out.H[E * nt * P + (size_t)c * P + i] = interior ? -tau * h : 0.0;
     }
     for (int k = tid; k < nt * nt; k += EBS) {              // J[(l,j)][(l',j')], block diagonal in l
         const int r = k / nt, c = k - r * nt, l = r / PF, j = r - l * PF, l2 = c / PF, j2 = c - l2 * PF;
