@@ -197,15 +197,32 @@ __global__ void k_givens(GmresCtl* ctl, const double* part, int nblk, double* H,
 }
 
 // y = R^{-1} g over the k steps of this cycle (upper triangular R in H, column-major).
-__global__ void k_backsolve(const GmresCtl* ctl, const double* H, int ldh, const double* g, double* y) {
-    if (threadIdx.x != 0) return;
+// Back substitution R y = g (R = the k x k upper triangle of the rotated H, column-major with
+// leading dimension ldh) by column sweeps: y_c = r_c / R_cc, then r_i -= R_ic y_c for i < c
+// in parallel. The triangle is staged in LDS (packed by columns) when it fits, else read
+// from global memory column by column.
+constexpr int BACKSOLVE_BS = 256;
+constexpr int BACKSOLVE_LDS = 4096;     // doubles of packed triangle: k <= 90
+__global__ __launch_bounds__(BACKSOLVE_BS) void k_backsolve(const GmresCtl* ctl, const double* H, int ldh,
+                                                            const double* g, double* y) {
+    __shared__ double tri[BACKSOLVE_LDS];
+    __shared__ double r[256];
     const int k = ctl->k;
-    for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * ldh + i] * y[c];
-        y[i] = s / H[(size_t)i * ldh + i];
+    const int tid = threadIdx.x;
+    const bool staged = (long)k * (k + 1) / 2 <= BACKSOLVE_LDS;
+    for (int i = tid; i < k; i += BACKSOLVE_BS) r[i] = g[i];
+    if (staged)
+        for (int c = 0; c < k; ++c)
+            for (int i = tid; i <= c; i += BACKSOLVE_BS) tri[c * (c + 1) / 2 + i] = H[(size_t)c * ldh + i];
+    __syncthreads();
+    for (int c = k - 1; c >= 0; --c) {
+        const double* col = staged ? tri + c * (c + 1) / 2 : H + (size_t)c * ldh;
+        const double yc = r[c] / col[c];
+        for (int i = tid; i < c; i += BACKSOLVE_BS) r[i] -= col[i] * yc;
+        if (tid == 0) y[c] = yc;
+        __syncthreads();
     }
-    for (int i = k; i < ldh - 1; ++i) y[i] = 0.0;
+    for (int i = k + tid; i < ldh - 1; i += BACKSOLVE_BS) y[i] = 0.0;
 }
 
 // Fused second Gram-Schmidt pass, part 1: w <- w - V h1 and partial dots V^T w
@@ -704,7 +721,11 @@ hdg_status krylov_givens(hdg_ctx ctx, GmresCtl* ctl, const double* part, int nbl
 
 hdg_status krylov_backsolve(hdg_ctx ctx, const GmresCtl* ctl, const double* H, int ldh, const double* g,
                             double* y) {
-    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, ctx->stream, ctl, H, ldh, g, y);
+    if (ldh - 1 > 256) {
+        ctx->err = "back substitution: Krylov dimension above 256";
+        return HDG_ERR_ARG;
+    }
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BACKSOLVE_BS), 0, ctx->stream, ctl, H, ldh, g, y);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
