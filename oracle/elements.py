@@ -30,6 +30,10 @@ Inputs (numpy, float64): the mesh's quadrature geometry
   src[e][q]           source at volume points; uD[e][l][q] Dirichlet data at face points
   bnd[e][l]           1 on boundary faces
 and the state u[e][i] (nodal), uhat_el[e][l][j] (the element's face values).
+Time term (one implicit stage, Section 2.2): with c = 1/(a_ii dt), the previous step's u_n and
+the earlier stages' contribution r_x (known), the u-rows become
+  R_u + c (u - u_n, phi_i) + r_x[i],   so E gains c M;
+c = 0 and no r_x is the steady system.
 Loops follow the formulas: one element at a time, one quadrature point at a time.
 """
 import numpy as np
@@ -82,8 +86,9 @@ def consistent_q(g, e, u, uh):
     return np.stack([-np.linalg.solve(Mm, Bd[d] @ u + Cd[d] @ uh.ravel()) for d in range(Bd.shape[0])])
 
 
-def residual(g, m, e, q, u, uh):
-    """(R_q (D, P), R_u (P,), R_t (L, PF)) of element e at the state (q, u, uhat)."""
+def residual(g, m, e, q, u, uh, tt=None):
+    """(R_q (D, P), R_u (P,), R_t (L, PF)) of element e at the state (q, u, uhat); tt = (c, u_n, r_x)
+    adds the implicit stage's time term to R_u (r_x may be None)."""
     wdet, dphix, phi, phif, psi, ndA, dA, src, uD, bnd = _element_geom(g, e)
     Qv, P = phi.shape
     L, Qf, _ = phif.shape
@@ -100,6 +105,10 @@ def residual(g, m, e, q, u, uh):
         Fk = flux(m, uk, qk)
         Ru -= wdet[k] * (dphix[k] @ Fk)
         Ru -= wdet[k] * src[k] * phi[k]
+        if tt is not None:
+            Ru += tt[0] * wdet[k] * (uk - phi[k] @ tt[1]) * phi[k]
+    if tt is not None and tt[2] is not None:
+        Ru += tt[2]
     for l in range(L):
         for k in range(Qf):
             uf = phif[l, k] @ u
@@ -116,9 +125,9 @@ def residual(g, m, e, q, u, uh):
     return Rq, Ru, Rt
 
 
-def jacobian(g, m, e, q, u, uh):
+def jacobian(g, m, e, q, u, uh, c=0.0):
     """D (P, D*P), E (P, P), F (P, L*PF), G (L*PF, D*P), H (L*PF, P), J (L*PF, L*PF): the
-    derivatives of R_u and R_t with respect to q (d, j), u and uhat (l, j)."""
+    derivatives of R_u and R_t with respect to q (d, j), u and uhat (l, j); c = time-term factor."""
     wdet, dphix, phi, phif, psi, ndA, dA, src, uD, bnd = _element_geom(g, e)
     Qv, P = phi.shape
     L, Qf, _ = phif.shape
@@ -137,6 +146,7 @@ def jacobian(g, m, e, q, u, uh):
         Fu = flux_du(m, uk, D)
         # -(dF/du phi_j, grad phi_i), -(dF/dq_d phi_j, grad phi_i)
         Em -= wdet[k] * np.outer(dphix[k] @ Fu, phi[k])
+        Em += c * wdet[k] * np.outer(phi[k], phi[k])
         for d in range(D):
             Dm[:, d, :] -= wdet[k] * np.outer(dphix[k] @ Fq[:, d], phi[k])
     for l in range(L):
@@ -165,17 +175,22 @@ def element_trace_values(uhat, e2f):
     return uhat[e2f]
 
 
-def element_blocks(g, m, u, uhat, e2f):
+def element_blocks(g, m, u, uhat, e2f, tt=None):
     """Every element's condensation inputs at the state (u, uhat) with consistent q:
-    Minv, Bd, Cd, D, E, F, G, H, J, ru = -R_u, rt = -R_t, and q itself."""
+    Minv, Bd, Cd, D, E, F, G, H, J, ru = -R_u, rt = -R_t, and q itself. tt = dict(c, u_prev (ne, P),
+    r_extra (ne, P) or None) adds an implicit stage's time term."""
     ne, P = u.shape
     uh_el = element_trace_values(uhat, e2f)
     out = {k: [] for k in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "q")}
     for e in range(ne):
         Mm, Bd, Cd = mass_and_q_operators(g, e)
         q = consistent_q(g, e, u[e], uh_el[e])
-        _, Ru, Rt = residual(g, m, e, q, u[e], uh_el[e])
-        Dm, Em, Fm, Gm, Hm, Jm = jacobian(g, m, e, q, u[e], uh_el[e])
+        tte = None
+        if tt is not None:
+            rx = tt.get("r_extra")
+            tte = (tt["c"], tt["u_prev"][e], None if rx is None else rx[e])
+        _, Ru, Rt = residual(g, m, e, q, u[e], uh_el[e], tte)
+        Dm, Em, Fm, Gm, Hm, Jm = jacobian(g, m, e, q, u[e], uh_el[e], 0.0 if tt is None else tt["c"])
         for k, v in (("Minv", np.linalg.inv(Mm)), ("Bd", Bd), ("Cd", Cd), ("D", Dm), ("E", Em), ("F", Fm),
                      ("G", Gm), ("H", Hm), ("J", Jm), ("ru", -Ru), ("rt", -Rt.ravel()), ("q", q)):
             out[k].append(v)

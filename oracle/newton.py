@@ -16,8 +16,8 @@ import scipy.sparse.linalg as spla
 from . import assemble, condense, elements
 
 
-def residual_norm(g, m, u, uhat, e2f, f2e, dims):
-    blk = elements.element_blocks(g, m, u, uhat, e2f)
+def residual_norm(g, m, u, uhat, e2f, f2e, dims, tt=None):
+    blk = elements.element_blocks(g, m, u, uhat, e2f, tt)
     return _norm_from_blocks(blk, e2f, f2e, dims), blk
 
 
@@ -28,11 +28,13 @@ def _norm_from_blocks(blk, e2f, f2e, dims):
     return float(np.sqrt(np.sum(blk["ru"] ** 2) + np.sum(r_face ** 2)))
 
 
-def damped_newton(g, m, u0, uhat0, e2f, f2e, dims, rtol=1e-10, atol=1e-14, max_steps=20, min_alpha=2.0 ** -10):
-    """Returns (u, uhat, history); history[k] = dict(norm, alpha) for step k (norm before it)."""
+def damped_newton(g, m, u0, uhat0, e2f, f2e, dims, rtol=1e-10, atol=1e-14, max_steps=20, min_alpha=2.0 ** -10,
+                  tt=None):
+    """Returns (u, uhat, history); history[k] = dict(norm, alpha) for step k (norm before it).
+    tt: the time term of an implicit stage (elements.element_blocks)."""
     u = u0.copy()
     uhat = uhat0.copy()
-    nrm, blk = residual_norm(g, m, u, uhat, e2f, f2e, dims)
+    nrm, blk = residual_norm(g, m, u, uhat, e2f, f2e, dims, tt)
     n0 = nrm
     hist = []
     for _ in range(max_steps):
@@ -47,7 +49,7 @@ def damped_newton(g, m, u0, uhat0, e2f, f2e, dims, rtol=1e-10, atol=1e-14, max_s
         while True:
             ut = u + alpha * du
             uht = uhat + alpha * duhat
-            nt_, blkt = residual_norm(g, m, ut, uht, e2f, f2e, dims)
+            nt_, blkt = residual_norm(g, m, ut, uht, e2f, f2e, dims, tt)
             if nt_ < nrm or alpha <= min_alpha:
                 break
             alpha *= 0.5

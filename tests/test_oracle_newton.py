@@ -6,11 +6,14 @@
 * the consistent q makes R_q vanish;
 * at the input generator's linearisation state the blocks equal the generator's own
   (an independent einsum implementation of the same weak form);
-* Newton on a linear problem converges in one full step, on Burgers quadratically.
+* Newton on a linear problem converges in one full step, on Burgers quadratically;
+* the DIRK tableaus meet their order conditions, the stage time term's derivative is c M, and
+  DIRK steps of the heat equation converge in time at orders 1, 2, 3.
 """
 import numpy as np
 import pytest
 
+import oracle.dirk as ODK
 import oracle.elements as OE
 import oracle.newton as ON
 from workloads import mesh as Mh
@@ -128,3 +131,63 @@ def test_newton_burgers_converges_quadratically():
     # the converged state solves the discrete equations: every element residual vanishes
     blk = OE.element_blocks(inp, _model(inp), u, uh, pb.mesh.e2f)
     assert np.abs(blk["ru"]).max() <= 1e-11 * n[0]
+
+
+# ---- implicit stages and DIRK time stepping (Section 2.2) ---------------------------------
+@pytest.mark.parametrize("scheme,order", [("be", 1), ("dirk22", 2), ("dirk33", 3)])
+def test_dirk_tableau_order_conditions(scheme, order):
+    A, b, c = ODK.tableau(scheme)
+    assert np.allclose(np.tril(A), A) and np.allclose(np.diag(A), A[0, 0])
+    assert np.allclose(b, A[-1]) and abs(c[-1] - 1.0) < 1e-15          # stiffly accurate
+    assert abs(b.sum() - 1.0) < 1e-14
+    if order >= 2:
+        assert abs(b @ c - 0.5) < 1e-14
+    if order >= 3:
+        assert abs(b @ c ** 2 - 1.0 / 3.0) < 1e-14
+        assert abs(b @ (A @ c) - 1.0 / 6.0) < 1e-14
+
+
+def test_time_term_derivatives_equal_central_differences():
+    pb = CASES["burgers_tri_p3"]()
+    inp = _np(pb.newton_inputs())
+    m = _model(inp)
+    rng = np.random.default_rng(9)
+    d = pb.dims()
+    P, PF, L, D = d["npe"], d["npf"], d["nlfe"], d["dim"]
+    e, c = 2, 3.7
+    q, u, uh = rng.standard_normal((D, P)), rng.standard_normal(P), rng.standard_normal((L, PF))
+    un, rx = rng.standard_normal(P), rng.standard_normal(P)
+    _, Em, *_ = OE.jacobian(inp, m, e, q, u, uh, c)
+    eps = 1e-3
+    cols = []
+    for k in range(P):
+        up, um = u.copy(), u.copy()
+        up[k] += eps
+        um[k] -= eps
+        cols.append((OE.residual(inp, m, e, q, up, uh, (c, un, rx))[1] -
+                     OE.residual(inp, m, e, q, um, uh, (c, un, rx))[1]) / (2 * eps))
+    assert np.abs(np.column_stack(cols) - Em).max() < 1e-9 * np.abs(Em).max()
+    # the time term itself: c M (u - u_n) + r_x
+    Mm, _, _ = OE.mass_and_q_operators(inp, e)
+    r1 = OE.residual(inp, m, e, q, u, uh, (c, un, rx))[1] - OE.residual(inp, m, e, q, u, uh)[1]
+    assert np.abs(r1 - (c * Mm @ (u - un) + rx)).max() < 1e-12 * np.abs(r1).max()
+
+
+def test_dirk_temporal_convergence_orders():
+    """Heat equation (Poisson flux, zero data) from sin(pi x) sin(pi y): the error at T against a
+    fine DIRK(3,3) reference falls by 2^p per halving of dt (p = 1, 2, 3)."""
+    from helpers import nodal_points
+    pb = HDGProblem(Mh.structured_tris(2, 0.0, 7), 2, Ph.Poisson(2, 1.0))
+    inp = _np(pb.newton_inputs())
+    m = _model(inp)
+    d = pb.dims()
+    xn = nodal_points(pb)
+    u0 = np.sin(np.pi * xn[..., 0]) * np.sin(np.pi * xn[..., 1])
+    uh0 = np.zeros_like(inp["uhat0"])
+    T = 0.1
+    args = (inp, m, u0, uh0, pb.mesh.e2f, pb.mesh.f2e, d)
+    ref, _, _ = ODK.dirk_steps(*args, T / 64, 64, "dirk33")
+    for scheme, p, ns in (("be", 1, (4, 8, 16)), ("dirk22", 2, (4, 8, 16)), ("dirk33", 3, (4, 8))):
+        err = [np.abs(ODK.dirk_steps(*args, T / n, n, scheme)[0] - ref).max() for n in ns]
+        rates = [np.log2(err[k] / err[k + 1]) for k in range(len(err) - 1)]
+        assert all(abs(r - p) < 0.35 for r in rates), (scheme, err, rates)
