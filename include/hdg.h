@@ -304,6 +304,16 @@ typedef struct {
     double nu, tau, beta[3], gamma[3];
 } hdg_conv_diff;
 
+/* Time term of one implicit stage (Section 2.2: a DIRK stage, or a backward-Euler step):
+ * the u-rows become R_u + c (u - u_n, phi_i) + r_extra[i] and E gains c M, with
+ * c = 1/(a_ii dt), u_n [ne][npe] the previous step's state (device) and r_extra [ne][npe]
+ * (device, may be NULL) the earlier stages' known contribution. NULL or c = 0: steady. */
+typedef struct {
+    double c;
+    const double* u_prev;
+    const double* r_extra;
+} hdg_time_term;
+
 /* Device outputs in the layouts hdg_condense reads, plus q [ne][dim][npe] (may be NULL). */
 typedef struct {
     double *Minv, *Bd, *Cd, *D, *E, *F, *G, *H, *J, *ru, *rt, *q;
@@ -313,7 +323,8 @@ typedef struct {
  *   canonical order; element e's face l is uhat[e2f[e][l]]), with q derived from the
  *   q-equation (M q_d + B_d u + C_d uhat = 0, eq. w16, so r_q = 0), writes ru = -R_u,
  *   rt = -R_t and, unless residual_only, Minv, Bd, Cd, D, E, F, G, H, J (the derivatives of
- *   R_u and R_t with respect to q, u, uhat). Outputs not written may be NULL. One workgroup
+ *   R_u and R_t with respect to q, u, uhat). time_term (may be NULL) adds an implicit stage's
+ *   mass term (HDG_ERR_ARG if c != 0 without u_prev). Outputs not written may be NULL. One workgroup
  *   per element with its data in LDS: HDG_ERR_SHAPE if the element needs more than 64 KiB;
  *   HDG_ERR_ARG for ncomp != 1. HDG_ERR_SINGULAR names the first element whose mass matrix
  *   has a non-positive pivot (synchronises to read it).
@@ -321,8 +332,9 @@ typedef struct {
  *   written above, R_f being face f's trace rows summed over its elements (perm = NULL
  *   assembly); result in *norm_h. Uses a context workspace; synchronises. */
 hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* geom,
-                              const hdg_conv_diff* model, const int32_t* e2f, const double* u,
-                              const double* uhat, int32_t residual_only, const hdg_elem_arrays* out);
+                              const hdg_conv_diff* model, const hdg_time_term* time_term,
+                              const int32_t* e2f, const double* u, const double* uhat,
+                              int32_t residual_only, const hdg_elem_arrays* out);
 hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
                              const double* rt, double* norm_h);
 

@@ -277,8 +277,8 @@ hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double*
 }
 
 hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* g, const hdg_conv_diff* m,
-                              const int32_t* e2f, const double* u, const double* uhat, int32_t residual_only,
-                              const hdg_elem_arrays* out) {
+                              const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
+                              int32_t residual_only, const hdg_elem_arrays* out) {
     if (!ctx) return HDG_ERR_ARG;
     GUARD_BEGIN
     hdg_status st = check_dims(ctx, dims, false, false);
@@ -293,6 +293,10 @@ hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_
     if (!residual_only && (!out->Minv || !out->Bd || !out->Cd || !out->D || !out->E || !out->F || !out->G ||
                            !out->H || !out->J))
         return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: NULL matrix output (residual_only = 0)");
+    if (tt && !std::isfinite(tt->c))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: time-term factor c is not finite");
+    if (tt && tt->c != 0.0 && !tt->u_prev)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: time term with c != 0 needs u_prev");
     if (element_blocks_lds_bytes(dims, g->nqv, g->nqf) > 65536)
         return set_err(ctx, HDG_ERR_SHAPE, "hdg_element_blocks: element data exceed 64 KiB of LDS");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
@@ -300,7 +304,7 @@ hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_
     if (!status) return st;
     const int big = 0x7fffffff;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-    if ((st = element_blocks_run(ctx, dims, g, m, e2f, u, uhat, residual_only, out, status)) != HDG_OK) return st;
+    if ((st = element_blocks_run(ctx, dims, g, m, tt, e2f, u, uhat, residual_only, out, status)) != HDG_OK) return st;
     int bad = big;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));

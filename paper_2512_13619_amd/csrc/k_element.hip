@@ -8,8 +8,9 @@
 // volume or face points. q is derived from the q-equation (M q_d + B_d u + C_d uhat = 0),
 // so r_q = 0.
 //
-// Residual rows (steady, the sign of the trace rows as everywhere in the library):
-//   R_u[i]   = -(F, grad phi_i) + <fhat, phi_i> - (s, phi_i)
+// Residual rows (the sign of the trace rows as everywhere in the library), with the time
+// term of an implicit stage (c = 1/(a_ii dt), u_n, r_x; c = 0 and no r_x: steady):
+//   R_u[i]   = -(F, grad phi_i) + <fhat, phi_i> - (s, phi_i) + c (u - u_n, phi_i) + r_x[i]
 //   R_t[l,j] = -<fhat, psi_j>_l (interior face), <uhat - u_D, psi_j>_l (Dirichlet face)
 // and ru = -R_u, rt = -R_t; D..J are their derivatives with respect to q, u and uhat.
 #include "hdg_internal.hpp"
@@ -26,13 +27,17 @@ struct ElemArgs {
     const double* u;       // [ne][P]
     const double* uhat;    // [nf][PF]
     hdg_elem_arrays out;
+    double c;              // implicit-stage mass factor 1/(a_ii dt); 0: steady
+    const double* u_prev;  // [ne][P], read when c != 0
+    const double* r_extra; // [ne][P] or null
     int* bad;              // first element with a non-positive mass pivot
     int ne, P, PF, L, D, residual_only;
 };
 
 // LDS offsets (in doubles) of the element's staged arrays
 struct ElemLds {
-    int phi, dphi, wdet, phif, psi, ndA, dA, src, uD, u, uh, M, t, q, uq, qq, uf, qf, uhf, wF, wFu, fhat, Z, total;
+    int phi, dphi, wdet, phif, psi, ndA, dA, src, uD, u, uh, up, M, t, q, uq, duq, qq, uf, qf, uhf, wF, wFu, fhat, Z,
+        total;
 };
 
 __host__ __device__ inline ElemLds elem_lds(int P, int PF, int L, int D, int Qv, int Qf) {
@@ -49,10 +54,12 @@ __host__ __device__ inline ElemLds elem_lds(int P, int PF, int L, int D, int Qv,
     o.uD = p;   p += L * Qf;
     o.u = p;    p += P;
     o.uh = p;   p += L * PF;
+    o.up = p;   p += P;
     o.M = p;    p += P * P;
     o.t = p;    p += D * P;
     o.q = p;    p += D * P;
     o.uq = p;   p += Qv;
+    o.duq = p;  p += Qv;
     o.qq = p;   p += Qv * D;
     o.uf = p;   p += L * Qf;
     o.qf = p;   p += L * Qf * D;
@@ -74,6 +81,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
     const ElemLds o = elem_lds(P, PF, L, D, Qv, Qf);
     double *phi = sm + o.phi, *dphi = sm + o.dphi, *wdet = sm + o.wdet, *phif = sm + o.phif, *psi = sm + o.psi;
     double *ndA = sm + o.ndA, *dA = sm + o.dA, *src = sm + o.src, *uD = sm + o.uD, *u = sm + o.u, *uh = sm + o.uh;
+    double *up = sm + o.up, *duq = sm + o.duq;
     double *Mm = sm + o.M, *t = sm + o.t, *q = sm + o.q, *uq = sm + o.uq, *qq = sm + o.qq, *uf = sm + o.uf;
     double *qf = sm + o.qf, *uhf = sm + o.uhf, *wF = sm + o.wF, *wFu = sm + o.wFu, *fhat = sm + o.fhat, *Z = sm + o.Z;
     const size_t E = (size_t)e;
@@ -92,7 +100,11 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
         dA[k] = a.g.dA[E * L * Qf + k];
         uD[k] = a.g.uD[E * L * Qf + k];
     }
-    for (int k = tid; k < P; k += EBS) u[k] = a.u[E * P + k];
+    const double cdt = a.c;
+    for (int k = tid; k < P; k += EBS) {
+        u[k] = a.u[E * P + k];
+        up[k] = cdt != 0.0 ? a.u_prev[E * P + k] : 0.0;
+    }
     for (int k = tid; k < nt; k += EBS) {
         const int l = k / PF, j = k - l * PF;
         uh[k] = a.uhat[(size_t)a.e2f[E * L + l] * PF + j];
@@ -143,9 +155,13 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
 
     // 3. u and uhat at the quadrature points
     for (int k = tid; k < Qv; k += EBS) {
-        double s = 0.0;
-        for (int i = 0; i < P; ++i) s += phi[k * P + i] * u[i];
+        double s = 0.0, sp = 0.0;
+        for (int i = 0; i < P; ++i) {
+            s += phi[k * P + i] * u[i];
+            sp += phi[k * P + i] * up[i];
+        }
         uq[k] = s;
+        duq[k] = s - sp;     // u - u_n at the point (time term)
     }
     for (int k = tid; k < L * Qf; k += EBS) {
         const int l = k / Qf, x = k - l * Qf;
@@ -215,9 +231,10 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
         for (int x = 0; x < Qv; ++x) {
             double g = 0.0;
             for (int d = 0; d < D; ++d) g += wF[x * D + d] * dphi[(x * P + i) * D + d];
-            s += g + wdet[x] * src[x] * phi[x * P + i];
+            s += g + wdet[x] * (src[x] - cdt * duq[x]) * phi[x * P + i];
         }
         for (int lx = 0; lx < L * Qf; ++lx) s -= fhat[lx] * phif[lx * P + i];
+        if (a.r_extra) s -= a.r_extra[E * P + i];
         a.out.ru[E * P + i] = s;
     }
     for (int k = tid; k < nt; k += EBS) {
@@ -238,8 +255,9 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
     for (int k = tid; k < P * P; k += EBS) a.out.Minv[E * P * P + k] = Mm[k];
     for (int it = tid; it < P * nJT; it += EBS) {        // Bd, D, E
         const int i = it / nJT, j0 = (it - i * nJT) * TJ;
-        double bd[3][TJ] = {}, sf[3][TJ] = {}, ev[TJ] = {}, ef[TJ] = {};
+        double bd[3][TJ] = {}, sf[3][TJ] = {}, ev[TJ] = {}, ef[TJ] = {}, mm[TJ] = {};
         for (int x = 0; x < Qv; ++x) {
+            const double wp = wdet[x] * phi[x * P + i];
             double wd[3], g = 0.0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -253,6 +271,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) bd[d][jj] += wd[d] * pj;
                 ev[jj] -= g * pj;
+                mm[jj] += wp * pj;
             }
         }
         for (int lx = 0; lx < L * Qf; ++lx) {
@@ -277,7 +296,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
                 a.out.Bd[E * D * P * P + (size_t)(d * P + i) * P + j] = bd[d][jj];
                 a.out.D[E * P * D * P + (size_t)i * D * P + d * P + j] = nu * (bd[d][jj] - sf[d][jj]);
             }
-            a.out.E[E * P * P + (size_t)i * P + j] = ev[jj] + tau * ef[jj];
+            a.out.E[E * P * P + (size_t)i * P + j] = ev[jj] + tau * ef[jj] + cdt * mm[jj];
         }
     }
     for (int it = tid; it < P * nt; it += EBS) {          // Cd, F, G, H for one (i, l, j)
@@ -321,8 +340,8 @@ size_t element_blocks_lds_bytes(const hdg_dims* d, int nqv, int nqf) {
 }
 
 hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geom* g, const hdg_conv_diff* m,
-                              const int32_t* e2f, const double* u, const double* uhat, int residual_only,
-                              const hdg_elem_arrays* out, int* bad) {
+                              const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
+                              int residual_only, const hdg_elem_arrays* out, int* bad) {
     if (d->ne == 0) return HDG_OK;
     ElemArgs a;
     a.g = *g;
@@ -331,6 +350,9 @@ hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geo
     a.u = u;
     a.uhat = uhat;
     a.out = *out;
+    a.c = tt ? tt->c : 0.0;
+    a.u_prev = tt ? tt->u_prev : nullptr;
+    a.r_extra = tt ? tt->r_extra : nullptr;
     a.bad = bad;
     a.ne = d->ne;
     a.P = d->npe;

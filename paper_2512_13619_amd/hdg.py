@@ -55,6 +55,10 @@ class ConvDiff(ctypes.Structure):
                 ("gamma", ctypes.c_double * 3)]
 
 
+class TimeTerm(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("u_prev", ctypes.c_void_p), ("r_extra", ctypes.c_void_p)]
+
+
 class ElemArrays(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "q")]
 
@@ -110,8 +114,8 @@ def load():
                                     ctypes.POINTER(SolveStats)]
     lib.hdg_recover_local.argtypes = [vp, pd, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_newton_update.argtypes = [vp, i64, dbl, vp, vp]
-    lib.hdg_element_blocks.argtypes = [vp, pd, ctypes.POINTER(ElemGeom), ctypes.POINTER(ConvDiff), vp, vp, vp, i32,
-                                       ctypes.POINTER(ElemArrays)]
+    lib.hdg_element_blocks.argtypes = [vp, pd, ctypes.POINTER(ElemGeom), ctypes.POINTER(ConvDiff),
+                                       ctypes.POINTER(TimeTerm), vp, vp, vp, i32, ctypes.POINTER(ElemArrays)]
     lib.hdg_residual_norm.argtypes = [vp, pd, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.hdg_matvec.argtypes = [vp, pd, vp, vp, vp, i32, vp, vp]
     lib.hdg_bj_setup.argtypes = [vp, pd, vp, vp, vp]
@@ -359,10 +363,11 @@ class Context:
         return self._check(self.lib.hdg_newton_update(self.h, n, float(alpha), _ptr(delta, torch.float64, n, "delta"),
                                                       _ptr(state, torch.float64, n, "state")))
 
-    def element_blocks(self, dims, geom, model, e2f, u, uhat, out, residual_only=False):
+    def element_blocks(self, dims, geom, model, e2f, u, uhat, out, residual_only=False, time_term=None):
         """Element residuals (and Jacobian blocks unless residual_only) at the state (u, uhat):
         geom holds the quadrature geometry (wdet, dphix, phi, phif, psi, ndA, dA, src, uD, bnd,
-        nqv, nqf), model the coefficients (nu, tau, beta, gamma), out the device outputs."""
+        nqv, nqf), model the coefficients (nu, tau, beta, gamma), out the device outputs;
+        time_term = dict(c, u_prev, r_extra=None) for an implicit stage."""
         import torch
         d = make_dims(dims)
         ne, nf, M, D, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe"))
@@ -380,8 +385,13 @@ class Context:
         osz = dict(Minv=P * P, Bd=D * P * P, Cd=D * P * nt, D=nu * nq, E=nu * nu, F=nu * nt, G=nt * nq,
                    H=nt * nu, J=nt * nt, ru=nu, rt=nt, q=nq)
         o = ElemArrays(*[_ptr(out.get(k), f64, ne * osz[k], k, allow_none=True) for k in osz])
+        tt = None
+        if time_term is not None:
+            tt = ctypes.byref(TimeTerm(float(time_term["c"]), _ptr(time_term.get("u_prev"), f64, ne * P, "u_prev",
+                                                                     allow_none=True),
+                                       _ptr(time_term.get("r_extra"), f64, ne * P, "r_extra", allow_none=True)))
         return self._check(self.lib.hdg_element_blocks(
-            self.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(m), _ptr(e2f, torch.int32, ne * L, "e2f"),
+            self.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(m), tt, _ptr(e2f, torch.int32, ne * L, "e2f"),
             _ptr(u, f64, ne * P, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"), int(bool(residual_only)),
             ctypes.byref(o)))
 

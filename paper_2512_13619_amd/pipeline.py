@@ -86,19 +86,21 @@ class Pipeline:
         return dict(Minv=z(P * P), Bd=z(D * P * P), Cd=z(D * P * nt), D=z(nu * nq), E=z(nu * nu), F=z(nu * nt),
                     G=z(nt * nq), H=z(nt * nu), J=z(nt * nt), ru=z(nu), rt=z(nt), q=z(nq))
 
-    def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, **solve_kw):
+    def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, time_term=None,
+               **solve_kw):
         """Damped Newton iteration (Section 4.3) on a scalar convection-diffusion model.
 
         u [ne*npe] and uhat [nf*npf] (device, float64) hold the state and are updated in place.
         Each step: element blocks at the state, condensation, assembly, preconditioned GMRES,
         recovery, then alpha = 1, 1/2, 1/4, ... until the residual norm decreases (or alpha
         reaches min_alpha); stops once the norm is at most max(tol * initial norm, atol).
+        time_term: an implicit stage's mass term (hdg_element_blocks).
         solve_kw go to the linear solves (restart, rtol, prec, ...). Returns one
         dict(norm, alpha, iters) per step and a last entry with the final norm. Sequencing
         only: evaluation, solve and updates run in libhdg.so."""
         d = self.dims
         blk = self.element_arrays()
-        self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk)
+        self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term)
         nrm = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
         n0 = nrm
         hist = []
@@ -118,7 +120,7 @@ class Pipeline:
                 self.ctx.newton_update(alpha - applied, self.x, uhat)
                 applied = alpha
                 # the trial state's blocks: kept as the next step's linearisation if accepted
-                self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk)
+                self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term)
                 trial = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
                 if trial < nrm or alpha <= min_alpha:
                     break
@@ -127,3 +129,49 @@ class Pipeline:
             nrm = trial
         hist.append(dict(norm=nrm, alpha=0.0, iters=0))
         return hist
+
+    def dirk(self, geom, model, u, uhat, dt, nsteps, scheme="dirk22", **newton_kw):
+        """nsteps steps of a stiffly accurate DIRK scheme (Section 2.2) of size dt; u, uhat are
+        advanced in place. Stage i solves, by Newton, the steady system plus the time term
+        c M (U_i - u_n) + sum_{j<i} (a_ij/a) R_s(U_j) with c = 1/(a dt), R_s the steady u-rows;
+        u_{n+1} = U_s. Returns the Newton histories of every stage."""
+        A = dirk_tableau(scheme)
+        s, a = len(A), A[0][0]
+        ne, P = self.dims["ne"], self.dims["npe"]
+        z = lambda: torch.zeros(ne * P, dtype=torch.float64, device=self.device)
+        un = z()
+        hists = []
+        res = {"ru": z(), "rt": torch.zeros(ne * self.nt, dtype=torch.float64, device=self.device)}
+        for _ in range(nsteps):
+            un.zero_()
+            self.ctx.newton_update(1.0, u, un)         # u_n
+            minus_rs = []                                 # -R_s(U_j) of the finished stages
+            for i in range(s):
+                rx = None
+                if i > 0:
+                    rx = z()
+                    for j in range(i):
+                        self.ctx.newton_update(-A[i][j] / a, minus_rs[j], rx)
+                tt = dict(c=1.0 / (a * dt), u_prev=un, r_extra=rx)
+                hists.append(self.newton(geom, model, u, uhat, time_term=tt, **newton_kw))
+                if i < s - 1:
+                    self.ctx.element_blocks(self.dims, geom, model, self.e2f, u, uhat, res, residual_only=True)
+                    minus_rs.append(res["ru"].clone())
+        return hists
+
+
+def dirk_tableau(scheme):
+    """Lower-triangular Butcher matrix of a stiffly accurate DIRK scheme (b = its last row):
+    backward Euler; Alexander's two-stage scheme with a = 1 - 1/sqrt(2); Alexander's three-stage
+    scheme with a = 0.43586652150845899942 (the root in (1/6, 1/2) of a^3 - 3a^2 + 3a/2 - 1/6)."""
+    if scheme == "be":
+        return [[1.0]]
+    if scheme == "dirk22":
+        a = 1.0 - 0.5 ** 0.5
+        return [[a, 0.0], [1.0 - a, a]]
+    if scheme == "dirk33":
+        a = 0.43586652150845899942
+        b1 = -(6.0 * a * a - 16.0 * a + 1.0) / 4.0
+        b2 = (6.0 * a * a - 20.0 * a + 5.0) / 4.0
+        return [[a, 0.0, 0.0], [(1.0 + a) / 2.0 - a, a, 0.0], [b1, b2, a]]
+    raise ValueError(f"unknown DIRK scheme {scheme!r}")

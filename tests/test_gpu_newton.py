@@ -148,3 +148,52 @@ def test_element_blocks_rejects_bad_input(ctx):
     per_elem = ("wdet", "dphix", "phif", "ndA", "dA", "src", "uD", "bnd")
     g0 = {k: (v[:0] if k in per_elem else v) for k, v in g.items()}
     ctx.element_blocks(dict(d, ne=0), g0, _model(inp), pl.e2f[:0], u[:0], uh, {k: v[:0] for k, v in out.items()})
+
+
+# ---- implicit stages and DIRK time stepping (Section 2.2) ----------------------------------
+def test_element_blocks_time_term_matches_oracle(ctx):
+    from paper_2512_13619_amd import hdg
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case("burgers_quad_p2")
+    d = pb.dims()
+    u, uh = _random_state(pb, inp_np, 4)
+    rng = np.random.default_rng(6)
+    un = rng.standard_normal(u.shape)
+    rx = rng.standard_normal(u.shape)
+    c = 7.5
+    ref = OE.element_blocks(inp_np, _model(inp_np), u, uh, pb.mesh.e2f, dict(c=c, u_prev=un, r_extra=rx))
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    out = pl.element_arrays()
+    tt = dict(c=c, u_prev=torch.as_tensor(un).cuda().flatten(), r_extra=torch.as_tensor(rx).cuda().flatten())
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, torch.as_tensor(u).cuda().flatten(),
+                       torch.as_tensor(uh).cuda().flatten(), out, time_term=tt)
+    torch.cuda.synchronize()
+    for k in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "q"):
+        err = relerr(out[k].cpu().numpy().reshape(ref[k].shape), ref[k])
+        assert err < 1e-12, (k, err)
+    with pytest.raises(hdg.HdgError):
+        ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, torch.as_tensor(u).cuda().flatten(),
+                           torch.as_tensor(uh).cuda().flatten(), out, time_term=dict(c=1.0))
+
+
+@pytest.mark.parametrize("name,scheme,dt,nsteps", [("burgers_quad_p2", "dirk22", 0.05, 2),
+                                                   ("burgers_tri_p3", "dirk33", 0.1, 1),
+                                                   ("poisson_tri_p2", "be", 0.02, 2)])
+def test_dirk_steps_match_oracle(ctx, name, scheme, dt, nsteps):
+    import oracle.dirk as ODK
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case(name)
+    d = pb.dims()
+    say("dirk", name, scheme, dt, nsteps)
+    u_ref, uh_ref, hists_ref = ODK.dirk_steps(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f,
+                                              pb.mesh.f2e, d, dt, nsteps, scheme, newton_rtol=1e-12)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    u = inp["u0"].cuda().flatten().clone()
+    uh = inp["uhat0"].cuda().flatten().clone()
+    hists = pl.dirk(_geom_dev(inp), _model(inp), u, uh, dt, nsteps, scheme, tol=1e-12, restart=50, max_iters=2000,
+                    rtol=1e-13, prec="bj")
+    assert len(hists) == len(hists_ref)
+    for h, hr in zip(hists, hists_ref):
+        assert [x["alpha"] for x in h] == [x["alpha"] for x in hr]
+    assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-9
+    assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-9
