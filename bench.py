@@ -218,7 +218,8 @@ def newton_bench(args):
     """Damped Newton on 2D viscous Burgers (nu = 0.01, smooth forcing) on n x n jittered quads of
     degree p: the element-block kernel timed alone, then the whole Newton loop (element blocks,
     condensation, assembly, GMRES(50) with block-Jacobi folded into the blocks and delayed CGS2
-    to 1e-10, recovery, step halving) to a residual reduction of 1e-10."""
+    to 1e-10, recovery, step halving) to a residual reduction of 1e-10; then two DIRK(2,2) steps of
+    dt = 0.05 from the same initial state, each stage solved the same way."""
     import numpy as np
     import torch
     from paper_2512_13619_amd import hdg
@@ -267,9 +268,21 @@ def newton_bench(args):
         torch.cuda.synchronize()
         runs["graph" if graph else "direct"] = time.perf_counter() - ts
     t_newton = min(runs.values())
+    # two DIRK(2,2) steps of dt = 0.05 from the initial state (a few Newton steps per stage)
+    u.copy_(inp["u0"].flatten())
+    uh.copy_(inp["uhat0"].flatten())
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    dh = pl.dirk(geom, model, u, uh, 0.05, 2, "dirk22", tol=1e-10, restart=50, max_iters=20000, rtol=1e-10,
+                 prec="bj", orth="dcgs2", fold_prec=True)
+    torch.cuda.synchronize()
+    t_dirk = time.perf_counter() - ts
+    dirk = dict(scheme="dirk22", dt=0.05, steps=2, s=t_dirk,
+                stages=[dict(newton_steps=len(h) - 1, gmres_iters=sum(x["iters"] for x in h),
+                             alphas=[x["alpha"] for x in h[:-1]]) for h in dh])
     print(json.dumps({"profile": "newton", "workload": f"2D viscous Burgers nu=0.01, {n}x{n} quads jitter 0.05, "
                       f"p={p}", "dims": d, "nqv": geom["nqv"], "nqf": geom["nqf"], "element_kernel": rates,
-                      "newton_s": t_newton, "newton_s_by_launch": runs, "steps": len(hist) - 1,
+                      "newton_s": t_newton, "newton_s_by_launch": runs, "dirk": dirk, "steps": len(hist) - 1,
                       "history": [dict(norm=h["norm"], alpha=h["alpha"], iters=h["iters"]) for h in hist]}),
           flush=True)
 

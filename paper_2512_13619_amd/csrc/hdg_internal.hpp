@@ -125,10 +125,20 @@ hdg_status face_op(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1
                    const FaceEpilogue& epi, const int* skip_flag);
 
 // ---------------------------------------------------------------------------
-// Vector kernels (Krylov). Reductions use fixed chunks of 2048 entries per block:
-// nblk must be krylov_nblk(n). `skip` (device flag, may be null): the kernel returns
-// at once when *skip != 0; `J_dev` (may be null) overrides J with a device value.
-static inline int krylov_nblk(size_t n) { return (int)((n + 2047) / 2048 > 0 ? (n + 2047) / 2048 : 1); }
+// Vector kernels (Krylov). Reductions give each block a chunk of krylov_chunk(n) entries:
+// 2048, halved (down to 256) while that leaves fewer than 512 blocks, so that short vectors
+// still spread over the chip; nblk must be krylov_nblk(n). `skip` (device flag, may be null):
+// the kernel returns at once when *skip != 0; `J_dev` (may be null) overrides J with a
+// device value.
+__host__ __device__ static inline int krylov_chunk(size_t n) {
+    int c = 2048;
+    while (c > 256 && (n + c - 1) / c < 512) c >>= 1;
+    return c;
+}
+static inline int krylov_nblk(size_t n) {
+    const size_t c = (size_t)krylov_chunk(n);
+    return (int)((n + c - 1) / c > 0 ? (n + c - 1) / c : 1);
+}
 hdg_status vec_multidot(hdg_ctx ctx, const double* V, size_t ldv, int J, const double* w, size_t n,
                         double* part, int nblk, const int* skip);
 hdg_status vec_reduce(hdg_ctx ctx, const double* part, int J, int nblk, double* out, double* add_to,

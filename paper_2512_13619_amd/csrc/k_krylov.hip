@@ -24,7 +24,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // part[i*nblk + b] = sum_{k in chunk b} V[i][k] w[k],  i < J.
 // The block's slice of w is staged in LDS; each wave owns a subset of the vectors and
 // streams them with U loads in flight per lane, so one wave writes each partial.
-constexpr int CHUNK = 2048;        // entries per block (the partial layout depends on it)
+constexpr int CHUNK = 2048;        // largest chunk (krylov_chunk): the LDS staging size
 constexpr int COEF_BS = 1024;      // threads of the delayed-CGS2 coefficient kernel
 
 template <int U>
@@ -33,8 +33,9 @@ __global__ __launch_bounds__(BS) void k_multidot(const double* __restrict__ V, s
                                                  double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
     __shared__ double ws[CHUNK];
-    const size_t k0 = (size_t)blockIdx.x * CHUNK;
-    const int len = (int)(k0 + CHUNK < n ? CHUNK : n - k0);
+    const int chunk = krylov_chunk(n);
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const int len = (int)(k0 + chunk < n ? chunk : n - k0);
     for (int k = threadIdx.x; k < len; k += BS) ws[k] = w[k0 + k];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -96,8 +97,9 @@ __global__ __launch_bounds__(BS) void k_sumsq(const double* __restrict__ w, size
                                               const int* skip) {
     if (skip && *skip) return;
     __shared__ double red[BS / 64];
-    const size_t k0 = (size_t)blockIdx.x * CHUNK;
-    const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
+    const int chunk = krylov_chunk(n);
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
     double acc = 0.0;
     for (size_t k = k0 + threadIdx.x; k < k1; k += BS) acc += w[k] * w[k];
     acc = wave_sum(acc);
@@ -241,8 +243,9 @@ __global__ __launch_bounds__(BS) void k_axpy_dot(const double* __restrict__ V, s
     __shared__ double red[BS / 64][JMAX];
     for (int i = threadIdx.x; i < JMAX; i += BS) hs[i] = i < J ? h1[i] : 0.0;
     __syncthreads();
-    const size_t k0 = (size_t)blockIdx.x * CHUNK;
-    const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
+    const int chunk = krylov_chunk(n);
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double acc = 0.0;
     for (size_t kb = k0 + (size_t)wave * 64; kb < k1; kb += BS) {
@@ -297,8 +300,9 @@ __global__ __launch_bounds__(BS) void k_axpy_sumsq(const double* __restrict__ V,
                                                    double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
     __shared__ double red[BS / 64];
-    const size_t k0 = (size_t)blockIdx.x * CHUNK;
-    const size_t k1 = k0 + CHUNK < n ? k0 + CHUNK : n;
+    const int chunk = krylov_chunk(n);
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const size_t k1 = k0 + chunk < n ? k0 + chunk : n;
     double acc = 0.0;
     for (size_t k = k0 + threadIdx.x; k < k1; k += BS) {
         double s = 0.0;
@@ -335,8 +339,9 @@ __global__ __launch_bounds__(BS) void k_multidot2(const double* __restrict__ V, 
                                                   size_t n, double* __restrict__ part, int nblk, const int* skip) {
     if (skip && *skip) return;
     __shared__ double xs[NRHS][CHUNK];
-    const size_t k0 = (size_t)blockIdx.x * CHUNK;
-    const int len = (int)(k0 + CHUNK < n ? CHUNK : n - k0);
+    const int chunk = krylov_chunk(n);
+    const size_t k0 = (size_t)blockIdx.x * chunk;
+    const int len = (int)(k0 + chunk < n ? chunk : n - k0);
     for (int k = threadIdx.x; k < len; k += BS) {
         xs[0][k] = x1[k0 + k];
         if (NRHS == 2) xs[NRHS - 1][k] = x2[k0 + k];
