@@ -82,3 +82,19 @@ def test_binding_rejects_host_tensors():
     from paper_2512_13619_amd import hdg
     with pytest.raises(hdg.HdgError):
         hdg._ptr(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "x")
+
+
+def test_package_dirk_tableaus_meet_order_conditions():
+    """The DIRK tableaus the device driver uses (written out in the package) are lower triangular
+    with one diagonal value, stiffly accurate, and of order 1, 2, 3 (Section 2.2's DIRK(s, p))."""
+    import numpy as np
+    from paper_2512_13619_amd.pipeline import dirk_tableau
+    for scheme, order in (("be", 1), ("dirk22", 2), ("dirk33", 3)):
+        A = np.array(dirk_tableau(scheme))
+        b, c = A[-1], A.sum(1)
+        assert np.allclose(np.tril(A), A) and np.allclose(np.diag(A), A[0, 0])
+        assert abs(c[-1] - 1.0) < 1e-15 and abs(b.sum() - 1.0) < 1e-15
+        if order >= 2:
+            assert abs(b @ c - 0.5) < 1e-14
+        if order >= 3:
+            assert abs(b @ c ** 2 - 1.0 / 3.0) < 1e-14 and abs(b @ (A @ c) - 1.0 / 6.0) < 1e-14
