@@ -764,10 +764,23 @@ int pick_panel(const CondDims& cd) {
     return 0;
 }
 
+// Threads of the elimination kernel: 128 for elements of at most 128 rows (more elements
+// in flight per CU), else 512 for panels of up to 32 columns and 256 for wider ones.
+const void* lu_kernel(const CondDims& cd, int NB, int* threads) {
+    if (cd.R <= 128) {
+        *threads = 128;
+        return NB <= 16 ? (const void*)k_cond_lu<16, 128> : NB <= 32 ? (const void*)k_cond_lu<32, 128>
+                                                                     : (const void*)k_cond_lu<64, 128>;
+    }
+    *threads = NB <= 32 ? 512 : 256;
+    return NB <= 16 ? (const void*)k_cond_lu<16, 512> : NB <= 32 ? (const void*)k_cond_lu<32, 512>
+                                                                 : (const void*)k_cond_lu<64, 256>;
+}
+
 hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
     const size_t lds = lu_lds_bytes(cd, NB);
-    const void* lu_fn = NB <= 16 ? (const void*)k_cond_lu<16, 512> : NB <= 32 ? (const void*)k_cond_lu<32, 512>
-                                                                               : (const void*)k_cond_lu<64, 256>;
+    int threads = 0;
+    const void* lu_fn = lu_kernel(cd, NB, &threads);
     if (lds > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_qelim, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -786,15 +799,12 @@ hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t 
                                double* Kout, double* rout, int* status, int64_t e_off, int32_t* ipiv = nullptr,
                                int keep = 0) {
     const size_t lds = lu_lds_bytes(cd, NB);
-    if (NB <= 16)
-        hipLaunchKernelGGL((k_cond_lu<16, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB, top, bot,
-                           status, (int)e_off, ipiv, keep);
-    else if (NB <= 32)
-        hipLaunchKernelGGL((k_cond_lu<32, 512>), dim3((unsigned)n), dim3(512), lds, ctx->stream, cd, NB, top, bot,
-                           status, (int)e_off, ipiv, keep);
-    else
-        hipLaunchKernelGGL((k_cond_lu<64, 256>), dim3((unsigned)n), dim3(256), lds, ctx->stream, cd, NB, top, bot,
-                           status, (int)e_off, ipiv, keep);
+    int threads = 0;
+    const void* lu_fn = lu_kernel(cd, NB, &threads);
+    int e_off_i = (int)e_off;
+    void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&bot, (void*)&status, (void*)&e_off_i, (void*)&ipiv,
+                    (void*)&keep};
+    HDG_HIP_CHECK(ctx, hipLaunchKernel(lu_fn, dim3((unsigned)n), dim3(threads), args, lds, ctx->stream));
     HDG_LAUNCH_CHECK(ctx);
     const int tm_n = div_up(cd.nt, GT);
     const long long ntile = (long long)n * tm_n * tm_n;
