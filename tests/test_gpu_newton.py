@@ -197,3 +197,82 @@ def test_dirk_steps_match_oracle(ctx, name, scheme, dt, nsteps):
         assert [x["alpha"] for x in h] == [x["alpha"] for x in hr]
     assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-9
     assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-9
+
+
+# ---- the bench-size workload (2D Burgers, 128^2 quads, p = 4): sampled elements ------------
+def _bench_problem():
+    return HDGProblem(Mh.structured_quads(128, 0.05, 6), 4, Ph.Burgers(nu=0.01, forcing=_forcing), device="cuda")
+
+
+def _sampled_geom(inp, elems):
+    """The oracle's geometry dict for the sampled elements only (element index = position)."""
+    per = ("wdet", "dphix", "phif", "ndA", "dA", "src", "uD", "bnd")
+    g = {k: inp[k][elems].cpu().numpy() for k in per}
+    g["phi"], g["psi"] = inp["phi"].cpu().numpy(), inp["psi"].cpu().numpy()
+    return g
+
+
+def test_element_blocks_full_size_sampled(ctx):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb = _bench_problem()
+    d = pb.dims()
+    say("element blocks full size", d)
+    inp = pb.newton_inputs()
+    geom = _geom_dev(inp)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f, keep_fp32=False)
+    out = pl.element_arrays()
+    rng = np.random.default_rng(12)
+    u = inp["u0"].flatten() + 0.2 * torch.as_tensor(rng.standard_normal(inp["u0"].numel())).cuda()
+    uh = inp["uhat0"].flatten() + 0.2 * torch.as_tensor(rng.standard_normal(inp["uhat0"].numel())).cuda()
+    ctx.element_blocks(d, geom, _model(inp), pl.e2f, u, uh, out)
+    torch.cuda.synchronize()
+    elems = np.sort(rng.choice(d["ne"], 24, replace=False))
+    g = _sampled_geom(inp, elems)
+    m = _model(inp)
+    P, PF, L, D = d["npe"], d["npf"], d["nlfe"], d["dim"]
+    nt = L * PF
+    un = u.cpu().numpy().reshape(d["ne"], P)
+    uhn = uh.cpu().numpy().reshape(d["nf"], PF)
+    for k, e in enumerate(elems):
+        ue, uhe = un[e], uhn[pb.mesh.e2f[e]]
+        Mm, Bd, Cd = OE.mass_and_q_operators(g, k)
+        q = OE.consistent_q(g, k, ue, uhe)
+        _, Ru, Rt = OE.residual(g, m, k, q, ue, uhe)
+        Dm, Em, Fm, Gm, Hm, Jm = OE.jacobian(g, m, k, q, ue, uhe)
+        ref = dict(Minv=np.linalg.inv(Mm), Bd=Bd, Cd=Cd, D=Dm, E=Em, F=Fm, G=Gm, H=Hm, J=Jm, ru=-Ru,
+                   rt=-Rt.ravel(), q=q)
+        for key, val in ref.items():
+            got = out[key].view(d["ne"], -1)[e].cpu().numpy().reshape(val.shape)
+            err = relerr(got, val)
+            assert err < 1e-12, (int(e), key, err)
+
+
+def test_newton_full_size_residual_property(ctx):
+    """At the bench size the Newton loop's final state solves the discrete equations: the
+    library's norm drops by 1e-10 and the oracle's residual of sampled elements at that state
+    is at the same level."""
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb = _bench_problem()
+    d = pb.dims()
+    inp = pb.newton_inputs()
+    geom = _geom_dev(inp)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f, keep_fp32=False)
+    u = inp["u0"].flatten().clone()
+    uh = inp["uhat0"].flatten().clone()
+    hist = pl.newton(geom, _model(inp), u, uh, tol=1e-10, restart=50, max_iters=20000, rtol=1e-10, prec="bj",
+                     orth="dcgs2", fold_prec=True)
+    say("  full-size newton", [(f"{h['norm']:.2e}", h["alpha"]) for h in hist])
+    assert hist[-1]["norm"] <= 1e-10 * hist[0]["norm"]
+    rng = np.random.default_rng(13)
+    elems = np.sort(rng.choice(d["ne"], 24, replace=False))
+    g = _sampled_geom(inp, elems)
+    m = _model(inp)
+    un = u.cpu().numpy().reshape(d["ne"], d["npe"])
+    uhn = uh.cpu().numpy().reshape(d["nf"], d["npf"])
+    worst = 0.0
+    for k, e in enumerate(elems):
+        ue, uhe = un[e], uhn[pb.mesh.e2f[e]]
+        q = OE.consistent_q(g, k, ue, uhe)
+        _, Ru, _ = OE.residual(g, m, k, q, ue, uhe)
+        worst = max(worst, np.abs(Ru).max())
+    assert worst <= 1e-9 * hist[0]["norm"], worst
