@@ -416,6 +416,26 @@ hdg_status hdg_batch_create(hdg_ctx ctx, int32_t n_inst, const hdg_dims* dims_h,
 hdg_status hdg_batch_destroy(hdg_batch b);
 hdg_status hdg_batch_offsets(hdg_batch b, int32_t array_id, int64_t* off_h /* [n_inst+1] */);
 int32_t    hdg_batch_tuned_grid(hdg_batch b);
+/* Batched element residuals / Jacobians and damped Newton support (scalar models; Section
+ * 4.1, Section 4.3, as hdg_element_blocks / hdg_residual_norm / hdg_newton_update):
+ * hdg_element_blocks_batch: nqv_h, nqf_h [n_inst] (host) are each instance's quadrature
+ *   sizes, models_h [n_inst] (host) its coefficients; the geometry arrays of geom (its nqv,
+ *   nqf fields unused) are the concatenation of the instances' arrays in instance order;
+ *   e2f, u (DU offsets), uhat (VEC offsets) and the outputs (MINV..RT, q at DQ offsets) are
+ *   batch arrays. No time term. Errors as hdg_element_blocks (the element named is global).
+ * hdg_residual_norm_batch: norms_h [n_inst] (host) receives each instance's ||R|| (element
+ *   u-rows and its faces' summed trace rows, f2e instance-local as for hdg_assemble_batch).
+ * hdg_newton_update_batch: u += alpha_h[i] du and uhat += alpha_h[i] x over instance i's parts
+ *   (DU and VEC offsets); alpha_h [n_inst] host, 0 leaves an instance unchanged.
+ * All three synchronise the context's stream before returning. */
+hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv_h, const int32_t* nqf_h,
+                                    const hdg_elem_geom* geom, const hdg_conv_diff* models_h,
+                                    const int32_t* e2f, const double* u, const double* uhat,
+                                    int32_t residual_only, const hdg_elem_arrays* out);
+hdg_status hdg_residual_norm_batch(hdg_ctx ctx, hdg_batch b, const int32_t* f2e, const double* ru,
+                                   const double* rt, double* norms_h);
+hdg_status hdg_newton_update_batch(hdg_ctx ctx, hdg_batch b, const double* alpha_h, const double* du,
+                                   double* u, const double* x, double* uhat);
 hdg_status hdg_condense_batch(hdg_ctx ctx, hdg_batch b, const hdg_elem_blocks* in,
                               double* Kbar, double* rbar, double* local);
 hdg_status hdg_assemble_batch(hdg_ctx ctx, hdg_batch b, const int32_t* f2e, const int32_t* e2f,

@@ -171,6 +171,135 @@ hdg_status hdg_batch_offsets(hdg_batch b, int32_t array_id, int64_t* off_h) {
 
 int32_t hdg_batch_tuned_grid(hdg_batch b) { return b ? b->tuned_grid : 0; }
 
+hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv_h, const int32_t* nqf_h,
+                                    const hdg_elem_geom* g, const hdg_conv_diff* models_h, const int32_t* e2f,
+                                    const double* u, const double* uhat, int32_t residual_only,
+                                    const hdg_elem_arrays* out) {
+    if (!ctx || !b) return HDG_ERR_ARG;
+    if (!nqv_h || !nqf_h || !g || !models_h || !e2f || !u || !uhat || !out || !out->ru || !out->rt || !g->wdet ||
+        !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD || !g->bnd) {
+        ctx->err = "hdg_element_blocks_batch: NULL pointer";
+        return HDG_ERR_ARG;
+    }
+    if (!residual_only && (!out->Minv || !out->Bd || !out->Cd || !out->D || !out->E || !out->F || !out->G ||
+                           !out->H || !out->J)) {
+        ctx->err = "hdg_element_blocks_batch: NULL matrix output (residual_only = 0)";
+        return HDG_ERR_ARG;
+    }
+    const int n = b->dev.n_inst;
+    std::vector<ElemInst> inst(n);
+    int64_t gw = 0, gdp = 0, gph = 0, gpf = 0, gps = 0, gn = 0, gda = 0, gs = 0, gud = 0;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+        const InstDesc& q = b->host[i];
+        const int Qv = nqv_h[i], Qf = nqf_h[i];
+        if (q.M != 1 || Qv < 1 || Qf < 1) {
+            ctx->err = "hdg_element_blocks_batch: instance " + std::to_string(i) +
+                       " is not a scalar model with nqv, nqf >= 1";
+            return HDG_ERR_ARG;
+        }
+        const size_t li = element_batch_lds_bytes(q.P, q.PF, q.L, q.D, Qv, Qf);
+        if (li > 65536) {
+            ctx->err = "hdg_element_blocks_batch: element data of instance " + std::to_string(i) +
+                       " exceed 64 KiB of LDS";
+            return HDG_ERR_SHAPE;
+        }
+        lds = std::max(lds, li);
+        const double nu_ = models_h[i].nu, tau_ = models_h[i].tau;
+        ElemInst& E = inst[i];
+        E.P = q.P; E.PF = q.PF; E.L = q.L; E.D = q.D; E.Qv = Qv; E.Qf = Qf;
+        E.e0 = q.e0;
+        E.g_wdet = gw;  gw += (int64_t)q.ne * Qv;
+        E.g_dphix = gdp; gdp += (int64_t)q.ne * Qv * q.P * q.D;
+        E.g_phi = gph;  gph += (int64_t)Qv * q.P;
+        E.g_phif = gpf; gpf += (int64_t)q.ne * q.L * Qf * q.P;
+        E.g_psi = gps;  gps += (int64_t)Qf * q.PF;
+        E.g_ndA = gn;   gn += (int64_t)q.ne * q.L * Qf * q.D;
+        E.g_dA = gda;   gda += (int64_t)q.ne * q.L * Qf;
+        E.g_src = gs;   gs += (int64_t)q.ne * Qv;
+        E.g_uD = gud;   gud += (int64_t)q.ne * q.L * Qf;
+        E.e2f_off = q.e2f_off;
+        E.u_off = q.du_off;
+        E.uh_off = q.vec_off;
+        E.q_off = q.dq_off;
+        for (int a = 0; a < 11; ++a) E.out_off[a] = q.off[a];
+        E.nu = nu_; E.tau = tau_;
+        for (int d = 0; d < 3; ++d) { E.beta[d] = models_h[i].beta[d]; E.gamma[d] = models_h[i].gamma[d]; }
+    }
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    hdg_status st;
+    char* base = (char*)ws_get(ctx, WS_NEWTON_BATCH, sizeof(ElemInst) * (size_t)n + 2 * sizeof(double) * n + 256,
+                               &st);
+    if (!base) return st;
+    int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
+    if (!status) return st;
+    const int big = 0x7fffffff;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(base, inst.data(), sizeof(ElemInst) * (size_t)n, hipMemcpyHostToDevice,
+                                      ctx->stream));
+    ElemBatchArgs a;
+    a.g = *g;
+    a.e2f = e2f;
+    a.u = u;
+    a.uhat = uhat;
+    a.out = *out;
+    a.bad = status;
+    a.residual_only = residual_only;
+    if (lds > 64 * 1024) lds = 64 * 1024;
+    if ((st = element_blocks_batch_run(ctx, b->dev.total_ne, (const ElemInst*)base, b->dev.eid, a, lds)) != HDG_OK)
+        return st;
+    int bad = big;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad != big) {
+        ctx->err = "hdg_element_blocks_batch: non-positive mass-matrix pivot in (global) element " +
+                   std::to_string(bad);
+        return HDG_ERR_SINGULAR;
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_residual_norm_batch(hdg_ctx ctx, hdg_batch b, const int32_t* f2e, const double* ru, const double* rt,
+                                   double* norms_h) {
+    if (!ctx || !b) return HDG_ERR_ARG;
+    if (!f2e || !ru || !rt || !norms_h) {
+        ctx->err = "hdg_residual_norm_batch: NULL pointer";
+        return HDG_ERR_ARG;
+    }
+    const int n = b->dev.n_inst;
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    hdg_status st;
+    char* base = (char*)ws_get(ctx, WS_NEWTON_BATCH, sizeof(ElemInst) * (size_t)n + 2 * sizeof(double) * n + 256,
+                               &st);
+    if (!base) return st;
+    double* norms = (double*)(base + sizeof(ElemInst) * (size_t)n);
+    if ((st = residual_norm_batch_run(ctx, n, b->dev.desc, ru, rt, f2e, norms)) != HDG_OK) return st;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(norms_h, norms, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return HDG_OK;
+}
+
+hdg_status hdg_newton_update_batch(hdg_ctx ctx, hdg_batch b, const double* alpha_h, const double* du, double* u,
+                                   const double* x, double* uhat) {
+    if (!ctx || !b) return HDG_ERR_ARG;
+    if (!alpha_h || !du || !u || !x || !uhat) {
+        ctx->err = "hdg_newton_update_batch: NULL pointer";
+        return HDG_ERR_ARG;
+    }
+    const int n = b->dev.n_inst;
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    hdg_status st;
+    char* base = (char*)ws_get(ctx, WS_NEWTON_BATCH, sizeof(ElemInst) * (size_t)n + 2 * sizeof(double) * n + 256,
+                               &st);
+    if (!base) return st;
+    double* alpha = (double*)(base + sizeof(ElemInst) * (size_t)n) + n;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(alpha, alpha_h, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = newton_update_batch_run(ctx, n, b->dev.desc, alpha, du, u, x, uhat)) != HDG_OK) return st;
+    // the host array is read by the copy above: keep the call synchronous for the caller
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return HDG_OK;
+}
+
 hdg_status hdg_condense_batch(hdg_ctx ctx, hdg_batch b, const hdg_elem_blocks* in, double* Kbar, double* rbar,
                               double* local) {
     if (!ctx || !b) return HDG_ERR_ARG;

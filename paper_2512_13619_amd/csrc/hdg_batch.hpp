@@ -41,6 +41,35 @@ struct BatchDev {
     int max_nb = 0, max_snb = 0, max_R = 0;
 };
 
+// Batched element residuals / Jacobian blocks (scalar convection-diffusion models): per
+// instance its sizes, the offsets of its parts of the concatenated geometry arrays and of
+// the batch arrays it reads and writes, and its model coefficients.
+struct ElemInst {
+    int P, PF, L, D, Qv, Qf;
+    int64_t e0;
+    int64_t g_wdet, g_dphix, g_phi, g_phif, g_psi, g_ndA, g_dA, g_src, g_uD;
+    int64_t e2f_off, u_off, uh_off, q_off;
+    int64_t out_off[11];            // Minv, Bd, Cd, D, E, F, G, H, J, ru, rt
+    double nu, tau, beta[3], gamma[3];
+};
+
+struct ElemBatchArgs {
+    hdg_elem_geom g;                // concatenated arrays (nqv, nqf unused)
+    const int32_t* e2f;
+    const double *u, *uhat;
+    hdg_elem_arrays out;
+    int* bad;
+    int residual_only;
+};
+
+size_t element_batch_lds_bytes(int P, int PF, int L, int D, int nqv, int nqf);
+hdg_status element_blocks_batch_run(hdg_ctx ctx, int64_t total_ne, const ElemInst* inst_dev, const int32_t* eid,
+                                    const ElemBatchArgs& a, size_t lds);
+hdg_status residual_norm_batch_run(hdg_ctx ctx, int n_inst, const InstDesc* desc, const double* ru, const double* rt,
+                                   const int32_t* f2e, double* norms);
+hdg_status newton_update_batch_run(hdg_ctx ctx, int n_inst, const InstDesc* desc, const double* alpha,
+                                   const double* du, double* u, const double* x, double* uhat);
+
 hdg_status batch_launch_condense(hdg_ctx ctx, const BatchDev& b, const BatchElemPtrs& in, double* Kbar, double* rbar,
                                  double* local, int* bad, int grid);
 hdg_status batch_launch_assemble(hdg_ctx ctx, const BatchDev& b, const int32_t* f2e, const int32_t* e2f,

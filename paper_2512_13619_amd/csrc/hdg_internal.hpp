@@ -27,6 +27,7 @@ enum WsSlot {
     WS_KFOLD,          // right-preconditioned operator blocks K M^{-1}
     WS_ASM,            // additive Schwarz: unit neighbour table, unit results, a work vector
     WS_NEWTON,         // residual norm: assembled trace residual and reduction partials
+    WS_NEWTON_BATCH,   // batched element generation / norms / updates: descriptors, norms, steps
     WS_NSLOTS
 };
 

@@ -25,7 +25,8 @@ SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg
            "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
            "hdg_bj_apply", "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
-           "hdg_gmres_solve_batch", "hdg_recover_batch"]
+           "hdg_gmres_solve_batch", "hdg_recover_batch", "hdg_element_blocks_batch", "hdg_residual_norm_batch",
+           "hdg_newton_update_batch"]
 
 BATCH_ARRAYS = ["Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "Kbar", "rbar", "local", "du", "dq",
                 "K", "nbr", "vec", "f2e", "e2f", "binv"]
@@ -136,6 +137,10 @@ def load():
     lib.hdg_gmres_solve_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                           ctypes.POINTER(SolveStats)]
     lib.hdg_recover_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_element_blocks_batch.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ElemGeom),
+                                             ctypes.POINTER(ConvDiff), vp, vp, vp, i32, ctypes.POINTER(ElemArrays)]
+    lib.hdg_residual_norm_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.hdg_newton_update_batch.argtypes = [vp, vp, ctypes.POINTER(dbl), vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("hdg_last_error", "hdg_local_size", "hdg_solve_opts_default",
                         "hdg_hessenberg_eigvals", "hdg_harmonic_ritz"):
@@ -525,6 +530,55 @@ class Batch:
         return self.ctx._check(self.lib.hdg_condense_batch(
             self.ctx.h, self.h, ctypes.byref(eb), _ptr(Kbar, f64, self.total("Kbar"), "Kbar"),
             _ptr(rbar, f64, self.total("rbar"), "rbar"), _ptr(local, f64, self.total("local"), "local")))
+
+    def element_blocks(self, nqv, nqf, geom, models, e2f, u, uhat, out, residual_only=False):
+        """Batched hdg_element_blocks: nqv, nqf and models (dicts nu, tau, beta, gamma) per
+        instance; geom's arrays concatenated in instance order; the rest are batch arrays."""
+        import torch
+        f64 = torch.float64
+        n = self.n
+        gsz = dict(wdet=0, dphix=0, phi=0, phif=0, psi=0, ndA=0, dA=0, src=0, uD=0, bnd=0)
+        for d, qv, qf in zip(self.dims_list, nqv, nqf):
+            ne, P, PF, L, D = (int(d[k]) for k in ("ne", "npe", "npf", "nlfe", "dim"))
+            gsz["wdet"] += ne * qv; gsz["dphix"] += ne * qv * P * D; gsz["phi"] += qv * P
+            gsz["phif"] += ne * L * qf * P; gsz["psi"] += qf * PF; gsz["ndA"] += ne * L * qf * D
+            gsz["dA"] += ne * L * qf; gsz["src"] += ne * qv; gsz["uD"] += ne * L * qf; gsz["bnd"] += ne * L
+        g = ElemGeom(0, 0, *[_ptr(geom[k], f64, gsz[k], k) for k in list(gsz)[:-1]],
+                     _ptr(geom["bnd"], torch.int32, gsz["bnd"], "bnd"))
+        ms = (ConvDiff * n)()
+        for i, m in enumerate(models):
+            beta = list(m["beta"]) + [0.0] * (3 - len(m["beta"]))
+            gamma = list(m["gamma"]) + [0.0] * (3 - len(m["gamma"]))
+            ms[i] = ConvDiff(float(m["nu"]), float(m["tau"]), (ctypes.c_double * 3)(*beta),
+                             (ctypes.c_double * 3)(*gamma))
+        qv_a = (ctypes.c_int32 * n)(*[int(v) for v in nqv])
+        qf_a = (ctypes.c_int32 * n)(*[int(v) for v in nqf])
+        names = ["Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt"]
+        ptrs = [_ptr(out.get(k), f64, self.total(k), k, allow_none=True) for k in names]
+        ptrs.append(_ptr(out.get("q"), f64, self.total("dq"), "q", allow_none=True))
+        o = ElemArrays(*ptrs)
+        return self.ctx._check(self.lib.hdg_element_blocks_batch(
+            self.ctx.h, self.h, qv_a, qf_a, ctypes.byref(g), ms, _ptr(e2f, torch.int32, self.total("e2f"), "e2f"),
+            _ptr(u, f64, self.total("du"), "u"), _ptr(uhat, f64, self.total("vec"), "uhat"), int(bool(residual_only)),
+            ctypes.byref(o)))
+
+    def residual_norms(self, f2e, ru, rt):
+        import torch
+        out = np.zeros(self.n)
+        self.ctx._check(self.lib.hdg_residual_norm_batch(
+            self.ctx.h, self.h, _ptr(f2e, torch.int32, self.total("f2e"), "f2e"),
+            _ptr(ru, torch.float64, self.total("ru"), "ru"), _ptr(rt, torch.float64, self.total("rt"), "rt"),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def newton_update(self, alpha, du, u, x, uhat):
+        import torch
+        al = np.ascontiguousarray(alpha, dtype=np.float64)
+        assert al.shape == (self.n,)
+        return self.ctx._check(self.lib.hdg_newton_update_batch(
+            self.ctx.h, self.h, al.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            _ptr(du, torch.float64, self.total("du"), "du"), _ptr(u, torch.float64, self.total("du"), "u"),
+            _ptr(x, torch.float64, self.total("vec"), "x"), _ptr(uhat, torch.float64, self.total("vec"), "uhat")))
 
     def assemble(self, f2e, e2f, Kbar, rbar, K64, K32, nbr, r):
         import torch

@@ -175,3 +175,91 @@ def dirk_tableau(scheme):
         b2 = (6.0 * a * a - 20.0 * a + 5.0) / 4.0
         return [[a, 0.0, 0.0], [(1.0 + a) / 2.0 - a, a, 0.0], [b1, b2, a]]
     raise ValueError(f"unknown DIRK scheme {scheme!r}")
+
+
+class BatchPipeline:
+    """Many independent instances (hdg_batch_* entry points): concatenated buffers of the
+    condensation, assembly, solve and recovery, and a damped Newton loop per instance."""
+
+    def __init__(self, ctx, dims_list, f2e_list, e2f_list, device="cuda", keep_fp32=True):
+        import numpy as np
+        self.ctx = ctx
+        self.bt = hdg.Batch(ctx, dims_list)
+        self.device = device
+        bt = self.bt
+        i32 = lambda arrs: torch.as_tensor(np.concatenate([np.asarray(a).reshape(-1) for a in arrs])
+                                           .astype(np.int32)).to(device)
+        self.f2e = i32(f2e_list)
+        self.e2f = i32(e2f_list)
+        z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device=device)
+        self.Kbar, self.rbar, self.local = z(bt.total("Kbar")), z(bt.total("rbar")), z(bt.total("local"))
+        self.K64 = z(bt.total("K"))
+        self.K32 = z(bt.total("K"), torch.float32) if keep_fp32 else None
+        self.nbr = torch.zeros(bt.total("nbr"), dtype=torch.int32, device=device)
+        self.r, self.x = z(bt.total("vec")), z(bt.total("vec"))
+        self.du, self.dq = z(bt.total("du")), z(bt.total("dq"))
+
+    def element_arrays(self):
+        z = lambda n: torch.zeros(n, dtype=torch.float64, device=self.device)
+        out = {k: z(self.bt.total(k)) for k in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt")}
+        out["q"] = z(self.bt.total("dq"))
+        return out
+
+    def condense(self, blk):
+        self.bt.condense(blk, self.Kbar, self.rbar, self.local)
+
+    def assemble(self):
+        self.bt.assemble(self.f2e, self.e2f, self.Kbar, self.rbar, self.K64, self.K32, self.nbr, self.r)
+
+    def solve(self, **kw):
+        self.x.zero_()
+        return self.bt.gmres_solve(self.K64, self.K32, self.nbr, self.r, self.x, **kw)
+
+    def recover(self, Minv, Bd, Cd):
+        self.bt.recover(self.local, Minv, Bd, Cd, self.e2f, self.x, self.du, self.dq)
+
+    def newton(self, nqv, nqf, geom, models, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10,
+               **solve_kw):
+        """Damped Newton (Section 4.3) for every instance at once: each instance has its own
+        residual norm, step halving and stopping test (max(tol * initial norm, atol)); a
+        converged instance gets a zero right-hand side and no update while the others go on.
+        u, uhat: batch arrays (DU / VEC offsets), updated in place. Returns one history per
+        instance (as Pipeline.newton)."""
+        import numpy as np
+        bt = self.bt
+        n = bt.n
+        blk = self.element_arrays()
+        bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk)
+        nrm = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
+        stop = np.maximum(tol * nrm, atol)
+        hists = [[] for _ in range(n)]
+        off = bt.offsets("vec")
+        for _ in range(max_steps):
+            active = nrm > stop
+            if not active.any():
+                break
+            self.condense(blk)
+            self.assemble()
+            for i in np.nonzero(~active)[0]:
+                self.r[off[i]:off[i + 1]] = 0.0           # converged: no correction
+            _, stats = self.solve(**solve_kw)
+            self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+            alpha = np.where(active, 1.0, 0.0)
+            applied = np.zeros(n)
+            pending = active.copy()
+            while True:
+                bt.newton_update(np.where(pending, alpha - applied, 0.0), self.du, u, self.x, uhat)
+                applied = np.where(pending, alpha, applied)
+                bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk)
+                trial = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
+                accept = pending & ((trial < nrm) | (alpha <= min_alpha))
+                for i in np.nonzero(accept)[0]:
+                    hists[i].append(dict(norm=float(nrm[i]), alpha=float(alpha[i]), iters=int(stats[i]["iters"])))
+                    nrm[i] = trial[i]
+                pending &= ~accept
+                if not pending.any():
+                    break
+                alpha = np.where(pending, alpha * 0.5, alpha)
+        for i in range(n):
+            hists[i].append(dict(norm=float(nrm[i]), alpha=0.0, iters=0))
+        return hists

@@ -276,3 +276,68 @@ def test_newton_full_size_residual_property(ctx):
         _, Ru, _ = OE.residual(g, m, k, q, ue, uhe)
         worst = max(worst, np.abs(Ru).max())
     assert worst <= 1e-9 * hist[0]["norm"], worst
+
+
+# ---- many independent instances (the batched Poisson/Burgers workload) ----------------------
+def _batch_instances():
+    def f2(x):
+        return (torch.cos(np.pi * x[..., 0]) * torch.sin(np.pi * x[..., 1]))[..., None]
+    return [HDGProblem(Mh.structured_quads(4, 0.0, 4), 2, Ph.Burgers(nu=0.01, forcing=_forcing)),
+            HDGProblem(Mh.structured_tris(3, 0.0, 4), 3, Ph.Burgers(nu=0.05)),
+            HDGProblem(Mh.structured_quads(4, 0.0, 4), 1, Ph.Poisson(2, 1.0, forcing=f2)),
+            HDGProblem(Mh.structured_tris(2, 0.0, 4), 4, Ph.Poisson(2, 1.0, forcing=_forcing)),
+            HDGProblem(Mh.structured_quads(3, 0.0, 4), 4, Ph.Burgers(nu=0.02, forcing=f2))]
+
+
+def test_batch_newton_matches_per_instance_oracle(ctx):
+    from paper_2512_13619_amd.pipeline import BatchPipeline
+    pbs = _batch_instances()
+    say("batch newton", [(pb.etype, pb.mesh.ne, pb.p, type(pb.phys).__name__) for pb in pbs])
+    inps = [pb.newton_inputs() for pb in pbs]
+    bp = BatchPipeline(ctx, [pb.dims() for pb in pbs], [pb.mesh.f2e for pb in pbs], [pb.mesh.e2f for pb in pbs])
+    keys = ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")
+    geom = {k: torch.cat([inp[k].reshape(-1) for inp in inps]).cuda().contiguous() for k in keys}
+    u = torch.cat([inp["u0"].reshape(-1) for inp in inps]).cuda().contiguous()
+    uh = torch.cat([inp["uhat0"].reshape(-1) for inp in inps]).cuda().contiguous()
+    models = [_model(inp) for inp in inps]
+    hists = bp.newton([inp["nqv"] for inp in inps], [inp["nqf"] for inp in inps], geom, models, u, uh, tol=1e-11,
+                      restart=50, max_iters=3000, rtol=1e-13, prec="bj")
+    ou, oh = bp.bt.offsets("du"), bp.bt.offsets("vec")
+    for i, (pb, inp) in enumerate(zip(pbs, inps)):
+        inp_np = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in inp.items()}
+        u_ref, uh_ref, h_ref = ON.damped_newton(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f,
+                                                pb.mesh.f2e, pb.dims(), rtol=1e-11)
+        say("  instance", i, [(f"{h['norm']:.2e}", h["alpha"]) for h in hists[i]])
+        assert [h["alpha"] for h in hists[i]] == [h["alpha"] for h in h_ref], i
+        for a, b in zip(hists[i], h_ref):
+            assert abs(a["norm"] - b["norm"]) <= 1e-7 * h_ref[0]["norm"], i
+        assert relerr(u[ou[i]:ou[i + 1]].cpu().numpy(), u_ref.ravel()) < 1e-9, i
+        assert relerr(uh[oh[i]:oh[i + 1]].cpu().numpy(), uh_ref.ravel()) < 1e-9, i
+
+
+def test_batch_element_blocks_match_single_instance(ctx):
+    """The batched kernel writes, for every instance, what the single-instance kernel writes."""
+    from paper_2512_13619_amd.pipeline import BatchPipeline, Pipeline
+    pbs = _batch_instances()
+    inps = [pb.newton_inputs() for pb in pbs]
+    bp = BatchPipeline(ctx, [pb.dims() for pb in pbs], [pb.mesh.f2e for pb in pbs], [pb.mesh.e2f for pb in pbs])
+    keys = ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")
+    geom = {k: torch.cat([inp[k].reshape(-1) for inp in inps]).cuda().contiguous() for k in keys}
+    rng = np.random.default_rng(21)
+    us = [inp["u0"].reshape(-1).cuda() + 0.3 * torch.as_tensor(rng.standard_normal(inp["u0"].numel())).cuda()
+          for inp in inps]
+    uhs = [inp["uhat0"].reshape(-1).cuda() + 0.3 * torch.as_tensor(rng.standard_normal(inp["uhat0"].numel())).cuda()
+           for inp in inps]
+    out = bp.element_arrays()
+    bp.bt.element_blocks([inp["nqv"] for inp in inps], [inp["nqf"] for inp in inps], geom,
+                         [_model(inp) for inp in inps], bp.e2f, torch.cat(us), torch.cat(uhs), out)
+    norms = bp.bt.residual_norms(bp.f2e, out["ru"], out["rt"])
+    for i, (pb, inp) in enumerate(zip(pbs, inps)):
+        pl = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+        ref = pl.element_arrays()
+        ctx.element_blocks(pb.dims(), _geom_dev(inp), _model(inp), pl.e2f, us[i], uhs[i], ref)
+        for k in ("Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "q"):
+            o = bp.bt.offsets("dq" if k == "q" else k)
+            assert torch.equal(out[k][o[i]:o[i + 1]], ref[k]), (i, k)
+        want = ctx.residual_norm(pb.dims(), pl.f2e, ref["ru"], ref["rt"])
+        assert abs(norms[i] - want) <= 1e-13 * want, (i, norms[i], want)
