@@ -287,6 +287,81 @@ def newton_bench(args):
           flush=True)
 
 
+def newton_batch_bench(args):
+    """Damped Newton on the 512-instance Poisson/Burgers workload (seeded instance draws: element
+    type, n in 4..32, p in 1..4, PDE, forcing), all instances in one batch: per-instance element
+    blocks, condensation, assembly, block-Jacobi FGMRES to 1e-10, recovery, step halving, each
+    instance stopping at a residual reduction of 1e-10."""
+    import numpy as np
+    import torch
+    from paper_2512_13619_amd import hdg
+    from paper_2512_13619_amd.pipeline import BatchPipeline
+    from workloads import configs
+
+    t0 = time.perf_counter()
+    pbs = [configs.c4_instance(i, device="cuda") for i in range(args.newton_batch)]
+    inps = [pb.newton_inputs() for pb in pbs]
+    keys = ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")
+    geom = {k: torch.cat([inp[k].reshape(-1) for inp in inps]).contiguous() for k in keys}
+    u0 = torch.cat([inp["u0"].reshape(-1) for inp in inps]).contiguous()
+    uh0 = torch.cat([inp["uhat0"].reshape(-1) for inp in inps]).contiguous()
+    models = [dict(nu=inp["nu"], tau=inp["tau"], beta=inp["beta"], gamma=inp["gamma"]) for inp in inps]
+    nqv, nqf = [inp["nqv"] for inp in inps], [inp["nqf"] for inp in inps]
+    ctx = hdg.Context(0)
+    bp = BatchPipeline(ctx, [pb.dims() for pb in pbs], [pb.mesh.f2e for pb in pbs], [pb.mesh.e2f for pb in pbs])
+    log(f"batch of {len(pbs)} instances, {sum(pb.mesh.ne for pb in pbs)} elements, "
+        f"{bp.bt.total('vec')} trace dofs ({time.perf_counter() - t0:.1f} s to generate)")
+    blk = bp.element_arrays()
+    bp.bt.element_blocks(nqv, nqf, geom, models, bp.e2f, u0, uh0, blk)
+    reps = 10
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        bp.bt.element_blocks(nqv, nqf, geom, models, bp.e2f, u0, uh0, blk)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_blk = ev0.elapsed_time(ev1) / 1e3 / reps
+    runs = []
+    for _ in range(2):
+        u, uh = u0.clone(), uh0.clone()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        hists = bp.newton(nqv, nqf, geom, models, u, uh, tol=1e-10, max_steps=30, restart=30, max_iters=5000,
+                          rtol=1e-10, prec="bj", use_graph=True)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - ts)
+    # pseudo-transient continuation (backward Euler in pseudo-time, SER growth of dtau)
+    u, uh = u0.clone(), uh0.clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ph = bp.pseudo_transient(nqv, nqf, geom, models, u, uh, 0.05, tol=1e-10, max_steps=200, restart=30,
+                             max_iters=5000, rtol=1e-10, prec="bj", use_graph=True)
+    torch.cuda.synchronize()
+    t_ptc = time.perf_counter() - ts
+    ptc_steps = [len(h) - 1 for h in ph]
+    ptc = dict(dtau0=0.05, s=t_ptc, converged=int(sum(h[-1]["norm"] <= 1e-10 * h[0]["norm"] for h in ph)),
+               steps_max=max(ptc_steps), steps_mean=float(np.mean(ptc_steps)))
+    steps = [len(h) - 1 for h in hists]
+    conv = [h[-1]["norm"] <= 1e-10 * h[0]["norm"] for h in hists]
+    damped = sum(1 for h in hists if any(x["alpha"] < 1.0 for x in h[:-1]))
+    print(json.dumps({"profile": "newton_batch", "workload": f"{len(pbs)} seeded Poisson/Burgers instances "
+                      "(quads/triangles, n 4..32, p 1..4)", "instances": len(pbs),
+                      "elements": int(sum(pb.mesh.ne for pb in pbs)), "trace_dofs": bp.bt.total("vec"),
+                      "element_blocks_s": t_blk, "newton_s": min(runs), "newton_runs_s": runs,
+                      "converged": int(sum(conv)), "steps_max": max(steps), "steps_mean": float(np.mean(steps)),
+                      "instances_damped": damped, "pseudo_transient": ptc,
+                      "not_converged": [dict(instance=i, etype=pbs[i].etype, ne=pbs[i].mesh.ne, p=pbs[i].p,
+                                             pde=type(pbs[i].phys).__name__, steps=steps[i],
+                                             reduction=hists[i][-1]["norm"] / hists[i][0]["norm"],
+                                             alphas=[x["alpha"] for x in hists[i][:-1]][-8:],
+                                             gmres_iters=[x["iters"] for x in hists[i][:-1]][-8:])
+                                        for i in range(len(hists)) if not conv[i]],
+                      "gmres_iters_per_step_max": [max((h[k]["iters"] for h in hists if k < len(h) - 1), default=0)
+                                                   for k in range(max(steps))],
+                      "burgers": int(sum(1 for pb in pbs if type(pb.phys).__name__ == "Burgers"))}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +390,9 @@ def main():
     ap.add_argument("--newton", type=int, default=0,
                     help="instead of the headline: damped Newton on 2D viscous Burgers with this many quads per "
                          "direction at degree --p (element-kernel rates and the Newton loop), then exit")
+    ap.add_argument("--newton-batch", type=int, default=0,
+                    help="instead of the headline: damped Newton on this many instances of the batched "
+                         "Poisson/Burgers workload in one batch (512: the whole workload), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the hot path is "
@@ -329,6 +407,9 @@ def main():
     torch.cuda.set_device(0)
     if args.newton > 0:
         newton_bench(args)
+        return
+    if args.newton_batch > 0:
+        newton_batch_bench(args)
         return
     t0 = time.perf_counter()
     pb = configs.c2(n=args.n, p=args.p, device="cuda")

@@ -57,3 +57,34 @@ def damped_newton(g, m, u0, uhat0, e2f, f2e, dims, rtol=1e-10, atol=1e-14, max_s
         u, uhat, nrm, blk = ut, uht, nt_, blkt
     hist.append(dict(norm=nrm, alpha=0.0))
     return u, uhat, hist
+
+
+def pseudo_transient(g, m, u0, uhat0, e2f, f2e, dims, dtau0, rtol=1e-10, atol=1e-14, max_steps=200, dtau_max=1e12):
+    """Pseudo-transient continuation (backward Euler in pseudo-time, Section 2.2's use of DIRK
+    schemes for pseudo-transient runs) with switched evolution relaxation (Mulder and Van Leer,
+    J. Comput. Phys. 59 (1985); analysed by Kelley and Keyes, SIAM J. Numer. Anal. 35 (1998)):
+    each pseudo-step is one full Newton step on R(u) + M (u - u_k) / dtau_k = 0 from u_k (whose
+    residual at u_k is the steady one), then dtau_{k+1} = min(dtau_k ||R(u_k)|| / ||R(u_{k+1})||,
+    dtau_max). Stops at ||R|| <= max(rtol ||R(u_0)||, atol) (steady norm). Returns (u, uhat,
+    history) with history[k] = dict(norm, dtau) before step k."""
+    u, uhat = u0.copy(), uhat0.copy()
+    nrm, _ = residual_norm(g, m, u, uhat, e2f, f2e, dims)
+    n0 = nrm
+    dtau = dtau0
+    hist = []
+    for _ in range(max_steps):
+        if nrm <= max(rtol * n0, atol):
+            break
+        blk = elements.element_blocks(g, m, u, uhat, e2f, dict(c=1.0 / dtau, u_prev=u.copy(), r_extra=None))
+        Kb, rb = condense.condense(blk, dims)
+        K, nbr, r = assemble.assemble(Kb, rb, f2e, e2f, dims)
+        dx = spla.spsolve(assemble.to_sparse(K, nbr).tocsc(), r)
+        _, du = condense.recover(blk, dx, e2f, dims)
+        u = u + du
+        uhat = uhat + dx.reshape(uhat.shape)
+        new, _ = residual_norm(g, m, u, uhat, e2f, f2e, dims)
+        hist.append(dict(norm=nrm, dtau=dtau))
+        dtau = min(dtau * nrm / new, dtau_max)
+        nrm = new
+    hist.append(dict(norm=nrm, dtau=0.0))
+    return u, uhat, hist

@@ -172,9 +172,9 @@ hdg_status hdg_batch_offsets(hdg_batch b, int32_t array_id, int64_t* off_h) {
 int32_t hdg_batch_tuned_grid(hdg_batch b) { return b ? b->tuned_grid : 0; }
 
 hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv_h, const int32_t* nqf_h,
-                                    const hdg_elem_geom* g, const hdg_conv_diff* models_h, const int32_t* e2f,
-                                    const double* u, const double* uhat, int32_t residual_only,
-                                    const hdg_elem_arrays* out) {
+                                    const hdg_elem_geom* g, const hdg_conv_diff* models_h, const double* c_h,
+                                    const double* u_prev, const int32_t* e2f, const double* u, const double* uhat,
+                                    int32_t residual_only, const hdg_elem_arrays* out) {
     if (!ctx || !b) return HDG_ERR_ARG;
     if (!nqv_h || !nqf_h || !g || !models_h || !e2f || !u || !uhat || !out || !out->ru || !out->rt || !g->wdet ||
         !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD || !g->bnd) {
@@ -224,6 +224,12 @@ hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv
         E.q_off = q.dq_off;
         for (int a = 0; a < 11; ++a) E.out_off[a] = q.off[a];
         E.nu = nu_; E.tau = tau_;
+        E.c = c_h ? c_h[i] : 0.0;
+        if (!std::isfinite(E.c) || (E.c != 0.0 && !u_prev)) {
+            ctx->err = "hdg_element_blocks_batch: instance " + std::to_string(i) +
+                       " has a non-finite time-term factor or no u_prev";
+            return HDG_ERR_ARG;
+        }
         for (int d = 0; d < 3; ++d) { E.beta[d] = models_h[i].beta[d]; E.gamma[d] = models_h[i].gamma[d]; }
     }
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
@@ -242,6 +248,7 @@ hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv
     a.e2f = e2f;
     a.u = u;
     a.uhat = uhat;
+    a.u_prev = u_prev;
     a.out = *out;
     a.bad = status;
     a.residual_only = residual_only;

@@ -51,12 +51,13 @@ struct ElemInst {
     int64_t e2f_off, u_off, uh_off, q_off;
     int64_t out_off[11];            // Minv, Bd, Cd, D, E, F, G, H, J, ru, rt
     double nu, tau, beta[3], gamma[3];
+    double c;                       // time-term factor of the instance (0: steady)
 };
 
 struct ElemBatchArgs {
     hdg_elem_geom g;                // concatenated arrays (nqv, nqf unused)
     const int32_t* e2f;
-    const double *u, *uhat;
+    const double *u, *uhat, *u_prev;   // u_prev: batch array like u (read where c != 0)
     hdg_elem_arrays out;
     int* bad;
     int residual_only;

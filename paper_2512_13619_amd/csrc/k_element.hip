@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks_batch(const ElemInst* __
     v.e2f = a.e2f + q.e2f_off + E * L;
     v.u = a.u + q.u_off + E * P;
     v.uhat = a.uhat + q.uh_off;
-    v.u_prev = nullptr;
+    v.u_prev = (q.c != 0.0) ? a.u_prev + q.u_off + E * P : nullptr;
     v.r_extra = nullptr;
     const bool mats = !a.residual_only;
     v.Minv = mats ? a.out.Minv + q.out_off[0] + E * P * P : nullptr;
@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks_batch(const ElemInst* __
     v.P = P; v.PF = PF; v.L = L; v.Dm = D; v.Qv = Qv; v.Qf = Qf;
     v.residual_only = a.residual_only;
     v.eid = (int)e;
-    v.nu = q.nu; v.tau = q.tau; v.c = 0.0;
+    v.nu = q.nu; v.tau = q.tau; v.c = q.c;
     for (int d = 0; d < 3; ++d) { v.beta[d] = q.beta[d]; v.gamma[d] = q.gamma[d]; }
     v.bad = a.bad;
     element_body(v, sm);

@@ -138,7 +138,8 @@ def load():
                                           ctypes.POINTER(SolveStats)]
     lib.hdg_recover_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_element_blocks_batch.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ElemGeom),
-                                             ctypes.POINTER(ConvDiff), vp, vp, vp, i32, ctypes.POINTER(ElemArrays)]
+                                             ctypes.POINTER(ConvDiff), ctypes.POINTER(dbl), vp, vp, vp, vp, i32,
+                                             ctypes.POINTER(ElemArrays)]
     lib.hdg_residual_norm_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.hdg_newton_update_batch.argtypes = [vp, vp, ctypes.POINTER(dbl), vp, vp, vp, vp]
     for name in SYMBOLS:
@@ -531,9 +532,10 @@ class Batch:
             self.ctx.h, self.h, ctypes.byref(eb), _ptr(Kbar, f64, self.total("Kbar"), "Kbar"),
             _ptr(rbar, f64, self.total("rbar"), "rbar"), _ptr(local, f64, self.total("local"), "local")))
 
-    def element_blocks(self, nqv, nqf, geom, models, e2f, u, uhat, out, residual_only=False):
+    def element_blocks(self, nqv, nqf, geom, models, e2f, u, uhat, out, residual_only=False, c=None, u_prev=None):
         """Batched hdg_element_blocks: nqv, nqf and models (dicts nu, tau, beta, gamma) per
-        instance; geom's arrays concatenated in instance order; the rest are batch arrays."""
+        instance; geom's arrays concatenated in instance order; the rest are batch arrays;
+        c (per instance) with u_prev: a time term per instance."""
         import torch
         f64 = torch.float64
         n = self.n
@@ -557,8 +559,15 @@ class Batch:
         ptrs = [_ptr(out.get(k), f64, self.total(k), k, allow_none=True) for k in names]
         ptrs.append(_ptr(out.get("q"), f64, self.total("dq"), "q", allow_none=True))
         o = ElemArrays(*ptrs)
+        c_a = None
+        if c is not None:
+            c_np = np.ascontiguousarray(c, dtype=np.float64)
+            assert c_np.shape == (n,)
+            c_a = c_np.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         return self.ctx._check(self.lib.hdg_element_blocks_batch(
-            self.ctx.h, self.h, qv_a, qf_a, ctypes.byref(g), ms, _ptr(e2f, torch.int32, self.total("e2f"), "e2f"),
+            self.ctx.h, self.h, qv_a, qf_a, ctypes.byref(g), ms, c_a,
+            _ptr(u_prev, f64, self.total("du"), "u_prev", allow_none=True),
+            _ptr(e2f, torch.int32, self.total("e2f"), "e2f"),
             _ptr(u, f64, self.total("du"), "u"), _ptr(uhat, f64, self.total("vec"), "uhat"), int(bool(residual_only)),
             ctypes.byref(o)))
 

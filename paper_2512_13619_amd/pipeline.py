@@ -263,3 +263,47 @@ class BatchPipeline:
         for i in range(n):
             hists[i].append(dict(norm=float(nrm[i]), alpha=0.0, iters=0))
         return hists
+
+    def pseudo_transient(self, nqv, nqf, geom, models, u, uhat, dtau0, tol=1e-10, atol=0.0, max_steps=200,
+                         dtau_max=1e12, **solve_kw):
+        """Pseudo-transient continuation for every instance (backward Euler in pseudo-time,
+        Section 2.2, with switched evolution relaxation): a pseudo-step is one full Newton step
+        on R(u) + M (u - u_k)/dtau_k = 0 from u_k, then dtau_{k+1} = min(dtau_k ||R(u_k)|| /
+        ||R(u_{k+1})||, dtau_max), per instance; each instance stops at max(tol ||R(u_0)||, atol)
+        of its steady residual. Returns one history per instance: dict(norm, dtau, iters) per
+        step and a last entry with the final norm."""
+        import numpy as np
+        bt = self.bt
+        n = bt.n
+        blk = self.element_arrays()
+        res = {"ru": blk["ru"], "rt": blk["rt"]}
+        u_prev = torch.zeros_like(u)
+        bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, res, residual_only=True)
+        nrm = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
+        stop = np.maximum(tol * nrm, atol)
+        dtau = np.full(n, float(dtau0))
+        hists = [[] for _ in range(n)]
+        off = bt.offsets("vec")
+        for _ in range(max_steps):
+            active = nrm > stop
+            if not active.any():
+                break
+            u_prev.copy_(u)
+            bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk, c=np.where(active, 1.0 / dtau, 0.0),
+                              u_prev=u_prev)
+            self.condense(blk)
+            self.assemble()
+            for i in np.nonzero(~active)[0]:
+                self.r[off[i]:off[i + 1]] = 0.0
+            _, stats = self.solve(**solve_kw)
+            self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+            bt.newton_update(np.where(active, 1.0, 0.0), self.du, u, self.x, uhat)
+            bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, res, residual_only=True)
+            new = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
+            for i in np.nonzero(active)[0]:
+                hists[i].append(dict(norm=float(nrm[i]), dtau=float(dtau[i]), iters=int(stats[i]["iters"])))
+                dtau[i] = min(dtau[i] * nrm[i] / new[i], dtau_max)
+                nrm[i] = new[i]
+        for i in range(n):
+            hists[i].append(dict(norm=float(nrm[i]), dtau=0.0, iters=0))
+        return hists

@@ -341,3 +341,29 @@ def test_batch_element_blocks_match_single_instance(ctx):
             assert torch.equal(out[k][o[i]:o[i + 1]], ref[k]), (i, k)
         want = ctx.residual_norm(pb.dims(), pl.f2e, ref["ru"], ref["rt"])
         assert abs(norms[i] - want) <= 1e-13 * want, (i, norms[i], want)
+
+
+def test_batch_pseudo_transient_matches_per_instance_oracle(ctx):
+    from paper_2512_13619_amd.pipeline import BatchPipeline
+    pbs = _batch_instances()
+    inps = [pb.newton_inputs() for pb in pbs]
+    bp = BatchPipeline(ctx, [pb.dims() for pb in pbs], [pb.mesh.f2e for pb in pbs], [pb.mesh.e2f for pb in pbs])
+    keys = ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")
+    geom = {k: torch.cat([inp[k].reshape(-1) for inp in inps]).cuda().contiguous() for k in keys}
+    u = torch.cat([inp["u0"].reshape(-1) for inp in inps]).cuda().contiguous()
+    uh = torch.cat([inp["uhat0"].reshape(-1) for inp in inps]).cuda().contiguous()
+    hists = bp.pseudo_transient([inp["nqv"] for inp in inps], [inp["nqf"] for inp in inps], geom,
+                                [_model(inp) for inp in inps], u, uh, 0.05, tol=1e-11, restart=50, max_iters=3000,
+                                rtol=1e-13, prec="bj")
+    ou, oh = bp.bt.offsets("du"), bp.bt.offsets("vec")
+    for i, (pb, inp) in enumerate(zip(pbs, inps)):
+        inp_np = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in inp.items()}
+        u_ref, uh_ref, h_ref = ON.pseudo_transient(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"],
+                                                   pb.mesh.e2f, pb.mesh.f2e, pb.dims(), 0.05, rtol=1e-11)
+        say("  ptc instance", i, len(hists[i]) - 1, f"{hists[i][-1]['norm']:.2e}")
+        assert len(hists[i]) == len(h_ref), i
+        for a, b in zip(hists[i], h_ref):
+            assert abs(a["norm"] - b["norm"]) <= 1e-7 * h_ref[0]["norm"], i
+            assert abs(a["dtau"] - b["dtau"]) <= 1e-6 * max(b["dtau"], 1e-300), i
+        assert relerr(u[ou[i]:ou[i + 1]].cpu().numpy(), u_ref.ravel()) < 1e-9, i
+        assert relerr(uh[oh[i]:oh[i + 1]].cpu().numpy(), uh_ref.ravel()) < 1e-9, i

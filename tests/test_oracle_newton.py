@@ -191,3 +191,29 @@ def test_dirk_temporal_convergence_orders():
         err = [np.abs(ODK.dirk_steps(*args, T / n, n, scheme)[0] - ref).max() for n in ns]
         rates = [np.log2(err[k] / err[k + 1]) for k in range(len(err) - 1)]
         assert all(abs(r - p) < 0.35 for r in rates), (scheme, err, rates)
+
+
+def test_pseudo_transient_reaches_the_newton_solution():
+    """Pseudo-transient continuation converges to the same discrete solution as damped Newton
+    (the steady equations have one solution near the start), its first step with dtau -> inf is
+    a Newton step, and on a linear problem it converges once dtau has grown."""
+    pb = CASES["burgers_quad_p2"]()
+    inp = _np(pb.newton_inputs())
+    m = _model(inp)
+    d = pb.dims()
+    args = (inp, m, inp["u0"], inp["uhat0"], pb.mesh.e2f, pb.mesh.f2e, d)
+    u_n, uh_n, _ = ON.damped_newton(*args, rtol=1e-12)
+    u_p, uh_p, hist = ON.pseudo_transient(*args, 0.05, rtol=1e-12)
+    assert hist[-1]["norm"] <= 1e-12 * hist[0]["norm"]
+    assert np.abs(u_p - u_n).max() < 1e-9 * np.abs(u_n).max()
+    assert np.abs(uh_p - uh_n).max() < 1e-9 * np.abs(uh_n).max()
+    # dtau -> inf: one pseudo-step is the undamped Newton step
+    u1, uh1, h1 = ON.pseudo_transient(*args, 1e300, max_steps=1)
+    un1, uhn1, hn1 = ON.damped_newton(*args, max_steps=1, min_alpha=1.0)
+    assert np.abs(u1 - un1).max() < 1e-12 * np.abs(un1).max()
+    # linear problem
+    pb2 = CASES["poisson_quad_p2"]()
+    inp2 = _np(pb2.newton_inputs())
+    _, _, h2 = ON.pseudo_transient(inp2, _model(inp2), inp2["u0"], inp2["uhat0"], pb2.mesh.e2f, pb2.mesh.f2e,
+                                   pb2.dims(), 0.01, rtol=1e-11)
+    assert h2[-1]["norm"] <= 1e-11 * h2[0]["norm"] and len(h2) < 30
