@@ -202,15 +202,20 @@ def second_stage(args, pl, blk, d, stream):
     return out
 
 
-def element_bytes(d, nqv, nqf, residual_only):
+def element_bytes(d, nqv, nqf, residual_only, keep_mass=False):
     """Algorithmic HBM bytes per element of hdg_element_blocks (scalar model): the element's
-    geometry and state read once, every output written once (reference tables not counted)."""
+    geometry and state read once, every output written once (reference tables not counted);
+    with the mass matrices kept, M^-1 is read and M^-1, B_d, C_d are not written."""
     P, PF, L, D = d["npe"], d["npf"], d["nlfe"], d["dim"]
     nt = L * PF
     rd = nqv * (1 + P * D + 1) + L * nqf * (P + D + 2) + P + nt + 2 * L * 4 / 8
     wr = P + nt + D * P
     if not residual_only:
-        wr += P * P + D * P * P + D * P * nt + P * D * P + P * P + P * nt + nt * D * P + nt * P + nt * nt
+        wr += P * D * P + P * P + P * nt + nt * D * P + nt * P + nt * nt
+    if keep_mass:
+        rd += P * P
+    elif not residual_only:
+        wr += P * P + D * P * P + D * P * nt
     return 8 * (rd + wr)
 
 
@@ -244,19 +249,20 @@ def newton_bench(args):
     uh = inp["uhat0"].flatten().clone()
     stream = torch.cuda.current_stream()
     rates = {}
-    for ro in (False, True):
-        ctx.element_blocks(d, geom, model, pl.e2f, u, uh, blk, residual_only=ro)
+    ctx.element_blocks(d, geom, model, pl.e2f, u, uh, blk)
+    for ro, keep in ((False, False), (True, False), (False, True), (True, True)):
         reps = 20
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(reps):
-            ctx.element_blocks(d, geom, model, pl.e2f, u, uh, blk, residual_only=ro)
+            ctx.element_blocks(d, geom, model, pl.e2f, u, uh, blk, residual_only=ro, keep_mass=keep)
         ev1.record(stream)
         torch.cuda.synchronize()
         t = ev0.elapsed_time(ev1) / 1e3 / reps
-        by = element_bytes(d, geom["nqv"], geom["nqf"], ro) * d["ne"]
-        rates["residual_only" if ro else "blocks"] = dict(ms=t * 1e3, bytes=by, GBs=by / t / 1e9)
+        by = element_bytes(d, geom["nqv"], geom["nqf"], ro, keep) * d["ne"]
+        name = ("residual_only" if ro else "blocks") + ("_kept_mass" if keep else "")
+        rates[name] = dict(ms=t * 1e3, bytes=by, GBs=by / t / 1e9)
     runs = {}
     for graph in (False, True):
         u.copy_(inp["u0"].flatten())

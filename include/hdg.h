@@ -314,6 +314,15 @@ typedef struct {
     const double* r_extra;
 } hdg_time_term;
 
+/* flags of hdg_element_blocks(_batch) */
+enum {
+    HDG_ELEM_RESIDUAL_ONLY = 1,  /* write ru, rt (and q) only */
+    HDG_ELEM_KEEP_MASS = 2       /* Minv, Bd, Cd in `out` already hold this mesh's (from an earlier
+                                    call): Minv is read instead of formed and inverted, and none
+                                    of the three is written (they depend on the geometry only,
+                                    Section 4.1 precomputes them once) */
+};
+
 /* Device outputs in the layouts hdg_condense reads, plus q [ne][dim][npe] (may be NULL). */
 typedef struct {
     double *Minv, *Bd, *Cd, *D, *E, *F, *G, *H, *J, *ru, *rt, *q;
@@ -322,9 +331,11 @@ typedef struct {
 /* hdg_element_blocks: at the state u [ne][npe] (nodal) and uhat [nf][npf] (face values,
  *   canonical order; element e's face l is uhat[e2f[e][l]]), with q derived from the
  *   q-equation (M q_d + B_d u + C_d uhat = 0, eq. w16, so r_q = 0), writes ru = -R_u,
- *   rt = -R_t and, unless residual_only, Minv, Bd, Cd, D, E, F, G, H, J (the derivatives of
- *   R_u and R_t with respect to q, u, uhat). time_term (may be NULL) adds an implicit stage's
- *   mass term (HDG_ERR_ARG if c != 0 without u_prev). Outputs not written may be NULL. One workgroup
+ *   rt = -R_t and, unless flags has HDG_ELEM_RESIDUAL_ONLY, Minv, Bd, Cd, D, E, F, G, H, J
+ *   (the derivatives of R_u and R_t with respect to q, u, uhat; with HDG_ELEM_KEEP_MASS,
+ *   Minv, Bd and Cd are inputs, Minv required). time_term (may be NULL) adds an implicit
+ *   stage's mass term (HDG_ERR_ARG if c != 0 without u_prev). Outputs not written may be
+ *   NULL. One workgroup
  *   per element with its data in LDS: HDG_ERR_SHAPE if the element needs more than 64 KiB;
  *   HDG_ERR_ARG for ncomp != 1. HDG_ERR_SINGULAR names the first element whose mass matrix
  *   has a non-positive pivot (synchronises to read it).
@@ -334,7 +345,7 @@ typedef struct {
 hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* geom,
                               const hdg_conv_diff* model, const hdg_time_term* time_term,
                               const int32_t* e2f, const double* u, const double* uhat,
-                              int32_t residual_only, const hdg_elem_arrays* out);
+                              int32_t flags, const hdg_elem_arrays* out);
 hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
                              const double* rt, double* norm_h);
 
@@ -435,7 +446,7 @@ hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv
                                     const hdg_elem_geom* geom, const hdg_conv_diff* models_h,
                                     const double* c_h, const double* u_prev,
                                     const int32_t* e2f, const double* u, const double* uhat,
-                                    int32_t residual_only, const hdg_elem_arrays* out);
+                                    int32_t flags, const hdg_elem_arrays* out);
 hdg_status hdg_residual_norm_batch(hdg_ctx ctx, hdg_batch b, const int32_t* f2e, const double* ru,
                                    const double* rt, double* norms_h);
 hdg_status hdg_newton_update_batch(hdg_ctx ctx, hdg_batch b, const double* alpha_h, const double* du,

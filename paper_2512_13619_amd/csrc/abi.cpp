@@ -278,7 +278,7 @@ hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double*
 
 hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* g, const hdg_conv_diff* m,
                               const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
-                              int32_t residual_only, const hdg_elem_arrays* out) {
+                              int32_t flags, const hdg_elem_arrays* out) {
     if (!ctx) return HDG_ERR_ARG;
     GUARD_BEGIN
     hdg_status st = check_dims(ctx, dims, false, false);
@@ -290,6 +290,11 @@ hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_
     if (!g->wdet || !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD ||
         !g->bnd || !e2f || !u || !uhat || !out->ru || !out->rt)
         return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: NULL pointer");
+    const bool residual_only = (flags & HDG_ELEM_RESIDUAL_ONLY) != 0;
+    if (flags & ~(HDG_ELEM_RESIDUAL_ONLY | HDG_ELEM_KEEP_MASS))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: unknown flags");
+    if ((flags & HDG_ELEM_KEEP_MASS) && !out->Minv)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: HDG_ELEM_KEEP_MASS needs the kept Minv");
     if (!residual_only && (!out->Minv || !out->Bd || !out->Cd || !out->D || !out->E || !out->F || !out->G ||
                            !out->H || !out->J))
         return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks: NULL matrix output (residual_only = 0)");
@@ -304,7 +309,7 @@ hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_
     if (!status) return st;
     const int big = 0x7fffffff;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-    if ((st = element_blocks_run(ctx, dims, g, m, tt, e2f, u, uhat, residual_only, out, status)) != HDG_OK) return st;
+    if ((st = element_blocks_run(ctx, dims, g, m, tt, e2f, u, uhat, flags, out, status)) != HDG_OK) return st;
     int bad = big;
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));

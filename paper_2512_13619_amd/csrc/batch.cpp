@@ -174,11 +174,17 @@ int32_t hdg_batch_tuned_grid(hdg_batch b) { return b ? b->tuned_grid : 0; }
 hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv_h, const int32_t* nqf_h,
                                     const hdg_elem_geom* g, const hdg_conv_diff* models_h, const double* c_h,
                                     const double* u_prev, const int32_t* e2f, const double* u, const double* uhat,
-                                    int32_t residual_only, const hdg_elem_arrays* out) {
+                                    int32_t flags, const hdg_elem_arrays* out) {
     if (!ctx || !b) return HDG_ERR_ARG;
     if (!nqv_h || !nqf_h || !g || !models_h || !e2f || !u || !uhat || !out || !out->ru || !out->rt || !g->wdet ||
         !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD || !g->bnd) {
         ctx->err = "hdg_element_blocks_batch: NULL pointer";
+        return HDG_ERR_ARG;
+    }
+    const bool residual_only = (flags & HDG_ELEM_RESIDUAL_ONLY) != 0;
+    if ((flags & ~(HDG_ELEM_RESIDUAL_ONLY | HDG_ELEM_KEEP_MASS)) ||
+        ((flags & HDG_ELEM_KEEP_MASS) && !out->Minv)) {
+        ctx->err = "hdg_element_blocks_batch: unknown flags, or HDG_ELEM_KEEP_MASS without the kept Minv";
         return HDG_ERR_ARG;
     }
     if (!residual_only && (!out->Minv || !out->Bd || !out->Cd || !out->D || !out->E || !out->F || !out->G ||
@@ -251,7 +257,8 @@ hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv
     a.u_prev = u_prev;
     a.out = *out;
     a.bad = status;
-    a.residual_only = residual_only;
+    a.residual_only = residual_only ? 1 : 0;
+    a.keep_mass = (flags & HDG_ELEM_KEEP_MASS) ? 1 : 0;
     if (lds > 64 * 1024) lds = 64 * 1024;
     if ((st = element_blocks_batch_run(ctx, b->dev.total_ne, (const ElemInst*)base, b->dev.eid, a, lds)) != HDG_OK)
         return st;

@@ -60,7 +60,7 @@ struct ElemBatchArgs {
     const double *u, *uhat, *u_prev;   // u_prev: batch array like u (read where c != 0)
     hdg_elem_arrays out;
     int* bad;
-    int residual_only;
+    int residual_only, keep_mass;
 };
 
 size_t element_batch_lds_bytes(int P, int PF, int L, int D, int nqv, int nqf);

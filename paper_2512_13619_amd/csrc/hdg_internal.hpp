@@ -222,7 +222,7 @@ hdg_status axpy_run(hdg_ctx ctx, int64_t n, double alpha, const double* x, doubl
 size_t element_blocks_lds_bytes(const hdg_dims* d, int nqv, int nqf);
 hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geom* g, const hdg_conv_diff* m,
                               const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
-                              int residual_only, const hdg_elem_arrays* out, int* bad);
+                              int flags, const hdg_elem_arrays* out, int* bad);
 
 // Host-side eigenvalues / harmonic Ritz values (ritz.cpp).
 int hessenberg_eigvals(int n, double* H, int ld, double* wr, double* wi);

@@ -27,7 +27,7 @@ struct ElemView {
     const int32_t *bnd, *e2f;
     const double *u, *uhat, *u_prev, *r_extra;
     double *Minv, *Bd, *Cd, *D, *E, *F, *G, *H, *J, *ru, *rt, *q;
-    int P, PF, L, Dm, Qv, Qf, residual_only, eid;
+    int P, PF, L, Dm, Qv, Qf, residual_only, keep_mass, eid;
     double nu, tau, beta[3], gamma[3], c;
     int* bad;              // first element with a non-positive mass pivot
 };
@@ -43,7 +43,7 @@ struct ElemArgs {
     const double* u_prev;  // [ne][P], read when c != 0
     const double* r_extra; // [ne][P] or null
     int* bad;
-    int ne, P, PF, L, D, residual_only;
+    int ne, P, PF, L, D, residual_only, keep_mass;
 };
 
 // LDS offsets (in doubles) of the element's staged arrays
@@ -124,46 +124,52 @@ __device__ __forceinline__ void element_body(const ElemView& a, double* sm) {
     }
     __syncthreads();
 
-    // 2. mass matrix and its inverse (Gauss-Jordan in place; M is SPD, no interchanges)
+    // 2. mass matrix and its inverse (Gauss-Jordan in place; M is SPD, no interchanges), or
+    //    the inverse kept from an earlier evaluation on the same mesh (state-independent)
     const int nJT = (P + TJ - 1) / TJ;    // column tiles of TJ entries: one row i per work item
-    for (int it = tid; it < P * nJT; it += EBS) {
-        const int i = it / nJT, j0 = (it - i * nJT) * TJ;
-        double acc[TJ] = {};
-        for (int x = 0; x < Qv; ++x) {
-            const double wi = wdet[x] * phi[x * P + i];
+    if (a.keep_mass) {
+        for (int k = tid; k < P * P; k += EBS) Mm[k] = a.Minv[k];
+        __syncthreads();
+    } else {
+        for (int it = tid; it < P * nJT; it += EBS) {
+            const int i = it / nJT, j0 = (it - i * nJT) * TJ;
+            double acc[TJ] = {};
+            for (int x = 0; x < Qv; ++x) {
+                const double wi = wdet[x] * phi[x * P + i];
+#pragma unroll
+                for (int jj = 0; jj < TJ; ++jj)
+                    if (j0 + jj < P) acc[jj] += wi * phi[x * P + j0 + jj];
+            }
 #pragma unroll
             for (int jj = 0; jj < TJ; ++jj)
-                if (j0 + jj < P) acc[jj] += wi * phi[x * P + j0 + jj];
-        }
-#pragma unroll
-        for (int jj = 0; jj < TJ; ++jj)
-            if (j0 + jj < P) Mm[i * P + j0 + jj] = acc[jj];
-    }
-    __syncthreads();
-    for (int k = 0; k < P; ++k) {
-        const double piv = Mm[k * P + k];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (tid == 0) atomicMin(a.bad, e);
-            return;    // uniform across the workgroup: every thread read the same pivot
-        }
-        const double rp = 1.0 / piv;
-        // row k scaled (entry k becomes 1/piv), other rows updated with the old column k
-        for (int idx = tid; idx < P * P; idx += EBS) {
-            const int i = idx / P, j = idx - i * P;
-            if (i == k) continue;
-            const double f = Mm[i * P + k] * rp;
-            if (j == k) continue;
-            Mm[idx] -= f * Mm[k * P + j];
+                if (j0 + jj < P) Mm[i * P + j0 + jj] = acc[jj];
         }
         __syncthreads();
-        for (int idx = tid; idx < P; idx += EBS) {
-            if (idx != k) {
-                Mm[idx * P + k] = -Mm[idx * P + k] * rp;
-                Mm[k * P + idx] *= rp;
+        for (int k = 0; k < P; ++k) {
+            const double piv = Mm[k * P + k];
+            if (!(piv > 0.0) || !isfinite(piv)) {
+                if (tid == 0) atomicMin(a.bad, e);
+                return;    // uniform across the workgroup: every thread read the same pivot
             }
+            const double rp = 1.0 / piv;
+            // row k scaled (entry k becomes 1/piv), other rows updated with the old column k
+            for (int idx = tid; idx < P * P; idx += EBS) {
+                const int i = idx / P, j = idx - i * P;
+                if (i == k) continue;
+                const double f = Mm[i * P + k] * rp;
+                if (j == k) continue;
+                Mm[idx] -= f * Mm[k * P + j];
+            }
+            __syncthreads();
+            for (int idx = tid; idx < P; idx += EBS) {
+                if (idx != k) {
+                    Mm[idx * P + k] = -Mm[idx * P + k] * rp;
+                    Mm[k * P + idx] *= rp;
+                }
+            }
+            if (tid == 0) Mm[k * P + k] = rp;
+            __syncthreads();
         }
-        if (tid == 0) Mm[k * P + k] = rp;
-        __syncthreads();
     }
 
     // 3. u and uhat at the quadrature points
@@ -267,7 +273,9 @@ __device__ __forceinline__ void element_body(const ElemView& a, double* sm) {
     // 7. matrices. With dF/dq = -nu I: the volume part of D is nu B_d, and G on an interior
     // face is -nu C_d^T; the (i, j) sums over volume and face points share one pass with
     // the row's per-point values held in registers.
-    for (int k = tid; k < P * P; k += EBS) a.Minv[k] = Mm[k];
+    const bool put_mass = !a.keep_mass;      // Minv, Bd, Cd: written unless kept
+    if (put_mass)
+        for (int k = tid; k < P * P; k += EBS) a.Minv[k] = Mm[k];
     for (int it = tid; it < P * nJT; it += EBS) {        // Bd, D, E
         const int i = it / nJT, j0 = (it - i * nJT) * TJ;
         double bd[3][TJ] = {}, sf[3][TJ] = {}, ev[TJ] = {}, ef[TJ] = {}, mm[TJ] = {};
@@ -308,7 +316,7 @@ __device__ __forceinline__ void element_body(const ElemView& a, double* sm) {
             const int j = j0 + jj;
             if (j >= P) continue;
             for (int d = 0; d < D; ++d) {
-                a.Bd[(size_t)(d * P + i) * P + j] = bd[d][jj];
+                if (put_mass) a.Bd[(size_t)(d * P + i) * P + j] = bd[d][jj];
                 a.D[(size_t)i * D * P + d * P + j] = nu * (bd[d][jj] - sf[d][jj]);
             }
             a.E[(size_t)i * P + j] = ev[jj] + tau * ef[jj] + cdt * mm[jj];
@@ -327,7 +335,7 @@ __device__ __forceinline__ void element_body(const ElemView& a, double* sm) {
         }
         const bool interior = a.bnd[l] == 0;
         for (int d = 0; d < D; ++d) {
-            a.Cd[(size_t)(d * P + i) * nt + c] = cd[d];
+            if (put_mass) a.Cd[(size_t)(d * P + i) * nt + c] = cd[d];
             a.G[(size_t)c * D * P + d * P + i] = interior ? -nu * cd[d] : 0.0;
         }
         a.F[(size_t)i * nt + c] = f;
@@ -368,7 +376,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
     v.u_prev = a.u_prev ? a.u_prev + E * P : nullptr;
     v.r_extra = a.r_extra ? a.r_extra + E * P : nullptr;
     const bool mats = !a.residual_only;
-    v.Minv = mats ? a.out.Minv + E * P * P : nullptr;
+    v.Minv = (mats || a.keep_mass) ? a.out.Minv + E * P * P : nullptr;
     v.Bd = mats ? a.out.Bd + E * D * P * P : nullptr;
     v.Cd = mats ? a.out.Cd + E * D * P * nt : nullptr;
     v.D = mats ? a.out.D + E * P * D * P : nullptr;
@@ -382,6 +390,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks(ElemArgs a) {
     v.q = a.out.q ? a.out.q + E * D * P : nullptr;
     v.P = P; v.PF = PF; v.L = L; v.Dm = D; v.Qv = Qv; v.Qf = Qf;
     v.residual_only = a.residual_only;
+    v.keep_mass = a.keep_mass;
     v.eid = (int)E;
     v.nu = a.m.nu; v.tau = a.m.tau; v.c = a.c;
     for (int d = 0; d < 3; ++d) { v.beta[d] = a.m.beta[d]; v.gamma[d] = a.m.gamma[d]; }
@@ -415,7 +424,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks_batch(const ElemInst* __
     v.u_prev = (q.c != 0.0) ? a.u_prev + q.u_off + E * P : nullptr;
     v.r_extra = nullptr;
     const bool mats = !a.residual_only;
-    v.Minv = mats ? a.out.Minv + q.out_off[0] + E * P * P : nullptr;
+    v.Minv = (mats || a.keep_mass) ? a.out.Minv + q.out_off[0] + E * P * P : nullptr;
     v.Bd = mats ? a.out.Bd + q.out_off[1] + E * D * P * P : nullptr;
     v.Cd = mats ? a.out.Cd + q.out_off[2] + E * D * P * nt : nullptr;
     v.D = mats ? a.out.D + q.out_off[3] + E * P * D * P : nullptr;
@@ -429,6 +438,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks_batch(const ElemInst* __
     v.q = a.out.q ? a.out.q + q.q_off + E * D * P : nullptr;
     v.P = P; v.PF = PF; v.L = L; v.Dm = D; v.Qv = Qv; v.Qf = Qf;
     v.residual_only = a.residual_only;
+    v.keep_mass = a.keep_mass;
     v.eid = (int)e;
     v.nu = q.nu; v.tau = q.tau; v.c = q.c;
     for (int d = 0; d < 3; ++d) { v.beta[d] = q.beta[d]; v.gamma[d] = q.gamma[d]; }
@@ -518,7 +528,7 @@ size_t element_blocks_lds_bytes(const hdg_dims* d, int nqv, int nqf) {
 
 hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geom* g, const hdg_conv_diff* m,
                               const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
-                              int residual_only, const hdg_elem_arrays* out, int* bad) {
+                              int flags, const hdg_elem_arrays* out, int* bad) {
     if (d->ne == 0) return HDG_OK;
     ElemArgs a;
     a.g = *g;
@@ -536,7 +546,8 @@ hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geo
     a.PF = d->npf;
     a.L = d->nlfe;
     a.D = d->dim;
-    a.residual_only = residual_only;
+    a.residual_only = (flags & HDG_ELEM_RESIDUAL_ONLY) != 0;
+    a.keep_mass = (flags & HDG_ELEM_KEEP_MASS) != 0;
     const size_t lds = element_blocks_lds_bytes(d, g->nqv, g->nqf);
     hipLaunchKernelGGL(k_element_blocks, dim3(d->ne), dim3(EBS), lds, ctx->stream, a);
     HDG_LAUNCH_CHECK(ctx);

@@ -369,11 +369,13 @@ class Context:
         return self._check(self.lib.hdg_newton_update(self.h, n, float(alpha), _ptr(delta, torch.float64, n, "delta"),
                                                       _ptr(state, torch.float64, n, "state")))
 
-    def element_blocks(self, dims, geom, model, e2f, u, uhat, out, residual_only=False, time_term=None):
+    def element_blocks(self, dims, geom, model, e2f, u, uhat, out, residual_only=False, time_term=None,
+                       keep_mass=False):
         """Element residuals (and Jacobian blocks unless residual_only) at the state (u, uhat):
         geom holds the quadrature geometry (wdet, dphix, phi, phif, psi, ndA, dA, src, uD, bnd,
         nqv, nqf), model the coefficients (nu, tau, beta, gamma), out the device outputs;
-        time_term = dict(c, u_prev, r_extra=None) for an implicit stage."""
+        time_term = dict(c, u_prev, r_extra=None) for an implicit stage; keep_mass: out's Minv,
+        Bd, Cd hold this mesh's from an earlier call (read, not recomputed or written)."""
         import torch
         d = make_dims(dims)
         ne, nf, M, D, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe"))
@@ -398,8 +400,8 @@ class Context:
                                        _ptr(time_term.get("r_extra"), f64, ne * P, "r_extra", allow_none=True)))
         return self._check(self.lib.hdg_element_blocks(
             self.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(m), tt, _ptr(e2f, torch.int32, ne * L, "e2f"),
-            _ptr(u, f64, ne * P, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"), int(bool(residual_only)),
-            ctypes.byref(o)))
+            _ptr(u, f64, ne * P, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"),
+            (1 if residual_only else 0) | (2 if keep_mass else 0), ctypes.byref(o)))
 
     def residual_norm(self, dims, f2e, ru, rt):
         import torch
@@ -532,7 +534,8 @@ class Batch:
             self.ctx.h, self.h, ctypes.byref(eb), _ptr(Kbar, f64, self.total("Kbar"), "Kbar"),
             _ptr(rbar, f64, self.total("rbar"), "rbar"), _ptr(local, f64, self.total("local"), "local")))
 
-    def element_blocks(self, nqv, nqf, geom, models, e2f, u, uhat, out, residual_only=False, c=None, u_prev=None):
+    def element_blocks(self, nqv, nqf, geom, models, e2f, u, uhat, out, residual_only=False, c=None, u_prev=None,
+                       keep_mass=False):
         """Batched hdg_element_blocks: nqv, nqf and models (dicts nu, tau, beta, gamma) per
         instance; geom's arrays concatenated in instance order; the rest are batch arrays;
         c (per instance) with u_prev: a time term per instance."""
@@ -568,8 +571,8 @@ class Batch:
             self.ctx.h, self.h, qv_a, qf_a, ctypes.byref(g), ms, c_a,
             _ptr(u_prev, f64, self.total("du"), "u_prev", allow_none=True),
             _ptr(e2f, torch.int32, self.total("e2f"), "e2f"),
-            _ptr(u, f64, self.total("du"), "u"), _ptr(uhat, f64, self.total("vec"), "uhat"), int(bool(residual_only)),
-            ctypes.byref(o)))
+            _ptr(u, f64, self.total("du"), "u"), _ptr(uhat, f64, self.total("vec"), "uhat"),
+            (1 if residual_only else 0) | (2 if keep_mass else 0), ctypes.byref(o)))
 
     def residual_norms(self, f2e, ru, rt):
         import torch

@@ -120,7 +120,8 @@ class Pipeline:
                 self.ctx.newton_update(alpha - applied, self.x, uhat)
                 applied = alpha
                 # the trial state's blocks: kept as the next step's linearisation if accepted
-                self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term)
+                # (M^-1, B_d, C_d depend on the mesh only: kept from the first evaluation)
+                self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term, keep_mass=True)
                 trial = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
                 if trial < nrm or alpha <= min_alpha:
                     break
@@ -250,7 +251,7 @@ class BatchPipeline:
             while True:
                 bt.newton_update(np.where(pending, alpha - applied, 0.0), self.du, u, self.x, uhat)
                 applied = np.where(pending, alpha, applied)
-                bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk)
+                bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk, keep_mass=True)
                 trial = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
                 accept = pending & ((trial < nrm) | (alpha <= min_alpha))
                 for i in np.nonzero(accept)[0]:
@@ -276,9 +277,9 @@ class BatchPipeline:
         bt = self.bt
         n = bt.n
         blk = self.element_arrays()
-        res = {"ru": blk["ru"], "rt": blk["rt"]}
+        res = {"ru": blk["ru"], "rt": blk["rt"], "Minv": blk["Minv"]}
         u_prev = torch.zeros_like(u)
-        bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, res, residual_only=True)
+        bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk)   # forms M^-1, B_d, C_d once
         nrm = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
         stop = np.maximum(tol * nrm, atol)
         dtau = np.full(n, float(dtau0))
@@ -290,7 +291,7 @@ class BatchPipeline:
                 break
             u_prev.copy_(u)
             bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk, c=np.where(active, 1.0 / dtau, 0.0),
-                              u_prev=u_prev)
+                              u_prev=u_prev, keep_mass=True)
             self.condense(blk)
             self.assemble()
             for i in np.nonzero(~active)[0]:
@@ -298,7 +299,7 @@ class BatchPipeline:
             _, stats = self.solve(**solve_kw)
             self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
             bt.newton_update(np.where(active, 1.0, 0.0), self.du, u, self.x, uhat)
-            bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, res, residual_only=True)
+            bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, res, residual_only=True, keep_mass=True)
             new = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
             for i in np.nonzero(active)[0]:
                 hists[i].append(dict(norm=float(nrm[i]), dtau=float(dtau[i]), iters=int(stats[i]["iters"])))

@@ -367,3 +367,44 @@ def test_batch_pseudo_transient_matches_per_instance_oracle(ctx):
             assert abs(a["dtau"] - b["dtau"]) <= 1e-6 * max(b["dtau"], 1e-300), i
         assert relerr(u[ou[i]:ou[i + 1]].cpu().numpy(), u_ref.ravel()) < 1e-9, i
         assert relerr(uh[oh[i]:oh[i + 1]].cpu().numpy(), uh_ref.ravel()) < 1e-9, i
+
+
+def test_kept_mass_matrices_give_identical_blocks(ctx):
+    """HDG_ELEM_KEEP_MASS (M^-1, B_d, C_d kept from an earlier call on the mesh) gives bitwise the
+    blocks and residuals of a full evaluation, single-mesh and batched, and leaves the kept
+    arrays untouched."""
+    from paper_2512_13619_amd.pipeline import BatchPipeline, Pipeline
+    pb, inp, inp_np = case("burgers_quad_p4")
+    d = pb.dims()
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    u0, uh0 = _random_state(pb, inp_np, 8)
+    u1, uh1 = _random_state(pb, inp_np, 9)
+    t = lambda a: torch.as_tensor(a).cuda().flatten()
+    full, kept = pl.element_arrays(), pl.element_arrays()
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, t(u0), t(uh0), kept)     # forms M^-1, B_d, C_d
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, t(u1), t(uh1), full)
+    saved = {k: kept[k].clone() for k in ("Minv", "Bd", "Cd")}
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, t(u1), t(uh1), kept, keep_mass=True)
+    for k in full:
+        assert torch.equal(full[k], kept[k]), k
+    for k, v in saved.items():
+        assert torch.equal(v, kept[k]), k
+    res = {"ru": torch.zeros_like(full["ru"]), "rt": torch.zeros_like(full["rt"]), "Minv": kept["Minv"]}
+    ctx.element_blocks(d, _geom_dev(inp), _model(inp), pl.e2f, t(u1), t(uh1), res, residual_only=True,
+                       keep_mass=True)
+    assert torch.equal(res["ru"], full["ru"]) and torch.equal(res["rt"], full["rt"])
+    # batched
+    pbs = _batch_instances()
+    inps = [q.newton_inputs() for q in pbs]
+    bp = BatchPipeline(ctx, [q.dims() for q in pbs], [q.mesh.f2e for q in pbs], [q.mesh.e2f for q in pbs])
+    keys = ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")
+    geom = {k: torch.cat([x[k].reshape(-1) for x in inps]).cuda().contiguous() for k in keys}
+    args = ([x["nqv"] for x in inps], [x["nqf"] for x in inps], geom, [_model(x) for x in inps], bp.e2f)
+    ub = torch.cat([x["u0"].reshape(-1) for x in inps]).cuda()
+    uhb = torch.cat([x["uhat0"].reshape(-1) for x in inps]).cuda()
+    fb, kb = bp.element_arrays(), bp.element_arrays()
+    bp.bt.element_blocks(*args, 0.5 * ub, 0.5 * uhb, kb)
+    bp.bt.element_blocks(*args, ub, uhb, fb)
+    bp.bt.element_blocks(*args, ub, uhb, kb, keep_mass=True)
+    for k in fb:
+        assert torch.equal(fb[k], kb[k]), k
