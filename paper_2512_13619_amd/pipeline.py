@@ -87,7 +87,7 @@ class Pipeline:
                     G=z(nt * nq), H=z(nt * nu), J=z(nt * nt), ru=z(nu), rt=z(nt), q=z(nq))
 
     def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, time_term=None,
-               **solve_kw):
+               forcing=None, **solve_kw):
         """Damped Newton iteration (Section 4.3) on a scalar convection-diffusion model.
 
         u [ne*npe] and uhat [nf*npf] (device, float64) hold the state and are updated in place.
@@ -95,6 +95,10 @@ class Pipeline:
         recovery, then alpha = 1, 1/2, 1/4, ... until the residual norm decreases (or alpha
         reaches min_alpha); stops once the norm is at most max(tol * initial norm, atol).
         time_term: an implicit stage's mass term (hdg_element_blocks).
+        forcing="ew": inexact Newton, the linear solves' relative tolerance follows Eisenstat and
+        Walker's choice 2 (SIAM J. Sci. Comput. 17 (1996)): eta_0 = 0.01, eta_k = 0.9 (||R_k|| /
+        ||R_{k-1}||)^2, kept above 0.9 eta_{k-1}^2 when that exceeds 0.1, at most 0.1, and not
+        below solve_kw["rtol"] nor below what the stopping test needs; None: solve_kw["rtol"].
         solve_kw go to the linear solves (restart, rtol, prec, ...). Returns one
         dict(norm, alpha, iters) per step and a last entry with the final norm. Sequencing
         only: evaluation, solve and updates run in libhdg.so."""
@@ -104,9 +108,18 @@ class Pipeline:
         nrm = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
         n0 = nrm
         hist = []
+        rtol_min = solve_kw.get("rtol", 1e-8)
+        eta, prev = 0.01, None
         for _ in range(max_steps):
             if nrm <= max(tol * n0, atol):
                 break
+            if forcing == "ew":
+                if prev is not None:
+                    e = 0.9 * (nrm / prev) ** 2
+                    if 0.9 * eta * eta > 0.1:
+                        e = max(e, 0.9 * eta * eta)
+                    eta = min(e, 0.1)
+                solve_kw["rtol"] = max(eta, rtol_min, 0.5 * max(tol * n0, atol) / nrm)
             self.condense(blk)
             self.assemble()
             if str(solve_kw.get("prec", "")).startswith("asm"):
@@ -127,7 +140,7 @@ class Pipeline:
                     break
                 alpha *= 0.5
             hist.append(dict(norm=nrm, alpha=alpha, iters=st["iters"]))
-            nrm = trial
+            prev, nrm = nrm, trial
         hist.append(dict(norm=nrm, alpha=0.0, iters=0))
         return hist
 

@@ -408,3 +408,23 @@ def test_kept_mass_matrices_give_identical_blocks(ctx):
     bp.bt.element_blocks(*args, ub, uhb, kb, keep_mass=True)
     for k in fb:
         assert torch.equal(fb[k], kb[k]), k
+
+
+def test_inexact_newton_reaches_the_same_solution(ctx):
+    """Eisenstat-Walker forcing (looser linear solves early on) converges to the oracle's
+    discrete solution, with no more Newton steps than the oracle needs plus two."""
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case("burgers_quad_p2")
+    d = pb.dims()
+    u_ref, uh_ref, h_ref = ON.damped_newton(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f,
+                                            pb.mesh.f2e, d, rtol=1e-11)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    u = inp["u0"].cuda().flatten().clone()
+    uh = inp["uhat0"].cuda().flatten().clone()
+    hist = pl.newton(_geom_dev(inp), _model(inp), u, uh, tol=1e-11, restart=50, max_iters=2000, rtol=1e-13,
+                     prec="bj", forcing="ew")
+    say("  inexact newton", [(f"{h['norm']:.2e}", h["alpha"], h["iters"]) for h in hist])
+    assert hist[-1]["norm"] <= 1e-11 * hist[0]["norm"]
+    assert len(hist) <= len(h_ref) + 2
+    assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-8
+    assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-8
