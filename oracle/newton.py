@@ -84,7 +84,7 @@ def pseudo_transient(g, m, u0, uhat0, e2f, f2e, dims, dtau0, rtol=1e-10, atol=1e
         uhat = uhat + dx.reshape(uhat.shape)
         new, _ = residual_norm(g, m, u, uhat, e2f, f2e, dims)
         hist.append(dict(norm=nrm, dtau=dtau))
-        dtau = min(dtau * nrm / new, dtau_max)
+        dtau = dtau_max if new == 0.0 else min(dtau * nrm / new, dtau_max)
         nrm = new
     hist.append(dict(norm=nrm, dtau=0.0))
     return u, uhat, hist

@@ -316,7 +316,8 @@ class BatchPipeline:
             new = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
             for i in np.nonzero(active)[0]:
                 hists[i].append(dict(norm=float(nrm[i]), dtau=float(dtau[i]), iters=int(stats[i]["iters"])))
-                dtau[i] = min(dtau[i] * nrm[i] / new[i], dtau_max)
+                # an exactly solved instance has reached its steady state: dtau at its cap
+                dtau[i] = dtau_max if new[i] == 0.0 else min(dtau[i] * nrm[i] / new[i], dtau_max)
                 nrm[i] = new[i]
         for i in range(n):
             hists[i].append(dict(norm=float(nrm[i]), dtau=0.0, iters=0))
