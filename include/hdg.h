@@ -433,10 +433,11 @@ int32_t    hdg_batch_tuned_grid(hdg_batch b);
  *   sizes, models_h [n_inst] (host) its coefficients; the geometry arrays of geom (its nqv,
  *   nqf fields unused) are the concatenation of the instances' arrays in instance order;
  *   e2f, u (DU offsets), uhat (VEC offsets) and the outputs (MINV..RT, q at DQ offsets) are
- *   batch arrays. c_h [n_inst] (host, may be NULL = all 0) and u_prev (batch array like u) give
- *   each instance a time term as hdg_time_term (no r_extra): pseudo-transient continuation
- *   takes c = 1/dtau and u_prev = the current state. Errors as hdg_element_blocks (the
- *   element named is global).
+ *   batch arrays. c_h [n_inst] (host, may be NULL = all 0), u_prev and r_extra (batch arrays
+ *   like u; r_extra may be NULL) give each instance a time term as hdg_time_term
+ *   (pseudo-transient continuation: c = 1/dtau, u_prev = the current state; a DIRK stage:
+ *   c = 1/(a dt), u_prev = u_n, r_extra = the earlier stages' term). Errors as
+ *   hdg_element_blocks (the element named is global).
  * hdg_residual_norm_batch: norms_h [n_inst] (host) receives each instance's ||R|| (element
  *   u-rows and its faces' summed trace rows, f2e instance-local as for hdg_assemble_batch).
  * hdg_newton_update_batch: u += alpha_h[i] du and uhat += alpha_h[i] x over instance i's parts
@@ -444,7 +445,7 @@ int32_t    hdg_batch_tuned_grid(hdg_batch b);
  * All three synchronise the context's stream before returning. */
 hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv_h, const int32_t* nqf_h,
                                     const hdg_elem_geom* geom, const hdg_conv_diff* models_h,
-                                    const double* c_h, const double* u_prev,
+                                    const double* c_h, const double* u_prev, const double* r_extra,
                                     const int32_t* e2f, const double* u, const double* uhat,
                                     int32_t flags, const hdg_elem_arrays* out);
 hdg_status hdg_residual_norm_batch(hdg_ctx ctx, hdg_batch b, const int32_t* f2e, const double* ru,

@@ -173,8 +173,9 @@ int32_t hdg_batch_tuned_grid(hdg_batch b) { return b ? b->tuned_grid : 0; }
 
 hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv_h, const int32_t* nqf_h,
                                     const hdg_elem_geom* g, const hdg_conv_diff* models_h, const double* c_h,
-                                    const double* u_prev, const int32_t* e2f, const double* u, const double* uhat,
-                                    int32_t flags, const hdg_elem_arrays* out) {
+                                    const double* u_prev, const double* r_extra, const int32_t* e2f,
+                                    const double* u, const double* uhat, int32_t flags,
+                                    const hdg_elem_arrays* out) {
     if (!ctx || !b) return HDG_ERR_ARG;
     if (!nqv_h || !nqf_h || !g || !models_h || !e2f || !u || !uhat || !out || !out->ru || !out->rt || !g->wdet ||
         !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD || !g->bnd) {
@@ -255,6 +256,7 @@ hdg_status hdg_element_blocks_batch(hdg_ctx ctx, hdg_batch b, const int32_t* nqv
     a.u = u;
     a.uhat = uhat;
     a.u_prev = u_prev;
+    a.r_extra = r_extra;
     a.out = *out;
     a.bad = status;
     a.residual_only = residual_only ? 1 : 0;

@@ -58,6 +58,7 @@ struct ElemBatchArgs {
     hdg_elem_geom g;                // concatenated arrays (nqv, nqf unused)
     const int32_t* e2f;
     const double *u, *uhat, *u_prev;   // u_prev: batch array like u (read where c != 0)
+    const double* r_extra;             // batch array like u, or null (known stage term)
     hdg_elem_arrays out;
     int* bad;
     int residual_only, keep_mass;

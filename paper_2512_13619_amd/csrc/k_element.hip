@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(EBS) k_element_blocks_batch(const ElemInst* __
     v.u = a.u + q.u_off + E * P;
     v.uhat = a.uhat + q.uh_off;
     v.u_prev = (q.c != 0.0) ? a.u_prev + q.u_off + E * P : nullptr;
-    v.r_extra = nullptr;
+    v.r_extra = a.r_extra ? a.r_extra + q.u_off + E * P : nullptr;
     const bool mats = !a.residual_only;
     v.Minv = (mats || a.keep_mass) ? a.out.Minv + q.out_off[0] + E * P * P : nullptr;
     v.Bd = mats ? a.out.Bd + q.out_off[1] + E * D * P * P : nullptr;

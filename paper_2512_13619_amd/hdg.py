@@ -138,8 +138,8 @@ def load():
                                           ctypes.POINTER(SolveStats)]
     lib.hdg_recover_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_element_blocks_batch.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ElemGeom),
-                                             ctypes.POINTER(ConvDiff), ctypes.POINTER(dbl), vp, vp, vp, vp, i32,
-                                             ctypes.POINTER(ElemArrays)]
+                                             ctypes.POINTER(ConvDiff), ctypes.POINTER(dbl), vp, vp, vp, vp, vp,
+                                             i32, ctypes.POINTER(ElemArrays)]
     lib.hdg_residual_norm_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.hdg_newton_update_batch.argtypes = [vp, vp, ctypes.POINTER(dbl), vp, vp, vp, vp]
     for name in SYMBOLS:
@@ -535,7 +535,7 @@ class Batch:
             _ptr(rbar, f64, self.total("rbar"), "rbar"), _ptr(local, f64, self.total("local"), "local")))
 
     def element_blocks(self, nqv, nqf, geom, models, e2f, u, uhat, out, residual_only=False, c=None, u_prev=None,
-                       keep_mass=False):
+                       keep_mass=False, r_extra=None):
         """Batched hdg_element_blocks: nqv, nqf and models (dicts nu, tau, beta, gamma) per
         instance; geom's arrays concatenated in instance order; the rest are batch arrays;
         c (per instance) with u_prev: a time term per instance."""
@@ -570,6 +570,7 @@ class Batch:
         return self.ctx._check(self.lib.hdg_element_blocks_batch(
             self.ctx.h, self.h, qv_a, qf_a, ctypes.byref(g), ms, c_a,
             _ptr(u_prev, f64, self.total("du"), "u_prev", allow_none=True),
+            _ptr(r_extra, f64, self.total("du"), "r_extra", allow_none=True),
             _ptr(e2f, torch.int32, self.total("e2f"), "e2f"),
             _ptr(u, f64, self.total("du"), "u"), _ptr(uhat, f64, self.total("vec"), "uhat"),
             (1 if residual_only else 0) | (2 if keep_mass else 0), ctypes.byref(o)))

@@ -144,6 +144,44 @@ class Pipeline:
         hist.append(dict(norm=nrm, alpha=0.0, iters=0))
         return hist
 
+    def pseudo_transient(self, geom, model, u, uhat, dtau0, tol=1e-10, atol=0.0, max_steps=200, dtau_max=1e12,
+                         **solve_kw):
+        """Pseudo-transient continuation (backward Euler in pseudo-time, Section 2.2, with switched
+        evolution relaxation) on one mesh: a pseudo-step is one full Newton step on
+        R(u) + M (u - u_k)/dtau_k = 0 from u_k, then dtau_{k+1} = min(dtau_k ||R(u_k)|| /
+        ||R(u_{k+1})||, dtau_max); stops at max(tol ||R(u_0)||, atol) of the steady residual.
+        u, uhat updated in place. Returns dict(norm, dtau, iters) per step and a final entry."""
+        d = self.dims
+        blk = self.element_arrays()
+        res = {"ru": blk["ru"], "rt": blk["rt"], "Minv": blk["Minv"]}
+        u_prev = torch.zeros_like(u)
+        self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk)      # forms M^-1, B_d, C_d once
+        nrm = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
+        stop = max(tol * nrm, atol)
+        dtau = float(dtau0)
+        hist = []
+        for _ in range(max_steps):
+            if nrm <= stop:
+                break
+            u_prev.copy_(u)
+            self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, keep_mass=True,
+                                    time_term=dict(c=1.0 / dtau, u_prev=u_prev))
+            self.condense(blk)
+            self.assemble()
+            if str(solve_kw.get("prec", "")).startswith("asm"):
+                self.asm_setup(fp32=solve_kw.get("precision", "fp64") == "mixed")
+            st = self.solve(**solve_kw)
+            self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
+            self.ctx.newton_update(1.0, self.du, u)
+            self.ctx.newton_update(1.0, self.x, uhat)
+            self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, res, residual_only=True, keep_mass=True)
+            new = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
+            hist.append(dict(norm=nrm, dtau=dtau, iters=st["iters"]))
+            dtau = dtau_max if new == 0.0 else min(dtau * nrm / new, dtau_max)
+            nrm = new
+        hist.append(dict(norm=nrm, dtau=0.0, iters=0))
+        return hist
+
     def dirk(self, geom, model, u, uhat, dt, nsteps, scheme="dirk22", **newton_kw):
         """nsteps steps of a stiffly accurate DIRK scheme (Section 2.2) of size dt; u, uhat are
         advanced in place. Stage i solves, by Newton, the steady system plus the time term
@@ -233,17 +271,20 @@ class BatchPipeline:
         self.bt.recover(self.local, Minv, Bd, Cd, self.e2f, self.x, self.du, self.dq)
 
     def newton(self, nqv, nqf, geom, models, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10,
-               **solve_kw):
+               time_term=None, **solve_kw):
         """Damped Newton (Section 4.3) for every instance at once: each instance has its own
         residual norm, step halving and stopping test (max(tol * initial norm, atol)); a
         converged instance gets a zero right-hand side and no update while the others go on.
-        u, uhat: batch arrays (DU / VEC offsets), updated in place. Returns one history per
-        instance (as Pipeline.newton)."""
+        u, uhat: batch arrays (DU / VEC offsets), updated in place. time_term = dict(c (per
+        instance), u_prev, r_extra=None): an implicit stage. Returns one history per instance
+        (as Pipeline.newton)."""
         import numpy as np
         bt = self.bt
         n = bt.n
         blk = self.element_arrays()
-        bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk)
+        tt = {} if time_term is None else dict(c=time_term["c"], u_prev=time_term["u_prev"],
+                                                r_extra=time_term.get("r_extra"))
+        bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk, **tt)
         nrm = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
         stop = np.maximum(tol * nrm, atol)
         hists = [[] for _ in range(n)]
@@ -264,7 +305,7 @@ class BatchPipeline:
             while True:
                 bt.newton_update(np.where(pending, alpha - applied, 0.0), self.du, u, self.x, uhat)
                 applied = np.where(pending, alpha, applied)
-                bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk, keep_mass=True)
+                bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, blk, keep_mass=True, **tt)
                 trial = bt.residual_norms(self.f2e, blk["ru"], blk["rt"])
                 accept = pending & ((trial < nrm) | (alpha <= min_alpha))
                 for i in np.nonzero(accept)[0]:
@@ -322,3 +363,33 @@ class BatchPipeline:
         for i in range(n):
             hists[i].append(dict(norm=float(nrm[i]), dtau=0.0, iters=0))
         return hists
+
+    def dirk(self, nqv, nqf, geom, models, u, uhat, dt, nsteps, scheme="dirk22", **newton_kw):
+        """nsteps DIRK steps (Section 2.2) of size dt for every instance: stage i solves the
+        steady system plus c M (U_i - u_n) + sum_{j<i} (a_ij/a) R_s(U_j), c = 1/(a dt), with the
+        batched damped Newton; u_{n+1} = U_s. Returns the per-instance Newton histories of every
+        stage (a list per stage)."""
+        import numpy as np
+        A = dirk_tableau(scheme)
+        s_, a = len(A), A[0][0]
+        bt = self.bt
+        n = bt.n
+        z = lambda: torch.zeros(bt.total("du"), dtype=torch.float64, device=self.device)
+        un = z()
+        res = {"ru": z(), "rt": torch.zeros(bt.total("rt"), dtype=torch.float64, device=self.device)}
+        out = []
+        for _ in range(nsteps):
+            un.copy_(u)
+            minus_rs = []
+            for i in range(s_):
+                rx = None
+                if i > 0:
+                    rx = z()
+                    for j in range(i):
+                        bt.newton_update(np.full(n, -A[i][j] / a), minus_rs[j], rx, self.x, torch.zeros_like(self.x))
+                tt = dict(c=np.full(n, 1.0 / (a * dt)), u_prev=un, r_extra=rx)
+                out.append(self.newton(nqv, nqf, geom, models, u, uhat, time_term=tt, **newton_kw))
+                if i < s_ - 1:
+                    bt.element_blocks(nqv, nqf, geom, models, self.e2f, u, uhat, res, residual_only=True)
+                    minus_rs.append(res["ru"].clone())
+        return out

@@ -28,8 +28,6 @@ class StandInBatch:
     def __init__(self, funcs):
         self.f = funcs
         self.n = len(funcs)
-        self.c = np.zeros(self.n)
-        self.up = np.zeros(self.n)
 
     def total(self, name):
         return self.n

@@ -428,3 +428,47 @@ def test_inexact_newton_reaches_the_same_solution(ctx):
     assert len(hist) <= len(h_ref) + 2
     assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-8
     assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["burgers_quad_p2", "burgers_tri_p3"])
+def test_pseudo_transient_single_mesh_matches_oracle(ctx, name):
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case(name)
+    d = pb.dims()
+    u_ref, uh_ref, h_ref = ON.pseudo_transient(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f,
+                                               pb.mesh.f2e, d, 0.05, rtol=1e-11)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    u = inp["u0"].cuda().flatten().clone()
+    uh = inp["uhat0"].cuda().flatten().clone()
+    hist = pl.pseudo_transient(_geom_dev(inp), _model(inp), u, uh, 0.05, tol=1e-11, restart=50, max_iters=2000,
+                               rtol=1e-13, prec="bj")
+    assert len(hist) == len(h_ref)
+    for a, b in zip(hist, h_ref):
+        assert abs(a["norm"] - b["norm"]) <= 1e-7 * h_ref[0]["norm"]
+        assert abs(a["dtau"] - b["dtau"]) <= 1e-6 * max(b["dtau"], 1e-300)
+    assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-9
+    assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-9
+
+
+def test_batch_dirk_matches_per_instance_oracle(ctx):
+    import oracle.dirk as ODK
+    from paper_2512_13619_amd.pipeline import BatchPipeline
+    pbs = _batch_instances()
+    inps = [pb.newton_inputs() for pb in pbs]
+    bp = BatchPipeline(ctx, [pb.dims() for pb in pbs], [pb.mesh.f2e for pb in pbs], [pb.mesh.e2f for pb in pbs])
+    keys = ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")
+    geom = {k: torch.cat([inp[k].reshape(-1) for inp in inps]).cuda().contiguous() for k in keys}
+    u = torch.cat([inp["u0"].reshape(-1) for inp in inps]).cuda().contiguous()
+    uh = torch.cat([inp["uhat0"].reshape(-1) for inp in inps]).cuda().contiguous()
+    stages = bp.dirk([inp["nqv"] for inp in inps], [inp["nqf"] for inp in inps], geom, [_model(inp) for inp in inps],
+                     u, uh, 0.05, 1, "dirk22", tol=1e-12, restart=50, max_iters=3000, rtol=1e-13, prec="bj")
+    assert len(stages) == 2
+    ou, oh = bp.bt.offsets("du"), bp.bt.offsets("vec")
+    for i, (pb, inp) in enumerate(zip(pbs, inps)):
+        inp_np = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in inp.items()}
+        u_ref, uh_ref, h_ref = ODK.dirk_steps(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f,
+                                              pb.mesh.f2e, pb.dims(), 0.05, 1, "dirk22", newton_rtol=1e-12)
+        for st, hr in zip(stages, h_ref):
+            assert [x["alpha"] for x in st[i]] == [x["alpha"] for x in hr], i
+        assert relerr(u[ou[i]:ou[i + 1]].cpu().numpy(), u_ref.ravel()) < 1e-9, i
+        assert relerr(uh[oh[i]:oh[i + 1]].cpu().numpy(), uh_ref.ravel()) < 1e-9, i
