@@ -371,6 +371,17 @@ def newton_batch_bench(args):
     ptc_loose = dict(dtau0=0.05, linear_rtol=1e-6, s=time.perf_counter() - ts,
                      converged=int(sum(h[-1]["norm"] <= 1e-10 * h[0]["norm"] for h in ph6)),
                      steps_max=max(st6), steps_mean=float(np.mean(st6)))
+    # two DIRK(2,2) steps of dt = 0.05 for every instance (damped Newton per stage)
+    u, uh = u0.clone(), uh0.clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    dst = bp.dirk(nqv, nqf, geom, models, u, uh, 0.05, 2, "dirk22", tol=1e-10, max_steps=30, restart=30,
+                  max_iters=5000, rtol=1e-10, prec="bj", use_graph=True)
+    torch.cuda.synchronize()
+    dirk = dict(scheme="dirk22", dt=0.05, steps=2, s=time.perf_counter() - ts,
+                stage_newton_steps_max=[max(len(h) - 1 for h in st) for st in dst],
+                converged_all_stages=int(sum(all(st[i][-1]["norm"] <= 1e-10 * st[i][0]["norm"] for st in dst)
+                                             for i in range(len(pbs)))))
     steps = [len(h) - 1 for h in hists]
     conv = [h[-1]["norm"] <= 1e-10 * h[0]["norm"] for h in hists]
     damped = sum(1 for h in hists if any(x["alpha"] < 1.0 for x in h[:-1]))
@@ -380,6 +391,7 @@ def newton_batch_bench(args):
                       "element_blocks_s": t_blk, "newton_s": min(runs), "newton_runs_s": runs,
                       "converged": int(sum(conv)), "steps_max": max(steps), "steps_mean": float(np.mean(steps)),
                       "instances_damped": damped, "pseudo_transient": ptc, "pseudo_transient_loose": ptc_loose,
+                      "dirk": dirk,
                       "not_converged": [dict(instance=i, etype=pbs[i].etype, ne=pbs[i].mesh.ne, p=pbs[i].p,
                                              pde=type(pbs[i].phys).__name__, steps=steps[i],
                                              reduction=hists[i][-1]["norm"] / hists[i][0]["norm"],
