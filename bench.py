@@ -243,7 +243,7 @@ def newton_bench(args):
     geom["nqv"], geom["nqf"] = inp["nqv"], inp["nqf"]
     model = dict(nu=inp["nu"], tau=inp["tau"], beta=inp["beta"], gamma=inp["gamma"])
     ctx = hdg.Context(0)
-    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f, keep_fp32=False)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f, keep_fp32=True)
     blk = pl.element_arrays()
     u = inp["u0"].flatten().clone()
     uh = inp["uhat0"].flatten().clone()
@@ -284,6 +284,16 @@ def newton_bench(args):
     torch.cuda.synchronize()
     ew = dict(s=time.perf_counter() - ts, steps=len(hew) - 1, gmres_iters=sum(x["iters"] for x in hew),
               reduction=hew[-1]["norm"] / hew[0]["norm"], alphas=[x["alpha"] for x in hew[:-1]])
+    # the same with the mixed-precision linear solves (FP32 blocks, FP64 restart residuals)
+    u.copy_(inp["u0"].flatten())
+    uh.copy_(inp["uhat0"].flatten())
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    hm = pl.newton(geom, model, u, uh, tol=1e-10, restart=50, max_iters=20000, rtol=1e-10, prec="bj",
+                   orth="dcgs2", fold_prec=True, forcing="ew", precision="mixed")
+    torch.cuda.synchronize()
+    ew["mixed"] = dict(s=time.perf_counter() - ts, steps=len(hm) - 1, gmres_iters=sum(x["iters"] for x in hm),
+                       reduction=hm[-1]["norm"] / hm[0]["norm"])
     # two DIRK(2,2) steps of dt = 0.05 from the initial state (a few Newton steps per stage)
     u.copy_(inp["u0"].flatten())
     uh.copy_(inp["uhat0"].flatten())
