@@ -14,9 +14,11 @@ computes, written from the paper:
                models from the weak form (Sections 2.2, 4.1)
   newton.py    damped Newton with step halving on the residual norm (Section 4.3)
   dirk.py      stiffly accurate DIRK time stepping, one Newton solve per stage (Section 2.2)
+  ilu_asm.py   additive Schwarz on multi-element subdomains with block ILU(0) local solves
+               (Section 3.3's ASM with the incomplete factorisation the conclusions propose)
 
 Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may import
 this package. It shares no code with the GPU library (paper_2512_13619_amd);
 the two meet only at the seeded inputs produced by `workloads`.
 """
-from . import condense, assemble, krylov, poly, elements, newton, dirk  # noqa: F401
+from . import condense, assemble, krylov, poly, elements, newton, dirk, ilu_asm  # noqa: F401
