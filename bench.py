@@ -413,6 +413,71 @@ def newton_batch_bench(args):
                       "burgers": int(sum(1 for pb in pbs if type(pb.phys).__name__ == "Burgers"))}), flush=True)
 
 
+def precond_bench(args):
+    """One linearisation of 2D viscous Burgers on n x n quads (degree --p): the trace system solved
+    with GMRES(50) + block-Jacobi, element-patch ASM and ILU-ASM on patches of G consecutive
+    elements (G = 2, 4, 8) to 1e-10: setup and solve times, iterations, the preconditioner
+    application's rate."""
+    import numpy as np
+    import torch
+    from paper_2512_13619_amd import hdg
+    from paper_2512_13619_amd.pipeline import Pipeline
+    from workloads import mesh as Mh
+    from workloads import physics as Ph
+    from workloads.blocks import HDGProblem
+
+    def forcing(x):
+        return (torch.sin(np.pi * x[..., 0]) * torch.sin(2 * np.pi * x[..., 1]))[..., None]
+    n, p = args.precond_compare, args.p
+    pb = HDGProblem(Mh.structured_quads(n, 0.05, 6), p, Ph.Burgers(nu=0.01, forcing=forcing), device="cuda")
+    d = pb.dims()
+    inp = pb.newton_inputs()
+    geom = {k: inp[k].contiguous() for k in ("wdet", "dphix", "phi", "phif", "psi", "ndA", "dA", "src", "uD", "bnd")}
+    geom["nqv"], geom["nqf"] = inp["nqv"], inp["nqf"]
+    model = dict(nu=inp["nu"], tau=inp["tau"], beta=inp["beta"], gamma=inp["gamma"])
+    ctx = hdg.Context(0)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f, keep_fp32=False)
+    blk = pl.element_arrays()
+    ctx.element_blocks(d, geom, model, pl.e2f, inp["u0"].flatten().contiguous(), inp["uhat0"].flatten().contiguous(),
+                       blk)
+    pl.condense(blk)
+    pl.assemble()
+    torch.cuda.synchronize()
+    N = d["nf"] * d["ncomp"] * d["npf"]
+    res = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    kw = dict(restart=50, max_iters=20000, rtol=1e-10, orth="dcgs2")
+    st, t = timed(lambda: pl.solve(prec="bj", **kw))
+    res["bj"] = dict(iters=st["iters"], solve_s=t)
+    _, ts = timed(lambda: pl.asm_setup(fp32=False))
+    st, t = timed(lambda: pl.solve(prec="asm", **kw))
+    res["asm"] = dict(iters=st["iters"], setup_s=ts, solve_s=t)
+    y = torch.randn(N, dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(y)
+    for G in (2, 4, 8):
+        try:
+            h, ts = timed(lambda: ctx.ilu_asm_create(d, pl.K64, pl.nbr, pl.e2f, G))
+        except hdg.HdgError as e:
+            res[f"ilu_asm_G{G}"] = dict(error=str(e))
+            continue
+        pl.x.zero_()
+        st, t = timed(lambda: ctx.gmres_solve(d, pl.K64, None, pl.nbr, pl.r, pl.x, prec="ilu_asm", ilu=h, **kw))
+        reps = 20
+        _, ta = timed(lambda: [ctx.ilu_asm_apply(h, y, z) for _ in range(reps)])
+        res[f"ilu_asm_G{G}"] = dict(iters=st["iters"], converged=bool(st["converged"]), setup_s=ts, solve_s=t,
+                                    apply_ms=ta / reps * 1e3)
+        h.close()
+    print(json.dumps({"profile": "preconditioners", "workload": f"2D viscous Burgers nu=0.01, {n}x{n} quads jitter "
+                      f"0.05, p={p}, first linearisation", "dims": d, "trace_dofs": N, "results": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,6 +509,9 @@ def main():
     ap.add_argument("--newton-batch", type=int, default=0,
                     help="instead of the headline: damped Newton on this many instances of the batched "
                          "Poisson/Burgers workload in one batch (512: the whole workload), then exit")
+    ap.add_argument("--precond-compare", type=int, default=0,
+                    help="instead of the headline: one Burgers linearisation on this many quads per direction "
+                         "solved with block-Jacobi, element ASM and ILU-ASM (patches of 2, 4, 8 elements), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the hot path is "
@@ -461,6 +529,9 @@ def main():
         return
     if args.newton_batch > 0:
         newton_batch_bench(args)
+        return
+    if args.precond_compare > 0:
+        precond_bench(args)
         return
     t0 = time.perf_counter()
     pb = configs.c2(n=args.n, p=args.p, device="cuda")

@@ -195,7 +195,8 @@ hdg_status hdg_assemble_rhs(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2
  * x: on entry the initial guess, on exit the solution.
  * Returns HDG_NOT_CONVERGED (positive) when max_iters is reached. */
 enum { HDG_PREC_NONE = 0, HDG_PREC_BJ = 1, HDG_PREC_BJ_POLY = 2, HDG_PREC_BJ_CHEB = 3,
-       HDG_PREC_ASM = 4, HDG_PREC_ASM_POLY = 5, HDG_PREC_ASM_CHEB = 6 };
+       HDG_PREC_ASM = 4, HDG_PREC_ASM_POLY = 5, HDG_PREC_ASM_CHEB = 6, HDG_PREC_ILU_ASM = 7 };
+typedef struct hdg_ilu_asm_s* hdg_ilu_asm;   /* see (6b) */
 enum { HDG_ORTH_CGS2 = 0, HDG_ORTH_CGS = 1, HDG_ORTH_MGS = 2, HDG_ORTH_DCGS2 = 3 };
 enum { HDG_FP64 = 0, HDG_MIXED = 1 };
 
@@ -235,6 +236,7 @@ typedef struct {
                                    (the matrix must not have changed since: Section 2.2's reuse
                                    across DIRK stages); HDG_ERR_ARG if the context holds none.
                                    Ignored for HDG_PREC_NONE and the additive Schwarz family. */
+    hdg_ilu_asm ilu_asm;        /* HDG_PREC_ILU_ASM: factors from hdg_ilu_asm_create on this K64 */
 } hdg_solve_opts;
 
 typedef struct {
@@ -369,6 +371,25 @@ hdg_status hdg_asm_setup(hdg_ctx ctx, const hdg_dims* dims, const double* Kbar, 
                          const int32_t* e2f, double* inv64, float* inv32);
 hdg_status hdg_asm_apply(hdg_ctx ctx, const hdg_dims* dims, const double* inv64, const float* inv32,
                          int32_t precision, const int32_t* f2e, const int32_t* e2f, const double* y, double* z);
+
+/* (6b) ILU-ASM: additive Schwarz on multi-element subdomains with block ILU(0) local solves --
+ * Section 3.3 (ASM on patches of elements) with the incomplete factorisation its conclusions
+ * propose for multi-element subdomains.
+ *
+ * hdg_ilu_asm_create: subdomain l is the patch of G consecutive elements, its unknowns the
+ *   trace blocks of the patch's faces in increasing face order, its matrix K restricted to them
+ *   (block (a, b) = K64[f_a][s] with nbr[f_a][s] = f_b). Each is factorised by block ILU(0) on
+ *   K's block pattern in that order. K64, nbr as from hdg_assemble_blocks (perm = NULL), e2f
+ *   as there (device; copied to the host once). Limits: face block edge M*P_F <= 16 and at most
+ *   88 dofs per subdomain (the subdomain is factorised in LDS): HDG_ERR_SHAPE otherwise.
+ *   HDG_ERR_SINGULAR names a subdomain with a singular pivot block. The handle owns its device
+ *   memory (factors, subdomain tables) until hdg_ilu_asm_destroy; it serves hdg_gmres_solve
+ *   with prec HDG_PREC_ILU_ASM (opts.ilu_asm) while K64 is unchanged.
+ * hdg_ilu_asm_apply (test hook): z = sum_l R_l^T (L_l U_l)^{-1} R_l y; y and z must not alias. */
+hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const int32_t* nbr,
+                              const int32_t* e2f, int32_t G, hdg_ilu_asm* out);
+hdg_status hdg_ilu_asm_destroy(hdg_ilu_asm h);
+hdg_status hdg_ilu_asm_apply(hdg_ctx ctx, hdg_ilu_asm h, const double* y, double* z);
 
 /* ---------------------------------------------------------------------------
  * Building blocks exposed for tests and benchmarks (same kernels as the solver).

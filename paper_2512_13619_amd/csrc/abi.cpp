@@ -228,7 +228,9 @@ hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims, const double* K64,
     if (o->restart < 1 || o->restart > 200) return set_err(ctx, HDG_ERR_ARG, "restart must be in [1, 200]");
     if (o->max_iters < 0) return set_err(ctx, HDG_ERR_ARG, "max_iters must be >= 0");
     if (!(o->rtol >= 0.0) || !(o->atol >= 0.0)) return set_err(ctx, HDG_ERR_ARG, "rtol/atol must be >= 0");
-    if (o->prec < HDG_PREC_NONE || o->prec > HDG_PREC_ASM_CHEB) return set_err(ctx, HDG_ERR_ARG, "unknown prec");
+    if (o->prec < HDG_PREC_NONE || o->prec > HDG_PREC_ILU_ASM) return set_err(ctx, HDG_ERR_ARG, "unknown prec");
+    if (o->prec == HDG_PREC_ILU_ASM && !ilu_matches(o->ilu_asm, dims))
+        return set_err(ctx, HDG_ERR_ARG, "HDG_PREC_ILU_ASM needs opts.ilu_asm built for these dims");
     if (o->orth < HDG_ORTH_CGS2 || o->orth > HDG_ORTH_DCGS2) return set_err(ctx, HDG_ERR_ARG, "unknown orth");
     if (o->precision != HDG_FP64 && o->precision != HDG_MIXED)
         return set_err(ctx, HDG_ERR_ARG, "precision must be HDG_FP64 or HDG_MIXED");

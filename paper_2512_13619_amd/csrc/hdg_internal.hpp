@@ -217,6 +217,12 @@ hdg_status recover_run(hdg_ctx ctx, const hdg_dims* d, const double* local, cons
                        const double* xhat, double* du, double* dq);
 hdg_status axpy_run(hdg_ctx ctx, int64_t n, double alpha, const double* x, double* y);
 
+// ILU-ASM (k_ilu.hip): out = epilogue(sum_l R_l^T (L_l U_l)^{-1} R_l y).
+hdg_status ilu_apply_op(hdg_ctx ctx, const hdg_ilu_asm_s* h, const double* y, const FaceEpilogue& e,
+                        const int* skip);
+double* ilu_tmp(const hdg_ilu_asm_s* h);
+bool ilu_matches(const hdg_ilu_asm_s* h, const hdg_dims* d);
+
 // Element residuals / Jacobian blocks (k_element.hip). `bad` receives the first element
 // whose mass matrix has a non-positive pivot (atomicMin; initialise it to INT_MAX).
 size_t element_blocks_lds_bytes(const hdg_dims* d, int nqv, int nqf);

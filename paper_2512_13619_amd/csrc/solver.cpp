@@ -38,7 +38,7 @@ namespace {
 
 // Preconditioner M^{-1} inside an operator: identity (block-Jacobi folded into K), block-Jacobi,
 // or element-patch additive Schwarz.
-enum { PK_IDENTITY = 0, PK_BJ = 1, PK_ASM = 2 };
+enum { PK_IDENTITY = 0, PK_BJ = 1, PK_ASM = 2, PK_ILU = 3 };
 
 struct Op {
     int nf, nb, S, L;
@@ -57,6 +57,7 @@ struct Op {
     double* zu = nullptr;
     double* tmp = nullptr;
     int64_t ne = 0;
+    const hdg_ilu_asm_s* ilu = nullptr;   // ILU-ASM factors
 };
 
 FaceEpilogue epi0() {
@@ -82,6 +83,7 @@ hdg_status op_matvec(hdg_ctx ctx, const Op& op, const double* x, double* y, cons
 hdg_status op_bj(hdg_ctx ctx, const Op& op, const double* y, const FaceEpilogue& e, const int* skip) {
     if (op.pk == PK_ASM)
         return asm_apply_op(ctx, op.nf, op.nb, op.L, op.ne, op.asm_inv, op.asm32, op.unbr, op.f2e, op.zu, y, e, skip);
+    if (op.pk == PK_ILU) return ilu_apply_op(ctx, op.ilu, y, e, skip);
     const void* M = op.pk == PK_BJ ? op.Binv : nullptr;      // nullptr: identity
     return face_op(ctx, op.nf, op.nb, 1, op.L, M, op.b32, nullptr, nullptr, false, y, e, skip);
 }
@@ -89,7 +91,7 @@ hdg_status op_bj(hdg_ctx ctx, const Op& op, const double* y, const FaceEpilogue&
 // out = epilogue(M^{-1} K x): one fused kernel for block-Jacobi (and the identity), the
 // product then the Schwarz operator otherwise
 hdg_status op_B(hdg_ctx ctx, const Op& op, const double* x, const FaceEpilogue& e, const int* skip) {
-    if (op.pk == PK_ASM) {
+    if (op.pk == PK_ASM || op.pk == PK_ILU) {
         hdg_status st = op_matvec(ctx, op, x, op.tmp, skip);
         if (st != HDG_OK) return st;
         return op_bj(ctx, op, op.tmp, e, skip);
@@ -190,7 +192,7 @@ hdg_status poly_apply(hdg_ctx ctx, const Op& op, const PolyPlan& pl, const doubl
 hdg_status prec_apply(hdg_ctx ctx, const Op& op, int prec, const PolyPlan& pl, const double* y, double* z,
                       double* work, size_t ld, const int* skip) {
     if (prec == HDG_PREC_NONE) return vec_lincomb(ctx, op.N, z, 1.0, y, 0.0, nullptr, skip);
-    if (prec == HDG_PREC_BJ || prec == HDG_PREC_ASM) {
+    if (prec == HDG_PREC_BJ || prec == HDG_PREC_ASM || prec == HDG_PREC_ILU_ASM) {
         FaceEpilogue e = epi0();
         e.out[0] = z;
         e.s[0] = 1.0;
@@ -384,6 +386,11 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         op.zu = op64.zu = zu;
         op.tmp = op64.tmp = tmp;
         op.ne = op64.ne = ne;
+    } else if (o->prec == HDG_PREC_ILU_ASM) {
+        // multi-element subdomains with block ILU(0): factors held by the handle
+        op.pk = op64.pk = PK_ILU;
+        op.ilu = op64.ilu = o->ilu_asm;
+        op.tmp = op64.tmp = ilu_tmp(o->ilu_asm);
     } else if (o->prec != HDG_PREC_NONE) {
         double* B64 = (double*)ws_get(ctx, WS_BINV64, sizeof(double) * (size_t)nf * nb * nb, &st);
         if (!B64) return st;
@@ -429,7 +436,8 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         op64.b32 = false;
     }
     // operator of the Arnoldi steps: K, or the folded K M^{-1} blocks
-    const bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE && !schwarz;
+    const bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE && !schwarz &&
+                      o->prec != HDG_PREC_ILU_ASM;
     Op opi = op;
     if (fold) {
         const size_t nblk_el = (size_t)nf * S * nb * nb;

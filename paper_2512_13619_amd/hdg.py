@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
 HDG_OK, HDG_NOT_CONVERGED = 0, 1
-PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3, "asm": 4, "asm_poly": 5, "asm_cheb": 6}
+PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3, "asm": 4, "asm_poly": 5, "asm_cheb": 6, "ilu_asm": 7}
 ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2, "dcgs2": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 
@@ -26,7 +26,7 @@ SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg
            "hdg_bj_apply", "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch", "hdg_element_blocks_batch", "hdg_residual_norm_batch",
-           "hdg_newton_update_batch"]
+           "hdg_newton_update_batch", "hdg_ilu_asm_create", "hdg_ilu_asm_destroy", "hdg_ilu_asm_apply"]
 
 BATCH_ARRAYS = ["Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt", "Kbar", "rbar", "local", "du", "dq",
                 "K", "nbr", "vec", "f2e", "e2f", "binv"]
@@ -71,7 +71,7 @@ class SolveOpts(ctypes.Structure):
                 ("resid_hist_h", ctypes.POINTER(ctypes.c_double)), ("resid_hist_len", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("time_phases", ctypes.c_int32), ("fold_prec", ctypes.c_int32),
                 ("asm_inv64", ctypes.c_void_p), ("asm_inv32", ctypes.c_void_p), ("asm_f2e", ctypes.c_void_p),
-                ("asm_e2f", ctypes.c_void_p), ("reuse_setup", ctypes.c_int32)]
+                ("asm_e2f", ctypes.c_void_p), ("reuse_setup", ctypes.c_int32), ("ilu_asm", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -141,6 +141,9 @@ def load():
                                              ctypes.POINTER(ConvDiff), ctypes.POINTER(dbl), vp, vp, vp, vp, vp,
                                              i32, ctypes.POINTER(ElemArrays)]
     lib.hdg_residual_norm_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.hdg_ilu_asm_create.argtypes = [vp, pd, vp, vp, vp, i32, ctypes.POINTER(vp)]
+    lib.hdg_ilu_asm_destroy.argtypes = [vp]
+    lib.hdg_ilu_asm_apply.argtypes = [vp, vp, vp, vp]
     lib.hdg_newton_update_batch.argtypes = [vp, vp, ctypes.POINTER(dbl), vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("hdg_last_error", "hdg_local_size", "hdg_solve_opts_default",
@@ -312,7 +315,7 @@ class Context:
     # (3)
     def gmres_solve(self, dims, K64, K32, nbr, r, x, restart=50, max_iters=1000, rtol=1e-8, atol=0.0,
                     prec="bj", poly_degree=10, poly_v0=None, orth="cgs2", precision="fp64", hist_len=0,
-                    use_graph=False, time_phases=False, fold_prec=False, asm=None, reuse_setup=False):
+                    use_graph=False, time_phases=False, fold_prec=False, asm=None, reuse_setup=False, ilu=None):
         import torch
         d = make_dims(dims)
         nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
@@ -327,6 +330,8 @@ class Context:
         o.time_phases = 1 if time_phases else 0
         o.fold_prec = 1 if fold_prec else 0
         o.reuse_setup = 1 if reuse_setup else 0
+        if ilu is not None:      # IluAsm from ilu_asm_create
+            o.ilu_asm = ilu.h
         if asm is not None:      # dict(inv64=..., inv32=..., f2e=..., e2f=...) from asm_setup
             nt2 = int(dims["ne"]) * (L * nb) ** 2
             o.asm_inv64 = _ptr(asm["inv64"], torch.float64, nt2, "asm_inv64")
@@ -413,6 +418,23 @@ class Context:
             _ptr(rt, torch.float64, ne * L * M * PF, "rt"), ctypes.byref(out)))
         return out.value
 
+    def ilu_asm_create(self, dims, K64, nbr, e2f, G):
+        """Block ILU(0) factors of the patches of G consecutive elements (hdg_ilu_asm_create)."""
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L, ne = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe", "ne"))
+        nb, S = M * PF, 2 * L - 1
+        h = ctypes.c_void_p()
+        self._check(self.lib.hdg_ilu_asm_create(self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64"),
+                                                _ptr(nbr, torch.int32, nf * S, "nbr"),
+                                                _ptr(e2f, torch.int32, ne * L, "e2f"), int(G), ctypes.byref(h)))
+        return IluAsm(self, h, nf * nb)
+
+    def ilu_asm_apply(self, ilu, y, z):
+        import torch
+        return self._check(self.lib.hdg_ilu_asm_apply(self.h, ilu.h, _ptr(y, torch.float64, ilu.n, "y"),
+                                                      _ptr(z, torch.float64, ilu.n, "z")))
+
     # building blocks
     def matvec(self, dims, K64, K32, nbr, x, y, precision="fp64"):
         import torch
@@ -483,6 +505,24 @@ class Context:
             _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision], len(th),
             tr.ctypes.data_as(pd), ti.ctypes.data_as(pd), _ptr(y, torch.float64, nf * nb, "y"),
             _ptr(z, torch.float64, nf * nb, "z")))
+
+
+class IluAsm:
+    """Handle of ILU-ASM factors (device memory owned by the library until close)."""
+
+    def __init__(self, ctx, h, n):
+        self.ctx, self.lib, self.h, self.n = ctx, ctx.lib, h, n
+
+    def close(self):
+        if self.h:
+            self.lib.hdg_ilu_asm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
