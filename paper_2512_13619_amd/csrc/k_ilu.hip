@@ -7,11 +7,12 @@
 // into LDS together with its block pattern and runs right-looking block ILU(0) on that
 // pattern (for each k: D_k = A_kk^{-1}; A_ik <- A_ik D_k for pattern blocks below; A_ij -=
 // A_ik A_kj where (i, j) is in the pattern), which gives the same factors as the row-wise
-// order for a fixed pattern. The factors (blocks outside the pattern stay zero) and the
-// inverted diagonal blocks are stored. Apply: per subdomain, block forward substitution
-// with the unit lower factor and backward substitution with U (diagonal blocks through
-// D_k), then every face sums the results of the (one or two) subdomains that hold it,
-// with the face operator's epilogue.
+// order for a fixed pattern. Only the off-diagonal pattern blocks are stored, grouped by
+// block column (the L blocks of column k, then its U blocks), with U_ik stored as D_i U_ik,
+// and the inverted diagonal blocks D_i. Apply: per subdomain, forward substitution with the
+// unit lower factor column by column, x <- D x, then x_i -= (D_i U_ik) x_k column by column
+// from the last; every face then sums the results of the (one or two) subdomains that hold
+// it, with the face operator's epilogue.
 #include <algorithm>
 #include <vector>
 
@@ -19,10 +20,12 @@
 
 struct hdg_ilu_asm_s {
     int device = 0;
-    int nsub = 0, nb = 0, nf = 0, G = 0, max_m = 0;
+    int nsub = 0, nb = 0, nf = 0, G = 0, max_m = 0, max_n = 0;
+    size_t solve_lds = 0;
     size_t N = 0;
     int32_t *sub_off = nullptr, *sub_faces = nullptr, *face_sub = nullptr;
-    int64_t* fac_off = nullptr;
+    int64_t* blk_off = nullptr;       // per subdomain: first stored block
+    int32_t *bij = nullptr, *cptr = nullptr, *cmid = nullptr;
     double *fac = nullptr, *dinv = nullptr, *zsub = nullptr, *tmp = nullptr;
     std::vector<void*> allocs;
 };
@@ -32,11 +35,13 @@ namespace {
 constexpr int IBS = 256;
 constexpr int ILU_MAX_M = 88;      // n_faces * nb of a subdomain: (88^2) doubles of LDS
 constexpr int ILU_MAX_NB = 16;
+constexpr int SBS = 64;           // substitution: one wave per subdomain
 
 __global__ void __launch_bounds__(IBS) k_ilu_factor(const double* __restrict__ K64, const int32_t* __restrict__ nbr,
                                                     int S, int nb, const int32_t* __restrict__ sub_off,
                                                     const int32_t* __restrict__ sub_faces, double* fac,
-                                                    const int64_t* __restrict__ fac_off, double* dinv, int* bad) {
+                                                    const int64_t* __restrict__ blk_off,
+                                                    const int32_t* __restrict__ bij, double* dinv, int* bad) {
     extern __shared__ double sm[];
     const int sub = blockIdx.x;
     const int tid = threadIdx.x;
@@ -103,7 +108,11 @@ __global__ void __launch_bounds__(IBS) k_ilu_factor(const double* __restrict__ K
             if (tid == 0) atomicMin(bad, sub);
             return;     // uniform: every thread read the same flag after the barrier
         }
-        for (int q = tid; q < nb * nb; q += IBS) dinv[((size_t)(f0 + k) * nb) * nb + q] = Dk[q];
+        // D_k goes to dinv and over A_kk, which no later step reads
+        for (int q = tid; q < nb * nb; q += IBS) {
+            dinv[((size_t)(f0 + k) * nb) * nb + q] = Dk[q];
+            A[(size_t)(k * nb + q / nb) * m + k * nb + q % nb] = Dk[q];
+        }
         // L_ik = A_ik D_k below the pivot (one thread per row of a block: reads, then writes its row)
         for (int ir = tid; ir < (n - k - 1) * nb; ir += IBS) {
             const int i = k + 1 + ir / nb, r = ir % nb;
@@ -131,53 +140,93 @@ __global__ void __launch_bounds__(IBS) k_ilu_factor(const double* __restrict__ K
         }
         __syncthreads();
     }
-    double* F = fac + fac_off[sub];
-    for (int q = tid; q < m * m; q += IBS) F[q] = A[q];
+    // the stored blocks: L_ik as factored, U_ik scaled to D_i U_ik
+    const int nb2 = nb * nb;
+    const int64_t b0 = blk_off[sub], nblk = blk_off[sub + 1] - b0;
+    for (int64_t q = tid; q < nblk * nb2; q += IBS) {
+        const int64_t b = q / nb2;
+        const int rc = (int)(q - b * nb2), r = rc / nb, c = rc - r * nb;
+        const int code = bij[b0 + b], i = code >> 16, k = code & 0xffff;
+        double v;
+        if (i > k) {
+            v = A[(size_t)(i * nb + r) * m + k * nb + c];
+        } else {
+            v = 0.0;
+            for (int t = 0; t < nb; ++t)
+                v += A[(size_t)(i * nb + r) * m + i * nb + t] * A[(size_t)(i * nb + t) * m + k * nb + c];
+        }
+        fac[(b0 + b) * nb2 + rc] = v;
+    }
 }
 
-__global__ void __launch_bounds__(IBS) k_ilu_solve(const double* __restrict__ y, int nb,
+// One wave per subdomain. Its stored blocks, their (row, column) codes, the column pointers and
+// the inverted diagonal blocks are first copied to LDS with coalesced loads, so every
+// substitution step reads LDS only and the dependent steps do not wait on HBM.
+__global__ void __launch_bounds__(SBS) k_ilu_solve(const double* __restrict__ y, int nb,
                                                    const int32_t* __restrict__ sub_off,
                                                    const int32_t* __restrict__ sub_faces,
                                                    const double* __restrict__ fac,
-                                                   const int64_t* __restrict__ fac_off,
+                                                   const int64_t* __restrict__ blk_off,
+                                                   const int32_t* __restrict__ bij,
+                                                   const int32_t* __restrict__ cptr,
+                                                   const int32_t* __restrict__ cmid,
                                                    const double* __restrict__ dinv, double* zsub, const int* skip) {
     if (skip && *skip) return;
     extern __shared__ double sm[];
     const int sub = blockIdx.x, tid = threadIdx.x;
-    const int f0 = sub_off[sub], n = sub_off[sub + 1] - f0, m = n * nb;
+    const int f0 = sub_off[sub], n = sub_off[sub + 1] - f0, m = n * nb, nb2 = nb * nb;
+    const int64_t b0 = blk_off[sub];
+    const int nblk = (int)(blk_off[sub + 1] - b0);
     const int32_t* faces = sub_faces + f0;
-    const double* F = fac + fac_off[sub];
-    double* x = sm;                 // m
-    double* t = x + m;              // nb
-    for (int q = tid; q < m; q += IBS) x[q] = y[(size_t)faces[q / nb] * nb + q % nb];
+    double* Bs = sm;                          // nblk blocks nb x nb
+    double* Ds = Bs + (size_t)nblk * nb2;     // n blocks nb x nb
+    double* xa = Ds + (size_t)n * nb2;        // m: y, then L^{-1} y
+    double* xb = xa + m;                      // m: the result
+    int32_t* code = (int32_t*)(xb + m);       // nblk
+    int32_t* cp = code + nblk;                // n + 1
+    int32_t* cm = cp + n + 1;                 // n
+    const double* Fg = fac + b0 * nb2;
+    const double* Dg = dinv + (size_t)f0 * nb2;
+    for (int q = tid; q < nblk * nb2; q += SBS) Bs[q] = Fg[q];
+    for (int q = tid; q < n * nb2; q += SBS) Ds[q] = Dg[q];
+    for (int q = tid; q < nblk; q += SBS) code[q] = bij[b0 + q];
+    for (int q = tid; q <= n; q += SBS) cp[q] = cptr[f0 + sub + q];
+    for (int q = tid; q < n; q += SBS) cm[q] = cmid[f0 + q];
+    for (int q = tid; q < m; q += SBS) xa[q] = y[(size_t)faces[q / nb] * nb + q % nb];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {               // unit block-lower: x_i -= L_ik x_k
-        for (int q = tid; q < (n - k - 1) * nb; q += IBS) {
-            const int row = (k + 1) * nb + q;
+    for (int k = 0; k < n; ++k) {               // unit block-lower, column k: x_i -= L_ik x_k
+        const double* xk = xa + k * nb;
+        const int bl = cp[k];
+        for (int q = tid; q < (cm[k] - bl) * nb; q += SBS) {
+            const int b = bl + q / nb, r = q % nb;
+            const double* L = Bs + (size_t)b * nb2 + r * nb;
             double s = 0.0;
-            for (int c = 0; c < nb; ++c) s += F[(size_t)row * m + k * nb + c] * x[k * nb + c];
-            x[row] -= s;
+            for (int c = 0; c < nb; ++c) s += L[c] * xk[c];
+            xa[(code[b] >> 16) * nb + r] -= s;
         }
         __syncthreads();
     }
-    for (int k = n - 1; k >= 0; --k) {          // block-upper: x_k = D_k x_k, then x_i -= U_ik x_k
-        const double* D = dinv + (size_t)(f0 + k) * nb * nb;
-        if (tid < nb) {
+    for (int q = tid; q < m; q += SBS) {         // x = D y
+        const int i = q / nb, r = q - i * nb;
+        const double* D = Ds + (size_t)i * nb2 + r * nb;
+        double s = 0.0;
+        for (int c = 0; c < nb; ++c) s += D[c] * xa[i * nb + c];
+        xb[q] = s;
+    }
+    __syncthreads();
+    for (int k = n - 1; k > 0; --k) {           // column k of D U: x_i -= (D_i U_ik) x_k, i < k
+        const double* xk = xb + k * nb;
+        const int bu = cm[k];
+        for (int q = tid; q < (cp[k + 1] - bu) * nb; q += SBS) {
+            const int b = bu + q / nb, r = q % nb;
+            const double* U = Bs + (size_t)b * nb2 + r * nb;
             double s = 0.0;
-            for (int c = 0; c < nb; ++c) s += D[tid * nb + c] * x[k * nb + c];
-            t[tid] = s;
-        }
-        __syncthreads();
-        if (tid < nb) x[k * nb + tid] = t[tid];
-        __syncthreads();
-        for (int q = tid; q < k * nb; q += IBS) {
-            double s = 0.0;
-            for (int c = 0; c < nb; ++c) s += F[(size_t)q * m + k * nb + c] * x[k * nb + c];
-            x[q] -= s;
+            for (int c = 0; c < nb; ++c) s += U[c] * xk[c];
+            xb[(code[b] >> 16) * nb + r] -= s;
         }
         __syncthreads();
     }
-    for (int q = tid; q < m; q += IBS) zsub[(size_t)f0 * nb + q] = x[q];
+    for (int q = tid; q < m; q += SBS) zsub[(size_t)f0 * nb + q] = xb[q];
 }
 
 // every face sums the (one or two) subdomain results that hold it; face epilogue as k_face_op
@@ -240,9 +289,8 @@ void free_handle(hdg_ilu_asm h) {
 
 hdg_status ilu_apply_op(hdg_ctx ctx, const hdg_ilu_asm_s* h, const double* y, const FaceEpilogue& e,
                         const int* skip) {
-    const size_t lds = sizeof(double) * ((size_t)h->max_m + h->nb);
-    hipLaunchKernelGGL(k_ilu_solve, dim3(h->nsub), dim3(IBS), lds, ctx->stream, y, h->nb, h->sub_off, h->sub_faces,
-                       h->fac, h->fac_off, h->dinv, h->zsub, skip);
+    hipLaunchKernelGGL(k_ilu_solve, dim3(h->nsub), dim3(SBS), h->solve_lds, ctx->stream, y, h->nb, h->sub_off,
+                       h->sub_faces, h->fac, h->blk_off, h->bij, h->cptr, h->cmid, h->dinv, h->zsub, skip);
     HDG_LAUNCH_CHECK(ctx);
     const size_t n = (size_t)h->nf * h->nb;
     if (n == 0) return HDG_OK;
@@ -277,9 +325,14 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
     std::vector<int32_t> e2f_h((size_t)d->ne * L);
     HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
     HDG_HIP_CHECK(ctx, hipMemcpy(e2f_h.data(), e2f, sizeof(int32_t) * e2f_h.size(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> nbr_h((size_t)d->nf * S);
+    HDG_HIP_CHECK(ctx, hipMemcpy(nbr_h.data(), nbr, sizeof(int32_t) * nbr_h.size(), hipMemcpyDeviceToHost));
     std::vector<int32_t> sub_off(1, 0), sub_faces, face_sub((size_t)d->nf * 2, -1);
-    std::vector<int64_t> fac_off(1, 0);
+    std::vector<int64_t> blk_off(1, 0);
+    std::vector<int32_t> bij, cptr, cmid;
+    std::vector<unsigned char> pat;
     int max_m = 0, max_n = 0;
+    size_t solve_lds = 0;
     for (int64_t e0 = 0; e0 < d->ne; e0 += G) {
         const int64_t e1 = std::min<int64_t>(e0 + G, d->ne);
         std::vector<int32_t> fs(e2f_h.begin() + e0 * L, e2f_h.begin() + e1 * L);
@@ -305,9 +358,30 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
                 return HDG_ERR_ARG;
             }
         }
+        // off-diagonal blocks of K's pattern inside the subdomain, by column: L part, then U part
+        pat.assign((size_t)n * n, 0);
+        for (int a = 0; a < n; ++a)
+            for (int sl = 0; sl < S; ++sl) {
+                const int32_t g = nbr_h[(size_t)fs[a] * S + sl];
+                const auto it = std::lower_bound(fs.begin(), fs.end(), g);
+                if (g >= 0 && it != fs.end() && *it == g) pat[(size_t)a * n + (it - fs.begin())] = 1;
+            }
+        const size_t first = bij.size();
+        for (int k = 0; k < n; ++k) {
+            cptr.push_back((int32_t)(bij.size() - first));
+            for (int a = k + 1; a < n; ++a)
+                if (pat[(size_t)a * n + k]) bij.push_back((a << 16) | k);
+            cmid.push_back((int32_t)(bij.size() - first));
+            for (int a = 0; a < k; ++a)
+                if (pat[(size_t)a * n + k]) bij.push_back((a << 16) | k);
+        }
+        cptr.push_back((int32_t)(bij.size() - first));
+        const size_t nblk = bij.size() - first;
+        solve_lds = std::max(solve_lds, sizeof(double) * ((nblk + n) * nb * nb + 2 * (size_t)n * nb) +
+                                            sizeof(int32_t) * (nblk + 2 * (size_t)n + 1));
         sub_faces.insert(sub_faces.end(), fs.begin(), fs.end());
         sub_off.push_back((int32_t)sub_faces.size());
-        fac_off.push_back(fac_off.back() + (int64_t)(n * nb) * (n * nb));
+        blk_off.push_back((int64_t)bij.size());
         max_m = std::max(max_m, n * nb);
         max_n = std::max(max_n, n);
     }
@@ -319,13 +393,18 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
     h->nf = d->nf;
     h->G = G;
     h->max_m = max_m;
+    h->max_n = max_n;
+    h->solve_lds = solve_lds;
     h->N = (size_t)d->nf * nb;
     hipError_t err = hipSuccess;
     h->sub_off = upload(h, sub_off, &err);
     if (err == hipSuccess) h->sub_faces = upload(h, sub_faces, &err);
     if (err == hipSuccess) h->face_sub = upload(h, face_sub, &err);
-    if (err == hipSuccess) h->fac_off = upload(h, fac_off, &err);
-    if (err == hipSuccess) h->fac = dev_alloc<double>(h, (size_t)fac_off.back(), &err);
+    if (err == hipSuccess) h->blk_off = upload(h, blk_off, &err);
+    if (err == hipSuccess) h->bij = upload(h, bij, &err);
+    if (err == hipSuccess) h->cptr = upload(h, cptr, &err);
+    if (err == hipSuccess) h->cmid = upload(h, cmid, &err);
+    if (err == hipSuccess) h->fac = dev_alloc<double>(h, bij.size() * nb * nb, &err);
     if (err == hipSuccess) h->dinv = dev_alloc<double>(h, sub_faces.size() * nb * nb, &err);
     if (err == hipSuccess) h->zsub = dev_alloc<double>(h, sub_faces.size() * nb, &err);
     if (err == hipSuccess) h->tmp = dev_alloc<double>(h, h->N, &err);
@@ -342,8 +421,12 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void*)k_ilu_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
+    if (h->solve_lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void*)k_ilu_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)h->solve_lds);
+    }
     hipLaunchKernelGGL(k_ilu_factor, dim3(h->nsub), dim3(IBS), lds, ctx->stream, K64, nbr, S, nb, h->sub_off,
-                       h->sub_faces, h->fac, h->fac_off, h->dinv, status);
+                       h->sub_faces, h->fac, h->blk_off, h->bij, h->dinv, status);
     if (hipGetLastError() != hipSuccess) {
         ctx->err = "hdg_ilu_asm_create: factorisation launch failed";
         free_handle(h);
