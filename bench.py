@@ -413,6 +413,23 @@ def newton_batch_bench(args):
                       "burgers": int(sum(1 for pb in pbs if type(pb.phys).__name__ == "Burgers"))}), flush=True)
 
 
+def ilu_apply_bytes(e2f, nbr, G, nb):
+    """Algorithmic bytes of one ILU-ASM application: per subdomain (n faces, b off-diagonal blocks
+    of K's pattern among them) the stored blocks and inverted pivots ((b + n) nb^2 doubles), their
+    codes and column pointers (b + 2n + 1 int32), the face list, y gathered and the local result
+    written (2 n nb doubles); then the face sum reads the local results and writes z."""
+    import numpy as np
+    total = 0
+    N = nbr.shape[0] * nb
+    for e0 in range(0, e2f.shape[0], G):
+        faces = np.unique(e2f[e0:e0 + G])
+        n = faces.size
+        g = nbr[faces]
+        b = int(np.isin(g, faces).sum()) - int((g == faces[:, None]).any(axis=1).sum())
+        total += 8 * ((b + n) * nb * nb + 2 * n * nb + n * nb) + 4 * (b + 3 * n + 1)
+    return total + 8 * N
+
+
 def precond_bench(args):
     """One linearisation of 2D viscous Burgers on n x n quads (degree --p): the trace system solved
     with GMRES(50) + block-Jacobi, element-patch ASM and ILU-ASM on patches of G consecutive
@@ -461,6 +478,7 @@ def precond_bench(args):
     res["asm"] = dict(iters=st["iters"], setup_s=ts, solve_s=t)
     y = torch.randn(N, dtype=torch.float64, device="cuda")
     z = torch.zeros_like(y)
+    nbr_h = pl.nbr.cpu().numpy().reshape(d["nf"], -1)
     for G in (2, 4, 8):
         try:
             h, ts = timed(lambda: ctx.ilu_asm_create(d, pl.K64, pl.nbr, pl.e2f, G))
@@ -469,10 +487,11 @@ def precond_bench(args):
             continue
         pl.x.zero_()
         st, t = timed(lambda: ctx.gmres_solve(d, pl.K64, None, pl.nbr, pl.r, pl.x, prec="ilu_asm", ilu=h, **kw))
-        reps = 20
+        reps = 200
         _, ta = timed(lambda: [ctx.ilu_asm_apply(h, y, z) for _ in range(reps)])
+        nbytes = ilu_apply_bytes(pb.mesh.e2f, nbr_h, G, d["ncomp"] * d["npf"])
         res[f"ilu_asm_G{G}"] = dict(iters=st["iters"], converged=bool(st["converged"]), setup_s=ts, solve_s=t,
-                                    apply_ms=ta / reps * 1e3)
+                                    apply_ms=ta / reps * 1e3, apply_bytes=nbytes, apply_GBps=nbytes / (ta / reps) / 1e9)
         h.close()
     print(json.dumps({"profile": "preconditioners", "workload": f"2D viscous Burgers nu=0.01, {n}x{n} quads jitter "
                       f"0.05, p={p}, first linearisation", "dims": d, "trace_dofs": N, "results": res}), flush=True)
