@@ -396,23 +396,37 @@ __global__ __launch_bounds__(COEF_BS) void k_dcgs2_coef(GmresCtl* ctl, const dou
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int J = j + 1;
     // the block partials of the inner-product sweep, one wave per sum (each lane adds its
-    // blocks in increasing order, eight loads in flight), and everything the serial part needs
+    // blocks in increasing order), three sums per pass so that each lane has 36 loads in
+    // flight, and everything the serial part needs
     const int nout = finish ? J : 2 * J;
-    for (int i = wave; i < nout; i += COEF_BS / 64) {
-        const double* pi = part + (size_t)i * nblk;
-        double sacc = 0.0;
-        for (int b0 = 0; b0 < nblk; b0 += 16 * 64) {
-            double m[16];
+    constexpr int NW = COEF_BS / 64, CS = 3, CU = 12;
+    for (int i0 = wave; i0 < nout; i0 += CS * NW) {
+        double acc[CS];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int b = b0 + 64 * u + lane;
-                m[u] = pi[b < nblk ? b : 0];
+        for (int q = 0; q < CS; ++q) acc[q] = 0.0;
+        for (int b0 = 0; b0 < nblk; b0 += CU * 64) {
+            double m[CS][CU];
+#pragma unroll
+            for (int q = 0; q < CS; ++q) {
+                const int i = i0 + q * NW;
+                const double* pi = part + (size_t)(i < nout ? i : i0) * nblk;
+#pragma unroll
+                for (int u = 0; u < CU; ++u) {
+                    const int b = b0 + 64 * u + lane;
+                    m[q][u] = b < nblk ? pi[b] : 0.0;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) sacc += b0 + 64 * u + lane < nblk ? m[u] : 0.0;
+            for (int q = 0; q < CS; ++q)
+#pragma unroll
+                for (int u = 0; u < CU; ++u) acc[q] += m[q][u];
         }
-        sacc = wave_sum(sacc);
-        if (lane == 0) ds[i] = sacc;
+#pragma unroll
+        for (int q = 0; q < CS; ++q) {
+            const double sacc = wave_sum(acc[q]);
+            const int i = i0 + q * NW;
+            if (lane == 0 && i < nout) ds[i] = sacc;
+        }
     }
     // columns 0..j-2 of Hu (rows 0..j) staged in LDS when they fit (hs_ld = j+1, else 0)
     if (hs_ld > 0) {
