@@ -97,3 +97,59 @@ def test_ilu_asm_rejects_oversized_subdomains_and_missing_handle(ctx):
     x = torch.zeros_like(r)
     with pytest.raises(hdg.HdgError):
         ctx.gmres_solve(d, K, K32, nbr, r, x, prec="ilu_asm")
+
+
+def _face_neighbours(f2e, e2f):
+    """nbr[f][s]: slot 0 = f, then the other faces of f's first element, then those of its second
+    (-1 on a boundary face): the face-block pattern of the trace system. f2e[f] = (e1, l1, e2, l2)."""
+    nf, L = f2e.shape[0], e2f.shape[1]
+    nbr = -np.ones((nf, 2 * L - 1), dtype=np.int32)
+    nbr[:, 0] = np.arange(nf)
+    for f in range(nf):
+        s = 1
+        for e in (f2e[f][0], f2e[f][2]):
+            if e < 0:
+                continue
+            for g in e2f[e]:
+                if g != f:
+                    nbr[f, s] = g
+                    s += 1
+    return nbr
+
+
+@pytest.mark.parametrize("G", [2, 4])
+def test_ilu_asm_full_size_sampled(ctx, G):
+    """At the size the preconditioners are compared on (128^2 quads, p = 4: 33024 faces of 5 dofs),
+    on a seeded matrix with the trace system's face-block pattern: the applied preconditioner on
+    sampled faces equals the sum of the oracle's local block-ILU(0) solves of the (one or two)
+    patches that hold each face."""
+    from workloads import mesh as Mh
+    mesh = Mh.structured_quads(128, 0.05, 6)
+    e2f, f2e = mesh.e2f, mesh.f2e
+    ne, L = e2f.shape
+    nf, nb = f2e.shape[0], 5
+    d = dict(ne=ne, nf=nf, ncomp=1, dim=2, npe=25, npf=nb, nlfe=L)
+    nbr = _face_neighbours(f2e, e2f)
+    rng = np.random.default_rng(100 + G)
+    K = 0.1 * rng.standard_normal((nf, nbr.shape[1], nb, nb))
+    K[nbr < 0] = 0.0
+    K[:, 0] += 4.0 * np.eye(nb)
+    y = rng.standard_normal(nf * nb)
+    say("ilu-asm full size", nf, G)
+    h = ctx.ilu_asm_create(d, torch.as_tensor(K).cuda().contiguous(), torch.as_tensor(nbr).cuda().contiguous(),
+                           torch.as_tensor(e2f.astype(np.int32)).cuda().contiguous(), G)
+    z = torch.zeros(nf * nb, dtype=torch.float64, device="cuda")
+    ctx.ilu_asm_apply(h, torch.as_tensor(y).cuda(), z)
+    torch.cuda.synchronize()
+    h.close()
+    zg = z.cpu().numpy().reshape(nf, nb)
+    Y = y.reshape(nf, nb)
+    for f in np.sort(rng.choice(nf, 32, replace=False)):
+        ref = np.zeros(nb)
+        for p in sorted({int(e) // G for e in (f2e[f][0], f2e[f][2]) if e >= 0}):
+            faces = np.unique(e2f[p * G:(p + 1) * G].ravel())
+            A, pat = ilu_asm.local_matrix(K, nbr, faces)
+            x = ilu_asm.lu_solve(ilu_asm.block_ilu0(A, pat), pat, Y[faces])
+            ref += x[int(np.searchsorted(faces, f))]
+        err = relerr(zg[f], ref)
+        assert err < 1e-11, (int(f), err)
