@@ -65,6 +65,41 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
     int Seff = S;
     if (valid && A.nbr1 != nullptr && S > A.nlfe && A.nbr1[f * S + A.nlfe] < 0) Seff = A.nlfe;
     const int ncols = Seff * nb;
+
+    const int nbv = nb / VEC;          // threads per column
+    const int G = TEAM / nbv;          // column groups
+    const int grp = t / nbv;
+    const int r0 = (t - grp * nbv) * VEC;
+    const bool active = valid && grp < G;
+    const V1* p = nullptr;
+    const size_t step = (size_t)G * nbv;        // in units of V1
+    // U independent streaming loads in flight per thread (more for 4-byte loads)
+    constexpr int U = (VEC == 1 && sizeof(T1) == 4) ? 8 : 4;
+    // small blocks (one row per thread): the first U loads of the block stream and the
+    // epilogue operands do not depend on x, so they are issued before the gather and their
+    // latency overlaps the nbr -> x chain (a thread has only a few loads in all)
+    constexpr bool PRE = VEC == 1;
+    const bool pre = PRE && active && grp + (U - 1) * G < ncols;
+    V1 m0[U];
+    if (active) {
+        const T1* Mf = static_cast<const T1*>(A.M1) + (size_t)f * S * nb * nb;
+        p = reinterpret_cast<const V1*>(Mf + (size_t)grp * nb + r0);
+    }
+    if (pre) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) m0[u] = __builtin_nontemporal_load(p + u * step);
+    }
+    double ex[3], ey[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) ex[o] = ey[o] = 0.0;
+    if (PRE && valid && t < nb) {
+        const size_t idx = (size_t)f * nb + t;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            if (A.epi.X[o]) ex[o] = A.epi.X[o][idx];
+            if (A.epi.Y[o]) ey[o] = A.epi.Y[o][idx];
+        }
+    }
     if (valid) {
         for (int i = t; i < ncols; i += TEAM) {
             const int s = i / nb;
@@ -75,20 +110,21 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
     }
     __syncthreads();
 
-    const int nbv = nb / VEC;          // threads per column
-    const int G = TEAM / nbv;          // column groups
-    const int grp = t / nbv;
-    const int r0 = (t - grp * nbv) * VEC;
     double acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
-    if (valid && grp < G) {
-        const T1* Mf = static_cast<const T1*>(A.M1) + (size_t)f * S * nb * nb;
-        const V1* p = reinterpret_cast<const V1*>(Mf + (size_t)grp * nb + r0);
-        const size_t step = (size_t)G * nbv;        // in units of V1
-        // U independent streaming loads in flight per thread (more for 4-byte loads)
-        constexpr int U = (VEC == 1 && sizeof(T1) == 4) ? 8 : 4;
+    if (active) {
         int k = grp;
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double xv = xs[k + u * G];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += lane_of(m0[u], v) * xv;
+            }
+            p += U * step;
+            k += U * G;
+        }
         for (; k + (U - 1) * G < ncols; k += U * G) {
             V1 m[U];
 #pragma unroll
@@ -145,8 +181,8 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
             v[o] = A.epi.s[o] * u;
-            if (A.epi.X[o]) v[o] += A.epi.a[o] * A.epi.X[o][idx];
-            if (A.epi.Y[o]) v[o] += A.epi.b[o] * A.epi.Y[o][idx];
+            if (A.epi.X[o]) v[o] += A.epi.a[o] * (PRE ? ex[o] : A.epi.X[o][idx]);
+            if (A.epi.Y[o]) v[o] += A.epi.b[o] * (PRE ? ey[o] : A.epi.Y[o][idx]);
         }
 #pragma unroll
         for (int o = 0; o < 3; ++o)
