@@ -69,9 +69,19 @@ class Pipeline:
         return dict(inv64=self.asm_inv64, inv32=self.asm_inv32, f2e=self.f2e, e2f=self.e2f)
 
     def solve(self, **kw):
+        """GMRES on the assembled system (kw as hdg.Context.gmres_solve). prec="asm*" uses the
+        patches of the last asm_setup; prec="ilu_asm" without a handle factorises the current K
+        on patches of kw.pop("ilu_patch", 2) consecutive elements for this solve only."""
         self.x.zero_()
         if str(kw.get("prec", "")).startswith("asm") and "asm" not in kw:
             kw["asm"] = dict(inv64=self.asm_inv64, inv32=self.asm_inv32, f2e=self.f2e, e2f=self.e2f)
+        G = kw.pop("ilu_patch", 2)
+        if kw.get("prec") == "ilu_asm" and kw.get("ilu") is None:
+            h = self.ctx.ilu_asm_create(self.dims, self.K64, self.nbr, self.e2f, G)
+            try:
+                return self.ctx.gmres_solve(self.dims, self.K64, self.K32, self.nbr, self.r, self.x, ilu=h, **kw)
+            finally:
+                h.close()
         return self.ctx.gmres_solve(self.dims, self.K64, self.K32, self.nbr, self.r, self.x, **kw)
 
     def recover(self, Minv, Bd, Cd):

@@ -100,7 +100,7 @@ def test_residual_only_and_norm(ctx):
 
 
 @pytest.mark.parametrize("name,prec", [("burgers_quad_p2", "bj"), ("burgers_tri_p3", "asm"),
-                                       ("poisson_tri_p2", "bj")])
+                                       ("poisson_tri_p2", "bj"), ("burgers_quad_p4", "ilu_asm")])
 def test_newton_matches_oracle(ctx, name, prec):
     from paper_2512_13619_amd.pipeline import Pipeline
     pb, inp, inp_np = case(name)
