@@ -379,10 +379,13 @@ hdg_status hdg_asm_apply(hdg_ctx ctx, const hdg_dims* dims, const double* inv64,
  * hdg_ilu_asm_create: subdomain l is the patch of G consecutive elements, its unknowns the
  *   trace blocks of the patch's faces in increasing face order, its matrix K restricted to them
  *   (block (a, b) = K64[f_a][s] with nbr[f_a][s] = f_b). Each is factorised by block ILU(0) on
- *   K's block pattern in that order. K64, nbr as from hdg_assemble_blocks (perm = NULL), e2f
- *   as there (device; copied to the host once). Limits: face block edge M*P_F <= 16 and at most
- *   88 dofs per subdomain (the subdomain is factorised in LDS): HDG_ERR_SHAPE otherwise.
- *   HDG_ERR_SINGULAR names a subdomain with a singular pivot block. The handle owns its device
+ *   K's block pattern in that order; only the off-diagonal pattern blocks and the inverted
+ *   pivot blocks are kept. K64, nbr as from hdg_assemble_blocks (perm = NULL), e2f as there
+ *   (device; e2f and nbr are copied to the host once to build the patch tables, so the call
+ *   synchronises the context's stream). Limits: face block edge M*P_F <= 16 and at most 88
+ *   dofs per subdomain (the subdomain is factorised in LDS): HDG_ERR_SHAPE otherwise; a face
+ *   number outside [0, nf) in e2f: HDG_ERR_ARG. HDG_ERR_SINGULAR names a subdomain with a
+ *   singular pivot block. The handle owns its device
  *   memory (factors, subdomain tables) until hdg_ilu_asm_destroy; it serves hdg_gmres_solve
  *   with prec HDG_PREC_ILU_ASM (opts.ilu_asm) while K64 is unchanged.
  * hdg_ilu_asm_apply (test hook): z = sum_l R_l^T (L_l U_l)^{-1} R_l y; y and z must not alias. */
