@@ -72,3 +72,40 @@ def test_fgmres_with_ilu_asm_reaches_the_direct_solution():
                             restart=50, rtol=1e-12, max_iters=500)
     assert info["converged"]
     assert np.abs(x - out["x"]).max() <= 1e-9 * np.abs(out["x"]).max()
+
+
+def test_ilu0_without_fill_is_the_exact_factorisation():
+    """On a block-tridiagonal pattern elimination creates no fill outside the pattern, so ILU(0)
+    is the exact block LU and its solve equals a dense solve (an ordering or pattern mistake in
+    the update would leave a residual)."""
+    rng = np.random.default_rng(21)
+    n, nb = 9, 3
+    pat = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        pat[i, max(0, i - 1):min(n, i + 2)] = True
+    A = np.where(pat[:, :, None, None], rng.standard_normal((n, n, nb, nb)), 0.0)
+    for i in range(n):
+        A[i, i] += 6.0 * np.eye(nb)
+    F = ilu_asm.block_ilu0(A, pat)
+    r = rng.standard_normal((n, nb))
+    x = ilu_asm.lu_solve(F, pat, r)
+    Ad = A.transpose(0, 2, 1, 3).reshape(n * nb, n * nb)
+    ref = np.linalg.solve(Ad, r.ravel())
+    assert np.abs(x.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+    # an arrow pattern (first block row and column full) does fill in: ILU(0) is then inexact
+    arrow = pat.copy()
+    arrow[0, :] = arrow[:, 0] = True
+    A2 = np.where(arrow[:, :, None, None], rng.standard_normal((n, n, nb, nb)), 0.0)
+    for i in range(n):
+        A2[i, i] += 6.0 * np.eye(nb)
+    F2 = ilu_asm.block_ilu0(A2, arrow)
+    x2 = ilu_asm.lu_solve(F2, arrow, r)
+    ref2 = np.linalg.solve(A2.transpose(0, 2, 1, 3).reshape(n * nb, n * nb), r.ravel())
+    assert np.abs(x2.ravel() - ref2).max() > 1e-8 * np.abs(ref2).max()
+    # ... yet L U matches A2 on every pattern block (fill is dropped, never propagated)
+    for i in range(n):
+        for j in range(n):
+            if arrow[i, j]:
+                lu = sum(F2[i, k] @ F2[k, j] for k in range(min(i, j + 1)) if arrow[i, k] and arrow[k, j])
+                lu = lu + (F2[i, j] if i <= j else 0.0)
+                assert np.abs(lu - A2[i, j]).max() <= 1e-11 * np.abs(A2).max(), (i, j)
