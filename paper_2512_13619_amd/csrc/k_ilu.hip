@@ -35,7 +35,6 @@ namespace {
 constexpr int IBS = 256;
 constexpr int ILU_MAX_M = 88;      // n_faces * nb of a subdomain: (88^2) doubles of LDS
 constexpr int ILU_MAX_NB = 16;
-constexpr int SBS = 64;           // substitution: one wave per subdomain
 
 __global__ void __launch_bounds__(IBS) k_ilu_factor(const double* __restrict__ K64, const int32_t* __restrict__ nbr,
                                                     int S, int nb, const int32_t* __restrict__ sub_off,
@@ -159,9 +158,11 @@ __global__ void __launch_bounds__(IBS) k_ilu_factor(const double* __restrict__ K
     }
 }
 
-// One wave per subdomain. Its stored blocks, their (row, column) codes, the column pointers and
+// One workgroup of SBS threads per subdomain: 64 (one wave) when a subdomain has at most 64
+// rows, else 128, so that a substitution step gives one row to each thread. Its stored blocks, their (row, column) codes, the column pointers and
 // the inverted diagonal blocks are first copied to LDS with coalesced loads, so every
 // substitution step reads LDS only and the dependent steps do not wait on HBM.
+template <int SBS>
 __global__ void __launch_bounds__(SBS) k_ilu_solve(const double* __restrict__ y, int nb,
                                                    const int32_t* __restrict__ sub_off,
                                                    const int32_t* __restrict__ sub_faces,
@@ -289,8 +290,13 @@ void free_handle(hdg_ilu_asm h) {
 
 hdg_status ilu_apply_op(hdg_ctx ctx, const hdg_ilu_asm_s* h, const double* y, const FaceEpilogue& e,
                         const int* skip) {
-    hipLaunchKernelGGL(k_ilu_solve, dim3(h->nsub), dim3(SBS), h->solve_lds, ctx->stream, y, h->nb, h->sub_off,
-                       h->sub_faces, h->fac, h->blk_off, h->bij, h->cptr, h->cmid, h->dinv, h->zsub, skip);
+    if (h->max_m <= 64)
+        hipLaunchKernelGGL(k_ilu_solve<64>, dim3(h->nsub), dim3(64), h->solve_lds, ctx->stream, y, h->nb, h->sub_off,
+                           h->sub_faces, h->fac, h->blk_off, h->bij, h->cptr, h->cmid, h->dinv, h->zsub, skip);
+    else
+        hipLaunchKernelGGL(k_ilu_solve<128>, dim3(h->nsub), dim3(128), h->solve_lds, ctx->stream, y, h->nb,
+                           h->sub_off, h->sub_faces, h->fac, h->blk_off, h->bij, h->cptr, h->cmid, h->dinv, h->zsub,
+                           skip);
     HDG_LAUNCH_CHECK(ctx);
     const size_t n = (size_t)h->nf * h->nb;
     if (n == 0) return HDG_OK;
@@ -422,7 +428,9 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
         (void)hipFuncSetAttribute((const void*)k_ilu_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
     if (h->solve_lds > 64 * 1024) {
-        (void)hipFuncSetAttribute((const void*)k_ilu_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_ilu_solve<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)h->solve_lds);
+        (void)hipFuncSetAttribute((const void*)k_ilu_solve<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)h->solve_lds);
     }
     hipLaunchKernelGGL(k_ilu_factor, dim3(h->nsub), dim3(IBS), lds, ctx->stream, K64, nbr, S, nb, h->sub_off,
