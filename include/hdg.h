@@ -277,7 +277,7 @@ hdg_status hdg_newton_update(hdg_ctx ctx, int64_t n, double alpha, const double*
 /* (5b) Element residuals and Jacobian blocks on the device -- Section 4.1 (the element
  *     matrices as products of reference basis tables with per-point weights, Jacobian
  *     determinants and flux derivatives), Section 2.2 (weak form, numerical flux), and the
- *     residual evaluation of Section 4.3's damped Newton iteration.
+ *     residual evaluation of Section 4.4's damped Newton iteration.
  *
  * Scalar convection-diffusion models (ncomp = 1):
  *   F(u, q) = beta u^2/2 + gamma u - nu q  (a dim-vector), source s(x),
@@ -452,7 +452,7 @@ hdg_status hdg_batch_destroy(hdg_batch b);
 hdg_status hdg_batch_offsets(hdg_batch b, int32_t array_id, int64_t* off_h /* [n_inst+1] */);
 int32_t    hdg_batch_tuned_grid(hdg_batch b);
 /* Batched element residuals / Jacobians and damped Newton support (scalar models; Section
- * 4.1, Section 4.3, as hdg_element_blocks / hdg_residual_norm / hdg_newton_update):
+ * 4.1, Section 4.4, as hdg_element_blocks / hdg_residual_norm / hdg_newton_update):
  * hdg_element_blocks_batch: nqv_h, nqf_h [n_inst] (host) are each instance's quadrature
  *   sizes, models_h [n_inst] (host) its coefficients; the geometry arrays of geom (its nqv,
  *   nqf fields unused) are the concatenation of the instances' arrays in instance order;

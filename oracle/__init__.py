@@ -12,7 +12,7 @@ computes, written from the paper:
                order, product-form apply (Sections 3.4, 4.7); Chebyshev smoother
   elements.py  element residuals and Jacobian blocks of scalar convection-diffusion
                models from the weak form (Sections 2.2, 4.1)
-  newton.py    damped Newton with step halving on the residual norm (Section 4.3)
+  newton.py    damped Newton with step halving on the residual norm (Section 4.4)
   dirk.py      stiffly accurate DIRK time stepping, one Newton solve per stage (Section 2.2)
   ilu_asm.py   additive Schwarz on multi-element subdomains with block ILU(0) local solves
                (Section 3.3's ASM with the incomplete factorisation the conclusions propose)

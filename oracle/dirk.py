@@ -9,7 +9,7 @@ hold at every stage), stage i solves
 i.e. after division by a: the steady system plus the time term c M (U_i - u_n) with
 c = 1/(a dt) and the known r_x = sum_{j < i} (a_ij / a) R_s(U_j). The schemes used here are
 stiffly accurate (b = the last row of the tableau), so u_{n+1} = U_s and uhat_{n+1} = Uhat_s.
-Each stage is solved by the damped Newton iteration of Section 4.3 (newton.py).
+Each stage is solved by the damped Newton iteration of Section 4.4 (newton.py).
 
 Tableaus (Alexander, SIAM J. Numer. Anal. 14 (1977)): backward Euler DIRK(1,1);
 DIRK(2,2) with a = 1 - 1/sqrt(2); DIRK(3,3) with a the root in (1/6, 1/2) of

@@ -1,6 +1,6 @@
 """Damped Newton iteration on the HDG system (oracle; test infrastructure only).
 
-Section 4.3: at each Newton step the residual is evaluated, the linearised system is
+Section 4.4: at each Newton step the residual is evaluated, the linearised system is
 condensed, assembled and solved for the trace correction, the element corrections are
 recovered, and the state is updated with a step alpha that starts at 1 and is halved while
 the residual norm does not decrease. Here the trace system is solved exactly (sparse LU),

@@ -1,4 +1,4 @@
-// Element residuals and Jacobian blocks on the device (Section 4.1, Section 4.3's residual
+// Element residuals and Jacobian blocks on the device (Section 4.1, Section 4.4's residual
 // evaluation) for scalar convection-diffusion models
 //   F(u, q) = beta u^2/2 + gamma u - nu q,   fhat = F(uhat, q).n + tau (u - uhat),
 // which cover Poisson (beta = gamma = 0, nu = 1) and viscous Burgers. Each element is one

@@ -421,8 +421,15 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
         free_handle(h);
         return HDG_ERR_NOMEM;
     }
+    // from here on every error return releases the handle's device memory
+    auto fail_hip = [&](hipError_t e, int line) {
+        ctx->err = std::string("HIP error: ") + hipGetErrorString(e) + " at " + __FILE__ + ":" + std::to_string(line);
+        free_handle(h);
+        return HDG_ERR_HIP;
+    };
     const int big = 0x7fffffff;
-    HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    err = hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+    if (err != hipSuccess) return fail_hip(err, __LINE__);
     const size_t lds = factor_lds(max_m, max_n, nb);
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void*)k_ilu_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -441,8 +448,10 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* d, const double* K64,
         return HDG_ERR_HIP;
     }
     int bad = big;
-    HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    err = hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (err != hipSuccess) return fail_hip(err, __LINE__);
+    err = hipStreamSynchronize(ctx->stream);
+    if (err != hipSuccess) return fail_hip(err, __LINE__);
     if (bad != big) {
         ctx->err = "hdg_ilu_asm_create: singular pivot block in subdomain " + std::to_string(bad);
         free_handle(h);

@@ -98,7 +98,7 @@ class Pipeline:
 
     def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, time_term=None,
                forcing=None, **solve_kw):
-        """Damped Newton iteration (Section 4.3) on a scalar convection-diffusion model.
+        """Damped Newton iteration (Section 4.4) on a scalar convection-diffusion model.
 
         u [ne*npe] and uhat [nf*npf] (device, float64) hold the state and are updated in place.
         Each step: element blocks at the state, condensation, assembly, preconditioned GMRES,
@@ -282,7 +282,7 @@ class BatchPipeline:
 
     def newton(self, nqv, nqf, geom, models, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10,
                time_term=None, **solve_kw):
-        """Damped Newton (Section 4.3) for every instance at once: each instance has its own
+        """Damped Newton (Section 4.4) for every instance at once: each instance has its own
         residual norm, step halving and stopping test (max(tol * initial norm, atol)); a
         converged instance gets a zero right-hand side and no update while the others go on.
         u, uhat: batch arrays (DU / VEC offsets), updated in place. time_term = dict(c (per

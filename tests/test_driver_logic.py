@@ -4,7 +4,7 @@ The library calls are replaced by a stand-in whose instances are scalar equation
 (the element evaluation returns -R_i, the "solve" returns the Newton correction of the
 linearised equation, with the time term where given). The drivers' per-instance bookkeeping
 (step halving on the residual norm, stopping, freezing converged instances, the pseudo-time
-step growth) is checked against plain loops written here from Section 4.3 and Section 2.2.
+step growth) is checked against plain loops written here from Section 4.4 and Section 2.2.
 """
 import math
 

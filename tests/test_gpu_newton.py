@@ -1,5 +1,5 @@
 """Device element residuals/Jacobian blocks and the damped Newton loop against the oracle
-(Section 4.1, Section 4.3): hdg_element_blocks, hdg_residual_norm, Pipeline.newton."""
+(Section 4.1, Section 4.4): hdg_element_blocks, hdg_residual_norm, Pipeline.newton."""
 import numpy as np
 import pytest
 import torch

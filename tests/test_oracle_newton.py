@@ -1,5 +1,5 @@
 """Pins of the oracle's element residual/Jacobian generation and damped Newton iteration
-(Section 4.1, Section 4.3) against mathematics and an independent implementation:
+(Section 4.1, Section 4.4) against mathematics and an independent implementation:
 
 * the Jacobian blocks equal central differences of the residual (exact up to rounding: the
   residual is at most quadratic in the state), including A = I (x) M, B_d and C_d from R_q;

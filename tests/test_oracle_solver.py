@@ -258,3 +258,98 @@ def test_asm_converges_faster_than_bj():
     assert i_asm["converged"] and i_bj["converged"] and i_asm["iters"] < i_bj["iters"]
     for x in (x1, x2):
         assert np.linalg.norm(x - out["x"]) <= 1e-9 * np.linalg.norm(out["x"])
+
+
+def test_bj_apply_inverts_each_diagonal_block():
+    """bj_apply(bj_inverses(K), K_ff y_f) = y_f face by face for non-symmetric blocks stored
+    column-major ([f][s][col][row]); a transposed apply (P_f^{-T}) fails this."""
+    rng = np.random.default_rng(21)
+    nf, nb, S = 7, 4, 3
+    K = rng.standard_normal((nf, S, nb, nb))
+    for f in range(nf):
+        K[f, 0] += 3.0 * np.eye(nb) + np.triu(rng.standard_normal((nb, nb)), 1) * 2.0
+    y = rng.standard_normal(nf * nb)
+    Ky = np.concatenate([K[f, 0].T @ y[f * nb:(f + 1) * nb] for f in range(nf)])   # K_ff[row][col] = K[f,0,col,row]
+    Binv = krylov.bj_inverses(K)
+    assert np.allclose(krylov.bj_apply(Binv, Ky), y, rtol=1e-12, atol=1e-12)
+    transposed = np.einsum("frc,fc->fr", Binv, Ky.reshape(nf, nb)).reshape(-1)
+    assert not np.allclose(transposed, y, atol=1e-3)
+
+
+def test_bj_apply_hand_example():
+    """One 2x2 face block K_ff = [[1, 2], [0, 1]] (row-major), stored column-major as
+    [[1, 0], [2, 1]]: P^{-1} = [[1, -2], [0, 1]], so P^{-1} (0, 1) = (-2, 1)."""
+    K = np.zeros((1, 1, 2, 2))
+    K[0, 0] = [[1.0, 0.0], [2.0, 1.0]]        # [col][row]
+    Binv = krylov.bj_inverses(K)
+    assert np.array_equal(Binv[0], np.array([[1.0, 0.0], [-2.0, 1.0]]))
+    assert np.array_equal(krylov.bj_apply(Binv, np.array([0.0, 1.0])), np.array([-2.0, 1.0]))
+
+
+def test_leja_greedy_choice_hand_example():
+    """Leja order of {1, 4.4, 0.5, 8}, worked by hand: start at the largest modulus 8; the
+    farthest from 8 is 0.5 (7.5); then the product of distances to {8, 0.5} is 7 x 0.5 = 3.5
+    for 1 and 3.6 x 3.9 = 14.04 for 4.4, so 4.4; then 1. (A sum of distances would tie at
+    7.5 and take 1 first.) The second example separates the product from a max-min rule:
+    {10, 0.1, 4, 1.5, 8.9} starts 10, 0.1 (9.9 away), then 4 (6 x 3.9 = 23.4 against
+    8.5 x 1.4 = 11.9 and 1.1 x 8.8 = 9.68); with {10, 0.1, 4} chosen, 8.9 scores
+    1.1 x 8.8 x 4.9 = 47.4 and 1.5 scores 8.5 x 1.4 x 2.5 = 29.8, so 8.9 comes before 1.5,
+    where the largest smallest distance (1.4 against 1.1) would take 1.5."""
+    o = poly.leja_order(np.array([1.0, 4.4, 0.5, 8.0]))
+    assert np.array_equal(o, np.array([8.0, 0.5, 4.4, 1.0], complex))
+    o = poly.leja_order(np.array([10.0, 0.1, 4.0, 1.5, 8.9]))
+    assert np.array_equal(o, np.array([10.0, 0.1, 4.0, 8.9, 1.5], complex))
+
+
+def test_leja_conjugate_pair_follows_partner():
+    """{3, 1+2i, 1-2i, 2.5}: start at 3 (|1+2i| = 2.24); |1+2i - 3| = 2.83 beats |2.5 - 3| = 0.5,
+    so the pair comes next, positive imaginary part first, then 2.5."""
+    o = poly.leja_order(np.array([3.0, 1 + 2j, 1 - 2j, 2.5]))
+    assert np.array_equal(o, np.array([3.0, 1 + 2j, 1 - 2j, 2.5]))
+
+
+def test_leja_drops_tiny_values():
+    o = poly.leja_order(np.array([2.0, 1e-14, 1.0]), drop_rel=1e-12)
+    assert np.array_equal(o, np.array([2.0, 1.0], complex))
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 7])
+def test_gmres_left_is_minimal_preconditioned_residual(k):
+    """Left-preconditioned GMRES (Section 3.1) after k steps minimises ||P^{-1}(b - K x)|| over
+    x in the Krylov space of P^{-1}K started at P^{-1}b (brute force), which differs from the
+    right-preconditioned minimum of ||b - K x||."""
+    A, Binv, b = _block_system(5)
+    prec = lambda v: krylov.bj_apply(Binv, v)
+    Pinv = np.array([prec(e) for e in np.eye(A.shape[0])]).T
+    x, info = krylov.gmres_left(lambda v: A @ v, b, prec, restart=50, rtol=0.0, max_iters=k)
+    assert info["iters"] == k
+    ref = _krylov_min_residual(Pinv @ A, Pinv @ b, k)
+    assert abs(np.linalg.norm(Pinv @ (b - A @ x)) - ref) <= 1e-10 * np.linalg.norm(Pinv @ b)
+    if k > 1:
+        xr, _ = krylov.fgmres(lambda v: A @ v, b, prec=prec, restart=50, rtol=0.0, max_iters=k)
+        assert np.linalg.norm(x - xr) > 1e-8 * np.linalg.norm(xr)
+
+
+def test_gmres_left_exact_preconditioner_one_step():
+    A, _, b = _block_system(6)
+    Ainv = np.linalg.inv(A)
+    x, info = krylov.gmres_left(lambda v: A @ v, b, lambda v: Ainv @ v, rtol=1e-12)
+    assert info["converged"] and info["iters"] == 1
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("orth", ["cgs", "mgs", "cgs2"])
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_fgmres_each_orth_is_minimal_residual(orth, k):
+    """Right-preconditioned FGMRES with a fixed preconditioner attains, after k steps, the
+    least-squares minimum of ||b - K M^{-1} u|| over the Krylov space (brute force), whichever
+    Gram-Schmidt variant builds the basis (Section 4.4 names CGS and MGS)."""
+    A, Binv, b = _block_system(7)
+    prec = lambda v: krylov.bj_apply(Binv, v)
+    B = A @ np.array([prec(e) for e in np.eye(A.shape[0])]).T
+    hist = []
+    x, info = krylov.fgmres(lambda v: A @ v, b, prec=prec, restart=50, rtol=0.0, max_iters=k, orth=orth,
+                            hist=hist)
+    ref = _krylov_min_residual(B, b, k)
+    assert abs(np.linalg.norm(b - A @ x) - ref) <= 1e-10 * np.linalg.norm(b)
+    assert abs(hist[k] - ref) <= 1e-10 * np.linalg.norm(b)
