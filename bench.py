@@ -69,11 +69,29 @@ def condense_flops(d):
             + 2 * nt * nu * (nt + 1))
 
 
-def measured_traffic(kind):
+# The single-mesh workloads bench.py runs (--config): the default is the headline. tag names the
+# workload in the profiles/ records; prec is the preconditioner the workload states.
+WORKLOADS = {
+    "c2": dict(tag="elasticity24_p3", prec="bj",
+               text="3D linear elasticity E=1 nu=0.3, unit cube {n}^3 hexes jitter 0.05h, p={p}, tau=1"),
+    "c3": dict(tag="ns_hex16_p2", prec="bj_cheb",
+               text="3D compressible Navier-Stokes linearisation Re=1000 Mach 0.5, unit cube {n}^3 hexes, p={p}, "
+                    "freestream + 5% Gaussian bumps, backward Euler dt=10h/((p+1)(|v|+c))"),
+    "c5": dict(tag="ns_tet32_p2", prec="bj_poly",
+               text="3D compressible Navier-Stokes linearisation Re=1000 Mach 0.5, unit cube {n}^3 x 6 Kuhn tets "
+                    "jitter 0.1h, p={p}, freestream + 5% Gaussian bumps, backward Euler dt=10h/((p+1)(|v|+c))"),
+}
+WORKLOAD_SIZES = {"c2": (24, 3), "c3": (16, 2), "c5": (32, 2)}
+PREC_TEXT = {"bj": "block-Jacobi", "bj_poly": "block-Jacobi + Ritz-Leja polynomial(10)",
+             "bj_cheb": "block-Jacobi + Chebyshev(10)", "asm": "element ASM", "asm_poly": "ASM + polynomial(10)",
+             "asm_cheb": "ASM + Chebyshev(10)", "none": "no preconditioner"}
+
+
+def measured_traffic(kind, tag="elasticity24_p3"):
     """Counter-measured HBM bytes per launch of the block matvec (profiles/ record), or None when the
     kernel source changed since the counters were taken."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "block_matvec_counters_elasticity24_p3.json")
+    rec_path = os.path.join(ROOT, "profiles", f"block_matvec_counters_{tag}.json")
     try:
         rec = json.load(open(rec_path))
         src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
@@ -508,13 +526,101 @@ def precond_bench(args):
                       f"0.05, p={p}, first linearisation", "dims": d, "trace_dofs": N, "results": res}), flush=True)
 
 
+def batch_linear_bench(args):
+    """The 512-instance batched workload's linear step: batched condensation (one persistent launch),
+    assembly, segmented GMRES(50) + block-Jacobi to rtol 1e-8 per instance (each restart cycle replayed
+    as a hipGraph) and recovery, over all instances' first linearisation; mixed precision (FP32 blocks
+    and inverses inside the cycles) against FP64, each warmed up and averaged over --steps."""
+    import numpy as np
+    import torch
+    from paper_2512_13619_amd import hdg
+    from workloads import configs
+
+    t0 = time.perf_counter()
+    pbs = [configs.c4_instance(i, device="cuda") for i in range(512)]
+    ctx = hdg.Context(0)
+    bt = hdg.Batch(ctx, [pb.dims() for pb in pbs])
+    names = ["Minv", "Bd", "Cd", "D", "E", "F", "G", "H", "J", "ru", "rt"]
+    parts = {k: [] for k in names}
+    for pb in pbs:
+        b = pb.element_blocks()
+        for k in names:
+            parts[k].append(b[k].reshape(-1))
+    blk = {k: torch.cat(parts[k]).contiguous() for k in names}
+    del parts
+    i32 = lambda arrs: torch.as_tensor(np.concatenate([a.reshape(-1) for a in arrs]).astype(np.int32)).cuda()
+    f2e, e2f = i32([pb.mesh.f2e for pb in pbs]), i32([pb.mesh.e2f for pb in pbs])
+    z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device="cuda")
+    Kbar, rbar, local = z(bt.total("Kbar")), z(bt.total("rbar")), z(bt.total("local"))
+    K64, K32 = z(bt.total("K")), z(bt.total("K"), torch.float32)
+    nbr = torch.zeros(bt.total("nbr"), dtype=torch.int32, device="cuda")
+    r, x = z(bt.total("vec")), z(bt.total("vec"))
+    du, dq = z(bt.total("du")), z(bt.total("dq"))
+    ne_all = sum(pb.mesh.ne for pb in pbs)
+    log(f"batch of 512 instances, {ne_all} elements, {bt.total('vec')} trace dofs "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    stream = torch.cuda.current_stream()
+
+    def step(precision):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        bt.condense(blk, Kbar, rbar, local)
+        ev[1].record(stream)
+        bt.assemble(f2e, e2f, Kbar, rbar, K64, K32, nbr, r)
+        ev[2].record(stream)
+        x.zero_()
+        st, stats = bt.gmres_solve(K64, K32, nbr, r, x, restart=50, max_iters=20000, rtol=1e-8, prec="bj",
+                                   precision=precision, use_graph=True)
+        ev[3].record(stream)
+        bt.recover(local, blk["Minv"], blk["Bd"], blk["Cd"], e2f, x, du, dq)
+        ev[4].record(stream)
+        torch.cuda.synchronize()
+        if st != 0 or not all(s_["converged"] for s_ in stats):
+            raise RuntimeError(f"{precision} batch solve: {sum(s_['converged'] for s_ in stats)} of 512 converged")
+        ph = dict(condense=ev[0].elapsed_time(ev[1]) / 1e3, assemble=ev[1].elapsed_time(ev[2]) / 1e3,
+                  solve=ev[2].elapsed_time(ev[3]) / 1e3, recover=ev[3].elapsed_time(ev[4]) / 1e3)
+        return stats, ph
+
+    out = {}
+    xs = {}
+    for precision in ("mixed", "fp64"):
+        for _ in range(max(args.warmup, 1)):
+            step(precision)
+        times, phs = [], []
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            stats, ph = step(precision)
+            times.append(time.perf_counter() - t1)
+            phs.append(ph)
+        its = [s_["iters"] for s_ in stats]
+        out[precision] = dict(step_s=float(np.mean(times)), step_s_minmax=[min(times), max(times)],
+                              phases_s={k: float(np.mean([p_[k] for p_ in phs])) for k in phs[0]},
+                              iters_max=max(its), iters_total=int(sum(its)),
+                              rel_resid_max=max(s_["rel_resid_true"] for s_ in stats))
+        xs[precision] = x.clone()
+        log(precision, out[precision])
+    dx = float(((xs["mixed"] - xs["fp64"]).norm() / xs["fp64"].norm()).item())
+    print(json.dumps({"profile": "batch_linear", "metric": METRIC, "unit": "s", "higher_is_better": False,
+                      "workload": "512 seeded 2D Poisson/Burgers instances (quads/triangles, n 4..32, p 1..4), "
+                                  "first linearisation; batched condensation, assembly, segmented GMRES(50) + "
+                                  "block-Jacobi to rtol 1e-8 per instance (hipGraph cycles), recovery",
+                      "instances": 512, "elements": ne_all, "trace_dofs": bt.total("vec"),
+                      "steps": args.steps, "warmup": max(args.warmup, 1), "mixed": out["mixed"],
+                      "fp64": out["fp64"], "mixed_vs_fp64_speedup": out["fp64"]["step_s"] / out["mixed"]["step_s"],
+                      "mixed_vs_fp64_solution_reldiff": dx, "tuned_grid": bt.tuned_grid()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=24, help="hexes per direction")
-    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c5", "c4"],
+                    help="workload: c2 the elasticity headline; c3 / c5 the Navier-Stokes linearisations on hexes / "
+                         "Kuhn tets; c4 the 512-instance batched linear solve")
+    ap.add_argument("--n", type=int, default=0, help="cells per direction (0: the workload's own size)")
+    ap.add_argument("--p", type=int, default=0, help="degree (0: the workload's own degree)")
+    ap.add_argument("--prec", default="", help="preconditioner of the timed solves (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--also", default="",
@@ -554,6 +660,10 @@ def main():
     from workloads import configs
 
     torch.cuda.set_device(0)
+    if args.config != "c4":
+        n0, p0 = WORKLOAD_SIZES[args.config]
+        args.n = args.n or n0
+        args.p = args.p or p0
     if args.newton > 0:
         newton_bench(args)
         return
@@ -563,8 +673,14 @@ def main():
     if args.precond_compare > 0:
         precond_bench(args)
         return
+    if args.config == "c4":
+        batch_linear_bench(args)
+        return
+    wl = WORKLOADS[args.config]
+    prec_main = args.prec or wl["prec"]
+    headline = args.config == "c2"
     t0 = time.perf_counter()
-    pb = configs.c2(n=args.n, p=args.p, device="cuda")
+    pb = getattr(configs, args.config)(n=args.n, p=args.p, device="cuda")
     d = pb.dims()
     log("workload", d)
     blk = gen_blocks(pb)
@@ -609,7 +725,7 @@ def main():
 
     v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(d["nf"] * d["ncomp"] * d["npf"])).cuda()
 
-    def step(precision, prec="bj"):
+    def step(precision, prec=prec_main):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         ev[0].record(stream)
         pl.condense(blk)
@@ -633,31 +749,37 @@ def main():
             raise RuntimeError(f"{precision} {prec} solve did not converge: {st}")
         return st, ph
 
-    for _ in range(args.warmup):
-        st, ph = step("mixed")
-        log("warmup mixed", st["iters"], ph)
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    phs = []
-    for _ in range(args.steps):
-        st, ph = step("mixed")
-        phs.append(ph)
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - ts) / max(args.steps, 1)
-    st_mixed = st
-    ph_mixed = {k: float(np.mean([p[k] for p in phs])) for k in phs[0]} if phs else ph
-    log("mixed step", t_mixed, st_mixed["iters"], ph_mixed)
+    def timed_steps(precision, warmup, steps):
+        """warmup untimed steps (they also size the context's workspaces for this precision), then
+        `steps` steps each timed by the host clock between device synchronisations; returns the mean
+        step time, the per-step times, the last stats and the mean phase times."""
+        for _ in range(warmup):
+            st, ph = step(precision)
+            log("warmup", precision, st["iters"], ph)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        times, phs = [], []
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            st, ph = step(precision)          # ends with a device synchronisation
+            times.append(time.perf_counter() - t1)
+            phs.append(ph)
+        torch.cuda.synchronize()
+        mean = (time.perf_counter() - ts) / max(steps, 1)
+        phm = {k: float(np.mean([p[k] for p in phs])) for k in phs[0]} if phs else ph
+        log(precision, "step", mean, st["iters"], phm)
+        return mean, times, st, phm
+
+    t_mixed, times_mixed, st_mixed, ph_mixed = timed_steps("mixed", args.warmup, args.steps)
     x_mixed = pl.x.clone()
     t_fp64 = None
+    times_fp64 = None
     st64 = None
     ph64 = None
     if not args.no_fp64:
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        st64, ph64 = step("fp64")
-        torch.cuda.synchronize()
-        t_fp64 = time.perf_counter() - ts
-        log("fp64 step", t_fp64, st64["iters"], ph64)
+        # the FP64 leg is warmed up and averaged like the mixed one (its warm-up also grows the
+        # context's folded-block workspace to the FP64 size outside the timed region)
+        t_fp64, times_fp64, st64, ph64 = timed_steps("fp64", max(1, min(args.warmup, 2)), args.steps)
         dx = float(((x_mixed - pl.x).norm() / pl.x.norm()).item())
     else:
         dx = None
@@ -678,15 +800,26 @@ def main():
         t_mv, t_bj = stt["t_matvec"] / n, stt["t_prec"] / n
         out = dict(n_timed=stt["n_timed"], matvec_ms=t_mv * 1e3, matvec_GBs=bmv / t_mv / 1e9,
                    t_matvec_s=stt["t_matvec"], t_prec_s=stt["t_prec"], t_orth_s=stt["t_orth"])
-        if not folded:        # with the inverses folded into the blocks no step applies block-Jacobi
-            out.update(bj_apply_ms=t_bj * 1e3, bj_apply_GBs=bbj / t_bj / 1e9)
+        if prec_main == "bj":
+            if not folded:    # with the inverses folded into the blocks no step applies block-Jacobi
+                out.update(bj_apply_ms=t_bj * 1e3, bj_apply_GBs=bbj / t_bj / 1e9)
+        elif prec_main in ("bj_poly", "bj_cheb") and t_bj > 0:
+            # a degree-P polynomial applies the operator P-1 times; with block-Jacobi folded each
+            # application is one block row product over the folded blocks (the matvec's bytes), else
+            # a product and a block-Jacobi apply; the vector traffic of the recurrences is not counted
+            P = 10
+            per = bmv if folded else bmv + bbj
+            pb_bytes = (P - 1) * per + (0 if folded else bbj)
+            out.update(prec_apply_ms=t_bj * 1e3, prec_apply_bytes_lower=pb_bytes,
+                       prec_apply_GBs_lower=pb_bytes / t_bj / 1e9, npoly=stt.get("npoly"),
+                       fallback_flags=stt.get("fallback_flags"))
         return out
     r32 = rates(st_mixed, b32, bj32)
     r64 = rates(st64, b64, bj64) if st64 else None
     log("in-solve rates mixed", r32)
     log("in-solve rates fp64", r64)
     bj_loop = None
-    if folded:
+    if folded and prec_main == "bj":
         # the block-Jacobi apply (once per cycle when folded) in a loop of its own
         B64 = torch.empty(d["nf"] * nb * nb, dtype=torch.float64, device="cuda")
         B32 = torch.empty(d["nf"] * nb * nb, dtype=torch.float32, device="cuda")
@@ -702,7 +835,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) / 1e3 / 50
-        bj_loop = dict(fp32_ms=t * 1e3, fp32_GBs=bj32 / t / 1e9, launches=50)
+        bj_loop = dict(fp32_ms=t * 1e3, fp32_GBs=bj32 / t / 1e9, launches=50, set_GB=bj32 / 1e9)
         del B64, B32
         log("block-Jacobi apply loop", bj_loop)
     line = {
@@ -717,18 +850,23 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 matrix/f64 vectors (mixed)",
-        "data": "synthetic (seeded jittered mesh, manufactured elasticity load)",
-        "config": {"workload": f"3D linear elasticity E=1 nu=0.3, unit cube {args.n}^3 hexes jitter 0.05h, p={args.p}, "
-                               f"tau=1; {'GMRES' if args.orth == 'dcgs2' else 'FGMRES'}(50)+block-Jacobi "
+        "data": ("synthetic (seeded jittered mesh, manufactured elasticity load)" if args.config == "c2" else
+                 "synthetic (seeded mesh, seeded Gaussian-bump linearisation state)"),
+        "config": {"workload": wl["text"].format(n=args.n, p=args.p) +
+                               f"; {'GMRES' if args.orth == 'dcgs2' else 'FGMRES'}(50)+{PREC_TEXT[prec_main]} "
                                f"({args.orth.upper()}"
-                               f"{', folded K M^-1' if args.orth == 'dcgs2' and not args.no_fold else ''}) rtol 1e-8",
+                               f"{', folded K M^-1' if folded else ''}) rtol 1e-8",
                    "ne": d["ne"], "nf": d["nf"], "ndof": d["nf"] * nb, "face_block": nb,
                    "element_schur": pl.nt},
         "solve_s_mixed": ph_mixed["solve"],
         "phases_s_mixed": ph_mixed,
         "iters_mixed": st_mixed["iters"],
         "rel_resid_mixed": st_mixed["rel_resid_true"],
+        "step_s_mixed_minmax": [min(times_mixed), max(times_mixed)] if times_mixed else None,
         "step_s_fp64": t_fp64,
+        "step_s_fp64_minmax": [min(times_fp64), max(times_fp64)] if times_fp64 else None,
+        "steps_fp64": len(times_fp64) if times_fp64 else 0,
+        "mixed_vs_fp64_speedup": (t_fp64 / t_mixed) if t_fp64 else None,
         "solve_s_fp64": ph64["solve"] if ph64 else None,
         "phases_s_fp64": ph64,
         "iters_fp64": st64["iters"] if st64 else None,
@@ -741,7 +879,8 @@ def main():
         "bj_apply_loop": bj_loop,
         "roofline": {"bound": "hbm", "achieved": r32["matvec_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": r32["matvec_GBs"] / PEAK_HBM_GBS,
-                     "traffic": (measured_traffic("fp32_matvec") if (args.n, args.p) == (24, 3) else None),
+                     "traffic": (measured_traffic("fp32_matvec", wl["tag"])
+                                 if (args.n, args.p) == WORKLOAD_SIZES[args.config] else None),
                      "kernel": "k_face_op<float,float,256,false,0,4> (FP32 block matvec)",
                      "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
                      "timing": "HIP events recorded at the start and end of each matvec kernel of the timed mixed "
@@ -762,7 +901,7 @@ def main():
             torch.cuda.empty_cache()
     if extra:
         line["other_preconditioners_mixed"] = extra
-    if not args.no_stage2:
+    if not args.no_stage2 and headline:
         line["second_stage_mixed"] = second_stage(args, pl, blk, d, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, blk, pl, st_mixed["iters"])

@@ -252,7 +252,26 @@ typedef struct {
                                    no separate apply), the step's one matvec (events recorded at
                                    the block-matvec kernel's own start and end), and
                                    orthogonalisation + Givens + normalisation */
+    double  cheb_alpha, cheb_beta;        /* Chebyshev interval [alpha, beta] of HDG_PREC_*_CHEB */
+    int32_t fallback_flags;     /* HDG_FALLBACK_* bits: what the solve changed on its own */
+    int32_t fp64_cycles;        /* mixed path: restart cycles run with the FP64 operator after
+                                   HDG_FALLBACK_MIXED_TO_FP64 */
 } hdg_solve_stats;
+
+/* Safeguards of hdg_gmres_solve (none is in the paper, which states no safeguard for its
+ * polynomial preconditioner or for precision):
+ *   HDG_FALLBACK_PP_BREAKDOWN    the Arnoldi(P) cycle of the polynomial setup broke down
+ *                                (h_{j+1,j} = 0) before step P;
+ *   HDG_FALLBACK_PP_SMALL_RITZ   harmonic Ritz values below 1e-12 max|theta| were dropped;
+ *   HDG_FALLBACK_PP_NO_INTERVAL  the Ritz values give no positive Chebyshev interval;
+ *   HDG_FALLBACK_PP_TO_BASE      one of the three above: the solve ran with the base
+ *                                preconditioner alone (block-Jacobi or additive Schwarz);
+ *   HDG_FALLBACK_MIXED_TO_FP64   a mixed-precision restart cycle's true FP64 residual fell by
+ *                                less than half and stayed above twice what that cycle's inner
+ *                                (FP32-operator) iteration estimated: the FP32 matrix limits the
+ *                                refinement, and the remaining cycles use K64 and FP64 inverses. */
+enum { HDG_FALLBACK_PP_BREAKDOWN = 1, HDG_FALLBACK_PP_SMALL_RITZ = 2, HDG_FALLBACK_PP_NO_INTERVAL = 4,
+       HDG_FALLBACK_PP_TO_BASE = 8, HDG_FALLBACK_MIXED_TO_FP64 = 16 };
 
 void       hdg_solve_opts_default(hdg_solve_opts* opts_h);
 hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims,
@@ -403,6 +422,11 @@ hdg_status hdg_ilu_asm_apply(hdg_ctx ctx, hdg_ilu_asm h, const double* y, double
  * hdg_bj_apply: z_f = P_f^{-1} y_f with Binv64 or Binv32 -- Section 4.5.
  * hdg_poly_apply: z = p(B) M^{-1} y for given Leja-ordered Ritz values (host arrays;
  *   conjugate pairs adjacent, positive imaginary part first) -- Section 4.7.
+ * hdg_cheb_apply: z = x_P, the P-th iterate (x_0 = 0, P-1 applications of B) of Chebyshev
+ *   acceleration for B x = M^{-1} y over the real interval [alpha, beta], 0 < alpha < beta
+ *   (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Algorithm 12.1), the
+ *   Chebyshev variant of the polynomial preconditioner (HDG_PREC_BJ_CHEB) -- Section 3.4.
+ *   HDG_ERR_ARG for degree outside [1, 64] or an interval that is not positive.
  */
 hdg_status hdg_matvec(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
                       const int32_t* nbr, int32_t precision, const double* x, double* y);
@@ -414,6 +438,9 @@ hdg_status hdg_poly_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, 
                           const int32_t* nbr, const double* Binv64, const float* Binv32,
                           int32_t precision, int32_t npoly, const double* theta_re_h,
                           const double* theta_im_h, const double* y, double* z);
+hdg_status hdg_cheb_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
+                          const int32_t* nbr, const double* Binv64, const float* Binv32, int32_t precision,
+                          int32_t degree, double alpha, double beta, const double* y, double* z);
 
 /* ---------------------------------------------------------------------------
  * Batched independent instances (many small meshes of different element types,

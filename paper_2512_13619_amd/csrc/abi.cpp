@@ -15,6 +15,9 @@ hdg_status poly_apply_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, con
                           const double* tim, const double* y, double* z);
 hdg_status op_apply_run(hdg_ctx ctx, const hdg_dims* d, const void* M1, bool m1_32, const int32_t* nbr, int S1,
                         const double* x, double* y);
+hdg_status cheb_apply_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const float* K32, const int32_t* nbr,
+                          const double* B64, const float* B32, int precision, int P, double alpha, double beta,
+                          const double* y, double* z);
 
 void* ws_get(hdg_ctx ctx, WsSlot slot, size_t bytes, hdg_status* st) {
     *st = HDG_OK;
@@ -455,6 +458,25 @@ hdg_status hdg_poly_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, 
     }
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
     return poly_apply_run(ctx, dims, K64, K32, nbr, Binv64, Binv32, precision, npoly, tre, tim, y, z);
+    GUARD_END
+}
+
+hdg_status hdg_cheb_apply(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32,
+                          const int32_t* nbr, const double* Binv64, const float* Binv32, int32_t precision,
+                          int32_t degree, double alpha, double beta, const double* y, double* z) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    const bool m32 = precision == HDG_MIXED;
+    if ((m32 ? (const void*)K32 : (const void*)K64) == nullptr || !nbr || !y || !z || y == z ||
+        (m32 ? (const void*)Binv32 : (const void*)Binv64) == nullptr)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_cheb_apply: NULL or aliased pointer");
+    if (degree < 1 || degree > 64) return set_err(ctx, HDG_ERR_ARG, "hdg_cheb_apply: degree must be in [1, 64]");
+    if (!(alpha > 0.0) || !(beta > alpha) || !std::isfinite(beta))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_cheb_apply: need 0 < alpha < beta < inf");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return cheb_apply_run(ctx, dims, K64, K32, nbr, Binv64, Binv32, precision, degree, alpha, beta, y, z);
     GUARD_END
 }
 

@@ -305,10 +305,15 @@ hdg_status arnoldi_setup(hdg_ctx ctx, const Op& op, const SolveWs& w, const doub
     std::vector<double> Hc((size_t)w.ldh * P);
     HDG_HIP_CHECK(ctx, hipMemcpyAsync(Hc.data(), w.H, sizeof(double) * Hc.size(), hipMemcpyDeviceToHost, ctx->stream));
     HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-    // stop at a breakdown (h_{j+1,j} == 0): use the leading block
+    // stop at a breakdown: h_{j+1,j} zero, or below 1e-12 of the norm of B v_j (the column's
+    // 2-norm), where rounding leaves a vector with no direction of its own; use the leading block
     int pe = P;
-    for (int j = 0; j < P; ++j)
-        if (!(Hc[(size_t)j * w.ldh + j + 1] > 0.0)) { pe = j + 1; break; }
+    for (int j = 0; j < P; ++j) {
+        double c2 = 0.0;
+        for (int i = 0; i <= j + 1; ++i) c2 += Hc[(size_t)j * w.ldh + i] * Hc[(size_t)j * w.ldh + i];
+        const double h = Hc[(size_t)j * w.ldh + j + 1];
+        if (!(h > 1e-12 * std::sqrt(c2))) { pe = j + 1; break; }
+    }
     // only rows 0..j+1 of column j are ever written on the device; the rest of
     // the Hessenberg matrix is zero by definition, not whatever the workspace holds
     Hh.assign((size_t)(pe + 1) * pe, 0.0);
@@ -436,8 +441,10 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         op64.b32 = false;
     }
     // operator of the Arnoldi steps: K, or the folded K M^{-1} blocks
-    const bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE && !schwarz &&
-                      o->prec != HDG_PREC_ILU_ASM;
+    bool fold = o->fold_prec != 0 && dcgs2 && o->prec != HDG_PREC_NONE && !schwarz && o->prec != HDG_PREC_ILU_ASM;
+    // the preconditioner the Arnoldi steps apply: o->prec, or its base (block-Jacobi or additive
+    // Schwarz alone) when the polynomial setup falls back
+    int prec = o->prec;
     Op opi = op;
     if (fold) {
         const size_t nblk_el = (size_t)nf * S * nb * nb;
@@ -487,6 +494,8 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             ctx->err = "polynomial preconditioner: eigenvalue iteration did not converge";
             return HDG_ERR_SINGULAR;
         }
+        if (pe < P) stats->fallback_flags |= HDG_FALLBACK_PP_BREAKDOWN;
+        if (nt < pe) stats->fallback_flags |= HDG_FALLBACK_PP_SMALL_RITZ;
         plan.tre.assign(tre.begin(), tre.begin() + nt);
         plan.tim.assign(tim.begin(), tim.begin() + nt);
         plan.P = P;
@@ -495,15 +504,21 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             stats->theta_re[i] = plan.tre[i];
             stats->theta_im[i] = plan.tim[i];
         }
-        if (plan.kind == HDG_PREC_BJ_CHEB) {
+        if (plan.kind == HDG_PREC_BJ_CHEB && nt > 0) {
             double lo = INFINITY, hi = -INFINITY;
             for (int i = 0; i < nt; ++i) { lo = std::min(lo, plan.tre[i]); hi = std::max(hi, plan.tre[i]); }
             plan.beta = 1.05 * hi;
             plan.alpha = std::max(lo, plan.beta / 1000.0);
-            if (!(plan.beta > 0.0) || !(plan.alpha < plan.beta)) {
-                ctx->err = "Chebyshev preconditioner: Ritz values give no positive interval";
-                return HDG_ERR_SINGULAR;
-            }
+            if (!(plan.beta > 0.0) || !(plan.alpha < plan.beta)) stats->fallback_flags |= HDG_FALLBACK_PP_NO_INTERVAL;
+            stats->cheb_alpha = plan.alpha;
+            stats->cheb_beta = plan.beta;
+        }
+        // an Arnoldi breakdown, dropped (near-zero) Ritz values or no positive Chebyshev interval:
+        // the polynomial is not trusted and the solve runs with its base preconditioner alone
+        if (stats->fallback_flags & (HDG_FALLBACK_PP_BREAKDOWN | HDG_FALLBACK_PP_SMALL_RITZ |
+                                     HDG_FALLBACK_PP_NO_INTERVAL)) {
+            stats->fallback_flags |= HDG_FALLBACK_PP_TO_BASE;
+            prec = schwarz ? HDG_PREC_ASM : HDG_PREC_BJ;
         }
     }
     stats->t_setup = now_s() - t0;
@@ -552,7 +567,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         return s3 != HDG_OK ? s3 : s4;
     };
     // the preconditioner is timed only where a step applies one (not with block-Jacobi folded)
-    const bool prec_timed = !(fold && o->prec == HDG_PREC_BJ);
+    bool prec_timed = !(fold && prec == HDG_PREC_BJ);
     // Delayed-CGS2 steps of one cycle (right preconditioning with a fixed preconditioner,
     // no Z): step j applies B = K M^{-1} to vt_j, one inner-product sweep, the coefficient
     // kernel (delayed pass for vt_j, column j-1 and its Givens rotation, new column), one
@@ -565,13 +580,13 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             double* vj = w.V + (size_t)j * w.ld;
             double* wv = w.V + (size_t)(j + 1) * w.ld;
             const double* src = zt;
-            if (fold && o->prec == HDG_PREC_BJ) {
+            if (fold && prec == HDG_PREC_BJ) {
                 src = vj;    // folded: nothing left to apply
             } else {
                 // block-Jacobi is one face-operator kernel; a polynomial takes a marker at its end
-                const bool one_kernel = opi.pk != PK_ASM && o->prec == HDG_PREC_BJ;
+                const bool one_kernel = opi.pk != PK_ASM && prec == HDG_PREC_BJ;
                 arm(timed ? ev.e[6 * j] : nullptr, timed && one_kernel ? ev.e[6 * j + 1] : nullptr);
-                if ((s2 = prec_apply(ctx, opi, o->prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
+                if ((s2 = prec_apply(ctx, opi, prec, plan, vj, zt, w.work, w.ld, skip)) != HDG_OK) return s2;
                 if ((s2 = settle()) != HDG_OK) return s2;
                 if (!one_kernel && (s2 = mark(j, 1)) != HDG_OK) return s2;
             }
@@ -592,17 +607,17 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
                                     w.ldh, w.hist)) != HDG_OK)
             return s2;
         if ((s2 = krylov_backsolve(ctx, w.ctl, w.H, w.ldh, w.g, w.y)) != HDG_OK) return s2;
-        if (o->prec == HDG_PREC_NONE) return vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
+        if (prec == HDG_PREC_NONE) return vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, x, N, nullptr, &w.ctl->k);
         if ((s2 = vec_lincomb(ctx, N, tv, 0.0, nullptr, 0.0, nullptr, nullptr)) != HDG_OK) return s2;
         if ((s2 = vec_multiaxpy(ctx, w.V, w.ld, jmax, w.y, 1.0, tv, N, nullptr, &w.ctl->k)) != HDG_OK) return s2;
         if (!fold) {
-            if ((s2 = prec_apply(ctx, op, o->prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
+            if ((s2 = prec_apply(ctx, op, prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
             return vec_lincomb(ctx, N, x, 1.0, x, 1.0, zt, nullptr);
         }
         // folded: x += M^{-1} q(K M^{-1}) (V y), q = 1 for block-Jacobi, the polynomial otherwise
         const double* u = tv;
-        if (o->prec != HDG_PREC_BJ) {
-            if ((s2 = prec_apply(ctx, opi, o->prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
+        if (prec != HDG_PREC_BJ) {
+            if ((s2 = prec_apply(ctx, opi, prec, plan, tv, zt, w.work, w.ld, nullptr)) != HDG_OK) return s2;
             u = zt;
         }
         FaceEpilogue e = epi0();
@@ -631,7 +646,7 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             double* zj = w.Z + (size_t)j * w.ld;
             double* wv = w.V + (size_t)(j + 1) * w.ld;
             if ((s2 = mark(j, 0)) != HDG_OK) return s2;
-            if ((s2 = prec_apply(ctx, op, o->prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
+            if ((s2 = prec_apply(ctx, op, prec, plan, vj, zj, w.work, w.ld, skip)) != HDG_OK) return s2;
             if ((s2 = mark(j, 1)) != HDG_OK) return s2;
             if ((s2 = timed_matvec(j, op, zj, wv)) != HDG_OK) return s2;
             if ((s2 = mark(j, 4)) != HDG_OK) return s2;
@@ -657,6 +672,8 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
     };
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    bool mixed_now = mixed, have_prev = false;
+    double prev_beta = 0.0, prev_est = 0.0;
     auto drop_graph = [&]() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -722,6 +739,25 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
             }
         }
         stats->rel_resid_true = bnorm > 0 ? hc.beta / bnorm : 0.0;
+        // Iterative refinement on the mixed path: if the last cycle's inner iteration reduced its
+        // (FP32-operator) residual estimate well below what the true FP64 residual now shows, and the
+        // true residual fell by less than half, the FP32 operator limits the refinement: the
+        // remaining cycles apply the FP64 blocks and inverses.
+        if (mixed && !mixed_now && hc.k > 0) ++stats->fp64_cycles;
+        if (mixed_now && have_prev && hc.beta > 0.5 * prev_beta && hc.beta > 2.0 * prev_est && hc.beta > target) {
+            mixed_now = false;
+            stats->fallback_flags |= HDG_FALLBACK_MIXED_TO_FP64;
+            op = op64;
+            opi = op64;
+            fold = false;
+            prec_timed = true;
+            drop_graph();
+        }
+        if (hc.k > 0) {
+            have_prev = true;
+            prev_beta = hc.beta;
+            prev_est = hc.est;
+        }
         if (hc.nonfinite) {
             ctx->err = "residual or Arnoldi data became NaN or Inf";
             result = HDG_ERR_NONFINITE;
@@ -765,6 +801,30 @@ hdg_status poly_apply_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, con
     pl.tre.assign(tre, tre + npoly);
     pl.tim.assign(tim, tim + npoly);
     pl.P = npoly;
+    return poly_apply(ctx, op, pl, y, z, w.work, w.ld, nullptr);
+}
+
+// Test hook: z = Chebyshev acceleration of degree P on B = M^{-1} K over [alpha, beta], applied to M^{-1} y.
+hdg_status cheb_apply_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const float* K32, const int32_t* nbr,
+                          const double* B64, const float* B32, int precision, int P, double alpha, double beta,
+                          const double* y, double* z) {
+    const int nb = d->ncomp * d->npf, L = d->nlfe, S = 2 * L - 1, nf = d->nf;
+    const size_t N = (size_t)nf * nb;
+    hdg_status st;
+    SolveWs w;
+    if ((st = alloc_solve_ws(ctx, N, 1, 1, 1, &w)) != HDG_OK) return st;
+    Op op;
+    const bool mixed = precision == HDG_MIXED;
+    op.nf = nf; op.nb = nb; op.S = S; op.L = L; op.N = N; op.nbr = nbr;
+    op.K = mixed ? (const void*)K32 : (const void*)K64;
+    op.k32 = mixed;
+    op.Binv = mixed ? (const void*)B32 : (const void*)B64;
+    op.b32 = mixed;
+    PolyPlan pl;
+    pl.kind = HDG_PREC_BJ_CHEB;
+    pl.P = P;
+    pl.alpha = alpha;
+    pl.beta = beta;
     return poly_apply(ctx, op, pl, y, z, w.work, w.ld, nullptr);
 }
 

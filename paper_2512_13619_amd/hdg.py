@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 HDG_OK, HDG_NOT_CONVERGED = 0, 1
 PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3, "asm": 4, "asm_poly": 5, "asm_cheb": 6, "ilu_asm": 7}
 ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2, "dcgs2": 3}
+FALLBACK = {"pp_breakdown": 1, "pp_small_ritz": 2, "pp_no_interval": 4, "pp_to_base": 8, "mixed_to_fp64": 16}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol declared in include/hdg.h
@@ -23,7 +24,7 @@ SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg
            "hdg_local_size", "hdg_condense", "hdg_condense_keep", "hdg_condense_rhs", "hdg_assemble_blocks",
            "hdg_assemble_rhs", "hdg_solve_opts_default", "hdg_gmres_solve",
            "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
-           "hdg_bj_apply", "hdg_poly_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
+           "hdg_bj_apply", "hdg_poly_apply", "hdg_cheb_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch", "hdg_element_blocks_batch", "hdg_residual_norm_batch",
            "hdg_newton_update_batch", "hdg_ilu_asm_create", "hdg_ilu_asm_destroy", "hdg_ilu_asm_apply"]
@@ -80,7 +81,8 @@ class SolveStats(ctypes.Structure):
                 ("t_setup", ctypes.c_double), ("t_total", ctypes.c_double),
                 ("theta_re", ctypes.c_double * 64), ("theta_im", ctypes.c_double * 64),
                 ("hist_len", ctypes.c_int32), ("n_timed", ctypes.c_int32), ("t_prec", ctypes.c_double),
-                ("t_matvec", ctypes.c_double), ("t_orth", ctypes.c_double)]
+                ("t_matvec", ctypes.c_double), ("t_orth", ctypes.c_double), ("cheb_alpha", ctypes.c_double),
+                ("cheb_beta", ctypes.c_double), ("fallback_flags", ctypes.c_int32), ("fp64_cycles", ctypes.c_int32)]
 
 
 _lib = None
@@ -125,6 +127,7 @@ def load():
     lib.hdg_asm_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp, vp, vp]
     lib.hdg_poly_apply.argtypes = [vp, pd, vp, vp, vp, vp, vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                    vp, vp]
+    lib.hdg_cheb_apply.argtypes = [vp, pd, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, vp, vp]
     pdbl = ctypes.POINTER(dbl)
     lib.hdg_hessenberg_eigvals.argtypes = [ctypes.c_int, pdbl, ctypes.c_int, pdbl, pdbl]
     lib.hdg_harmonic_ritz.argtypes = [ctypes.c_int, pdbl, dbl, pdbl, pdbl, ctypes.POINTER(ctypes.c_int)]
@@ -504,6 +507,19 @@ class Context:
             _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64", allow_none=True),
             _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision], len(th),
             tr.ctypes.data_as(pd), ti.ctypes.data_as(pd), _ptr(y, torch.float64, nf * nb, "y"),
+            _ptr(z, torch.float64, nf * nb, "z")))
+
+    def cheb_apply(self, dims, K64, K32, nbr, Binv64, Binv32, degree, alpha, beta, y, z, precision="fp64"):
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        return self._check(self.lib.hdg_cheb_apply(
+            self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64", allow_none=True),
+            _ptr(K32, torch.float32, nf * S * nb * nb, "K32", allow_none=True), _ptr(nbr, torch.int32, nf * S, "nbr"),
+            _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64", allow_none=True),
+            _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), PRECISION[precision],
+            int(degree), float(alpha), float(beta), _ptr(y, torch.float64, nf * nb, "y"),
             _ptr(z, torch.float64, nf * nb, "z")))
 
 

@@ -77,7 +77,15 @@ def orth_kw(orth):
     return dict(orth=orth)
 
 
-ORTHS = ["cgs2", "dcgs2", "dcgs2+fold"]
+ORTHS = ["cgs2", "dcgs2", "dcgs2+fold", "cgs", "mgs"]
+
+
+def oracle_solver(orth):
+    """The oracle routine a GPU orthogonalisation option is compared with: flexible GMRES with the
+    same Gram-Schmidt variant, or GMRES with delayed CGS2 (whose iterates equal CGS2's)."""
+    if orth in ("cgs2", "cgs", "mgs"):
+        return lambda *a, **k: krylov.fgmres(*a, orth=orth, **k)
+    return krylov.gmres_dcgs2
 
 
 def relerr(a, b):
@@ -332,9 +340,8 @@ def test_gmres_history_matches_oracle_fgmres(ctx, orth):
                          hist_len=600, **orth_kw(orth))
     Binv = krylov.bj_inverses(out["K"])
     hist = []
-    solver = krylov.fgmres if orth == "cgs2" else krylov.gmres_dcgs2
-    _, info = solver(lambda v: out["A"] @ v, out["r"], prec=lambda v: krylov.bj_apply(Binv, v),
-                     restart=50, rtol=1e-12, max_iters=500, hist=hist)
+    _, info = oracle_solver(orth)(lambda v: out["A"] @ v, out["r"], prec=lambda v: krylov.bj_apply(Binv, v),
+                                  restart=50, rtol=1e-12, max_iters=500, hist=hist)
     assert abs(st["iters"] - info["iters"]) <= 1
     n = min(20, len(hist), len(st["hist"]))
     assert np.allclose(st["hist"][:n], hist[:n], rtol=1e-6)
@@ -353,8 +360,8 @@ def test_gmres_long_cycle_matches_oracle(ctx, orth):
     st = ctx.gmres_solve(pb.dims(), K, None, nbr, r, x, restart=200, max_iters=1000, rtol=1e-12, prec="none",
                          hist_len=300, **orth_kw(orth))
     hist = []
-    solver = krylov.fgmres if orth == "cgs2" else krylov.gmres_dcgs2
-    _, info = solver(lambda v: out["A"] @ v, out["r"], restart=200, rtol=1e-12, max_iters=1000, hist=hist)
+    _, info = oracle_solver(orth)(lambda v: out["A"] @ v, out["r"], restart=200, rtol=1e-12, max_iters=1000,
+                                  hist=hist)
     assert st["converged"] and st["cycles"] == 1 and st["iters"] > 80, st
     assert abs(st["iters"] - info["iters"]) <= 1
     n = min(80, len(hist), len(st["hist"]))
@@ -452,3 +459,138 @@ def test_failure_paths(ctx):
     with pytest.raises(hdg.HdgError) as ei:
         ctx.gmres_solve(pb.dims(), K, None, nbr, r, x, precision="mixed")
     assert ei.value.status == -1
+
+
+def _oracle_theta(out, v0, P):
+    """Leja-ordered harmonic Ritz values of one MGS Arnoldi(P) cycle on B = M^{-1} K (block-Jacobi M)
+    started at v0 (Section 4.7), computed by the oracle."""
+    Binv = krylov.bj_inverses(out["K"])
+    opB = lambda v: krylov.bj_apply(Binv, out["A"] @ v)
+    H, _ = poly.arnoldi_mgs(opB, v0, P)
+    return Binv, opB, poly.leja_order(poly.harmonic_ritz(H))
+
+
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p1", "ns_tet_p2"])
+def test_poly_setup_theta_matches_oracle(ctx, name):
+    """The Ritz values a BJ-PP(10) solve uses (its device MGS Arnoldi on B = M^{-1}K, harmonic Ritz
+    values and Leja order on the host) against the oracle's from the same start vector, value by
+    value in the same order; and the solve's Chebyshev interval against the reading's formula on the
+    oracle's values."""
+    pb, out = case_data(name)
+    say("theta", name)
+    K, K32, nbr = _dev_matrix(out)
+    N = out["r"].shape[0]
+    v0 = np.random.default_rng(7).standard_normal(N)
+    _, _, th = _oracle_theta(out, v0, 10)
+    r = torch.as_tensor(out["r"]).cuda()
+    v0d = torch.as_tensor(v0).cuda()
+    x = torch.zeros_like(r)
+    st = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=30, max_iters=2000, rtol=1e-12, prec="bj_poly",
+                         poly_v0=v0d, poly_degree=10, precision="fp64")
+    assert st["converged"] and st["fallback_flags"] == 0, st
+    scale = np.abs(th).max()
+    say("theta errors", len(th), np.abs(st["theta"] - th).max() / scale)
+    assert st["theta"].shape == th.shape
+    assert np.abs(st["theta"] - th).max() <= 1e-9 * scale
+    # Chebyshev interval: beta = 1.05 max Re theta, alpha = max(min Re theta, beta / 1000)
+    x.zero_()
+    st = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=30, max_iters=2000, rtol=1e-12, prec="bj_cheb",
+                         poly_v0=v0d, poly_degree=10, precision="fp64")
+    beta = 1.05 * th.real.max()
+    alpha = max(th.real.min(), beta / 1000)
+    assert st["converged"], st
+    assert abs(st["cheb_beta"] - beta) <= 1e-9 * beta and abs(st["cheb_alpha"] - alpha) <= 1e-9 * beta
+
+
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p1", "ns_tet_p2"])
+@pytest.mark.parametrize("degree", [1, 2, 10])
+def test_cheb_apply_matches_oracle(ctx, name, degree):
+    """The Chebyshev preconditioner's apply (fused face-operator steps) entry by entry against the
+    oracle's Chebyshev acceleration (Saad, Algorithm 12.1) on B = M^{-1}K applied to M^{-1}y, over the
+    interval the solve would take from the oracle's Ritz values."""
+    pb, out = case_data(name)
+    say("cheb apply", name, degree)
+    K, K32, nbr = _dev_matrix(out)
+    N = out["r"].shape[0]
+    rng = np.random.default_rng(9)
+    Binv, opB, th = _oracle_theta(out, rng.standard_normal(N), 10)
+    beta = 1.05 * th.real.max()
+    alpha = max(th.real.min(), beta / 1000)
+    y = rng.standard_normal(N)
+    ref = poly.chebyshev(opB, krylov.bj_apply(Binv, y), alpha, beta, degree)
+    B64 = torch.as_tensor(Binv).cuda().contiguous()
+    yd = torch.as_tensor(y).cuda()
+    z = torch.zeros_like(yd)
+    ctx.cheb_apply(pb.dims(), K, None, nbr, B64, None, degree, alpha, beta, yd, z)
+    e = relerr(z.cpu().numpy(), ref)
+    say("cheb errors", e)
+    assert e < 1e-10, e
+    # mixed: FP32 blocks and inverses, FP64 vectors -- within a few FP32 rounding units
+    z32 = torch.zeros_like(yd)
+    ctx.cheb_apply(pb.dims(), None, K32, nbr, None, B64.float().contiguous(), degree, alpha, beta, yd, z32,
+                   precision="mixed")
+    assert relerr(z32.cpu().numpy(), ref) < 1e-4
+
+
+def test_cheb_apply_rejects_bad_interval(ctx):
+    from paper_2512_13619_amd import hdg
+    pb, out = case_data("c1")
+    K, K32, nbr = _dev_matrix(out)
+    B64 = torch.as_tensor(krylov.bj_inverses(out["K"])).cuda().contiguous()
+    y = torch.ones(out["r"].shape[0], dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(y)
+    for a, b, deg in ((0.0, 1.0, 3), (2.0, 1.0, 3), (0.5, 1.0, 0), (0.5, 1.0, 65)):
+        with pytest.raises(hdg.HdgError) as ei:
+            ctx.cheb_apply(pb.dims(), K, None, nbr, B64, None, deg, a, b, y, z)
+        assert ei.value.status == -1
+    assert torch.count_nonzero(z).item() == 0
+
+
+@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+def test_mixed_refinement_stagnation_switches_to_fp64(ctx, orth):
+    """The mixed path's safeguard, forced from the host: an FP32 matrix that is not K's rounding (its
+    off-diagonal blocks scaled by 1.6) makes every inner cycle converge on the wrong operator, so the
+    true FP64 residual stalls; the solve switches its remaining cycles to the FP64 blocks, sets
+    HDG_FALLBACK_MIXED_TO_FP64 and still reaches the oracle's solution."""
+    from paper_2512_13619_amd import hdg
+    pb, out = case_data("c1")
+    say("mixed fallback", orth)
+    K, K32, nbr = _dev_matrix(out)
+    bad = K.clone()
+    bad[:, 1:] *= 1.6
+    bad32 = bad.float().contiguous()
+    r = torch.as_tensor(out["r"]).cuda()
+    x = torch.zeros_like(r)
+    st = ctx.gmres_solve(pb.dims(), K, bad32, nbr, r, x, restart=20, max_iters=4000, rtol=1e-13, prec="bj",
+                         precision="mixed", **orth_kw(orth))
+    say("  ", st["iters"], st["cycles"], st["fallback_flags"], st["fp64_cycles"])
+    assert st["converged"] and st["fallback_flags"] & hdg.FALLBACK["mixed_to_fp64"], st
+    assert 0 < st["fp64_cycles"] < st["cycles"]
+    assert relerr(x.cpu().numpy(), out["x"]) < 1e-10
+    # the proper FP32 rounding never triggers it
+    x.zero_()
+    st = ctx.gmres_solve(pb.dims(), K, K32, nbr, r, x, restart=20, max_iters=4000, rtol=1e-13, prec="bj",
+                         precision="mixed", **orth_kw(orth))
+    assert st["converged"] and st["fallback_flags"] == 0 and st["fp64_cycles"] == 0, st
+
+
+@pytest.mark.parametrize("prec", ["bj_poly", "bj_cheb"])
+def test_poly_breakdown_falls_back_to_block_jacobi(ctx, prec):
+    """The polynomial setup's safeguard, forced from the host: with the off-diagonal blocks zeroed,
+    B = M^{-1}K is the identity, so the setup's Arnoldi breaks down at its first step; the solve
+    flags the breakdown, runs with block-Jacobi alone, and converges in one step."""
+    from paper_2512_13619_amd import hdg
+    pb, out = case_data("c1")
+    K, K32, nbr = _dev_matrix(out)
+    Kd = K.clone()
+    Kd[:, 1:] = 0.0
+    r = torch.as_tensor(out["r"]).cuda()
+    x = torch.zeros_like(r)
+    v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(r.numel())).cuda()
+    st = ctx.gmres_solve(pb.dims(), Kd, Kd.float().contiguous(), nbr, r, x, restart=20, max_iters=100, rtol=1e-12,
+                         prec=prec, poly_v0=v0, poly_degree=10)
+    f = st["fallback_flags"]
+    assert f & hdg.FALLBACK["pp_breakdown"] and f & hdg.FALLBACK["pp_to_base"], st
+    assert st["converged"] and st["iters"] == 1, st
+    Binv = krylov.bj_inverses(Kd.cpu().numpy())
+    assert relerr(x.cpu().numpy(), krylov.bj_apply(Binv, out["r"])) < 1e-12
