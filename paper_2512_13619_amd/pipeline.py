@@ -97,7 +97,7 @@ class Pipeline:
                     G=z(nt * nq), H=z(nt * nu), J=z(nt * nt), ru=z(nu), rt=z(nt), q=z(nq))
 
     def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, time_term=None,
-               forcing=None, **solve_kw):
+               forcing=None, reuse=None, refresh=0.25, **solve_kw):
         """Damped Newton iteration (Section 4.4) on a scalar convection-diffusion model.
 
         u [ne*npe] and uhat [nf*npf] (device, float64) hold the state and are updated in place.
@@ -109,12 +109,42 @@ class Pipeline:
         Walker's choice 2 (SIAM J. Sci. Comput. 17 (1996)): eta_0 = 0.01, eta_k = 0.9 (||R_k|| /
         ||R_{k-1}||)^2, kept above 0.9 eta_{k-1}^2 when that exceeds 0.1, at most 0.1, and not
         below solve_kw["rtol"] nor below what the stopping test needs; None: solve_kw["rtol"].
+        reuse="chord": the linearisation (condensation factors, assembled blocks, block-Jacobi
+        inverses and folded blocks) is kept from the step that formed it, and later steps only
+        evaluate the residual, condense and assemble its right-hand side with the kept factors
+        (hdg_condense_rhs, hdg_assemble_rhs) and solve with the kept preconditioner setup; a step
+        whose residual norm fell by less than the factor `refresh`, or that needed a damped step,
+        makes the next step form the linearisation afresh. The residual is always the exact one,
+        so the iteration reaches the same solution (chord Newton with refresh). The kept
+        linearisation also carries over to the next call with the same time-term factor c (the
+        stages of a DIRK step, Section 2.2); self.jac_valid = False forgets it.
         solve_kw go to the linear solves (restart, rtol, prec, ...). Returns one
-        dict(norm, alpha, iters) per step and a last entry with the final norm. Sequencing
+        dict(norm, alpha, iters, fresh) per step and a last entry with the final norm. Sequencing
         only: evaluation, solve and updates run in libhdg.so."""
         d = self.dims
-        blk = self.element_arrays()
-        self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term)
+        chord = reuse == "chord"
+        if reuse not in (None, "chord"):
+            raise ValueError(f"reuse must be None or 'chord', not {reuse!r}")
+        c = float(time_term["c"]) if time_term else 0.0
+        if chord and getattr(self, "jac_c", None) != c:
+            self.jac_valid = False
+        if not chord:
+            self.jac_valid = False
+        if getattr(self, "_blk", None) is None:
+            self._blk = self.element_arrays()
+            self._mass_ready = False
+        blk = self._blk
+
+        def evaluate(residual_only):
+            """Element residuals (and, unless residual-only, matrices) at the state; returns whether
+            the matrices were left out."""
+            ro = residual_only and self._mass_ready
+            self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term, residual_only=ro,
+                                    keep_mass=self._mass_ready)
+            self._mass_ready = True
+            return ro
+
+        have_matrices = not evaluate(residual_only=chord and self.jac_valid)
         nrm = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
         n0 = nrm
         hist = []
@@ -130,12 +160,25 @@ class Pipeline:
                         e = max(e, 0.9 * eta * eta)
                     eta = min(e, 0.1)
                 solve_kw["rtol"] = max(eta, rtol_min, 0.5 * max(tol * n0, atol) / nrm)
-            self.condense(blk)
-            self.assemble()
-            if str(solve_kw.get("prec", "")).startswith("asm"):
-                # additive Schwarz patches of this linearisation
-                self.asm_setup(fp32=solve_kw.get("precision", "fp64") == "mixed")
-            st = self.solve(**solve_kw)
+            fresh = not (chord and self.jac_valid)
+            if fresh:
+                if not have_matrices:
+                    evaluate(residual_only=False)
+                self.condense(blk, keep=chord)
+                self.assemble()
+                if str(solve_kw.get("prec", "")).startswith("asm"):
+                    # additive Schwarz patches of this linearisation
+                    self.asm_setup(fp32=solve_kw.get("precision", "fp64") == "mixed")
+                st = self.solve(**solve_kw)
+                if chord:
+                    self.jac_valid, self.jac_c = True, c
+            else:
+                self.condense_rhs(blk["ru"], blk["rt"])
+                self.assemble_rhs()
+                kw = dict(solve_kw)
+                if kw.get("prec", "bj") in ("bj", "bj_poly", "bj_cheb"):
+                    kw["reuse_setup"] = True
+                st = self.solve(**kw)
             self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
             alpha, applied = 1.0, 0.0
             while True:
@@ -143,15 +186,18 @@ class Pipeline:
                 self.ctx.newton_update(alpha - applied, self.x, uhat)
                 applied = alpha
                 # the trial state's blocks: kept as the next step's linearisation if accepted
-                # (M^-1, B_d, C_d depend on the mesh only: kept from the first evaluation)
-                self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term, keep_mass=True)
+                # (M^-1, B_d, C_d depend on the mesh only: kept from the first evaluation); with a
+                # kept linearisation only the residual
+                have_matrices = not evaluate(residual_only=chord)
                 trial = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
                 if trial < nrm or alpha <= min_alpha:
                     break
                 alpha *= 0.5
-            hist.append(dict(norm=nrm, alpha=alpha, iters=st["iters"]))
+            if chord and (alpha < 1.0 or trial > refresh * nrm):
+                self.jac_valid = False
+            hist.append(dict(norm=nrm, alpha=alpha, iters=st["iters"], fresh=fresh))
             prev, nrm = nrm, trial
-        hist.append(dict(norm=nrm, alpha=0.0, iters=0))
+        hist.append(dict(norm=nrm, alpha=0.0, iters=0, fresh=False))
         return hist
 
     def pseudo_transient(self, geom, model, u, uhat, dtau0, tol=1e-10, atol=0.0, max_steps=200, dtau_max=1e12,
@@ -196,10 +242,13 @@ class Pipeline:
         """nsteps steps of a stiffly accurate DIRK scheme (Section 2.2) of size dt; u, uhat are
         advanced in place. Stage i solves, by Newton, the steady system plus the time term
         c M (U_i - u_n) + sum_{j<i} (a_ij/a) R_s(U_j) with c = 1/(a dt), R_s the steady u-rows;
-        u_{n+1} = U_s. Returns the Newton histories of every stage."""
+        u_{n+1} = U_s. newton_kw go to Pipeline.newton; with reuse="chord" the stages share one
+        kept linearisation (all stages have the same c), refreshed by newton's rule. Returns the
+        Newton histories of every stage."""
         A = dirk_tableau(scheme)
         s, a = len(A), A[0][0]
         ne, P = self.dims["ne"], self.dims["npe"]
+        self.jac_valid = False
         z = lambda: torch.zeros(ne * P, dtype=torch.float64, device=self.device)
         un = z()
         hists = []

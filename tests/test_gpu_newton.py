@@ -199,6 +199,34 @@ def test_dirk_steps_match_oracle(ctx, name, scheme, dt, nsteps):
     assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-9
 
 
+@pytest.mark.parametrize("name,scheme,dt,nsteps", [("burgers_quad_p2", "dirk22", 0.05, 2),
+                                                   ("burgers_tri_p3", "dirk33", 0.1, 1),
+                                                   ("poisson_tri_p2", "be", 0.02, 2)])
+def test_dirk_chord_reuse_reaches_the_oracle_states(ctx, name, scheme, dt, nsteps):
+    """DIRK steps whose Newton solves keep the linearisation (condensation factors, assembled blocks,
+    block-Jacobi setup) across Newton steps and stages, refreshing it after a weak step: the states
+    equal the oracle's exact-Newton DIRK states, and most steps reuse the kept linearisation."""
+    import oracle.dirk as ODK
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, inp, inp_np = case(name)
+    d = pb.dims()
+    say("dirk chord", name, scheme, dt, nsteps)
+    u_ref, uh_ref, _ = ODK.dirk_steps(inp_np, _model(inp_np), inp_np["u0"], inp_np["uhat0"], pb.mesh.e2f,
+                                      pb.mesh.f2e, d, dt, nsteps, scheme, newton_rtol=1e-12)
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    u = inp["u0"].cuda().flatten().clone()
+    uh = inp["uhat0"].cuda().flatten().clone()
+    hists = pl.dirk(_geom_dev(inp), _model(inp), u, uh, dt, nsteps, scheme, tol=1e-12, max_steps=60, restart=50,
+                    max_iters=2000, rtol=1e-13, prec="bj", reuse="chord")
+    steps = [x for h in hists for x in h[:-1]]
+    fresh = sum(x["fresh"] for x in steps)
+    say("  steps", len(steps), "fresh", fresh)
+    assert all(h[-1]["norm"] <= 1e-12 * h[0]["norm"] for h in hists)
+    assert fresh < len(steps)
+    assert relerr(u.cpu().numpy(), u_ref.ravel()) < 1e-9
+    assert relerr(uh.cpu().numpy(), uh_ref.ravel()) < 1e-9
+
+
 # ---- the bench-size workload (2D Burgers, 128^2 quads, p = 4): sampled elements ------------
 def _bench_problem():
     return HDGProblem(Mh.structured_quads(128, 0.05, 6), 4, Ph.Burgers(nu=0.01, forcing=_forcing), device="cuda")
