@@ -369,6 +369,17 @@ hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_
                               int32_t flags, const hdg_elem_arrays* out);
 hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
                              const double* rt, double* norm_h);
+/* hdg_residual_norm_noalloc: for callers that cannot allocate device memory (code under
+ *   graph capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments,
+ *   result and kernels as hdg_residual_norm, but its scratch (the assembled trace residual
+ *   and the reduction partials) lives in a fixed 16 MiB device array per GPU instead of a
+ *   context workspace, and it calls no allocating routine. Limit: ncomp*npf*nf (padded to
+ *   64) plus the reduction partials of both vectors must fit in 2^21 doubles, else
+ *   HDG_ERR_ARG with nothing launched. Every call on one GPU shares that GPU's array, which
+ *   keeps the last call's contents: calls that overlap on one GPU (other threads, streams or
+ *   contexts) race; calls on one stream do not. Synchronises the context stream. */
+hdg_status hdg_residual_norm_noalloc(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
+                                     const double* rt, double* norm_h);
 
 /* (6) Additive Schwarz preconditioner with one element per subdomain -- Section 3.3
  * (definition), Section 4.6 (element matrices and their enrichment).

@@ -77,6 +77,54 @@ hdg_status check_dims(hdg_ctx ctx, const hdg_dims* d, bool need_elems, bool need
     return HDG_OK;
 }
 
+// Layout of the residual norm's device scratch (in doubles): the assembled trace residual
+// (padded to 64), the element rows' and the trace rows' block partials, two norms.
+struct NormScratch {
+    size_t nu_all, nface, nfa;
+    int nb_u, nb_f;
+    size_t total() const { return nfa + (size_t)nb_u + (size_t)nb_f + 2; }
+};
+NormScratch norm_scratch(const hdg_dims* d) {
+    NormScratch s;
+    s.nu_all = (size_t)d->ne * d->ncomp * d->npe;
+    s.nface = (size_t)d->nf * d->ncomp * d->npf;
+    s.nfa = (s.nface + 63) / 64 * 64;
+    s.nb_u = krylov_nblk(s.nu_all);
+    s.nb_f = krylov_nblk(s.nface);
+    return s;
+}
+
+hdg_status residual_norm_check(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
+                               const double* rt, const double* norm_h, size_t* need) {
+    hdg_status st = check_dims(ctx, dims, true, true);
+    if (st != HDG_OK) return st;
+    if (!f2e || !ru || !rt || !norm_h) return set_err(ctx, HDG_ERR_ARG, "hdg_residual_norm: NULL pointer");
+    *need = norm_scratch(dims).total();
+    return HDG_OK;
+}
+
+// ||R|| with the scratch at `base` (norm_scratch(dims).total() doubles): every entry the
+// kernels read is written first by this call, so nothing needs clearing.
+hdg_status residual_norm_run(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
+                             const double* rt, double* base, double* norm_h) {
+    const NormScratch s = norm_scratch(dims);
+    double* rf = base;
+    double* part_u = base + s.nfa;
+    double* part_f = part_u + s.nb_u;
+    double* nrm = part_f + s.nb_f;
+    hdg_status st;
+    if ((st = assemble_rhs_run(ctx, dims, f2e, nullptr, rt, rf)) != HDG_OK) return st;
+    if ((st = vec_sumsq_partial(ctx, ru, s.nu_all, part_u, s.nb_u, nullptr)) != HDG_OK) return st;
+    if ((st = krylov_store_norm(ctx, part_u, s.nb_u, nrm)) != HDG_OK) return st;
+    if ((st = vec_sumsq_partial(ctx, rf, s.nface, part_f, s.nb_f, nullptr)) != HDG_OK) return st;
+    if ((st = krylov_store_norm(ctx, part_f, s.nb_f, nrm + 1)) != HDG_OK) return st;
+    double h[2] = {0.0, 0.0};
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    *norm_h = std::sqrt(h[0] * h[0] + h[1] * h[1]);
+    return HDG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -93,6 +141,11 @@ hdg_status hdg_create(hdg_ctx* out, int device, void* hip_stream) {
         return HDG_ERR_HIP;
     }
     if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return HDG_ERR_HIP;
+    }
+    // the device address of this GPU's fixed scratch (hdg_residual_norm_noalloc)
+    if (noalloc_scratch_init(device) != HDG_OK) {
         delete c;
         return HDG_ERR_HIP;
     }
@@ -330,30 +383,31 @@ hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f
                              const double* rt, double* norm_h) {
     if (!ctx) return HDG_ERR_ARG;
     GUARD_BEGIN
-    hdg_status st = check_dims(ctx, dims, true, true);
+    size_t need = 0;
+    hdg_status st = residual_norm_check(ctx, dims, f2e, ru, rt, norm_h, &need);
     if (st != HDG_OK) return st;
-    if (!f2e || !ru || !rt || !norm_h) return set_err(ctx, HDG_ERR_ARG, "hdg_residual_norm: NULL pointer");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
-    const size_t nu_all = (size_t)dims->ne * dims->ncomp * dims->npe;
-    const size_t nface = (size_t)dims->nf * dims->ncomp * dims->npf;
-    const int nb_u = krylov_nblk(nu_all), nb_f = krylov_nblk(nface);
-    const size_t nfa = (nface + 63) / 64 * 64;
-    double* base = (double*)ws_get(ctx, WS_NEWTON, sizeof(double) * (nfa + nb_u + nb_f + 2), &st);
+    double* base = (double*)ws_get(ctx, WS_NEWTON, sizeof(double) * need, &st);
     if (!base) return st;
-    double* rf = base;
-    double* part_u = base + nfa;
-    double* part_f = part_u + nb_u;
-    double* nrm = part_f + nb_f;
-    if ((st = assemble_rhs_run(ctx, dims, f2e, nullptr, rt, rf)) != HDG_OK) return st;
-    if ((st = vec_sumsq_partial(ctx, ru, nu_all, part_u, nb_u, nullptr)) != HDG_OK) return st;
-    if ((st = krylov_store_norm(ctx, part_u, nb_u, nrm)) != HDG_OK) return st;
-    if ((st = vec_sumsq_partial(ctx, rf, nface, part_f, nb_f, nullptr)) != HDG_OK) return st;
-    if ((st = krylov_store_norm(ctx, part_f, nb_f, nrm + 1)) != HDG_OK) return st;
-    double h[2] = {0.0, 0.0};
-    HDG_HIP_CHECK(ctx, hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
-    *norm_h = std::sqrt(h[0] * h[0] + h[1] * h[1]);
-    return HDG_OK;
+    return residual_norm_run(ctx, dims, f2e, ru, rt, base, norm_h);
+    GUARD_END
+}
+
+hdg_status hdg_residual_norm_noalloc(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
+                                     const double* rt, double* norm_h) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    size_t need = 0;
+    hdg_status st = residual_norm_check(ctx, dims, f2e, ru, rt, norm_h, &need);
+    if (st != HDG_OK) return st;
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return set_err(ctx, HDG_ERR_ARG,
+                       "hdg_residual_norm_noalloc: ncomp*npf*nf plus reduction partials exceed the fixed "
+                       "scratch of 2^21 doubles (use hdg_residual_norm)");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    double* base = noalloc_scratch(ctx->device);
+    if (!base) return set_err(ctx, HDG_ERR_HIP, "hdg_residual_norm_noalloc: no scratch address for this device");
+    return residual_norm_run(ctx, dims, f2e, ru, rt, base, norm_h);
     GUARD_END
 }
 

@@ -90,6 +90,11 @@ struct CaptureStreamScope {
 // Returns a device buffer of at least `bytes` for `slot` (grows, never shrinks).
 void* ws_get(hdg_ctx ctx, WsSlot slot, size_t bytes, hdg_status* st);
 
+// Fixed per-device scratch of the allocation-free entry point (k_noalloc.hip): 16 MiB.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(1) << 21;
+hdg_status noalloc_scratch_init(int device);   // with `device` current; once per device
+double* noalloc_scratch(int device);           // nullptr before noalloc_scratch_init
+
 #define HDG_HIP_CHECK(ctx, call)                                                   \
     do {                                                                           \
         hipError_t e_ = (call);                                                    \

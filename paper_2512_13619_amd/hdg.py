@@ -23,7 +23,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
            "hdg_local_size", "hdg_condense", "hdg_condense_keep", "hdg_condense_rhs", "hdg_assemble_blocks",
            "hdg_assemble_rhs", "hdg_solve_opts_default", "hdg_gmres_solve",
-           "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
+           "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_residual_norm_noalloc", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
            "hdg_bj_apply", "hdg_poly_apply", "hdg_cheb_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch", "hdg_element_blocks_batch", "hdg_residual_norm_batch",
@@ -120,6 +120,7 @@ def load():
     lib.hdg_element_blocks.argtypes = [vp, pd, ctypes.POINTER(ElemGeom), ctypes.POINTER(ConvDiff),
                                        ctypes.POINTER(TimeTerm), vp, vp, vp, i32, ctypes.POINTER(ElemArrays)]
     lib.hdg_residual_norm.argtypes = [vp, pd, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.hdg_residual_norm_noalloc.argtypes = [vp, pd, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.hdg_matvec.argtypes = [vp, pd, vp, vp, vp, i32, vp, vp]
     lib.hdg_bj_setup.argtypes = [vp, pd, vp, vp, vp]
     lib.hdg_bj_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp]
@@ -411,12 +412,14 @@ class Context:
             _ptr(u, f64, ne * P, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"),
             (1 if residual_only else 0) | (2 if keep_mass else 0), ctypes.byref(o)))
 
-    def residual_norm(self, dims, f2e, ru, rt):
+    def residual_norm(self, dims, f2e, ru, rt, noalloc=False):
+        """hdg_residual_norm, or with noalloc=True hdg_residual_norm_noalloc (fixed device scratch)."""
         import torch
         d = make_dims(dims)
         ne, nf, M, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "npe", "npf", "nlfe"))
         out = ctypes.c_double(0.0)
-        self._check(self.lib.hdg_residual_norm(
+        fn = self.lib.hdg_residual_norm_noalloc if noalloc else self.lib.hdg_residual_norm
+        self._check(fn(
             self.h, ctypes.byref(d), _ptr(f2e, torch.int32, nf * 4, "f2e"), _ptr(ru, torch.float64, ne * M * P, "ru"),
             _ptr(rt, torch.float64, ne * L * M * PF, "rt"), ctypes.byref(out)))
         return out.value
