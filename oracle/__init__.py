@@ -12,6 +12,8 @@ computes, written from the paper:
                order, product-form apply (Sections 3.4, 4.7); Chebyshev smoother
   elements.py  element residuals and Jacobian blocks of scalar convection-diffusion
                models from the weak form (Sections 2.2, 4.1)
+  elements_sys.py  the same for M-component models: linear elasticity and compressible
+               Navier-Stokes (Section 2.1), flux derivatives by complex step
   newton.py    damped Newton with step halving on the residual norm (Section 4.4)
   dirk.py      stiffly accurate DIRK time stepping, one Newton solve per stage (Section 2.2)
   ilu_asm.py   additive Schwarz on multi-element subdomains with block ILU(0) local solves
@@ -21,4 +23,4 @@ Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may import
 this package. It shares no code with the GPU library (paper_2512_13619_amd);
 the two meet only at the seeded inputs produced by `workloads`.
 """
-from . import condense, assemble, krylov, poly, elements, newton, dirk, ilu_asm  # noqa: F401
+from . import condense, assemble, krylov, poly, elements, elements_sys, newton, dirk, ilu_asm  # noqa: F401

@@ -13,11 +13,18 @@ consistent states).
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from . import assemble, condense, elements
+from . import assemble, condense, elements, elements_sys
+
+
+def element_blocks(g, m, u, uhat, e2f, tt=None):
+    """The element blocks of the model: M-component models (m has a "kind") through
+    elements_sys, scalar convection-diffusion models through elements."""
+    mod = elements_sys if "kind" in m else elements
+    return mod.element_blocks(g, m, u, uhat, e2f, tt)
 
 
 def residual_norm(g, m, u, uhat, e2f, f2e, dims, tt=None):
-    blk = elements.element_blocks(g, m, u, uhat, e2f, tt)
+    blk = element_blocks(g, m, u, uhat, e2f, tt)
     return _norm_from_blocks(blk, e2f, f2e, dims), blk
 
 
@@ -44,6 +51,7 @@ def damped_newton(g, m, u0, uhat0, e2f, f2e, dims, rtol=1e-10, atol=1e-14, max_s
         K, nbr, r = assemble.assemble(Kb, rb, f2e, e2f, dims)
         dx = spla.spsolve(assemble.to_sparse(K, nbr).tocsc(), r)
         _, du = condense.recover(blk, dx, e2f, dims)
+        du = du.reshape(u.shape)
         duhat = dx.reshape(uhat.shape)
         alpha = 1.0
         while True:
@@ -75,12 +83,12 @@ def pseudo_transient(g, m, u0, uhat0, e2f, f2e, dims, dtau0, rtol=1e-10, atol=1e
     for _ in range(max_steps):
         if nrm <= max(rtol * n0, atol):
             break
-        blk = elements.element_blocks(g, m, u, uhat, e2f, dict(c=1.0 / dtau, u_prev=u.copy(), r_extra=None))
+        blk = element_blocks(g, m, u, uhat, e2f, dict(c=1.0 / dtau, u_prev=u.copy(), r_extra=None))
         Kb, rb = condense.condense(blk, dims)
         K, nbr, r = assemble.assemble(Kb, rb, f2e, e2f, dims)
         dx = spla.spsolve(assemble.to_sparse(K, nbr).tocsc(), r)
         _, du = condense.recover(blk, dx, e2f, dims)
-        u = u + du
+        u = u + du.reshape(u.shape)
         uhat = uhat + dx.reshape(uhat.shape)
         new, _ = residual_norm(g, m, u, uhat, e2f, f2e, dims)
         hist.append(dict(norm=nrm, dtau=dtau))

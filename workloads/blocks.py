@@ -21,6 +21,7 @@ import torch
 from . import basis as B
 from . import quadrature as Q
 from .mesh import LOCAL_FACES, REF_VERTS
+from . import physics as Ph
 
 
 def _frame_tables(etype):
@@ -345,6 +346,32 @@ class HDGProblem:
             bnd=self.bnd.to(torch.int32).contiguous(), nqv=int(self.wv.shape[0]), nqf=int(self.wf.shape[0]),
             nu=float(cd["nu"]), tau=float(self.phys.tau), beta=list(cd["beta"]), gamma=list(cd["gamma"]),
             u0=u0[:, 0].contiguous(), uhat0=uhat0)
+
+    def newton_inputs_sys(self):
+        """Inputs of the element residual/Jacobian generation for the M-component models
+        (elasticity, Navier-Stokes): the mesh's quadrature geometry and reference tables as in
+        newton_inputs, the source src (ne, nqv, M) and Dirichlet data uD (ne, nlfe, nqf, M) at
+        quadrature points, the model description and the linearisation state as the initial
+        state: u0 (ne, M, npe) nodal, uhat0 (nf, M, npf) canonical face values."""
+        ph = self.phys
+        assert self.M > 1
+        ne = self.mesh.ne
+        g = self.geometry(0, ne)
+        u0, uh_el = self._state(0, ne, g)
+        f2e = torch.as_tensor(self.mesh.f2e, device=self.device).long()
+        uhat0 = uh_el[f2e[:, 0], f2e[:, 1]].contiguous()                 # (nf, M, npf)
+        if isinstance(ph, Ph.Elasticity):
+            model = dict(kind="elasticity", tau=float(ph.tau), lam=float(ph.lam), mu=float(ph.mu))
+        else:
+            model = dict(kind="navier_stokes", tau=float(ph.tau), Re=float(ph.Re), Pr=float(ph.Pr),
+                         gamma=float(ph.gamma), dt=float(ph.dt))
+        return dict(
+            wdet=g["wdet"].contiguous(), dphix=g["dphix"].contiguous(), phi=self.phi.contiguous(),
+            phif=g["phif"].contiguous(), psi=self.psi.contiguous(), ndA=g["ndA"].contiguous(),
+            dA=g["dA"].contiguous(), src=ph.source(g["xq"]).contiguous(),
+            uD=ph.dirichlet(g["xf"]).contiguous(),
+            bnd=self.bnd.to(torch.int32).contiguous(), nqv=int(self.wv.shape[0]), nqf=int(self.wf.shape[0]),
+            model=model, u0=u0.contiguous(), uhat0=uhat0)
 
     def state_dofs(self, e0=0, e1=None):
         """Nodal linearisation state (u0 (E,M,npe), uhat0 (E,L,M,npf))."""
