@@ -3,10 +3,10 @@
 // For each element the kernels build the (nu+nt) x (nu+nt+1) matrix
 //     T = [[E F r_u], [H J r_t]] - [D; G] A^{-1} [B C 0]
 //       = [[Ebar Fbar r_u], [Hbar Jbar r_t]]                       (q eliminated, r_q = 0)
-// and then eliminate its first nu columns by Gaussian elimination with partial
-// pivoting restricted to the Ebar rows, which gives
-//     Kbar = Jbar - Hbar Ebar^{-1} Fbar   and   rbar = r_t - Hbar Ebar^{-1} r_u,
-// while the top rows hold [U | L^{-1}P Fbar | L^{-1}P r_u], which recovery uses.
+// then factorise Ebar with partial pivoting (P Ebar = L U) and solve on the Ebar rows, so
+// that they hold [U | X | x_r] with X = Ebar^{-1} Fbar and x_r = Ebar^{-1} r_u (eq. w19,
+// which recovery uses directly), and finally
+//     Kbar = Jbar - Hbar X   and   rbar = r_t - Hbar x_r                  (eq. w22).
 //
 // A^{-1} = I_{MD} (x) M^{-1} and B, C are component-diagonal (eq. w16), so
 // [D;G] A^{-1} [B C] restricted to the columns of component m is
@@ -16,19 +16,18 @@
 // cores (v_mfma_f64_16x16x4f64). Three stages:
 //   1. q-elimination: LDS-staged 64x64 tiles (one block per element, component and
 //      tile), giving [[Ebar Fbar r_u], [Hbar Jbar r_t]];
-//   2. right-looking blocked elimination of the Ebar columns (panel of NB columns
-//      in LDS, pivot rows among the Ebar rows): the Ebar rows are updated over all
-//      trailing columns (they become [U | L^{-1}P Fbar | L^{-1}P r_u]); the trace
-//      rows only over the Ebar columns, which yields their multipliers
-//      L21 = Hbar U^{-1};
-//   3. Schur product Kbar = Jbar - L21 (L^{-1}P Fbar), rbar = r_t - L21 (L^{-1}P r_u):
-//      one product of depth nu in LDS-staged 64x64 tiles.
+//   2. on the Ebar rows only: right-looking blocked LU of the first nu columns (panel
+//      factorised in LDS by one wave, trailing updates on the matrix cores), then block
+//      back substitution X = U^{-1} (L^{-1} P [Fbar | r_u]);
+//   3. Schur product Kbar = Jbar - Hbar X, rbar = r_t - Hbar x_r: one product of depth
+//      nu in LDS-staged 64x64 tiles.
 //
 // Storage of T per element: the top nu rows live directly in the caller's
 // `local` buffer (row stride nu+nt+1), the bottom nt rows in a workspace.
 #include <cmath>
 
 #include "hdg_internal.hpp"
+#include "wave_ops.hpp"
 
 namespace {
 
@@ -387,34 +386,48 @@ __device__ __forceinline__ double lane_value(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// ---- blocked elimination of the first nu columns ----------------------------------------------
-// NBT: compile-time bound of the panel width (the triangular solve keeps one
-// column of U12 in registers). LBS threads share the LDS panel (512 for panels of
-// up to 32 columns, so eight waves hide the trailing update's memory latency).
-// Dynamic LDS: the R x (NB+1) panel, then nu + 2*NBT ints for the row interchanges.
+// Orders the LDS accesses of one wave: its lanes exchange data through LDS without a
+// block barrier (the LDS executes one wave's operations in issue order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- LU of Ebar and X = Ebar^{-1} [Fbar | r_u] on the Ebar rows ------------------------------
+// Works on the top nu rows of T only (row stride C): [Ebar | Fbar | r_u] becomes
+// [U | X | x_r] with P Ebar = L U. The trace rows are not touched: they keep
+// [Hbar | Jbar | r_t] for the Schur product Kbar = Jbar - Hbar X.
+//   1. right-looking blocked LU over the first nu columns, panels of NB columns: the panel
+//      (rows k0.., NB columns) is factorised in LDS by one wave, with no block barrier per
+//      column (the pivot of a column is one DPP arg-max over the Ebar rows); then the
+//      panel's interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread per
+//      column) and the trailing update A22 -= L21 U12 (the panel's multipliers times the
+//      new U rows) on the matrix cores;
+//   2. back substitution X = U^{-1} Y by row panels from the bottom: the panel's rows take
+//      the solved rows below them (matrix cores), then its NB x NB triangle (one thread
+//      per column, the triangle in LDS).
+// NBT: compile-time bound of the panel width. Dynamic LDS: the nu x (NB+1) panel, then
+// nu + 2*NBT ints for the row interchanges.
 template <int NBT, int LBS>
-__global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top,
-                                                 double* __restrict__ bot, int* bad_elem, int e_off,
-                                                 int32_t* __restrict__ ipiv_out, int keep) {
+__global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top, int* bad_elem,
+                                                 int e_off, int32_t* __restrict__ ipiv_out, int keep) {
     extern __shared__ double sm[];
-    __shared__ double pval;
-    __shared__ int pidx;
     __shared__ int ndisp;
+    __shared__ int sing;
     const long long e = blockIdx.x;
-    const int nu = cd.nu, R = cd.R, C = cd.C;
+    const int nu = cd.nu, C = cd.C;
     double* Te = top + (size_t)e * nu * C;
-    double* Be = bot + (size_t)e * cd.nt * C;
-    auto rowp = [&](int r) -> double* { return r < nu ? Te + (size_t)r * C : Be + (size_t)(r - nu) * C; };
     const int ldp = NB + 1;
-    double* Pn = sm;                                   // R x ldp (panel; L21 stays here)
-    int* rsrc = (int*)(sm + (size_t)R * ldp);          // [nu]: row interchanges of the panel
+    double* Pn = sm;                                   // nu x ldp: the panel, later a triangle of U
+    int* rsrc = (int*)(sm + (size_t)nu * ldp);         // [nu]: row interchanges of the panel
     int* dsrc = rsrc + nu;                             // [NBT]: displaced rows (source)
     int* ddst = dsrc + NBT;                            // [NBT]: displaced rows (destination)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    bool singular = false;
+    if (threadIdx.x == 0) sing = 0;
     for (int k0 = 0; k0 < nu; k0 += NB) {
         const int nbk = (nu - k0) < NB ? (nu - k0) : NB;
-        const int nrow = R - k0;
+        const int nrow = nu - k0;
         // 1. load the panel (four loads in flight per thread)
         for (int base = threadIdx.x; base < nrow * nbk; base += 4 * LBS) {
             double v[4];
@@ -422,7 +435,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
             for (int u = 0; u < 4; ++u) {
                 const int idx = base + u * LBS;
                 const int li = idx / nbk, kk = idx - li * nbk;
-                v[u] = idx < nrow * nbk ? rowp(k0 + li)[k0 + kk] : 0.0;
+                v[u] = idx < nrow * nbk ? Te[(size_t)(k0 + li) * C + k0 + kk] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -431,74 +444,68 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                 if (idx < nrow * nbk) Pn[li * ldp + kk] = v[u];
             }
         }
-        for (int r = threadIdx.x; r < nu - k0; r += LBS) rsrc[r] = r;
+        for (int r = threadIdx.x; r < nrow; r += LBS) rsrc[r] = r;
         if (threadIdx.x == 0) ndisp = 0;
         __syncthreads();
-        // 2. factorise the panel (pivot rows restricted to the Ebar rows)
-        for (int kk = 0; kk < nbk; ++kk) {
-            if (wave == 0) {
+        // 2. one wave factorises the panel (pivot rows among the panel's Ebar rows)
+        if (wave == 0) {
+            bool bad = false;
+            for (int kk = 0; kk < nbk; ++kk) {
                 double best = -1.0;
                 int bi = kk;
-                for (int li = kk + lane; li < nu - k0; li += 64) {
+                for (int li = kk + lane; li < nrow; li += 64) {
                     const double v = fabs(Pn[li * ldp + kk]);
                     if (v > best || (v == best && li < bi)) { best = v; bi = li; }
                 }
                 wave_argmax(best, bi);
+                double pv = Pn[bi * ldp + kk];
                 if (lane == 0) {
-                    pidx = bi;
-                    pval = Pn[bi * ldp + kk];
                     if (ipiv_out) ipiv_out[(size_t)e * nu + k0 + kk] = k0 + bi;
                     const int t = rsrc[kk];
                     rsrc[kk] = rsrc[bi];
                     rsrc[bi] = t;
                 }
-            }
-            __syncthreads();
-            const int p = pidx;
-            double pv = pval;
-            if (!(fabs(pv) > 0.0) || !isfinite(pv)) { singular = true; pv = 1.0; }
-            if (p != kk) {
-                for (int c = threadIdx.x; c < nbk; c += LBS) {
-                    const double t = Pn[kk * ldp + c];
-                    Pn[kk * ldp + c] = Pn[p * ldp + c];
-                    Pn[p * ldp + c] = t;
+                if (!(fabs(pv) > 0.0) || !isfinite(pv)) { bad = true; pv = 1.0; }
+                if (bi != kk) {
+                    for (int c = lane; c < nbk; c += 64) {
+                        const double t = Pn[kk * ldp + c];
+                        Pn[kk * ldp + c] = Pn[bi * ldp + c];
+                        Pn[bi * ldp + c] = t;
+                    }
                 }
+                wave_lds_sync();
+                const double inv = 1.0 / pv;
+                for (int li = kk + 1 + lane; li < nrow; li += 64) {
+                    const double mlt = Pn[li * ldp + kk] * inv;
+                    Pn[li * ldp + kk] = mlt;
+                    for (int c = kk + 1; c < nbk; ++c) Pn[li * ldp + c] -= mlt * Pn[kk * ldp + c];
+                }
+                wave_lds_sync();
             }
-            __syncthreads();
-            const double inv = 1.0 / pv;
-            for (int li = kk + 1 + threadIdx.x; li < nrow; li += LBS) {
-                const double mlt = Pn[li * ldp + kk] * inv;
-                Pn[li * ldp + kk] = mlt;
-                for (int c = kk + 1; c < nbk; ++c) Pn[li * ldp + c] -= mlt * Pn[kk * ldp + c];
-            }
-            __syncthreads();
+            if (bad && lane == 0) sing = 1;
         }
+        __syncthreads();
         // rows at or below nbk whose content moved (at most nbk of them); the order of
         // the list does not matter, each destination appears once
-        for (int r = nbk + threadIdx.x; r < nu - k0; r += LBS) {
+        for (int r = nbk + threadIdx.x; r < nrow; r += LBS) {
             if (rsrc[r] != r) {
                 const int q = atomicAdd(&ndisp, 1);
                 dsrc[q] = rsrc[r];
                 ddst[q] = r;
             }
         }
-        // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final), and the trace
-        //    rows' multipliers (L21 = Hbar U^{-1}, panel columns) for the Schur product
+        // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final); with keep also the
+        //    multipliers below them (unit lower L, in this panel's row order; later
+        //    interchanges move only the trailing columns)
         for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
-            rowp(k0 + li)[k0 + kk] = Pn[li * ldp + kk];
+            Te[(size_t)(k0 + li) * C + k0 + kk] = Pn[li * ldp + kk];
         }
         if (keep) {
-            // the Ebar rows' multipliers below the panel as well (unit lower L, in this
-            // panel's row order; later interchanges move only the trailing columns)
-            for (int idx = threadIdx.x; idx < (nu - k0 - nbk) * nbk; idx += LBS) {
+            for (int idx = threadIdx.x; idx < (nrow - nbk) * nbk; idx += LBS) {
                 const int li = nbk + idx / nbk, kk = idx - (li - nbk) * nbk;
                 Te[(size_t)(k0 + li) * C + k0 + kk] = Pn[li * ldp + kk];
             }
-        }
-        for (int idx = threadIdx.x; idx < cd.nt * nbk; idx += LBS) {
-            const int r = idx / nbk, kk = idx - r * nbk;
-            Be[(size_t)r * C + k0 + kk] = Pn[(nu - k0 + r) * ldp + kk];
         }
         __syncthreads();
         // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread
@@ -506,9 +513,8 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
         const int cbeg = k0 + nbk;
         const int ncol = C - cbeg;
         const int nd = ndisp;
-        // all rows involved are Ebar rows (top part); the pivot rows' offsets from row k0
-        // are read from LDS once, before any global load (reads past the valid entries stay
-        // inside the LDS allocation and are replaced by row 0)
+        // the pivot rows' offsets from row k0 are read from LDS once, before any global load
+        // (reads past the valid entries stay inside the LDS allocation and are replaced by row 0)
         int rs[NBT];
 #pragma unroll
         for (int t = 0; t < NBT; ++t) rs[t] = rsrc[t];
@@ -537,26 +543,14 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                 if (t < nbk) Tc[(size_t)t * C] = u[t];
         }
         __syncthreads();
-        // 5. trailing update (MFMA, 32x32 tiles per wave): the Ebar rows over every
-        //    trailing column, the trace rows over the remaining Ebar columns only (their
-        //    Schur update Jbar - L21 U12 is one product after the elimination)
-        const int na = nu - cbeg, nbc = nu - cbeg;
+        // 5. trailing update of the Ebar rows over every trailing column (MFMA, 32x32 tiles
+        //    per wave)
+        const int na = nu - cbeg;
         const int ta_c = (ncol + 31) / 32;
         const int tA = ((na + 31) / 32) * ta_c;
-        const int tb_c = (nbc + 31) / 32;
-        const int tB = ((cd.nt + 31) / 32) * tb_c;
-        for (int tile = wave; tile < tA + tB; tile += LBS / 64) {
-            int rlo, rhi, clo, chi, r0, c0;
-            if (tile < tA) {
-                rlo = cbeg; rhi = nu; clo = cbeg; chi = C;
-                r0 = cbeg + (tile / ta_c) * 32;
-                c0 = cbeg + (tile % ta_c) * 32;
-            } else {
-                const int tt = tile - tA;
-                rlo = nu; rhi = R; clo = cbeg; chi = nu;
-                r0 = nu + (tt / tb_c) * 32;
-                c0 = cbeg + (tt % tb_c) * 32;
-            }
+        for (int tile = wave; tile < tA; tile += LBS / 64) {
+            const int r0 = cbeg + (tile / ta_c) * 32;
+            const int c0 = cbeg + (tile % ta_c) * 32;
             double4_t acc[2][2];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
@@ -566,20 +560,20 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        const bool ok = r < rhi && c < chi;
-                        const double v = rowp(ok ? r : rlo)[ok ? c : clo];
+                        const bool ok = r < nu && c < C;
+                        const double v = Te[ok ? (size_t)r * C + c : (size_t)cbeg * C + cbeg];
                         acc[bi][bj][q] = ok ? v : 0.0;
                     }
             auto la = [&](int i, int k) -> double {
                 const int r = r0 + i;
-                const bool ok = r < rhi && k < nbk;
+                const bool ok = r < nu && k < nbk;
                 const double v = Pn[ok ? (r - k0) * ldp + k : 0];
                 return ok ? -v : 0.0;
             };
             auto lb = [&](int k, int j) -> double {
                 const int c = c0 + j;
-                const bool ok = k < nbk && c < chi;
-                const double v = rowp(k0 + (ok ? k : 0))[ok ? c : clo];
+                const bool ok = k < nbk && c < C;
+                const double v = Te[ok ? (size_t)(k0 + k) * C + c : (size_t)k0 * C + cbeg];
                 return ok ? v : 0.0;
             };
             mfma_32x32(la, lb, nbk, acc);
@@ -591,17 +585,97 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        if (r < rhi && c < chi) rowp(r)[c] = acc[bi][bj][q];
+                        if (r < nu && c < C) Te[(size_t)r * C + c] = acc[bi][bj][q];
                     }
         }
         __syncthreads();
     }
-    if (singular && threadIdx.x == 0) atomicMin(bad_elem, e_off + (int)e);
+    // back substitution X = U^{-1} Y on the columns nu..C-1, row panels from the bottom
+    const int ncx = C - nu;
+    const int npan = (nu + NB - 1) / NB;
+    for (int pk = npan - 1; pk >= 0; --pk) {
+        const int kb = pk * NB;
+        const int nbk = (nu - kb) < NB ? (nu - kb) : NB;
+        const int kend = kb + nbk;
+        // a. Y_kb -= U[kb:kend, kend:nu] X[kend:nu, :] (MFMA, 32x32 tiles per wave)
+        if (kend < nu) {
+            const int tr = (nbk + 31) / 32, tc = (ncx + 31) / 32;
+            const int K = nu - kend;
+            for (int tile = wave; tile < tr * tc; tile += LBS / 64) {
+                const int r0 = kb + (tile / tc) * 32;
+                const int c0 = nu + (tile % tc) * 32;
+                double4_t acc[2][2];
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                            const int c = c0 + 16 * bj + (lane & 15);
+                            const bool ok = r < kend && c < C;
+                            const double v = Te[ok ? (size_t)r * C + c : (size_t)kb * C + nu];
+                            acc[bi][bj][q] = ok ? v : 0.0;
+                        }
+                auto la = [&](int i, int k) -> double {
+                    const int r = r0 + i;
+                    const bool ok = r < kend && k < K;
+                    const double v = Te[ok ? (size_t)r * C + kend + k : (size_t)kb * C + kend];
+                    return ok ? -v : 0.0;
+                };
+                auto lb = [&](int k, int j) -> double {
+                    const int c = c0 + j;
+                    const bool ok = k < K && c < C;
+                    const double v = Te[ok ? (size_t)(kend + k) * C + c : (size_t)kend * C + nu];
+                    return ok ? v : 0.0;
+                };
+                mfma_32x32(la, lb, K, acc);
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                            const int c = c0 + 16 * bj + (lane & 15);
+                            if (r < kend && c < C) Te[(size_t)r * C + c] = acc[bi][bj][q];
+                        }
+            }
+        }
+        // the panel's triangle of U into LDS
+        for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
+            const int li = idx / nbk, c = idx - li * nbk;
+            Pn[li * ldp + c] = Te[(size_t)(kb + li) * C + kb + c];
+        }
+        __syncthreads();
+        // b. X_kb = U_kb^{-1} Y_kb, one thread per column
+        for (int cl = threadIdx.x; cl < ncx; cl += LBS) {
+            double* Tc = Te + (size_t)kb * C + nu + cl;
+            double u[NBT];
+#pragma unroll
+            for (int t = 0; t < NBT; ++t) u[t] = t < nbk ? Tc[(size_t)t * C] : 0.0;
+#pragma unroll
+            for (int t = NBT - 1; t >= 0; --t) {
+                if (t < nbk) {
+                    double v = u[t];
+#pragma unroll
+                    for (int q = t + 1; q < NBT; ++q)
+                        if (q < nbk) v -= Pn[t * ldp + q] * u[q];
+                    u[t] = v / Pn[t * ldp + t];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NBT; ++t)
+                if (t < nbk) Tc[(size_t)t * C] = u[t];
+        }
+        __syncthreads();
+    }
+    if (sing && threadIdx.x == 0) atomicMin(bad_elem, e_off + (int)e);
 }
 
-// ---- Kbar = Jbar - L21 U12, rbar = r_t - L21 (L^{-1} P r_u)   per (element, 64x64 tile) -----
-// L21 = the trace rows' multipliers (bottom rows, first nu columns), U12 = the Ebar rows'
-// trailing columns after the elimination (top rows, columns nu..): one product of depth nu.
+// ---- Kbar = Jbar - Hbar X, rbar = r_t - Hbar x_r   per (element, 64x64 tile) ----------------
+// Hbar = the trace rows' first nu columns, X and x_r = the Ebar rows' columns nu.. after the
+// elimination and back substitution: one product of depth nu.
 __global__ __launch_bounds__(BS, 2) void k_cond_schur(CondDims cd, long long ntile, int tm_n, int tn_n,
                                                    const double* __restrict__ top, const double* __restrict__ bot,
                                                    double* __restrict__ Kbar, double* __restrict__ rbar) {
@@ -657,15 +731,15 @@ __global__ __launch_bounds__(BS, 2) void k_cond_schur(CondDims cd, long long nti
     }
 }
 
-// The trace rows' multipliers L21 = Hbar U^{-1} (first nu columns of the trace rows), per
-// element, out of the elimination workspace into a caller buffer [n][nt][nu].
-__global__ __launch_bounds__(BS) void k_copy_l21(CondDims cd, const double* __restrict__ bot,
-                                                 double* __restrict__ L21) {
+// Hbar (the trace rows' first nu columns, which the elimination leaves as they are), per
+// element, out of the workspace into a caller buffer [n][nt][nu].
+__global__ __launch_bounds__(BS) void k_copy_hbar(CondDims cd, const double* __restrict__ bot,
+                                                  double* __restrict__ Hbar) {
     const long long e = blockIdx.x;
     const int nu = cd.nu, nt = cd.nt, C = cd.C;
     for (int idx = threadIdx.x; idx < nt * nu; idx += BS) {
         const int t = idx / nu, r = idx - t * nu;
-        L21[(size_t)e * nt * nu + idx] = bot[((size_t)e * nt + t) * C + r];
+        Hbar[(size_t)e * nt * nu + idx] = bot[((size_t)e * nt + t) * C + r];
     }
 }
 
@@ -674,10 +748,11 @@ __global__ __launch_bounds__(BS) void k_copy_l21(CondDims cd, const double* __re
 // with the same matrix and new right-hand sides, Section 2.2):
 //     c = L^{-1} P r_u   panel by panel as the elimination went (the panel's interchanges,
 //                         its unit lower triangle, then its multipliers below it),
-//     rbar = r_t - L21 c.
-// c replaces the last column of `local` (recovery reads it). One block per element, y in LDS.
+//     x_r = U^{-1} c,    rbar = r_t - Hbar x_r.
+// x_r replaces the last column of `local` (recovery reads it). One block per element, the
+// vector in LDS.
 __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __restrict__ local,
-                                                 const double* __restrict__ L21, const int32_t* __restrict__ ipiv,
+                                                 const double* __restrict__ Hbar, const int32_t* __restrict__ ipiv,
                                                  const double* __restrict__ ru, const double* __restrict__ rt,
                                                  double* __restrict__ rbar) {
     extern __shared__ double y[];          // nu
@@ -723,8 +798,9 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
         }
         __syncthreads();
     }
+    wave_ops::upper_solve_lds<BS>(Te, C, nu, y);
     for (int i = threadIdx.x; i < nu; i += BS) Te[(size_t)i * C + C - 1] = y[i];
-    // rbar = r_t - L21 c, four rows per wave at a time
+    // rbar = r_t - Hbar x_r, four rows per wave at a time
     for (int t0 = 4 * wave; t0 < nt; t0 += 4 * (BS / 64)) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int r0 = 0; r0 < nu; r0 += 64) {
@@ -734,7 +810,7 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int t = t0 + q < nt ? t0 + q : nt - 1;
-                const double a = L21[((size_t)e * nt + t) * nu + (ok ? r : 0)];
+                const double a = Hbar[((size_t)e * nt + t) * nu + (ok ? r : 0)];
                 acc[q] += ok ? a * yv : 0.0;
             }
         }
@@ -749,7 +825,7 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
 }
 
 size_t lu_lds_bytes(const CondDims& cd, int NB) {
-    return sizeof(double) * (size_t)cd.R * (NB + 1) + sizeof(int) * ((size_t)cd.nu + 2 * 64);
+    return sizeof(double) * (size_t)cd.nu * (NB + 1) + sizeof(int) * ((size_t)cd.nu + 2 * 64);
 }
 
 // Panel width of the elimination: all nu columns when nu <= 64 and the panel fits in LDS,
@@ -764,17 +840,17 @@ int pick_panel(const CondDims& cd) {
     return 0;
 }
 
-// Threads of the elimination kernel: 128 for elements of at most 128 rows (more elements
-// in flight per CU), else 512 for panels of up to 32 columns and 256 for wider ones.
+// Threads of the elimination kernel: 128 when Ebar is one panel (nu <= 64: more elements in
+// flight per CU), else 256 (four waves share the trailing updates while several elements
+// share a CU: the panel of one element is factorised while others run on the matrix cores).
 const void* lu_kernel(const CondDims& cd, int NB, int* threads) {
-    if (cd.R <= 128) {
+    if (NB >= cd.nu) {
         *threads = 128;
         return NB <= 16 ? (const void*)k_cond_lu<16, 128> : NB <= 32 ? (const void*)k_cond_lu<32, 128>
                                                                      : (const void*)k_cond_lu<64, 128>;
     }
-    *threads = NB <= 32 ? 512 : 256;
-    return NB <= 16 ? (const void*)k_cond_lu<16, 512> : NB <= 32 ? (const void*)k_cond_lu<32, 512>
-                                                                 : (const void*)k_cond_lu<64, 256>;
+    *threads = 256;
+    return NB <= 16 ? (const void*)k_cond_lu<16, 256> : (const void*)k_cond_lu<32, 256>;
 }
 
 hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
@@ -791,10 +867,10 @@ hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
 }
 
 // Stages 2 and 3 on n elements whose matrices T are in place (top rows at `top`, row stride
-// cd.C, trace rows at `bot`): elimination of the first nu columns, then the Schur product
-// into Kout [n][nt][nt] and rout [n][nt]. A zero pivot records e_off + element in status.
-// ipiv (optional, [n][nu]) receives the row interchanges; keep = 1 also leaves the Ebar
-// multipliers below the diagonal of the top rows.
+// cd.C, trace rows at `bot`): LU of Ebar and X = Ebar^{-1}[Fbar | r_u] on the top rows, then
+// the Schur product into Kout [n][nt][nt] and rout [n][nt]. A zero pivot records e_off +
+// element in status. ipiv (optional, [n][nu]) receives the row interchanges; keep = 1 also
+// leaves the Ebar multipliers below the diagonal of the top rows.
 hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t n, double* top, double* bot,
                                double* Kout, double* rout, int* status, int64_t e_off, int32_t* ipiv = nullptr,
                                int keep = 0) {
@@ -802,8 +878,7 @@ hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t 
     int threads = 0;
     const void* lu_fn = lu_kernel(cd, NB, &threads);
     int e_off_i = (int)e_off;
-    void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&bot, (void*)&status, (void*)&e_off_i, (void*)&ipiv,
-                    (void*)&keep};
+    void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&status, (void*)&e_off_i, (void*)&ipiv, (void*)&keep};
     HDG_HIP_CHECK(ctx, hipLaunchKernel(lu_fn, dim3((unsigned)n), dim3(threads), args, lds, ctx->stream));
     HDG_LAUNCH_CHECK(ctx);
     const int tm_n = div_up(cd.nt, GT);
@@ -871,7 +946,7 @@ __global__ __launch_bounds__(BS) void k_asm_store(int nb, int L, const double* _
 }  // namespace
 
 hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_elem_blocks* in, double* Kbar,
-                        double* rbar, double* local, double* L21, int32_t* ipiv) {
+                        double* rbar, double* local, double* Hbar_out, int32_t* ipiv) {
     CondDims cd;
     cd.M = d->ncomp; cd.D = d->dim; cd.P = d->npe; cd.PF = d->npf; cd.L = d->nlfe;
     cd.nu = cd.M * cd.P; cd.nq = cd.M * cd.D * cd.P; cd.nt = cd.L * cd.M * cd.PF;
@@ -914,14 +989,14 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
                                local + e0 * cd.nu * cd.C, bot);
             HDG_LAUNCH_CHECK(ctx);
         }
-        const bool keep = L21 != nullptr;
+        const bool keep = Hbar_out != nullptr;
         if ((st = eliminate_and_schur(ctx, cd, NB, n, local + e0 * cd.nu * cd.C, bot, Kbar + e0 * cd.nt * cd.nt,
                                       rbar + e0 * cd.nt, status, e0, keep ? ipiv + e0 * cd.nu : nullptr,
                                       keep ? 1 : 0)) != HDG_OK)
             return st;
         if (keep) {
-            hipLaunchKernelGGL(k_copy_l21, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,
-                               L21 + e0 * cd.nt * cd.nu);
+            hipLaunchKernelGGL(k_copy_hbar, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,
+                               Hbar_out + e0 * cd.nt * cd.nu);
             HDG_LAUNCH_CHECK(ctx);
         }
     }
@@ -988,7 +1063,7 @@ hdg_status asm_setup_run(hdg_ctx ctx, const hdg_dims* d, const double* Kbar, con
     return HDG_OK;
 }
 
-hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* local, const double* L21,
+hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* local, const double* Hbar,
                             const int32_t* ipiv, const double* ru, const double* rt, double* rbar) {
     CondDims cd;
     cd.M = d->ncomp; cd.D = d->dim; cd.P = d->npe; cd.PF = d->npf; cd.L = d->nlfe;
@@ -1001,7 +1076,7 @@ hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* 
         return HDG_ERR_SHAPE;
     }
     hipLaunchKernelGGL(k_cond_rhs, dim3((unsigned)ne), dim3(BS), sizeof(double) * cd.nu, ctx->stream, cd, NB, local,
-                       L21, ipiv, ru, rt, rbar);
+                       Hbar, ipiv, ru, rt, rbar);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
