@@ -87,6 +87,16 @@ PREC_TEXT = {"bj": "block-Jacobi", "bj_poly": "block-Jacobi + Ritz-Leja polynomi
              "asm_cheb": "ASM + Chebyshev(10)", "none": "no preconditioner"}
 
 
+def fp32_matvec_kernel(tuned, nb, S):
+    """Name of the FP32 block-matvec kernel instance the timed solves launched: the measured
+    configuration (threads per face, rows per thread) when the autotuner ran."""
+    if tuned:
+        for k, v in tuned["table"].items():
+            if k.startswith(f"face:m32:p32:m20:k0:nb{nb}:S{S}:"):
+                return f"k_face_op<float,float,{v[0]},false,0,{v[1]}> (FP32 block matvec, measured configuration)"
+    return "k_face_op<float,float,TEAM,false,0,VEC> (FP32 block matvec, built-in configuration rule)"
+
+
 def measured_traffic(kind, tag="elasticity24_p3"):
     """Counter-measured HBM bytes per launch of the block matvec (profiles/ record), or None when the
     kernel source changed since the counters were taken."""
@@ -214,7 +224,7 @@ def second_stage(args, pl, blk, d, stream):
                rel_resid=st2["rel_resid_true"], first_stage_iters=st1["iters"],
                note="same matrix, seeded new element right-hand sides; condensation factors kept from the "
                     "first stage, block-Jacobi inverses and folded blocks reused")
-    pl.L21 = pl.ipiv = None
+    pl.Hbar = pl.ipiv = None
     torch.cuda.empty_cache()
     log("second stage", out)
     return out
@@ -639,6 +649,9 @@ def main():
     ap.add_argument("--also", default="",
                     help="comma-separated preconditioners (asm, asm_poly, bj_poly, ...) to time in one extra "
                          "mixed-precision step each after the headline")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the measurement of the face operator's launch configurations (setup, untimed) and "
+                         "use the library's built-in rule")
     ap.add_argument("--no-fold", action="store_true",
                     help="apply block-Jacobi separately in every step instead of folding it into the blocks")
     ap.add_argument("--orth", default="dcgs2", choices=["cgs2", "dcgs2", "cgs", "mgs"],
@@ -783,6 +796,22 @@ def main():
         log(precision, "step", mean, st["iters"], phm)
         return mean, times, st, phm
 
+    tuned = None
+    if not args.no_tune:
+        # setup, outside the timed region: the library measures the face operator's launch
+        # configurations (threads per face, rows per thread) on this workload's assembled matrix and
+        # block-Jacobi inverses, and every later launch of the process uses the fastest
+        pl.condense(blk)
+        pl.assemble()
+        nbt = d["ncomp"] * d["npf"]
+        B64 = torch.empty(d["nf"] * nbt * nbt, dtype=torch.float64, device="cuda")
+        B32 = torch.empty(d["nf"] * nbt * nbt, dtype=torch.float32, device="cuda")
+        ctx.bj_setup(pl.dims, pl.K64, B64, B32)
+        t0t = time.perf_counter()
+        ntuned = ctx.autotune(pl.dims, pl.K64, pl.K32, pl.nbr, B64, B32, reps=10)
+        tuned = dict(variants=ntuned, seconds=time.perf_counter() - t0t, table=hdg.tune_table().get("entries", {}))
+        del B64, B32
+        log("autotune", tuned)
     t_mixed, times_mixed, st_mixed, ph_mixed = timed_steps("mixed", args.warmup, args.steps)
     x_mixed = pl.x.clone()
     t_fp64 = None
@@ -890,11 +919,12 @@ def main():
         "kernels_mixed": r32,
         "kernels_fp64": r64,
         "bj_apply_loop": bj_loop,
+        "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": r32["matvec_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": r32["matvec_GBs"] / PEAK_HBM_GBS,
                      "traffic": (measured_traffic("fp32_matvec", wl["tag"])
                                  if (args.n, args.p) == WORKLOAD_SIZES[args.config] else None),
-                     "kernel": "k_face_op<float,float,256,false,0,4> (FP32 block matvec)",
+                     "kernel": fp32_matvec_kernel(tuned, nb, 2 * d["nlfe"] - 1),
                      "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
                      "timing": "HIP events recorded at the start and end of each matvec kernel of the timed mixed "
                                "solves (hipExtLaunchKernelGGL on the library's stream)"},

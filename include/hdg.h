@@ -91,8 +91,8 @@ hdg_status  hdg_release_workspace(hdg_ctx ctx);
  * Outputs:
  *   Kbar  [ne][nt][nt]   element trace Schur complement (row = trace test dof)
  *   rbar  [ne][nt]
- *   local [ne][nu][nu+nt+1]   factorised local solver for recovery: rows hold
- *         [U | L^{-1} P Fbar | L^{-1} P ru] with P Ebar = L U (partial pivoting);
+ *   local [ne][nu][nu+nt+1]   the local solver for recovery (eq. w19): rows hold
+ *         [U | Ebar^{-1} Fbar | Ebar^{-1} ru] with P Ebar = L U (partial pivoting);
  *         only the upper triangle of the first nu columns is meaningful.
  * Errors: HDG_ERR_SINGULAR if some Ebar has a zero/non-finite pivot (first
  * such element named). Synchronises the stream to read that status. */
@@ -109,7 +109,8 @@ hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
  *     with the condensed right-hand side of Section 4.1 eq. w19 / Section 4.2 eq. w22.
  *
  * hdg_condense_keep: hdg_condense that also keeps what a later right-hand side needs:
- *   L21  [ne][nt][nu]  the trace rows' multipliers Hbar U^{-1};
+ *   Hbar [ne][nt][nu]  Hbar = H - G A^{-1} B, the trace rows' coupling to the element
+ *                      unknowns after the q-elimination;
  *   ipiv [ne][nu]      row interchanges of the elimination: at step k the rows at
  *                      (element-local) positions k and ipiv[k] >= k were exchanged;
  *   local additionally holds the unit lower L below the diagonal of its first nu
@@ -119,16 +120,17 @@ hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
  *         to earlier columns of L).
  *   All outputs are caller-owned device buffers; the same errors as hdg_condense.
  * hdg_condense_rhs: for new right-hand sides ru [ne][nu], rt [ne][nt] of the same element
- *   matrices: c = L^{-1} P ru (panel by panel: the panel's interchanges, its unit lower
- *   triangle, its multipliers below it) replaces the last column of `local`, and
- *   rbar = rt - L21 c. `local`, L21 and ipiv must come from hdg_condense_keep on the same
+ *   matrices: x_r = Ebar^{-1} ru = U^{-1} L^{-1} P ru (the forward part panel by panel:
+ *   the panel's interchanges, its unit lower triangle, its multipliers below it) replaces
+ *   the last column of `local`, and rbar = rt - Hbar x_r. `local`, Hbar and ipiv must
+ *   come from hdg_condense_keep on the same
  *   dims (the panel width is derived from dims as it was there). Enqueued only, no
  *   synchronisation; no pivots are re-checked. */
 hdg_status hdg_condense_keep(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
                              const hdg_elem_blocks* in, double* Kbar, double* rbar, double* local,
-                             double* L21, int32_t* ipiv);
+                             double* Hbar, int32_t* ipiv);
 hdg_status hdg_condense_rhs(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, double* local,
-                            const double* L21, const int32_t* ipiv, const double* ru, const double* rt,
+                            const double* Hbar, const int32_t* ipiv, const double* ru, const double* rt,
                             double* rbar);
 
 /* ---------------------------------------------------------------------------
@@ -269,9 +271,15 @@ typedef struct {
  *   HDG_FALLBACK_MIXED_TO_FP64   a mixed-precision restart cycle's true FP64 residual fell by
  *                                less than half and stayed above twice what that cycle's inner
  *                                (FP32-operator) iteration estimated: the FP32 matrix limits the
- *                                refinement, and the remaining cycles use K64 and FP64 inverses. */
+ *                                refinement, and the remaining cycles use K64 and FP64 inverses;
+ *   HDG_FALLBACK_STAGNATED       (hdg_gmres_solve_batch, per instance) five restart cycles in a
+ *                                row met the target in their inner estimate while the true
+ *                                residual at the next restart stayed above the target and above
+ *                                0.9 times the best true residual so far: the FP64 residual
+ *                                cannot show more accuracy, and the instance stops early, not
+ *                                converged. */
 enum { HDG_FALLBACK_PP_BREAKDOWN = 1, HDG_FALLBACK_PP_SMALL_RITZ = 2, HDG_FALLBACK_PP_NO_INTERVAL = 4,
-       HDG_FALLBACK_PP_TO_BASE = 8, HDG_FALLBACK_MIXED_TO_FP64 = 16 };
+       HDG_FALLBACK_PP_TO_BASE = 8, HDG_FALLBACK_MIXED_TO_FP64 = 16, HDG_FALLBACK_STAGNATED = 32 };
 
 void       hdg_solve_opts_default(hdg_solve_opts* opts_h);
 hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims,
@@ -381,6 +389,41 @@ hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f
 hdg_status hdg_residual_norm_noalloc(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
                                      const double* rt, double* norm_h);
 
+/* (5c) Element residuals and Jacobian blocks of M-component models in 3D (Section 2.1 with
+ *     M > 1; Section 2.2's weak form and numerical flux; Section 4.1's element matrices):
+ *   HDG_MODEL_ELASTICITY (ncomp = 3):      F = -sigma(q), sigma = lam tr(eps) I + 2 mu eps,
+ *                                          eps = (q + q^T)/2, u the displacement;
+ *   HDG_MODEL_NAVIER_STOKES (ncomp = 5):   F = F_c(u) - F_v(u, q) in conservative variables
+ *                                          (rho, rho v, rho E), p = (gamma-1)(rho E - |rho v|^2/(2 rho)),
+ *                                          F_c = (rho v, rho v v^T + p I, (rho E + p) v),
+ *                                          F_v = (0, tau_v, tau_v v + (mu gamma/Pr) grad e), mu = 1/Re,
+ *                                          tau_v = mu (grad v + grad v^T) - (2/3) mu (div v) I,
+ *                                          e = E - |v|^2/2, grad v and grad e from q = grad u.
+ *   fhat = F(uhat, q).n + tau (u - uhat); Dirichlet trace rows uhat - u_D on boundary faces.
+ *   Residual rows as for the scalar models, per component m:
+ *     R_u[m,i] = -(F_m, grad phi_i) + <fhat_m, phi_i> - (s_m, phi_i)  (+ the time term)
+ *     R_t[l,m,j] = -<fhat_m, psi_j>_l (interior face), <uhat_m - u_D,m, psi_j>_l (boundary face)
+ * hdg_element_blocks_sys: as hdg_element_blocks, for dim = 3 and these models, with
+ *   geom->src [ne][nqv][ncomp] and geom->uD [ne][nlfe][nqf][ncomp]; state u [ne][ncomp][npe]
+ *   (component-major, the u dof order of hdg_condense) and uhat [nf][ncomp][npf];
+ *   time_term->u_prev [ne][ncomp][npe], r_extra [ne][ncomp*npe]; out->q [ne][ncomp][dim][npe].
+ *   The flux derivatives come from forward-mode dual numbers per quadrature point. Uses a
+ *   context workspace for the per-point flux data (elements in chunks of about 1 GiB of it).
+ *   HDG_ERR_ARG for an unknown model, a model whose ncomp does not match, or dim != 3;
+ *   HDG_ERR_SHAPE if an element's staged data exceed 150 KiB of LDS; HDG_ERR_SINGULAR as for
+ *   hdg_element_blocks (synchronises). hdg_residual_norm applies to its ru, rt unchanged. */
+enum { HDG_MODEL_ELASTICITY = 1, HDG_MODEL_NAVIER_STOKES = 2 };
+typedef struct {
+    int32_t kind;
+    double tau;               /* S = tau I */
+    double lam, mu;           /* elasticity: Lame constants */
+    double Re, Pr, gamma;     /* Navier-Stokes */
+} hdg_sys_model;
+hdg_status hdg_element_blocks_sys(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* geom,
+                                  const hdg_sys_model* model, const hdg_time_term* time_term,
+                                  const int32_t* e2f, const double* u, const double* uhat,
+                                  int32_t flags, const hdg_elem_arrays* out);
+
 /* (6) Additive Schwarz preconditioner with one element per subdomain -- Section 3.3
  * (definition), Section 4.6 (element matrices and their enrichment).
  *
@@ -423,6 +466,25 @@ hdg_status hdg_ilu_asm_create(hdg_ctx ctx, const hdg_dims* dims, const double* K
                               const int32_t* e2f, int32_t G, hdg_ilu_asm* out);
 hdg_status hdg_ilu_asm_destroy(hdg_ilu_asm h);
 hdg_status hdg_ilu_asm_apply(hdg_ctx ctx, hdg_ilu_asm h, const double* y, double* z);
+
+/* Autotuning of the face operator's launch configuration (threads per face, rows per
+ * thread) by measurement -- the block matvec of Section 4.3 and the block-Jacobi apply of
+ * Section 4.5 are the bandwidth-bound kernels of every solve, and their best mapping depends
+ * on the block size, slot count, precision and problem size.
+ * hdg_autotune: times every supported configuration of the FP64 and FP32 block matvec
+ *   (K64 required, K32 may be NULL), the block-Jacobi apply (Binv64 / Binv32, may be NULL)
+ *   and the fused polynomial step (K and Binv of one precision) on this matrix, reps launches
+ *   each, and keeps the fastest per (operand types, product kind, nb, slots, power-of-two
+ *   bucket of nf) in a table that every later launch in the process consults. With the
+ *   environment variable HDG_TUNE_CACHE naming a file, the table is read from it on first use
+ *   and written back here (JSON). *n_tuned_h (may be NULL) receives the number of variants
+ *   timed. Uses a context work vector; synchronises. Results of later solves change only by
+ *   the order of the sums inside a face (rounding).
+ * hdg_tune_table: the table as JSON text into buf_h (len bytes, NUL-terminated, truncated
+ *   if short); returns the bytes the whole text needs. */
+hdg_status hdg_autotune(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32, const int32_t* nbr,
+                        const double* Binv64, const float* Binv32, int32_t reps, int32_t* n_tuned_h);
+size_t     hdg_tune_table(char* buf_h, size_t len);
 
 /* ---------------------------------------------------------------------------
  * Building blocks exposed for tests and benchmarks (same kernels as the solver).

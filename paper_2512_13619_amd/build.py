@@ -9,8 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhdg.so")
-SOURCES = ["k_face.hip", "k_krylov.hip", "k_bj.hip", "k_assemble.hip", "k_recover.hip", "k_condense.hip", "k_element.hip", "k_ilu.hip", "k_batch.hip", "k_noalloc.hip", "batch.cpp",
-           "solver.cpp", "ritz.cpp", "abi.cpp"]
+SOURCES = ["k_face.hip", "k_krylov.hip", "k_bj.hip", "k_assemble.hip", "k_recover.hip", "k_condense.hip", "k_element.hip", "k_element_sys.hip", "k_ilu.hip", "k_batch.hip", "k_noalloc.hip", "batch.cpp",
+           "solver.cpp", "ritz.cpp", "tune.cpp", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result",

@@ -212,7 +212,7 @@ hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, con
 }
 
 hdg_status hdg_condense_keep(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, const hdg_elem_blocks* in,
-                             double* Kbar, double* rbar, double* local, double* L21, int32_t* ipiv) {
+                             double* Kbar, double* rbar, double* local, double* Hbar, int32_t* ipiv) {
     if (!ctx) return HDG_ERR_ARG;
     GUARD_BEGIN
     hdg_status st = check_dims(ctx, dims, false, false);
@@ -221,16 +221,16 @@ hdg_status hdg_condense_keep(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk
     if (ne_chunk == 0) return HDG_OK;
     if (ne_chunk > 0x7fffffff) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk too large");
     if (!in || !in->Minv || !in->Bd || !in->Cd || !in->D || !in->E || !in->F || !in->G || !in->H || !in->J ||
-        !in->ru || !in->rt || !Kbar || !rbar || !local || !L21 || !ipiv)
+        !in->ru || !in->rt || !Kbar || !rbar || !local || !Hbar || !ipiv)
         return set_err(ctx, HDG_ERR_ARG, "hdg_condense_keep: NULL input or output pointer");
     if ((size_t)dims->ncomp * dims->npe > 4096)
         return set_err(ctx, HDG_ERR_SHAPE, "hdg_condense_keep: nu above 4096");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
-    return condense_run(ctx, dims, ne_chunk, in, Kbar, rbar, local, L21, ipiv);
+    return condense_run(ctx, dims, ne_chunk, in, Kbar, rbar, local, Hbar, ipiv);
     GUARD_END
 }
 
-hdg_status hdg_condense_rhs(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, double* local, const double* L21,
+hdg_status hdg_condense_rhs(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk, double* local, const double* Hbar,
                             const int32_t* ipiv, const double* ru, const double* rt, double* rbar) {
     if (!ctx) return HDG_ERR_ARG;
     GUARD_BEGIN
@@ -239,10 +239,10 @@ hdg_status hdg_condense_rhs(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
     if (ne_chunk < 0) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk must be >= 0");
     if (ne_chunk == 0) return HDG_OK;
     if (ne_chunk > 0x7fffffff) return set_err(ctx, HDG_ERR_SHAPE, "ne_chunk too large");
-    if (!local || !L21 || !ipiv || !ru || !rt || !rbar)
+    if (!local || !Hbar || !ipiv || !ru || !rt || !rbar)
         return set_err(ctx, HDG_ERR_ARG, "hdg_condense_rhs: NULL pointer");
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
-    return condense_rhs_run(ctx, dims, ne_chunk, local, L21, ipiv, ru, rt, rbar);
+    return condense_rhs_run(ctx, dims, ne_chunk, local, Hbar, ipiv, ru, rt, rbar);
     GUARD_END
 }
 
@@ -379,6 +379,69 @@ hdg_status hdg_element_blocks(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_
     GUARD_END
 }
 
+hdg_status hdg_element_blocks_sys(hdg_ctx ctx, const hdg_dims* dims, const hdg_elem_geom* g, const hdg_sys_model* m,
+                                  const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
+                                  int32_t flags, const hdg_elem_arrays* out) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, false);
+    if (st != HDG_OK) return st;
+    if (!g || !m || !out) return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: NULL argument struct");
+    if (dims->dim != 3) return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: dim must be 3");
+    if (!((m->kind == HDG_MODEL_ELASTICITY && dims->ncomp == 3) ||
+          (m->kind == HDG_MODEL_NAVIER_STOKES && dims->ncomp == 5)))
+        return set_err(ctx, HDG_ERR_ARG,
+                       "hdg_element_blocks_sys: model must be elasticity (ncomp 3) or Navier-Stokes (ncomp 5)");
+    if (m->kind == HDG_MODEL_NAVIER_STOKES && !(m->Re > 0.0 && m->Pr > 0.0 && m->gamma > 1.0))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: need Re > 0, Pr > 0, gamma > 1");
+    if (!std::isfinite(m->tau)) return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: tau is not finite");
+    if (g->nqv < 1 || g->nqf < 1)
+        return set_err(ctx, HDG_ERR_SHAPE, "hdg_element_blocks_sys: nqv and nqf must be >= 1");
+    if (dims->ne == 0) return HDG_OK;
+    if (!g->wdet || !g->dphix || !g->phi || !g->phif || !g->psi || !g->ndA || !g->dA || !g->src || !g->uD ||
+        !g->bnd || !e2f || !u || !uhat || !out->ru || !out->rt)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: NULL pointer");
+    const bool residual_only = (flags & HDG_ELEM_RESIDUAL_ONLY) != 0;
+    if (flags & ~(HDG_ELEM_RESIDUAL_ONLY | HDG_ELEM_KEEP_MASS))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: unknown flags");
+    if ((flags & HDG_ELEM_KEEP_MASS) && !out->Minv)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: HDG_ELEM_KEEP_MASS needs the kept Minv");
+    if (!residual_only && (!out->Minv || !out->Bd || !out->Cd || !out->D || !out->E || !out->F || !out->G ||
+                           !out->H || !out->J))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: NULL matrix output (residual_only = 0)");
+    if (tt && !std::isfinite(tt->c))
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: time-term factor c is not finite");
+    if (tt && tt->c != 0.0 && !tt->u_prev)
+        return set_err(ctx, HDG_ERR_ARG, "hdg_element_blocks_sys: time term with c != 0 needs u_prev");
+    if (element_sys_lds_bytes(dims, g->nqv, g->nqf) > 150 * 1024)
+        return set_err(ctx, HDG_ERR_SHAPE, "hdg_element_blocks_sys: element data exceed 150 KiB of LDS");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const size_t per = element_sys_ws_doubles(dims, g->nqv, g->nqf);
+    int64_t chunk = (int64_t)(((size_t)1 << 30) / (per * sizeof(double)));
+    if (chunk < 1) chunk = 1;
+    if (chunk > dims->ne) chunk = dims->ne;
+    double* ws = (double*)ws_get(ctx, WS_ELEM_SYS, sizeof(double) * per * (size_t)chunk, &st);
+    if (!ws) return st;
+    int* status = (int*)ws_get(ctx, WS_STATUS, 64, &st);
+    if (!status) return st;
+    const int big = 0x7fffffff;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    for (int64_t e0 = 0; e0 < dims->ne; e0 += chunk) {
+        const int64_t n = (dims->ne - e0) < chunk ? (dims->ne - e0) : chunk;
+        if ((st = element_sys_run(ctx, dims, g, m, tt, e2f, u, uhat, flags, out, status, ws, e0, n)) != HDG_OK)
+            return st;
+    }
+    int bad = big;
+    HDG_HIP_CHECK(ctx, hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad != big) {
+        ctx->err = "hdg_element_blocks_sys: non-positive mass-matrix pivot in element " + std::to_string(bad);
+        return HDG_ERR_SINGULAR;
+    }
+    return HDG_OK;
+    GUARD_END
+}
+
 hdg_status hdg_residual_norm(hdg_ctx ctx, const hdg_dims* dims, const int32_t* f2e, const double* ru,
                              const double* rt, double* norm_h) {
     if (!ctx) return HDG_ERR_ARG;
@@ -423,6 +486,62 @@ hdg_status hdg_matvec(hdg_ctx ctx, const hdg_dims* dims, const double* K64, cons
     HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
     return op_apply_run(ctx, dims, m32 ? (const void*)K32 : (const void*)K64, m32, nbr, 2 * dims->nlfe - 1, x, y);
     GUARD_END
+}
+
+hdg_status hdg_autotune(hdg_ctx ctx, const hdg_dims* dims, const double* K64, const float* K32, const int32_t* nbr,
+                        const double* Binv64, const float* Binv32, int32_t reps, int32_t* n_tuned_h) {
+    if (!ctx) return HDG_ERR_ARG;
+    GUARD_BEGIN
+    hdg_status st = check_dims(ctx, dims, false, true);
+    if (st != HDG_OK) return st;
+    if (!K64 || !nbr) return set_err(ctx, HDG_ERR_ARG, "hdg_autotune: K64 and nbr are required");
+    if (reps < 1 || reps > 1000) return set_err(ctx, HDG_ERR_ARG, "hdg_autotune: reps must be in [1, 1000]");
+    HDG_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    const int nb = dims->ncomp * dims->npf, L = dims->nlfe, S = 2 * L - 1, nf = dims->nf;
+    const size_t N = (size_t)nf * nb;
+    double* x = (double*)ws_get(ctx, WS_VEC, sizeof(double) * 2 * N, &st);
+    if (!x) return st;
+    double* y = x + N;
+    HDG_HIP_CHECK(ctx, hipMemsetAsync(x, 0, sizeof(double) * N, ctx->stream));
+    int n = 0;
+    double us = 0.0;
+    struct V {
+        const void* M1;
+        bool m1_32;
+        const int32_t* nbr;
+        int S1;
+        const void* M2;
+        bool m2_32;
+    };
+    const V vars[6] = {{K64, false, nbr, S, nullptr, false},       {K32, true, nbr, S, nullptr, false},
+                       {Binv64, false, nullptr, 1, nullptr, false}, {Binv32, true, nullptr, 1, nullptr, false},
+                       {K64, false, nbr, S, Binv64, false},         {K32, true, nbr, S, Binv32, true}};
+    for (int v = 0; v < 6; ++v) {
+        const V& c = vars[v];
+        if (!c.M1 || (v >= 4 && !c.M2)) continue;
+        if ((st = face_autotune(ctx, nf, nb, c.S1, L, c.M1, c.m1_32, c.nbr, c.M2, c.m2_32, x, y, reps, &us)) !=
+            HDG_OK)
+            return st;
+        ++n;
+    }
+    if (!tune_save()) return set_err(ctx, HDG_ERR_ARG, "hdg_autotune: could not write the HDG_TUNE_CACHE file");
+    if (n_tuned_h) *n_tuned_h = n;
+    return HDG_OK;
+    GUARD_END
+}
+
+size_t hdg_tune_table(char* buf_h, size_t len) {
+    try {
+        const std::string t = tune_json();
+        if (buf_h && len > 0) {
+            const size_t k = t.size() < len - 1 ? t.size() : len - 1;
+            std::memcpy(buf_h, t.data(), k);
+            buf_h[k] = '\0';
+        }
+        return t.size() + 1;
+    } catch (...) {
+        return 0;
+    }
 }
 
 hdg_status hdg_bj_setup(hdg_ctx ctx, const hdg_dims* dims, const double* K64, double* Binv64, float* Binv32) {

@@ -534,6 +534,12 @@ hdg_status hdg_gmres_solve_batch(hdg_ctx ctx, hdg_batch b, const double* K64, co
         graph = nullptr;
     };
     std::vector<BatchCtl> hc(ni);
+    // stagnation: an instance whose inner estimate met its target at every restart while its
+    // true residual stayed above the target and above 0.9 times the best true residual it had
+    // shown, five cycles in a row, has reached the accuracy its FP64 residual can show; it
+    // stops (not converged, flagged)
+    std::vector<double> best_beta(ni, INFINITY), prev_est(ni, INFINITY);
+    std::vector<int> stalls(ni, 0);
     int iters = 0;
     hdg_status result = HDG_NOT_CONVERGED;
     while (true) {
@@ -584,6 +590,20 @@ hdg_status hdg_gmres_solve_batch(hdg_ctx ctx, hdg_batch b, const double* K64, co
             }
         }
         iters += any_active ? m : 0;
+        for (int i = 0; i < ni; ++i) {
+            if (hc[i].k == 0) continue;
+            const bool stall = prev_est[i] <= tg_h[i] && hc[i].beta > tg_h[i] && hc[i].beta > 0.9 * best_beta[i];
+            stalls[i] = stall ? stalls[i] + 1 : 0;
+            best_beta[i] = std::min(best_beta[i], hc[i].beta);
+            prev_est[i] = hc[i].est;
+            if (stalls[i] >= 5) {
+                stats[i].fallback_flags |= HDG_FALLBACK_STAGNATED;
+                const double stop = INFINITY;     // the next cycle's start marks it done
+                HDG_HIP_CHECK(ctx, hipMemcpyAsync(target + i, &stop, sizeof(double), hipMemcpyHostToDevice,
+                                                  ctx->stream));
+                HDG_HIP_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+            }
+        }
         if (bad) {
             ctx->err = "batched solve: residual or Arnoldi data became NaN or Inf";
             result = HDG_ERR_NONFINITE;

@@ -28,6 +28,7 @@ enum WsSlot {
     WS_ASM,            // additive Schwarz: unit neighbour table, unit results, a work vector
     WS_NEWTON,         // residual norm: assembled trace residual and reduction partials
     WS_NEWTON_BATCH,   // batched element generation / norms / updates: descriptors, norms, steps
+    WS_ELEM_SYS,       // element generation of M-component models: per-point flux data of a chunk
     WS_NSLOTS
 };
 
@@ -89,6 +90,17 @@ struct CaptureStreamScope {
 
 // Returns a device buffer of at least `bytes` for `slot` (grows, never shrinks).
 void* ws_get(hdg_ctx ctx, WsSlot slot, size_t bytes, hdg_status* st);
+
+// Measured launch configurations (tune.cpp): key -> (a, b); HDG_TUNE_CACHE names a JSON file
+// the table is read from on first use and written back by tune_save.
+bool tune_get(const std::string& key, int* a, int* b);
+void tune_put(const std::string& key, int a, int b, double us);
+bool tune_have_entries();
+std::string tune_json();
+bool tune_save();
+hdg_status face_autotune(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1, bool m1_fp32,
+                         const int32_t* nbr1, const void* M2, bool m2_fp32, const double* x, double* y, int reps,
+                         double* best_us);
 
 // Fixed per-device scratch of the allocation-free entry point (k_noalloc.hip): 16 MiB.
 constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(1) << 21;
@@ -209,8 +221,8 @@ hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, doub
 
 // Condensation, assembly, recovery launchers.
 hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_elem_blocks* in,
-                        double* Kbar, double* rbar, double* local, double* L21 = nullptr, int32_t* ipiv = nullptr);
-hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* local, const double* L21,
+                        double* Kbar, double* rbar, double* local, double* Hbar = nullptr, int32_t* ipiv = nullptr);
+hdg_status condense_rhs_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, double* local, const double* Hbar,
                             const int32_t* ipiv, const double* ru, const double* rt, double* rbar);
 hdg_status assemble_rhs_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, const int32_t* perm,
                             const double* rbar, double* r);
@@ -238,3 +250,10 @@ hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geo
 // Host-side eigenvalues / harmonic Ritz values (ritz.cpp).
 int hessenberg_eigvals(int n, double* H, int ld, double* wr, double* wi);
 int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout);
+
+// Element residuals / Jacobian blocks of M-component models (k_element_sys.hip).
+size_t element_sys_lds_bytes(const hdg_dims* d, int nqv, int nqf);
+size_t element_sys_ws_doubles(const hdg_dims* d, int nqv, int nqf);
+hdg_status element_sys_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geom* g, const hdg_sys_model* m,
+                           const hdg_time_term* tt, const int32_t* e2f, const double* u, const double* uhat,
+                           int32_t flags, const hdg_elem_arrays* out, int* bad, double* ws, int64_t e0, int64_t n);

@@ -14,6 +14,9 @@
 // (boundary faces) are trailing and are never read.
 #include <hip/hip_ext.h>
 
+#include <cstdio>
+#include <string>
+
 #include "hdg_internal.hpp"
 
 namespace {
@@ -243,6 +246,30 @@ __global__ __launch_bounds__(256) void k_asm_unit_nbr(long long ne, int L, const
     unbr[idx] = e2f[e * L + lp];
 }
 
+// A configuration (threads per face, rows per thread) the kernel supports for these operands:
+// the instantiated pairs, every row of the face owned by a thread, and vector loads that
+// divide nb and are aligned to the matrix.
+bool face_config_ok(const FaceArgs& a, size_t t1_bytes, int team, int vec) {
+    const bool inst = (vec == 1 && (team == 16 || team == 32 || team == 64 || team == 128 || team == 256)) ||
+                      ((vec == 2 || vec == 4) && (team == 128 || team == 256));
+    if (!inst || team < a.nb || a.nb % vec != 0 || vec * t1_bytes > 16) return false;
+    return reinterpret_cast<uintptr_t>(a.M1) % (vec * t1_bytes) == 0;
+}
+
+// Key of a launch configuration in the measured table: operand types, product kind, block
+// size, slots per face and the power-of-two bucket of the face count.
+std::string face_key(const FaceArgs& a, size_t t1_bytes, size_t t2_bytes, bool has_m2, int kind) {
+    int lg = 0;
+    while (lg < 40 && ((long long)1 << (lg + 1)) <= (long long)a.nf) ++lg;
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "face:m%zu:p%zu:m2%d:k%d:nb%d:S%d:nf2^%d", t1_bytes * 8, t2_bytes * 8,
+                  has_m2 ? 1 : 0, kind, a.nb, a.S1, lg);
+    return buf;
+}
+
+// Set by the tuner while it times one configuration (this thread only).
+thread_local int g_force_team = 0, g_force_vec = 0;
+
 template <typename T1, typename T2, bool HAS_M2, int KIND>
 hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     // 16-byte loads (4 floats or 2 doubles per thread) when nb and the matrix pointer
@@ -263,6 +290,18 @@ hdg_status launch_team(hdg_ctx ctx, const FaceArgs& a) {
     else team = 16;
     if (team < 128) vec = 1;           // vector loads only for the wide teams
     if (team < a.nb / vec) team = 256;
+    // a measured choice (hdg_autotune) replaces the rule above; the tuner forces its candidates
+    if (g_force_team) {
+        team = g_force_team;
+        vec = g_force_vec;
+    } else if (tune_have_entries()) {
+        int tt = 0, tv = 0;
+        if (tune_get(face_key(a, sizeof(T1), sizeof(T2), HAS_M2, KIND), &tt, &tv) &&
+            face_config_ok(a, sizeof(T1), tt, tv)) {
+            team = tt;
+            vec = tv;
+        }
+    }
     const int fpb = 256 / team;
     const size_t lds = sizeof(double) * ((size_t)fpb * a.S1 * a.nb + 256 * (size_t)vec + (size_t)fpb * a.nb);
     const int grid = div_up(a.nf, fpb);
@@ -337,6 +376,75 @@ hdg_status face_op(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1
     if (!m1_fp32 && !m2_fp32) return launch_team<double, double, true, 0>(ctx, a);
     if (m1_fp32) return launch_team<float, double, true, 0>(ctx, a);
     return launch_team<double, float, true, 0>(ctx, a);
+}
+
+// Times every supported configuration of one face-operator variant (the product's operands
+// as in face_op, output to y) with `reps` launches each and records the fastest in the table.
+// Returns the chosen configuration's time per launch in *best_us.
+hdg_status face_autotune(hdg_ctx ctx, int nf, int nb, int S1, int nlfe, const void* M1, bool m1_fp32,
+                         const int32_t* nbr1, const void* M2, bool m2_fp32, const double* x, double* y, int reps,
+                         double* best_us) {
+    FaceArgs a;
+    a.M1 = M1;
+    a.nbr1 = nbr1;
+    a.M2 = M2;
+    a.x = x;
+    a.skip = nullptr;
+    a.nf = nf;
+    a.nb = nb;
+    a.S1 = S1;
+    a.nlfe = nlfe;
+    for (int o = 0; o < 3; ++o) {
+        a.epi.out[o] = nullptr;
+        a.epi.X[o] = nullptr;
+        a.epi.Y[o] = nullptr;
+        a.epi.s[o] = a.epi.a[o] = a.epi.b[o] = 0.0;
+    }
+    a.epi.out[0] = y;
+    a.epi.s[0] = 1.0;
+    const size_t b1 = m1_fp32 ? 4 : 8, b2 = M2 ? (m2_fp32 ? 4 : 8) : b1;
+    const int kind = (nbr1 == nullptr && M2 == nullptr) ? 1 : 0;
+    static const int cands[9][2] = {{256, 4}, {128, 4}, {256, 2}, {128, 2}, {256, 1}, {128, 1}, {64, 1}, {32, 1},
+                                    {16, 1}};
+    hipEvent_t e0, e1;
+    HDG_HIP_CHECK(ctx, hipEventCreate(&e0));
+    HDG_HIP_CHECK(ctx, hipEventCreate(&e1));
+    double best = -1.0;
+    int bt = 0, bv = 0;
+    hdg_status st = HDG_OK;
+    for (const auto& c : cands) {
+        if (!face_config_ok(a, b1, c[0], c[1])) continue;
+        g_force_team = c[0];
+        g_force_vec = c[1];
+        st = face_op(ctx, nf, nb, S1, nlfe, M1, m1_fp32, nbr1, M2, m2_fp32, x, a.epi, nullptr);   // warm-up
+        if (st == HDG_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) st = HDG_ERR_HIP;
+        for (int r = 0; r < reps && st == HDG_OK; ++r)
+            st = face_op(ctx, nf, nb, S1, nlfe, M1, m1_fp32, nbr1, M2, m2_fp32, x, a.epi, nullptr);
+        if (st == HDG_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            st = HDG_ERR_HIP;
+        g_force_team = g_force_vec = 0;
+        if (st != HDG_OK) break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = HDG_ERR_HIP;
+            break;
+        }
+        const double us = 1e3 * ms / reps;
+        if (best < 0.0 || us < best) {
+            best = us;
+            bt = c[0];
+            bv = c[1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HDG_OK) {
+        if (ctx->err.empty()) ctx->err = "autotune: a timed launch failed";
+        return st;
+    }
+    if (best >= 0.0) tune_put(face_key(a, b1, b2, M2 != nullptr, kind), bt, bv, best);
+    *best_us = best;
+    return HDG_OK;
 }
 
 hdg_status asm_unit_nbr(hdg_ctx ctx, int64_t ne, int L, const int32_t* e2f, int32_t* unbr) {

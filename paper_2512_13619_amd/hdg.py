@@ -16,14 +16,14 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 HDG_OK, HDG_NOT_CONVERGED = 0, 1
 PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3, "asm": 4, "asm_poly": 5, "asm_cheb": 6, "ilu_asm": 7}
 ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2, "dcgs2": 3}
-FALLBACK = {"pp_breakdown": 1, "pp_small_ritz": 2, "pp_no_interval": 4, "pp_to_base": 8, "mixed_to_fp64": 16}
+FALLBACK = {"pp_breakdown": 1, "pp_small_ritz": 2, "pp_no_interval": 4, "pp_to_base": 8, "mixed_to_fp64": 16, "stagnated": 32}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol declared in include/hdg.h
 SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg_release_workspace",
            "hdg_local_size", "hdg_condense", "hdg_condense_keep", "hdg_condense_rhs", "hdg_assemble_blocks",
            "hdg_assemble_rhs", "hdg_solve_opts_default", "hdg_gmres_solve",
-           "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_residual_norm_noalloc", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
+           "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_residual_norm_noalloc", "hdg_element_blocks_sys", "hdg_autotune", "hdg_tune_table", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
            "hdg_bj_apply", "hdg_poly_apply", "hdg_cheb_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch", "hdg_element_blocks_batch", "hdg_residual_norm_batch",
@@ -55,6 +55,15 @@ class ElemGeom(ctypes.Structure):
 class ConvDiff(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("tau", ctypes.c_double), ("beta", ctypes.c_double * 3),
                 ("gamma", ctypes.c_double * 3)]
+
+
+class SysModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tau", ctypes.c_double), ("lam", ctypes.c_double),
+                ("mu", ctypes.c_double), ("Re", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
+
+
+MODEL_KIND = {"elasticity": 1, "navier_stokes": 2}
 
 
 class TimeTerm(ctypes.Structure):
@@ -121,6 +130,11 @@ def load():
                                        ctypes.POINTER(TimeTerm), vp, vp, vp, i32, ctypes.POINTER(ElemArrays)]
     lib.hdg_residual_norm.argtypes = [vp, pd, vp, vp, vp, ctypes.POINTER(dbl)]
     lib.hdg_residual_norm_noalloc.argtypes = [vp, pd, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.hdg_autotune.argtypes = [vp, pd, vp, vp, vp, vp, vp, i32, ctypes.POINTER(i32)]
+    lib.hdg_tune_table.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.hdg_tune_table.restype = ctypes.c_size_t
+    lib.hdg_element_blocks_sys.argtypes = [vp, pd, ctypes.POINTER(ElemGeom), ctypes.POINTER(SysModel),
+                                           ctypes.POINTER(TimeTerm), vp, vp, vp, i32, ctypes.POINTER(ElemArrays)]
     lib.hdg_matvec.argtypes = [vp, pd, vp, vp, vp, i32, vp, vp]
     lib.hdg_bj_setup.argtypes = [vp, pd, vp, vp, vp]
     lib.hdg_bj_apply.argtypes = [vp, pd, vp, vp, i32, vp, vp]
@@ -151,7 +165,7 @@ def load():
     lib.hdg_newton_update_batch.argtypes = [vp, vp, ctypes.POINTER(dbl), vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("hdg_last_error", "hdg_local_size", "hdg_solve_opts_default",
-                        "hdg_hessenberg_eigvals", "hdg_harmonic_ritz"):
+                        "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_tune_table"):
             getattr(lib, name).restype = ctypes.c_int
     lib.hdg_hessenberg_eigvals.restype = ctypes.c_int
     lib.hdg_harmonic_ritz.restype = ctypes.c_int
@@ -183,6 +197,16 @@ def _ptr(t, dtype, numel=None, name="array", allow_none=False):
 
 
 # ---- host-only helpers (no GPU needed) ----------------------------------------------------
+def tune_table():
+    """The measured launch-configuration table (hdg_tune_table) as a dict."""
+    import json
+    lib = load()
+    n = lib.hdg_tune_table(None, 0)
+    buf = ctypes.create_string_buffer(max(int(n), 1))
+    lib.hdg_tune_table(buf, len(buf))
+    return json.loads(buf.value.decode()) if buf.value else {}
+
+
 def hessenberg_eigvals(H):
     lib = load()
     H = np.ascontiguousarray(H, dtype=np.float64)
@@ -264,7 +288,7 @@ class Context:
                                                  _ptr(Kbar, f64, ne * nt * nt, "Kbar"), _ptr(rbar, f64, ne * nt, "rbar"),
                                                  _ptr(local, f64, ne * nu * (nu + nt + 1), "local")))
 
-    def condense_keep(self, dims, blk, Kbar, rbar, local, L21, ipiv, ne_chunk=None):
+    def condense_keep(self, dims, blk, Kbar, rbar, local, Hbar, ipiv, ne_chunk=None):
         import torch
         d = make_dims(dims)
         ne = int(dims["ne"]) if ne_chunk is None else int(ne_chunk)
@@ -278,9 +302,9 @@ class Context:
         return self._check(self.lib.hdg_condense_keep(
             self.h, ctypes.byref(d), ne, ctypes.byref(eb), _ptr(Kbar, f64, ne * nt * nt, "Kbar"),
             _ptr(rbar, f64, ne * nt, "rbar"), _ptr(local, f64, ne * nu * (nu + nt + 1), "local"),
-            _ptr(L21, f64, ne * nt * nu, "L21"), _ptr(ipiv, torch.int32, ne * nu, "ipiv")))
+            _ptr(Hbar, f64, ne * nt * nu, "Hbar"), _ptr(ipiv, torch.int32, ne * nu, "ipiv")))
 
-    def condense_rhs(self, dims, local, L21, ipiv, ru, rt, rbar, ne_chunk=None):
+    def condense_rhs(self, dims, local, Hbar, ipiv, ru, rt, rbar, ne_chunk=None):
         import torch
         d = make_dims(dims)
         ne = int(dims["ne"]) if ne_chunk is None else int(ne_chunk)
@@ -289,7 +313,7 @@ class Context:
         f64 = torch.float64
         return self._check(self.lib.hdg_condense_rhs(
             self.h, ctypes.byref(d), ne, _ptr(local, f64, ne * nu * (nu + nt + 1), "local"),
-            _ptr(L21, f64, ne * nt * nu, "L21"), _ptr(ipiv, torch.int32, ne * nu, "ipiv"),
+            _ptr(Hbar, f64, ne * nt * nu, "Hbar"), _ptr(ipiv, torch.int32, ne * nu, "ipiv"),
             _ptr(ru, f64, ne * nu, "ru"), _ptr(rt, f64, ne * nt, "rt"), _ptr(rbar, f64, ne * nt, "rbar")))
 
     def assemble_rhs(self, dims, f2e, perm, rbar, r):
@@ -411,6 +435,55 @@ class Context:
             self.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(m), tt, _ptr(e2f, torch.int32, ne * L, "e2f"),
             _ptr(u, f64, ne * P, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"),
             (1 if residual_only else 0) | (2 if keep_mass else 0), ctypes.byref(o)))
+
+    def element_blocks_sys(self, dims, geom, model, e2f, u, uhat, out, residual_only=False, time_term=None,
+                           keep_mass=False):
+        """hdg_element_blocks_sys for the M-component models: geom as for element_blocks with
+        src (ne, nqv, M) and uD (ne, nlfe, nqf, M); model = dict(kind="elasticity", tau, lam, mu)
+        or dict(kind="navier_stokes", tau, Re, Pr, gamma); u (ne, M, npe) and uhat (nf, M, npf)
+        flattened; time_term = dict(c, u_prev, r_extra=None)."""
+        import torch
+        d = make_dims(dims)
+        ne, nf, M, D, P, PF, L = (int(dims[k]) for k in ("ne", "nf", "ncomp", "dim", "npe", "npf", "nlfe"))
+        Qv, Qf = int(geom["nqv"]), int(geom["nqf"])
+        f64 = torch.float64
+        gsz = dict(wdet=ne * Qv, dphix=ne * Qv * P * D, phi=Qv * P, phif=ne * L * Qf * P, psi=Qf * PF,
+                   ndA=ne * L * Qf * D, dA=ne * L * Qf, src=ne * Qv * M, uD=ne * L * Qf * M)
+        g = ElemGeom(Qv, Qf, *[_ptr(geom[k], f64, gsz[k], k) for k in gsz],
+                     _ptr(geom["bnd"], torch.int32, ne * L, "bnd"))
+        if model["kind"] not in MODEL_KIND:
+            raise HdgError(-1, f"unknown model kind {model['kind']!r}")
+        m = SysModel(MODEL_KIND[model["kind"]], float(model["tau"]), float(model.get("lam", 0.0)),
+                     float(model.get("mu", 0.0)), float(model.get("Re", 0.0)), float(model.get("Pr", 0.0)),
+                     float(model.get("gamma", 0.0)))
+        nu, nq, nt = M * P, M * D * P, L * M * PF
+        osz = dict(Minv=P * P, Bd=D * P * P, Cd=D * P * L * PF, D=nu * nq, E=nu * nu, F=nu * nt, G=nt * nq,
+                   H=nt * nu, J=nt * nt, ru=nu, rt=nt, q=nq)
+        o = ElemArrays(*[_ptr(out.get(k), f64, ne * osz[k], k, allow_none=True) for k in osz])
+        tt = None
+        if time_term is not None:
+            tt = ctypes.byref(TimeTerm(float(time_term["c"]), _ptr(time_term.get("u_prev"), f64, ne * nu, "u_prev",
+                                                                     allow_none=True),
+                                       _ptr(time_term.get("r_extra"), f64, ne * nu, "r_extra", allow_none=True)))
+        return self._check(self.lib.hdg_element_blocks_sys(
+            self.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(m), tt, _ptr(e2f, torch.int32, ne * L, "e2f"),
+            _ptr(u, f64, ne * nu, "u"), _ptr(uhat, f64, nf * PF * M, "uhat"),
+            (1 if residual_only else 0) | (2 if keep_mass else 0), ctypes.byref(o)))
+
+    def autotune(self, dims, K64, K32, nbr, Binv64=None, Binv32=None, reps=10):
+        """hdg_autotune: measure the face operator's launch configurations on this matrix (and
+        its block-Jacobi inverses when given); returns the number of variants timed."""
+        import torch
+        d = make_dims(dims)
+        nf, M, PF, L = (int(dims[k]) for k in ("nf", "ncomp", "npf", "nlfe"))
+        nb, S = M * PF, 2 * L - 1
+        n = ctypes.c_int32(0)
+        self._check(self.lib.hdg_autotune(
+            self.h, ctypes.byref(d), _ptr(K64, torch.float64, nf * S * nb * nb, "K64"),
+            _ptr(K32, torch.float32, nf * S * nb * nb, "K32", allow_none=True), _ptr(nbr, torch.int32, nf * S, "nbr"),
+            _ptr(Binv64, torch.float64, nf * nb * nb, "Binv64", allow_none=True),
+            _ptr(Binv32, torch.float32, nf * nb * nb, "Binv32", allow_none=True), int(reps), ctypes.byref(n)))
+        return n.value
 
     def residual_norm(self, dims, f2e, ru, rt, noalloc=False):
         """hdg_residual_norm, or with noalloc=True hdg_residual_norm_noalloc (fixed device scratch)."""

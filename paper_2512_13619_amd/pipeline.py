@@ -41,16 +41,16 @@ class Pipeline:
             self.ctx.condense(self.dims, blk, self.Kbar[e0:e1], self.rbar[e0:e1], self.local[e0:e1],
                               ne_chunk=e1 - e0)
             return
-        if getattr(self, "L21", None) is None:
+        if getattr(self, "Hbar", None) is None:
             ne = self.dims["ne"]
-            self.L21 = torch.zeros(ne, self.nt, self.nu, dtype=torch.float64, device=self.device)
+            self.Hbar = torch.zeros(ne, self.nt, self.nu, dtype=torch.float64, device=self.device)
             self.ipiv = torch.zeros(ne, self.nu, dtype=torch.int32, device=self.device)
         self.ctx.condense_keep(self.dims, blk, self.Kbar[e0:e1], self.rbar[e0:e1], self.local[e0:e1],
-                               self.L21[e0:e1], self.ipiv[e0:e1], ne_chunk=e1 - e0)
+                               self.Hbar[e0:e1], self.ipiv[e0:e1], ne_chunk=e1 - e0)
 
     def condense_rhs(self, ru, rt):
         """New element right-hand sides with the kept factors (the matrices unchanged)."""
-        self.ctx.condense_rhs(self.dims, self.local, self.L21, self.ipiv, ru, rt, self.rbar)
+        self.ctx.condense_rhs(self.dims, self.local, self.Hbar, self.ipiv, ru, rt, self.rbar)
 
     def assemble_rhs(self):
         self.ctx.assemble_rhs(self.dims, self.f2e, self.perm, self.rbar, self.r)
@@ -88,19 +88,29 @@ class Pipeline:
         self.ctx.recover(self.dims, self.local, Minv, Bd, Cd, self.e2f, self.perm, self.x, self.du, self.dq)
 
     def element_arrays(self):
-        """Device buffers for the element blocks of a scalar model (hdg_element_blocks)."""
+        """Device buffers for the element blocks (hdg_element_blocks, hdg_element_blocks_sys)."""
         d = self.dims
         ne, D, P = d["ne"], d["dim"], d["npe"]
         z = lambda n: torch.zeros(ne * n, dtype=torch.float64, device=self.device)
         nu, nq, nt = self.nu, self.nq, self.nt
-        return dict(Minv=z(P * P), Bd=z(D * P * P), Cd=z(D * P * nt), D=z(nu * nq), E=z(nu * nu), F=z(nu * nt),
+        return dict(Minv=z(P * P), Bd=z(D * P * P), Cd=z(D * P * d["nlfe"] * d["npf"]), D=z(nu * nq), E=z(nu * nu),
+                    F=z(nu * nt),
                     G=z(nt * nq), H=z(nt * nu), J=z(nt * nt), ru=z(nu), rt=z(nt), q=z(nq))
+
+    def element_blocks(self, geom, model, u, uhat, out, **kw):
+        """Element residuals / blocks of the model: M-component models (a dict with "kind")
+        through hdg_element_blocks_sys, scalar convection-diffusion models through
+        hdg_element_blocks."""
+        if "kind" in model:
+            return self.ctx.element_blocks_sys(self.dims, geom, model, self.e2f, u, uhat, out, **kw)
+        return self.ctx.element_blocks(self.dims, geom, model, self.e2f, u, uhat, out, **kw)
 
     def newton(self, geom, model, u, uhat, tol=1e-10, atol=0.0, max_steps=20, min_alpha=2.0 ** -10, time_term=None,
                forcing=None, reuse=None, refresh=0.25, **solve_kw):
-        """Damped Newton iteration (Section 4.4) on a scalar convection-diffusion model.
+        """Damped Newton iteration (Section 4.4) on a scalar convection-diffusion model or an
+        M-component model (elasticity, Navier-Stokes: model has a "kind").
 
-        u [ne*npe] and uhat [nf*npf] (device, float64) hold the state and are updated in place.
+        u [ne*M*npe] and uhat [nf*M*npf] (device, float64) hold the state and are updated in place.
         Each step: element blocks at the state, condensation, assembly, preconditioned GMRES,
         recovery, then alpha = 1, 1/2, 1/4, ... until the residual norm decreases (or alpha
         reaches min_alpha); stops once the norm is at most max(tol * initial norm, atol).
@@ -139,8 +149,8 @@ class Pipeline:
             """Element residuals (and, unless residual-only, matrices) at the state; returns whether
             the matrices were left out."""
             ro = residual_only and self._mass_ready
-            self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, time_term=time_term, residual_only=ro,
-                                    keep_mass=self._mass_ready)
+            self.element_blocks(geom, model, u, uhat, blk, time_term=time_term, residual_only=ro,
+                                keep_mass=self._mass_ready)
             self._mass_ready = True
             return ro
 
@@ -211,7 +221,7 @@ class Pipeline:
         blk = self.element_arrays()
         res = {"ru": blk["ru"], "rt": blk["rt"], "Minv": blk["Minv"]}
         u_prev = torch.zeros_like(u)
-        self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk)      # forms M^-1, B_d, C_d once
+        self.element_blocks(geom, model, u, uhat, blk)      # forms M^-1, B_d, C_d once
         nrm = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
         stop = max(tol * nrm, atol)
         dtau = float(dtau0)
@@ -220,8 +230,7 @@ class Pipeline:
             if nrm <= stop:
                 break
             u_prev.copy_(u)
-            self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, blk, keep_mass=True,
-                                    time_term=dict(c=1.0 / dtau, u_prev=u_prev))
+            self.element_blocks(geom, model, u, uhat, blk, keep_mass=True, time_term=dict(c=1.0 / dtau, u_prev=u_prev))
             self.condense(blk)
             self.assemble()
             if str(solve_kw.get("prec", "")).startswith("asm"):
@@ -230,7 +239,7 @@ class Pipeline:
             self.recover(blk["Minv"], blk["Bd"], blk["Cd"])
             self.ctx.newton_update(1.0, self.du, u)
             self.ctx.newton_update(1.0, self.x, uhat)
-            self.ctx.element_blocks(d, geom, model, self.e2f, u, uhat, res, residual_only=True, keep_mass=True)
+            self.element_blocks(geom, model, u, uhat, res, residual_only=True, keep_mass=True)
             new = self.ctx.residual_norm(d, self.f2e, blk["ru"], blk["rt"])
             hist.append(dict(norm=nrm, dtau=dtau, iters=st["iters"]))
             dtau = dtau_max if new == 0.0 else min(dtau * nrm / new, dtau_max)
@@ -247,9 +256,9 @@ class Pipeline:
         Newton histories of every stage."""
         A = dirk_tableau(scheme)
         s, a = len(A), A[0][0]
-        ne, P = self.dims["ne"], self.dims["npe"]
+        ne, nu = self.dims["ne"], self.nu
         self.jac_valid = False
-        z = lambda: torch.zeros(ne * P, dtype=torch.float64, device=self.device)
+        z = lambda: torch.zeros(ne * nu, dtype=torch.float64, device=self.device)
         un = z()
         hists = []
         res = {"ru": z(), "rt": torch.zeros(ne * self.nt, dtype=torch.float64, device=self.device)}
@@ -266,7 +275,7 @@ class Pipeline:
                 tt = dict(c=1.0 / (a * dt), u_prev=un, r_extra=rx)
                 hists.append(self.newton(geom, model, u, uhat, time_term=tt, **newton_kw))
                 if i < s - 1:
-                    self.ctx.element_blocks(self.dims, geom, model, self.e2f, u, uhat, res, residual_only=True)
+                    self.element_blocks(geom, model, u, uhat, res, residual_only=True)
                     minus_rs.append(res["ru"].clone())
         return hists
 
