@@ -271,9 +271,14 @@ __device__ __forceinline__ int qelim_col(int c, int m, int P, int PF, int M, int
     return nu + (l * M + m) * PF + j;
 }
 
-// ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, component m, 64x64 tile) ------------------
-// One block per tile; tiles are numbered element-major, then component, row tile, column
-// tile. nblk is a multiple of 8 (trailing blocks exit).
+// ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, 64x64 tile), every component m ------------
+// One block per (element, row tile, column tile); the M components' products run through one
+// pipeline: chunk c of the stream is component c / nch, depth slice (c % nch) * GK of the
+// product [D;G][:, q(m,:,:)] (rows m0.., columns m KD..) times W (the same W for every
+// component), so the next component's first slices are loaded while the current one's last
+// ones are multiplied, and a block fills its pipeline once instead of once per component.
+// Each component's result, T0 minus the product, goes to its own columns of T (qelim_col)
+// when its last slice is done. nblk is a multiple of 8 (trailing blocks exit).
 __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
                                                    const double* __restrict__ Dm, const double* __restrict__ Em,
                                                    const double* __restrict__ Fm, const double* __restrict__ Gm,
@@ -282,18 +287,14 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
                                                    const double* __restrict__ W, double* __restrict__ top,
                                                    double* __restrict__ bot) {
     extern __shared__ double lds[];
-    const long long L = xcd_linear(gridDim.x);
-    if (L >= ntile) return;
-    const int per_e = cd.M * tm_n * tn_n;
-    const long long e = L / per_e;
-    int rem = (int)(L - e * per_e);
-    const int m = rem / (tm_n * tn_n);
-    rem -= m * tm_n * tn_n;
+    const long long Lb = xcd_linear(gridDim.x);
+    if (Lb >= ntile) return;
+    const int per_e = tm_n * tn_n;
+    const long long e = Lb / per_e;
+    const int rem = (int)(Lb - e * per_e);
     const int m0 = (rem / tn_n) * GT, n0 = (rem % tn_n) * GT;
     const int nu = cd.nu, nt = cd.nt, nq = cd.nq, R = cd.R, C = cd.C, NW = cd.NW, KD = cd.KD;
     const int P = cd.P, PF = cd.PF, M = cd.M;
-    const double* De = Dm + (size_t)e * nu * nq + (size_t)m * KD;
-    const double* Ge = Gm + (size_t)e * nt * nq + (size_t)m * KD;
     const double* We = W + (size_t)e * KD * NW;
     double* Te = top + (size_t)e * nu * C;
     double* Be = bot + (size_t)e * nt * C;
@@ -301,47 +302,156 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
     const double* Fe = Fm + (size_t)e * nu * nt;
     const double* He = Hm + (size_t)e * nt * nu;
     const double* Je = Jm + (size_t)e * nt * nt;
-    const MatA Am{De, Ge, nu, nq, R, KD};
-    const MatB Bm{We, NW, KD, NW};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = m0 + (wave >> 1) * 32, c0 = n0 + (wave & 1) * 32;
-    // T0 entries of this wave's quadrant, loaded before the product
-    double t0[2][2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int r0 = m0 + wr, c0 = n0 + wc;
+    const int nch = (KD + GK - 1) / GK;
+    const int nall = M * nch;
+    // staging roles: A rows m0 + (tid>>5) + 8u at depth k0 + (tid&31); B rows k0 + (tid>>6) + 4u at
+    // column n0 + (tid&63)
+    const int ka = tid & 31, jb = tid & 63;
+    const double* arow[8];
+    unsigned aokm = 0;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int u = 0; u < 8; ++u) {
+        const int r = m0 + (tid >> 5) + 8 * u;
+        aokm |= (r < R ? 1u : 0u) << u;
+        const int rr = r < R ? r : 0;
+        arow[u] = rr < nu ? Dm + ((size_t)e * nu + rr) * nq : Gm + ((size_t)e * nt + (rr - nu)) * nq;
+    }
+    const bool bok_c = n0 + jb < NW;
+    const double* bcol = We + (bok_c ? n0 + jb : 0);
+    double ra[2][8], rb[2][8];
+    int kst[2] = {0, 0};
+    // loads of stream chunk c into register set s (clamped addresses; masks applied at the LDS store)
+    auto gload = [&](int s, int c) __attribute__((always_inline)) {
+        const int m = c / nch, k0 = (c - m * nch) * GK;
+        kst[s] = k0;
+        const int k = k0 + ka;
+        const int kc = m * KD + (k < KD ? k : 0);
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int u = 0; u < 8; ++u) ra[s][u] = arow[u][kc];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
-                const int c = c0 + 16 * bj + (lane & 15);
-                const bool ok = r < R && c < NW;
-                const int tcol = qelim_col(c, m, P, PF, M, nu);
-                const double* src = r < nu ? (tcol < nu ? Ee + (size_t)r * nu + tcol : Fe + (size_t)r * nt + (tcol - nu))
-                                           : (tcol < nu ? He + (size_t)(r - nu) * nu + tcol
-                                                        : Je + (size_t)(r - nu) * nt + (tcol - nu));
-                t0[bi][bj][q] = *(ok ? src : Ee);
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int kb = k0 + (tid >> 6) + 4 * u;
+            rb[s][u] = bcol[(size_t)(kb < KD ? kb : 0) * NW];
+        }
+    };
+    auto lstore = [&](int s, int b) __attribute__((always_inline)) {
+        double* As = lds + b * (GK * GLDA);
+        double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
+        const bool kok = kst[s] + ka < KD;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = (kok && ((aokm >> u) & 1u)) ? ra[s][u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kb = kst[s] + (tid >> 6) + 4 * u;
+            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (bok_c && kb < KD) ? rb[s][u] : 0.0;
+        }
+    };
     double4_t acc[2][2];
     acc_zero(acc);
-    gemm_tile64(Am, Bm, m0, n0, lds, acc);
+    auto compute = [&](int b) __attribute__((always_inline)) {
+        const double* As = lds + b * (GK * GLDA);
+        const double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
+        // two halves of the slice: half the operand registers of loading all eight k-steps first
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+        for (int h = 0; h < 2; ++h) {
+            double a[4][2], bb[4][2];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k = 4 * (4 * h + ks) + kq;
+                a[ks][0] = As[k * GLDA + wr + i16];
+                a[ks][1] = As[k * GLDA + wr + 16 + i16];
+                bb[ks][0] = Bs[k * GLDB + wc + i16];
+                bb[ks][1] = Bs[k * GLDB + wc + 16 + i16];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][0], bb[ks][0], acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][0], bb[ks][1], acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bb[ks][0], acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bb[ks][1], acc[1][1], 0, 0, 0);
+            }
+        }
+    };
+    // this lane's two columns of the quadrant: T's column for component m is cb[bj] + m * cs[bj]
+    // (u columns of m: c + m P; trace columns: nu + (l M + m) PF + j, l = (c - P) / PF)
+    int cb[2], cs[2];
+    bool cu[2], cin[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int c = c0 + 16 * bj + (lane & 15);
+        cin[bj] = c < NW;
+        cu[bj] = c < P;
+        const int cc = c - P, l = cc / PF, j = cc - l * PF;
+        cb[bj] = cu[bj] ? c : nu + l * M * PF + j;
+        cs[bj] = cu[bj] ? P : PF;
+    }
+    // T = T0 - product for component m: T0 is E, F, H or J at T's column, read when the
+    // component's product is complete
+    auto store_t = [&](int m) __attribute__((always_inline)) {
+        // one 16-row half at a time (eight T0 loads in flight, then eight stores): the next
+        // slices' prefetched operands are live here, so the half keeps the register count down
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+            double t0[4][2];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
-                const int c = c0 + 16 * bj + (lane & 15);
-                if (r >= R || c >= NW) continue;
-                const int tcol = qelim_col(c, m, P, PF, M, nu);
-                const double v = t0[bi][bj][q] - acc[bi][bj][q];
-                if (r < nu) Te[(size_t)r * C + tcol] = v;
-                else Be[(size_t)(r - nu) * C + tcol] = v;
+                const bool rok = r < R, top_row = r < nu;
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    const int tcol = cb[bj] + m * cs[bj];
+                    const double* src = top_row ? (cu[bj] ? Ee + (size_t)r * nu + tcol : Fe + (size_t)r * nt + (tcol - nu))
+                                                : (cu[bj] ? He + (size_t)(r - nu) * nu + tcol
+                                                          : Je + (size_t)(r - nu) * nt + (tcol - nu));
+                    t0[q][bj] = *((rok && cin[bj]) ? src : Ee);
+                }
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                if (r >= R) continue;
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    if (!cin[bj]) continue;
+                    const int tcol = cb[bj] + m * cs[bj];
+                    const double v = t0[q][bj] - acc[bi][bj][q];
+                    if (r < nu) Te[(size_t)r * C + tcol] = v;
+                    else Be[(size_t)(r - nu) * C + tcol] = v;
+                }
+            }
+        }
+        acc_zero(acc);
+    };
+    // even stream chunks in LDS buffer 0 (their loads in set 0), odd ones in buffer 1 (set 1)
+    gload(0, 0);
+    if (nall > 1) gload(1, 1);
+    lstore(0, 0);
+    __syncthreads();
+    auto finish = [&](int cc) __attribute__((always_inline)) {                 // after chunk cc: component m complete?
+        const int m = cc / nch;
+        if (cc - m * nch == nch - 1) store_t(m);
+    };
+#pragma unroll 1
+    for (int c = 0; c < nall; c += 2) {
+        if (c + 2 < nall) gload(0, c + 2);
+        compute(0);
+        if (c + 1 < nall) lstore(1, 1);
+        finish(c);
+        __syncthreads();
+        if (c + 1 >= nall) break;
+        if (c + 3 < nall) gload(1, c + 3);
+        compute(1);
+        if (c + 2 < nall) lstore(0, 0);
+        finish(c + 1);
+        __syncthreads();
+    }
     // the right-hand-side column (once per element and row tile)
-    if (m == 0 && n0 == 0) {
-        for (int r = m0 + threadIdx.x; r < m0 + GT && r < R; r += BS) {
+    if (n0 == 0) {
+        for (int r = m0 + tid; r < m0 + GT && r < R; r += BS) {
             if (r < nu) Te[(size_t)r * C + (C - 1)] = ru[(size_t)e * nu + r];
             else Be[(size_t)(r - nu) * C + (C - 1)] = rt[(size_t)e * nt + (r - nu)];
         }
@@ -410,7 +520,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // NBT: compile-time bound of the panel width. Dynamic LDS: the nu x (NB+1) panel, then
 // nu + 2*NBT ints for the row interchanges.
 template <int NBT, int LBS>
-__global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top, int* bad_elem,
+__global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top, int* bad_elem,
                                                  int e_off, int32_t* __restrict__ ipiv_out, int keep) {
     extern __shared__ double sm[];
     __shared__ int ndisp;
@@ -475,11 +585,35 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                 }
                 wave_lds_sync();
                 const double inv = 1.0 / pv;
-                for (int li = kk + 1 + lane; li < nrow; li += 64) {
-                    const double mlt = Pn[li * ldp + kk] * inv;
-                    Pn[li * ldp + kk] = mlt;
-                    for (int c = kk + 1; c < nbk; ++c) Pn[li * ldp + c] -= mlt * Pn[kk * ldp + c];
+                // rank-1 update of the rows below, CW columns at a time: the pivot row's and the
+                // lane's row entries are all loaded before any is written (independent LDS loads in
+                // flight instead of one read-modify-write chain per entry)
+                constexpr int CW = NBT < 32 ? NBT : 32;
+                for (int cb = 0; cb < nbk; cb += CW) {
+                    if (cb + CW <= kk + 1) continue;
+                    double prow[CW];
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) {
+                        const int cc = cb + c;
+                        prow[c] = Pn[kk * ldp + ((cc > kk && cc < nbk) ? cc : kk)];
+                    }
+                    for (int li = kk + 1 + lane; li < nrow; li += 64) {
+                        double* row = Pn + li * ldp;
+                        double r[CW];
+#pragma unroll
+                        for (int c = 0; c < CW; ++c) {
+                            const int cc = cb + c;
+                            r[c] = row[(cc > kk && cc < nbk) ? cc : kk];
+                        }
+                        const double mlt = row[kk] * inv;
+#pragma unroll
+                        for (int c = 0; c < CW; ++c) {
+                            const int cc = cb + c;
+                            if (cc > kk && cc < nbk) row[cc] = r[c] - mlt * prow[c];
+                        }
+                    }
                 }
+                for (int li = kk + 1 + lane; li < nrow; li += 64) Pn[li * ldp + kk] *= inv;
                 wave_lds_sync();
             }
             if (bad && lane == 0) sing = 1;
@@ -525,9 +659,17 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
             double u[NBT];
 #pragma unroll
             for (int t = 0; t < NBT; ++t) u[t] = Tc[rs[t]];
-            // displaced rows: sources lie among the first nbk rows, destinations below them,
-            // and the pivot rows are already loaded, so the moves may go one at a time
-            for (int q = 0; q < nd; ++q) Tc[(size_t)ddst[q] * C] = Tc[(size_t)dsrc[q] * C];
+            // displaced rows: sources lie among the first nbk rows, destinations below them, and
+            // the pivot rows are already loaded; eight moves at a time, their loads issued together
+            // (one global round trip per eight moves instead of one per move)
+            for (int q0 = 0; q0 < nd; q0 += 8) {
+                double mv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) mv[q] = Tc[(size_t)dsrc[q0 + q < nd ? q0 + q : q0] * C];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q0 + q < nd) Tc[(size_t)ddst[q0 + q] * C] = mv[q];
+            }
             // forward substitution with the unit lower L11
 #pragma unroll
             for (int kk = 1; kk < NBT; ++kk) {
@@ -642,10 +784,11 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
                         }
             }
         }
-        // the panel's triangle of U into LDS
+        // the panel's triangle of U into LDS, with the reciprocals of its diagonal in place of it
         for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
             const int li = idx / nbk, c = idx - li * nbk;
-            Pn[li * ldp + c] = Te[(size_t)(kb + li) * C + kb + c];
+            const double v = Te[(size_t)(kb + li) * C + kb + c];
+            Pn[li * ldp + c] = li == c ? 1.0 / v : v;
         }
         __syncthreads();
         // b. X_kb = U_kb^{-1} Y_kb, one thread per column
@@ -661,7 +804,7 @@ __global__ __launch_bounds__(LBS) void k_cond_lu(CondDims cd, int NB, double* __
 #pragma unroll
                     for (int q = t + 1; q < NBT; ++q)
                         if (q < nbk) v -= Pn[t * ldp + q] * u[q];
-                    u[t] = v / Pn[t * ldp + t];
+                    u[t] = v * Pn[t * ldp + t];
                 }
             }
 #pragma unroll
@@ -980,7 +1123,7 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
         HDG_LAUNCH_CHECK(ctx);
         {
             const int tm_n = div_up(cd.R, GT), tn_n = div_up(cd.NW, GT);
-            const long long ntile = (long long)n * cd.M * tm_n * tn_n;
+            const long long ntile = (long long)n * tm_n * tn_n;
             const long long nblk = (ntile + 7) / 8 * 8;
             hipLaunchKernelGGL(k_cond_qelim, dim3((unsigned)nblk), dim3(BS), GEMM_LDS, ctx->stream, cd, ntile, tm_n,
                                tn_n, in->D + e0 * cd.nu * cd.nq, in->E + e0 * cd.nu * cd.nu,
