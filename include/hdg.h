@@ -272,6 +272,12 @@ typedef struct {
  *                                less than half and stayed above twice what that cycle's inner
  *                                (FP32-operator) iteration estimated: the FP32 matrix limits the
  *                                refinement, and the remaining cycles use K64 and FP64 inverses;
+ *   HDG_FALLBACK_PP_ADDED_ROOT   the residual polynomial prod_j (1 - z/theta_j) of the harmonic
+ *                                Ritz values exceeds 1 in modulus at 1.1 times the root of largest
+ *                                real part (where the spectrum of M^{-1}K may still reach, and
+ *                                z p(z) would turn negative): one or two more copies of that root
+ *                                (and of its conjugate) were added, raising the degree by up to 4
+ *                                (hdg_poly_roots computes the roots);
  *   HDG_FALLBACK_STAGNATED       (hdg_gmres_solve_batch, per instance) five restart cycles in a
  *                                row met the target in their inner estimate while the true
  *                                residual at the next restart stayed above the target and above
@@ -279,7 +285,8 @@ typedef struct {
  *                                cannot show more accuracy, and the instance stops early, not
  *                                converged. */
 enum { HDG_FALLBACK_PP_BREAKDOWN = 1, HDG_FALLBACK_PP_SMALL_RITZ = 2, HDG_FALLBACK_PP_NO_INTERVAL = 4,
-       HDG_FALLBACK_PP_TO_BASE = 8, HDG_FALLBACK_MIXED_TO_FP64 = 16, HDG_FALLBACK_STAGNATED = 32 };
+       HDG_FALLBACK_PP_TO_BASE = 8, HDG_FALLBACK_MIXED_TO_FP64 = 16, HDG_FALLBACK_STAGNATED = 32,
+       HDG_FALLBACK_PP_ADDED_ROOT = 64 };
 
 void       hdg_solve_opts_default(hdg_solve_opts* opts_h);
 hdg_status hdg_gmres_solve(hdg_ctx ctx, const hdg_dims* dims,
@@ -593,10 +600,18 @@ hdg_status hdg_recover_batch(hdg_ctx ctx, hdg_batch b, const double* local, cons
  *   leading dimension ld) by the shifted QR algorithm; returns 0 on success.
  * hdg_harmonic_ritz: from H_{P+1,P} (row-major (P+1) x P) the harmonic Ritz values
  *   (eigenvalues of H_P + h_{P+1,P}^2 H_P^{-T} e_P e_P^T) in Leja order with conjugate
- *   pairs adjacent; values below drop_rel * max|theta| are dropped. Writes *n_out. */
+ *   pairs adjacent; values below drop_rel * max|theta| are dropped. Writes *n_out.
+ * hdg_poly_roots: the roots hdg_gmres_solve's polynomial preconditioner uses from the same
+ *   H: the harmonic Ritz values plus the safeguard of HDG_FALLBACK_PP_ADDED_ROOT (up to two
+ *   more copies of the root of largest real part, and of its conjugate, each added while the
+ *   residual polynomial exceeds 1 in modulus at 1.1 times that root), in Leja order (a copy
+ *   has distance zero to its twin and comes after every other value). theta_re_h /
+ *   theta_im_h need P + 4 entries; *n_added receives the number of values added (0 to 4). */
 int hdg_hessenberg_eigvals(int n, const double* H_h, int ld, double* wr_h, double* wi_h);
 int hdg_harmonic_ritz(int P, const double* H_h, double drop_rel,
                       double* theta_re_h, double* theta_im_h, int* n_out);
+int hdg_poly_roots(int P, const double* H_h, double drop_rel, double* theta_re_h, double* theta_im_h,
+                   int* n_out, int* n_added);
 
 #ifdef __cplusplus
 }

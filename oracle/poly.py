@@ -55,8 +55,9 @@ def leja_order(theta, drop_rel=1e-12):
 
     Start with the value of largest modulus; then repeatedly take the candidate
     maximising the product of distances to the values already chosen (sum of
-    logs); ties go to the lower index. Values with |theta| < drop_rel*max|theta|
-    are dropped."""
+    logs; a value equal to a chosen one scores minus infinity); ties go to the lower
+    index. Values with |theta| < drop_rel*max|theta| are dropped. A repeated value (the
+    added roots of the safeguard below) is a candidate as often as it occurs."""
     th = np.asarray(theta, complex)
     th = th[np.abs(th) >= drop_rel * np.abs(th).max()]
     # canonicalise: real values exactly real, pairs as (a+ib, a-ib) with b > 0 kept once
@@ -78,6 +79,54 @@ def leja_order(theta, drop_rel=1e-12):
         if t.imag > 0.0:
             out.append(np.conj(t))
     return np.array(out)
+
+
+def pof(theta, k):
+    """Product of the other factors at root k: prod_{i != k} |1 - theta_k / theta_i| (Loe and
+    Morgan, Numer. Linear Algebra Appl. 29 (2022) e2427). |pi(lambda)| near theta_k grows like
+    pof(k) |lambda - theta_k| / |theta_k|."""
+    th = np.asarray(theta, complex)
+    return float(np.prod([abs(1 - th[k] / th[i]) for i in range(th.size) if i != k]))
+
+
+def added_roots(theta, reach=1.1, max_copies=2):
+    """Safeguard (not in the paper): extra copies of the outermost root.
+
+    Harmonic Ritz values from one short Arnoldi cycle can stop short of the upper end of the
+    spectrum of B. Just beyond the root of largest real part t the residual polynomial
+    pi(z) = prod_j (1 - z / theta_j) grows like pof(k) times the relative distance, and where it
+    exceeds 1 in modulus with the wrong sign, z p(z) = 1 - pi(z) turns negative: p(B) B becomes
+    indefinite and GMRES stalls. While |pi(reach * t)| > 1 (the polynomial is not safe 10%
+    beyond its outermost root), one more copy of t (and of its conjugate, for a complex root) is
+    added, up to max_copies: each copy multiplies pi by (1 - z/t), of modulus below 1 on
+    (0, 2 Re t) for real t, so it only damps pi over the spectrum, and by 0.1 at reach * t. This
+    is the added-roots idea of Loe and Morgan applied to the outermost root with a test on pi
+    itself. Returns the values to add (possibly empty)."""
+    th = np.asarray(theta, complex)
+    if th.size < 2:
+        return np.zeros(0, complex)
+    t = th[int(np.argmax(th.real))]
+    if not t.real > 0.0:
+        return np.zeros(0, complex)
+    add = []
+    for _ in range(max_copies):
+        if abs(residual_poly(np.concatenate([th, np.array(add, complex)]), reach * t)) <= 1.0:
+            break
+        add += [t, np.conj(t)] if t.imag != 0.0 else [t]
+    return np.array(add, complex)
+
+
+def pp_roots(H, drop_rel=1e-12):
+    """The roots the polynomial preconditioner uses: the harmonic Ritz values (those below
+    drop_rel of the largest modulus dropped), the added copies of added_roots, all in Leja
+    order (a duplicate has distance zero to its twin and so comes after every other value).
+    Returns (roots, number added)."""
+    th = np.asarray(harmonic_ritz(H), complex)
+    th = th[np.abs(th) >= drop_rel * np.abs(th).max()]
+    # canonical pairs: exactly conjugate members
+    th = np.array([complex(t.real, 0.0) if t.imag == 0.0 else t for t in th])
+    add = added_roots(th)
+    return leja_order(np.concatenate([th, add]), drop_rel=0.0), int(add.size)
 
 
 def apply_product(opB, theta, t):

@@ -674,4 +674,13 @@ int hdg_harmonic_ritz(int P, const double* H_h, double drop_rel, double* tre, do
     }
 }
 
+int hdg_poly_roots(int P, const double* H_h, double drop_rel, double* tre, double* tim, int* n_out, int* n_added) {
+    if (P < 1 || !H_h || !tre || !tim || !n_out || !n_added) return -1;
+    try {
+        return poly_roots(P, H_h, drop_rel, tre, tim, n_out, n_added);
+    } catch (...) {
+        return -3;
+    }
+}
+
 }  // extern "C"

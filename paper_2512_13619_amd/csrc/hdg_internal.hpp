@@ -250,6 +250,7 @@ hdg_status element_blocks_run(hdg_ctx ctx, const hdg_dims* d, const hdg_elem_geo
 // Host-side eigenvalues / harmonic Ritz values (ritz.cpp).
 int hessenberg_eigvals(int n, double* H, int ld, double* wr, double* wi);
 int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout);
+int poly_roots(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout, int* nadded);
 
 // Element residuals / Jacobian blocks of M-component models (k_element_sys.hip).
 size_t element_sys_lds_bytes(const hdg_dims* d, int nqv, int nqf);

@@ -11,6 +11,7 @@
 // (first the value of largest modulus, then repeatedly the candidate that
 // maximises the product of distances to the values already chosen) with each
 // complex value immediately followed by its conjugate.
+// poly_roots: the same values plus the safeguard's added copy of the outermost root.
 #include <cfloat>
 #include <cmath>
 #include <vector>
@@ -142,10 +143,11 @@ int hessenberg_eigvals(int n, double* H, int ld, double* wr, double* wi) {
     return 0;
 }
 
-int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout) {
-    *nout = 0;
-    if (P < 1) return -1;
-    // Hm = H_P + h^2 f e_P^T with H_P^T f = e_P
+namespace {
+
+// Harmonic Ritz values of one Arnoldi cycle: the eigenvalues of H_P + h^2 f e_P^T with
+// H_P^T f = e_P (H is (P+1) x P, row-major).
+int harmonic_values(int P, const double* H, std::vector<double>& wr, std::vector<double>& wi) {
     std::vector<double> Hm((size_t)P * P), At((size_t)P * P), f(P, 0.0);
     for (int i = 0; i < P; ++i)
         for (int j = 0; j < P; ++j) {
@@ -155,8 +157,6 @@ int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, dou
     const double hs = H[(size_t)P * P + (P - 1)];
     f[P - 1] = 1.0;
     // Gaussian elimination with partial pivoting on At f = e_P
-    std::vector<int> perm(P);
-    for (int i = 0; i < P; ++i) perm[i] = i;
     bool ok = true;
     for (int k = 0; k < P && ok; ++k) {
         int p = k;
@@ -181,18 +181,16 @@ int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, dou
         }
         for (int i = 0; i < P; ++i) Hm[(size_t)i * P + (P - 1)] += hs * hs * f[i];
     }
-    std::vector<double> wr(P), wi(P);
-    if (hessenberg_eigvals(P, Hm.data(), P, wr.data(), wi.data()) != 0) return -2;
-    double amax = 0.0;
-    for (int i = 0; i < P; ++i) amax = std::fmax(amax, std::hypot(wr[i], wi[i]));
-    // candidates: real values and the positive-imaginary member of each pair
-    std::vector<double> cr, ci;
-    for (int i = 0; i < P; ++i) {
-        if (std::hypot(wr[i], wi[i]) < drop_rel * amax) continue;
-        if (wi[i] < 0.0) continue;
-        cr.push_back(wr[i]);
-        ci.push_back(wi[i]);
-    }
+    wr.assign(P, 0.0);
+    wi.assign(P, 0.0);
+    return hessenberg_eigvals(P, Hm.data(), P, wr.data(), wi.data()) != 0 ? -2 : 0;
+}
+
+// Leja order of the candidates (real values and the positive-imaginary member of each pair):
+// first the largest modulus, then repeatedly the candidate maximising the sum of log distances
+// to the values already chosen (a candidate equal to a chosen value scores minus infinity; ties
+// to the lower index); each complex value is followed by its conjugate.
+void leja(const std::vector<double>& cr, const std::vector<double>& ci, double* tre, double* tim, int* nout) {
     const int nc = (int)cr.size();
     std::vector<char> used(nc, 0);
     std::vector<double> sr, si;   // selected values (both members of pairs)
@@ -227,5 +225,76 @@ int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, dou
             si.push_back(-ci[best]);
         }
     }
+}
+
+// The candidates of the harmonic Ritz values whose modulus is at least drop_rel of the largest.
+void candidates(const std::vector<double>& wr, const std::vector<double>& wi, double drop_rel,
+                std::vector<double>& cr, std::vector<double>& ci) {
+    double amax = 0.0;
+    for (size_t i = 0; i < wr.size(); ++i) amax = std::fmax(amax, std::hypot(wr[i], wi[i]));
+    for (size_t i = 0; i < wr.size(); ++i) {
+        if (std::hypot(wr[i], wi[i]) < drop_rel * amax) continue;
+        if (wi[i] < 0.0) continue;
+        cr.push_back(wr[i]);
+        ci.push_back(wi[i]);
+    }
+}
+
+}  // namespace
+
+int harmonic_ritz_leja(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout) {
+    *nout = 0;
+    if (P < 1) return -1;
+    std::vector<double> wr, wi, cr, ci;
+    if (harmonic_values(P, H, wr, wi) != 0) return -2;
+    candidates(wr, wi, drop_rel, cr, ci);
+    leja(cr, ci, tre, tim, nout);
+    return 0;
+}
+
+// The roots the polynomial preconditioner uses: the harmonic Ritz values (small ones dropped)
+// plus, as a safeguard, up to two more copies of the root of largest real part t (and of its
+// conjugate), each added while the residual polynomial pi(z) = prod_j (1 - z/theta_j) has
+// modulus above 1 at 1.1 t -- the spectrum of B can reach beyond the outermost harmonic Ritz
+// value, and there 1 - pi(z) = z p(z) turns negative -- all in Leja order. tre/tim need P + 4
+// entries.
+int poly_roots(int P, const double* H, double drop_rel, double* tre, double* tim, int* nout, int* nadded) {
+    *nout = 0;
+    *nadded = 0;
+    if (P < 1) return -1;
+    std::vector<double> wr, wi, cr, ci;
+    if (harmonic_values(P, H, wr, wi) != 0) return -2;
+    candidates(wr, wi, drop_rel, cr, ci);
+    int nval = 0;
+    for (size_t c = 0; c < cr.size(); ++c) nval += ci[c] > 0.0 ? 2 : 1;
+    if (nval >= 2) {
+        size_t k = 0;
+        for (size_t c = 1; c < cr.size(); ++c)
+            if (cr[c] > cr[k]) k = c;
+        const double tr = cr[k], ti = ci[k];
+        // at most two more copies, each added while |pi(1.1 t)| > 1 over every value (both
+        // members of the pairs, the copies included)
+        for (int copy = 0; copy < 2 && tr > 0.0; ++copy) {
+            const double zr = 1.1 * tr, zi = 1.1 * ti;
+            double pr = 1.0, pim = 0.0;
+            for (size_t c = 0; c < cr.size(); ++c) {
+                for (int sgn = 1; sgn >= (ci[c] > 0.0 ? -1 : 1); sgn -= 2) {
+                    const double a = cr[c], b = sgn * ci[c];
+                    const double den = a * a + b * b;
+                    // 1 - z / theta = 1 - z conj(theta) / |theta|^2
+                    const double fr = 1.0 - (zr * a + zi * b) / den;
+                    const double fi = -(zi * a - zr * b) / den;
+                    const double nr = pr * fr - pim * fi;
+                    pim = pr * fi + pim * fr;
+                    pr = nr;
+                }
+            }
+            if (!(std::hypot(pr, pim) > 1.0)) break;
+            cr.push_back(tr);
+            ci.push_back(ti);
+            *nadded += ti > 0.0 ? 2 : 1;
+        }
+    }
+    leja(cr, ci, tre, tim, nout);
     return 0;
 }

@@ -488,14 +488,19 @@ hdg_status solve_run(hdg_ctx ctx, const hdg_dims* d, const double* K64, const fl
         std::vector<double> Hh;
         int pe = 0;
         if ((st = arnoldi_setup(ctx, op, w, o->poly_v0, P, Hh, &pe)) != HDG_OK) return st;
-        std::vector<double> tre(pe + 1), tim(pe + 1);
-        int nt = 0;
-        if (harmonic_ritz_leja(pe, Hh.data(), 1e-12, tre.data(), tim.data(), &nt) != 0) {
+        std::vector<double> tre(pe + 4), tim(pe + 4);
+        int nt = 0, nadd = 0;
+        // the Chebyshev interval needs only the extreme values: no added roots there
+        const int rc = plan.kind == HDG_PREC_BJ_CHEB
+                           ? harmonic_ritz_leja(pe, Hh.data(), 1e-12, tre.data(), tim.data(), &nt)
+                           : poly_roots(pe, Hh.data(), 1e-12, tre.data(), tim.data(), &nt, &nadd);
+        if (rc != 0) {
             ctx->err = "polynomial preconditioner: eigenvalue iteration did not converge";
             return HDG_ERR_SINGULAR;
         }
         if (pe < P) stats->fallback_flags |= HDG_FALLBACK_PP_BREAKDOWN;
-        if (nt < pe) stats->fallback_flags |= HDG_FALLBACK_PP_SMALL_RITZ;
+        if (nt - nadd < pe) stats->fallback_flags |= HDG_FALLBACK_PP_SMALL_RITZ;
+        if (nadd > 0) stats->fallback_flags |= HDG_FALLBACK_PP_ADDED_ROOT;
         plan.tre.assign(tre.begin(), tre.begin() + nt);
         plan.tim.assign(tim.begin(), tim.begin() + nt);
         plan.P = P;

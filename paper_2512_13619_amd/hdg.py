@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 HDG_OK, HDG_NOT_CONVERGED = 0, 1
 PREC = {"none": 0, "bj": 1, "bj_poly": 2, "bj_cheb": 3, "asm": 4, "asm_poly": 5, "asm_cheb": 6, "ilu_asm": 7}
 ORTH = {"cgs2": 0, "cgs": 1, "mgs": 2, "dcgs2": 3}
-FALLBACK = {"pp_breakdown": 1, "pp_small_ritz": 2, "pp_no_interval": 4, "pp_to_base": 8, "mixed_to_fp64": 16, "stagnated": 32}
+FALLBACK = {"pp_breakdown": 1, "pp_small_ritz": 2, "pp_no_interval": 4, "pp_to_base": 8, "mixed_to_fp64": 16, "stagnated": 32, "pp_added_root": 64}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 # every symbol declared in include/hdg.h
@@ -24,7 +24,7 @@ SYMBOLS = ["hdg_create", "hdg_destroy", "hdg_set_stream", "hdg_last_error", "hdg
            "hdg_local_size", "hdg_condense", "hdg_condense_keep", "hdg_condense_rhs", "hdg_assemble_blocks",
            "hdg_assemble_rhs", "hdg_solve_opts_default", "hdg_gmres_solve",
            "hdg_recover_local", "hdg_newton_update", "hdg_element_blocks", "hdg_residual_norm", "hdg_residual_norm_noalloc", "hdg_element_blocks_sys", "hdg_autotune", "hdg_tune_table", "hdg_asm_setup", "hdg_asm_apply", "hdg_matvec", "hdg_bj_setup",
-           "hdg_bj_apply", "hdg_poly_apply", "hdg_cheb_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_batch_create", "hdg_batch_destroy",
+           "hdg_bj_apply", "hdg_poly_apply", "hdg_cheb_apply", "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_poly_roots", "hdg_batch_create", "hdg_batch_destroy",
            "hdg_batch_offsets", "hdg_batch_tuned_grid", "hdg_condense_batch", "hdg_assemble_batch",
            "hdg_gmres_solve_batch", "hdg_recover_batch", "hdg_element_blocks_batch", "hdg_residual_norm_batch",
            "hdg_newton_update_batch", "hdg_ilu_asm_create", "hdg_ilu_asm_destroy", "hdg_ilu_asm_apply"]
@@ -146,6 +146,8 @@ def load():
     pdbl = ctypes.POINTER(dbl)
     lib.hdg_hessenberg_eigvals.argtypes = [ctypes.c_int, pdbl, ctypes.c_int, pdbl, pdbl]
     lib.hdg_harmonic_ritz.argtypes = [ctypes.c_int, pdbl, dbl, pdbl, pdbl, ctypes.POINTER(ctypes.c_int)]
+    lib.hdg_poly_roots.argtypes = [ctypes.c_int, pdbl, dbl, pdbl, pdbl, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int)]
     lib.hdg_batch_create.argtypes = [vp, i32, pd, ctypes.POINTER(vp)]
     lib.hdg_batch_destroy.argtypes = [vp]
     lib.hdg_batch_offsets.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
@@ -165,10 +167,11 @@ def load():
     lib.hdg_newton_update_batch.argtypes = [vp, vp, ctypes.POINTER(dbl), vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("hdg_last_error", "hdg_local_size", "hdg_solve_opts_default",
-                        "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_tune_table"):
+                        "hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_poly_roots", "hdg_tune_table"):
             getattr(lib, name).restype = ctypes.c_int
     lib.hdg_hessenberg_eigvals.restype = ctypes.c_int
     lib.hdg_harmonic_ritz.restype = ctypes.c_int
+    lib.hdg_poly_roots.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -218,6 +221,24 @@ def hessenberg_eigvals(H):
     if rc != 0:
         raise HdgError(rc, "eigenvalue iteration failed")
     return wr + 1j * wi
+
+
+def poly_roots(H, drop_rel=1e-12):
+    """H: (P+1) x P Arnoldi Hessenberg. Returns (roots in Leja order, number of added copies):
+    the roots the solver's polynomial preconditioner uses (hdg_poly_roots)."""
+    lib = load()
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    P = H.shape[1]
+    tr = np.zeros(P + 4)
+    ti = np.zeros(P + 4)
+    n = ctypes.c_int(0)
+    na = ctypes.c_int(0)
+    pd = ctypes.POINTER(ctypes.c_double)
+    rc = lib.hdg_poly_roots(P, H.ctypes.data_as(pd), drop_rel, tr.ctypes.data_as(pd), ti.ctypes.data_as(pd),
+                            ctypes.byref(n), ctypes.byref(na))
+    if rc != 0:
+        raise HdgError(rc, "polynomial root computation failed")
+    return tr[:n.value] + 1j * ti[:n.value], na.value
 
 
 def harmonic_ritz(H, drop_rel=1e-12):

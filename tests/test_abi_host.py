@@ -77,6 +77,31 @@ def test_harmonic_ritz_matches_oracle(P, seed):
         assert score(got[k]) >= max(score(z) for z in rest) - 1e-9
 
 
+@pytest.mark.parametrize("spectrum,seed", [("geometric", 0), ("geometric", 1), ("geometric", 7), ("random", 3)])
+def test_poly_roots_match_oracle(spectrum, seed):
+    """The roots the solver's polynomial preconditioner uses (harmonic Ritz values, the added
+    copies of the outermost one, Leja order) against the oracle's, value by value in order, on
+    Arnoldi cycles whose Ritz values stop short of the spectrum (geometric on [0.01, 3.1]: copies
+    are added) and on a nonsymmetric matrix."""
+    from paper_2512_13619_amd import hdg
+    rng = np.random.default_rng(seed)
+    N = 300
+    if spectrum == "geometric":
+        lam = np.geomspace(0.01, 3.1, N)
+        op = lambda v: lam * v
+    else:
+        Bm = rng.standard_normal((N, N)) * 0.1 + np.diag(np.linspace(0.5, 4, N))
+        op = lambda v: Bm @ v
+    H, _ = poly.arnoldi_mgs(op, rng.standard_normal(N), 10)
+    got, n_added = hdg.poly_roots(H)
+    ref, ref_added = poly.pp_roots(H)
+    assert n_added == ref_added and len(got) == len(ref)
+    if spectrum == "geometric":
+        assert n_added > 0
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-9 * scale, (got, ref)
+
+
 def test_binding_rejects_host_tensors():
     torch = pytest.importorskip("torch")
     from paper_2512_13619_amd import hdg

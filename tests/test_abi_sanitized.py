@@ -31,7 +31,7 @@ SCRIPT = textwrap.dedent("""
         fn = getattr(lib, name)
         ats = fn.argtypes or []
         if name in ("hdg_hessenberg_eigvals", "hdg_harmonic_ritz", "hdg_last_error", "hdg_local_size",
-                    "hdg_solve_opts_default", "hdg_batch_tuned_grid", "hdg_tune_table") or not ats:
+                    "hdg_solve_opts_default", "hdg_batch_tuned_grid", "hdg_tune_table", "hdg_poly_roots") or not ats:
             continue
         args = []
         for t in ats:

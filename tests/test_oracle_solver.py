@@ -308,6 +308,83 @@ def test_leja_conjugate_pair_follows_partner():
     assert np.array_equal(o, np.array([3.0, 1 + 2j, 1 - 2j, 2.5]))
 
 
+def test_pof_hand_example():
+    """theta = {1, 2, 4}: at the root 1 the other factors are |1 - 1/2| |1 - 1/4| = 0.375; at 4 they
+    are |1 - 4| |1 - 2| = 3."""
+    assert poly.pof(np.array([1.0, 2.0, 4.0]), 0) == pytest.approx(0.375, rel=1e-15)
+    assert poly.pof(np.array([1.0, 2.0, 4.0]), 2) == pytest.approx(3.0, rel=1e-15)
+
+
+def test_added_roots_hand_examples():
+    """pi(z) = prod (1 - z/theta) at 1.1 t, t the root of largest real part, worked by hand:
+    {1, 2}: (1 - 1.1)(1 - 2.2) = 0.12, nothing added; {0.05, 1}: (1 - 22)(1 - 1.1) = 2.1 > 1, one
+    copy of 1 makes it 2.1 x (-0.1) = -0.21, so one copy; {0.001, 1}: (1 - 1100)(-0.1) = 109.9, then
+    10.99, then 1.099 -- still above 1, but at most two copies are added."""
+    assert poly.added_roots(np.array([1.0, 2.0])).size == 0
+    assert np.array_equal(poly.added_roots(np.array([0.05, 1.0])), np.array([1.0], complex))
+    assert np.array_equal(poly.added_roots(np.array([0.001, 1.0])), np.array([1.0, 1.0], complex))
+    # a complex outermost root t = 1 + 0.1i goes in with its conjugate. At 1.1 t the factors of t
+    # and conj(t) have moduli |1 - 1.1| = 0.1 and |1 - 1.1 t / conj(t)| = |1 - 1.1 (0.99 + 0.2i) /
+    # 1.01| = |-0.07822 - 0.21782i| = 0.23144; with 0.03 as the third value its factor is
+    # |1 - (36.667 + 3.667i)| = 35.855 and |pi| = 0.8298, nothing added; with 0.002 it is
+    # |1 - (550 + 55i)| = 551.75, |pi| = 12.77, and one pair brings it to 12.77 x 0.02314 = 0.2955
+    t = 1 + 0.1j
+    assert abs(poly.residual_poly(np.array([0.03, t, np.conj(t)]), 1.1 * t)) == pytest.approx(0.8298, rel=1e-3)
+    assert poly.added_roots(np.array([0.03, t, np.conj(t)])).size == 0
+    add = poly.added_roots(np.array([0.002, t, np.conj(t)]))
+    assert add.size == 2 and set(np.round(add, 15)) == {t, np.conj(t)}
+    # a single value or a spectrum in the left half plane: nothing to add
+    assert poly.added_roots(np.array([0.5])).size == 0
+    assert poly.added_roots(np.array([-1.0, -2.0])).size == 0
+
+
+def test_added_roots_only_damp_the_residual_polynomial():
+    """Each copy of a real root t multiplies pi by (1 - z/t), of modulus below 1 on (0, 2t): the
+    residual polynomial with the copies is nowhere larger in modulus there."""
+    th = np.array([0.01, 0.2, 0.9, 1.7, 2.4, 2.95])
+    add = poly.added_roots(th)
+    assert add.size >= 1
+    z = np.linspace(1e-3, 2 * 2.95 - 1e-3, 4001)
+    old = np.abs([poly.residual_poly(th, x) for x in z])
+    new = np.abs([poly.residual_poly(np.concatenate([th, add]), x) for x in z])
+    assert np.all(new <= old * (1 + 1e-14))
+
+
+@pytest.mark.parametrize("spectrum", ["geometric", "outliers"])
+def test_added_roots_make_p_b_b_positive_on_model_spectra(spectrum):
+    """The safeguard's purpose, on diagonal matrices whose spectra reach past the harmonic Ritz
+    values of a 10-step Arnoldi cycle (geometric on [0.01, 3.1]; uniform on [0.01, 2.6] with three
+    outliers at 2.9, 3.0, 3.4): with the added roots, lambda p(lambda) = 1 - pi(lambda) is
+    positive at every eigenvalue for eight start vectors, so p(B) B is positive definite; on the
+    geometric spectrum it is negative at some eigenvalue for at least one start vector without
+    them."""
+    N = 300
+    lam = (np.geomspace(0.01, 3.1, N) if spectrum == "geometric"
+           else np.concatenate([np.linspace(0.01, 2.6, N - 3), [2.9, 3.0, 3.4]]))
+    worst_without = np.inf
+    for seed in range(8):
+        rng = np.random.default_rng(seed)
+        H, _ = poly.arnoldi_mgs(lambda v: lam * v, rng.standard_normal(N), 10)
+        roots, n_added = poly.pp_roots(H)
+        th = poly.harmonic_ritz(H)
+        assert n_added == roots.size - th.size
+        with_add = min((1 - poly.residual_poly(roots, x)).real for x in lam)
+        without = min((1 - poly.residual_poly(th, x)).real for x in lam)
+        assert with_add > 0.1, (seed, with_add)
+        worst_without = min(worst_without, without)
+    assert worst_without < 0 or spectrum == "outliers"
+
+
+def test_pp_roots_leja_order_with_copies():
+    """{0.05, 1} gets one copy of 1 (hand example above); Leja order starts at the largest
+    modulus, 1, then 0.05, and the copy, at distance zero from its twin, comes last."""
+    o = poly.leja_order(np.concatenate([np.array([0.05, 1.0]), poly.added_roots(np.array([0.05, 1.0]))]),
+                        drop_rel=0.0)
+    assert np.array_equal(o, np.array([1.0, 0.05, 1.0], complex))
+    o = poly.leja_order(np.array([3.0, 0.5, 3.0, 3.0, 1.0]), drop_rel=0.0)
+    assert np.array_equal(o, np.array([3.0, 0.5, 1.0, 3.0, 3.0], complex))
+
+
 def test_leja_drops_tiny_values():
     o = poly.leja_order(np.array([2.0, 1e-14, 1.0]), drop_rel=1e-12)
     assert np.array_equal(o, np.array([2.0, 1.0], complex))
