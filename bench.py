@@ -97,11 +97,13 @@ def fp32_matvec_kernel(tuned, nb, S):
     return "k_face_op<float,float,TEAM,false,0,VEC> (FP32 block matvec, built-in configuration rule)"
 
 
-def measured_traffic(kind, tag="elasticity24_p3"):
-    """Counter-measured HBM bytes per launch of the block matvec (profiles/ record), or None when the
-    kernel source changed since the counters were taken."""
+def measured_traffic(kernel, tag):
+    """Counter-measured HBM bytes per launch of a face-operator kernel instance (the profiles/
+    record face_operator_counters_<tag>.json, FETCH_SIZE and WRITE_SIZE calibrated on a device
+    copy), or None when the record has no entry for it or the kernel source changed since the
+    counters were taken."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", f"block_matvec_counters_{tag}.json")
+    rec_path = os.path.join(ROOT, "profiles", f"face_operator_counters_{tag}.json")
     try:
         rec = json.load(open(rec_path))
         src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
@@ -109,7 +111,8 @@ def measured_traffic(kind, tag="elasticity24_p3"):
         return None
     if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
         return None
-    return rec[kind]["traffic_bytes"]
+    k = rec["kernels"].get(kernel.split(" ")[0])
+    return k["traffic_bytes"] if k else None
 
 
 def time_matvec(ctx, pl, precision, reps=100):
@@ -663,8 +666,9 @@ def main():
     ap.add_argument("--profile-condense", type=int, default=0,
                     help="condense the resident elements this many times (for MFMA counters), then exit")
     ap.add_argument("--profile-matvec", type=int, default=0,
-                    help="build the workload's matrix, run this many FP32 and FP64 block matvecs and a 1 GiB "
-                         "device copy (counter calibration), then exit")
+                    help="build the workload's matrix, tune the face operator, run this many FP32 and FP64 block "
+                         "matvecs and block-Jacobi applies, a third as many FP32 Chebyshev(10) applies, and three "
+                         "1 GiB device copies (counter calibration), then exit")
     ap.add_argument("--newton", type=int, default=0,
                     help="instead of the headline: damped Newton on 2D viscous Burgers with this many quads per "
                          "direction at degree --p (element-kernel rates and the Newton loop), then exit")
@@ -733,20 +737,53 @@ def main():
         del blk
         torch.cuda.synchronize()
         reps = args.profile_matvec
+        nb = d["ncomp"] * d["npf"]
+        N = d["nf"] * nb
+        B64 = torch.empty(d["nf"] * nb * nb, dtype=torch.float64, device="cuda")
+        B32 = torch.empty(d["nf"] * nb * nb, dtype=torch.float32, device="cuda")
+        ctx.bj_setup(pl.dims, pl.K64, B64, B32)
+        tuned = None
+        if not args.no_tune:      # the configuration the bench's timed solves launch
+            ctx.autotune(pl.dims, pl.K64, pl.K32, pl.nbr, B64, B32, reps=10)
+            tuned = dict(table=hdg.tune_table().get("entries", {}))
         t32 = time_matvec(ctx, pl, "mixed", reps)
         t64 = time_matvec(ctx, pl, "fp64", reps)
+        y = torch.randn(N, dtype=torch.float64, device="cuda")
+        z = torch.empty_like(y)
+
+        def timed(fn, n):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(n):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 1e3 / n
+        tbj32 = timed(lambda: ctx.bj_apply(pl.dims, None, B32, y, z, "mixed"), reps)
+        tbj64 = timed(lambda: ctx.bj_apply(pl.dims, B64, None, y, z, "fp64"), reps)
+        # Chebyshev(10) on B = M^-1 K (interval [0.05, 2]): nine fused steps (block row product, block
+        # inverse, three-term recurrence in the epilogue) after one block-Jacobi apply
+        tch32 = timed(lambda: ctx.cheb_apply(pl.dims, None, pl.K32, pl.nbr, None, B32, 10, 0.05, 2.0, y, z, "mixed"),
+                      max(1, reps // 3))
         nbr_np = pl.nbr.cpu().numpy()
-        nb = d["ncomp"] * d["npf"]
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        bj_bytes = lambda w: d["nf"] * nb * nb * w + 2 * N * 8
+        # one fused Chebyshev step: K's non-empty blocks, nbr, the block inverses, the gathered input
+        # (read once), r and x_c read, r, d_next and x_c written
+        step_bytes = matvec_bytes(nbr_np, nb, 4) - 2 * N * 8 + d["nf"] * nb * nb * 4 + 3 * N * 8 + 3 * N * 8
         print(json.dumps({"profile": "block matvec", "fp32_ms": t32 * 1e3, "fp64_ms": t64 * 1e3,
                           "fp32_bytes": matvec_bytes(nbr_np, nb, 4), "fp64_bytes": matvec_bytes(nbr_np, nb, 8),
                           "fp32_GBs": matvec_bytes(nbr_np, nb, 4) / t32 / 1e9,
                           "fp64_GBs": matvec_bytes(nbr_np, nb, 8) / t64 / 1e9,
-                          "copy_bytes_each_way": src.numel() * 8}), flush=True)
+                          "bj32_ms": tbj32 * 1e3, "bj32_bytes": bj_bytes(4), "bj32_GBs": bj_bytes(4) / tbj32 / 1e9,
+                          "bj64_ms": tbj64 * 1e3, "bj64_bytes": bj_bytes(8), "bj64_GBs": bj_bytes(8) / tbj64 / 1e9,
+                          "cheb32_apply_ms": tch32 * 1e3, "cheb32_step_bytes": step_bytes,
+                          "copy_bytes_each_way": src.numel() * 8, "tuned": tuned}), flush=True)
         return
 
     v0 = torch.as_tensor(np.random.default_rng(7).standard_normal(d["nf"] * d["ncomp"] * d["npf"])).cuda()
@@ -922,7 +959,7 @@ def main():
         "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": r32["matvec_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": r32["matvec_GBs"] / PEAK_HBM_GBS,
-                     "traffic": (measured_traffic("fp32_matvec", wl["tag"])
+                     "traffic": (measured_traffic(fp32_matvec_kernel(tuned, nb, 2 * d["nlfe"] - 1), wl["tag"])
                                  if (args.n, args.p) == WORKLOAD_SIZES[args.config] else None),
                      "kernel": fp32_matvec_kernel(tuned, nb, 2 * d["nlfe"] - 1),
                      "bytes_per_launch": b32, "launches_timed": r32["n_timed"],
