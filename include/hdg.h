@@ -92,8 +92,8 @@ hdg_status  hdg_release_workspace(hdg_ctx ctx);
  *   Kbar  [ne][nt][nt]   element trace Schur complement (row = trace test dof)
  *   rbar  [ne][nt]
  *   local [ne][nu][nu+nt+1]   the local solver for recovery (eq. w19): rows hold
- *         [U | Ebar^{-1} Fbar | Ebar^{-1} ru] with P Ebar = L U (partial pivoting);
- *         only the upper triangle of the first nu columns is meaningful.
+ *         [L\U | Ebar^{-1} Fbar | Ebar^{-1} ru] with P Ebar = L U (partial pivoting,
+ *         the unit lower L below the diagonal with every interchange applied to it).
  * Errors: HDG_ERR_SINGULAR if some Ebar has a zero/non-finite pivot (first
  * such element named). Synchronises the stream to read that status. */
 typedef struct {
@@ -113,18 +113,14 @@ hdg_status hdg_condense(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
  *                      unknowns after the q-elimination;
  *   ipiv [ne][nu]      row interchanges of the elimination: at step k the rows at
  *                      (element-local) positions k and ipiv[k] >= k were exchanged;
- *   local additionally holds the unit lower L below the diagonal of its first nu
- *         columns, each panel's columns in that panel's row order (the elimination runs
- *         in panels of 32 columns, or of all nu columns when nu <= 64, 16 or 8 when the
- *         element is too large for LDS; the interchanges of later panels are not applied
- *         to earlier columns of L).
+ *   local holds the unit lower L below the diagonal of its first nu columns, with every
+ *         interchange applied to every column of L (P Ebar = L U as LAPACK's getrf leaves
+ *         it; hdg_condense leaves the same there).
  *   All outputs are caller-owned device buffers; the same errors as hdg_condense.
  * hdg_condense_rhs: for new right-hand sides ru [ne][nu], rt [ne][nt] of the same element
- *   matrices: x_r = Ebar^{-1} ru = U^{-1} L^{-1} P ru (the forward part panel by panel:
- *   the panel's interchanges, its unit lower triangle, its multipliers below it) replaces
- *   the last column of `local`, and rbar = rt - Hbar x_r. `local`, Hbar and ipiv must
- *   come from hdg_condense_keep on the same
- *   dims (the panel width is derived from dims as it was there). Enqueued only, no
+ *   matrices: x_r = Ebar^{-1} ru = U^{-1} L^{-1} P ru (P: the interchanges of ipiv in
+ *   order) replaces the last column of `local`, and rbar = rt - Hbar x_r. `local`, Hbar
+ *   and ipiv must come from hdg_condense_keep on the same dims. Enqueued only, no
  *   synchronisation; no pivots are re-checked. */
 hdg_status hdg_condense_keep(hdg_ctx ctx, const hdg_dims* dims, int64_t ne_chunk,
                              const hdg_elem_blocks* in, double* Kbar, double* rbar, double* local,

@@ -17,9 +17,14 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.jo
          "-Wno-unknown-pragmas"]
 
 
+# per-source flags: the condensation's register-resident solve unrolls its whole sequence of
+# block products (up to 42 for six 32-row blocks), above the default full-unroll size limit
+EXTRA = {"k_condense.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, obj, r
 

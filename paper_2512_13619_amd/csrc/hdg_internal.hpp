@@ -29,6 +29,7 @@ enum WsSlot {
     WS_NEWTON,         // residual norm: assembled trace residual and reduction partials
     WS_NEWTON_BATCH,   // batched element generation / norms / updates: descriptors, norms, steps
     WS_ELEM_SYS,       // element generation of M-component models: per-point flux data of a chunk
+    WS_LU,             // condensation: inverted diagonal blocks of L and U, row permutations
     WS_NSLOTS
 };
 

@@ -504,24 +504,133 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Entry c of row slot os of lane ol, as a uniform value (os, ol uniform).
+// (Each slot is read from lane ol, then the uniform results are selected: a select between
+// the slots' registers would let the compiler turn it into an indexed load and keep the panel
+// in scratch memory.)
+template <int RPL, int NBT>
+__device__ __forceinline__ double panel_entry(const double (&a)[RPL][NBT], int os, int c, int ol) {
+    double x = lane_value(a[0][c], ol);
+#pragma unroll
+    for (int r = 1; r < RPL; ++r) {
+        const double y = lane_value(a[r][c], ol);
+        x = os == r ? y : x;
+    }
+    return x;
+}
+
+// LU with partial pivoting of the panel in LDS (nrow rows, nbk <= NBT columns, row stride
+// ldp) in one wave's registers: lane l holds the panel rows l + 64 r (r < RPL). No row moves
+// while the panel is factorised: each lane tracks where its rows stand in the interchanged
+// order, and the pivot of column kk is the largest |entry| among the rows not yet chosen,
+// ties going to the lower position (what a search down the interchanged column finds).
+// The multipliers and the rank-1 update run on registers; the pivot row reaches every lane
+// through readlane. At the end the panel goes back to LDS in the interchanged order and
+// rsrc[position] receives the row's index before the interchanges; ipiv[kk] (if given)
+// ipiv_off plus the position interchanged with kk at step kk. Returns whether a pivot was
+// zero or not finite.
+template <int NBT, int RPL>
+__device__ __forceinline__ bool panel_lu_regs(double* Pn, int ldp, int nrow, int nbk, int* rsrc, int32_t* ipiv,
+                                              int ipiv_off) {
+    bool bad = false;
+    const int lane = threadIdx.x & 63;
+    double a[RPL][NBT];
+    int pos[RPL];
+    bool live[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int li = lane + 64 * r;
+        live[r] = li < nrow;
+        pos[r] = li;
+#pragma unroll
+        for (int c = 0; c < NBT; ++c) {
+            const bool ok = li < nrow && c < nbk;
+            const double v = Pn[ok ? li * ldp + c : 0];
+            a[r][c] = ok ? v : 0.0;
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < NBT; ++kk) {
+        if (kk < nbk) {
+            double best = -1.0;
+            int key = 0x7fffffff;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                // a NaN entry wins (the pivot check then flags the element): some live row is
+                // always chosen
+                double v = live[r] ? fabs(a[r][kk]) : -1.0;
+                if (live[r] && !(v >= 0.0)) v = INFINITY;
+                const int k = (pos[r] << 8) | (lane + 64 * r);
+                if (v > best || (v == best && k < key)) { best = v; key = k; }
+            }
+            wave_argmax(best, key);
+            const int ob = key & 255, p = key >> 8;
+            const int ol = ob & 63, os = ob >> 6;
+            double pv = panel_entry(a, os, kk, ol);
+            if (ipiv && lane == 0) ipiv[kk] = ipiv_off + p;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                if (pos[r] == kk) pos[r] = p;
+                if (lane == ol && r == os) { pos[r] = kk; live[r] = false; }
+            }
+            if (!(fabs(pv) > 0.0) || !isfinite(pv)) { bad = true; pv = 1.0; }
+            const double inv = 1.0 / pv;
+            double m[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                m[r] = live[r] ? a[r][kk] * inv : 0.0;
+                if (live[r]) a[r][kk] = m[r];
+            }
+#pragma unroll
+            for (int c = 0; c < NBT; ++c) {
+                if (c > kk) {   // (constant trip count: both loops unroll, a stays in registers)
+                    const double pc = panel_entry(a, os, c, ol);
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) a[r][c] = fma(-m[r], pc, a[r][c]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int li = lane + 64 * r;
+        if (li < nrow) {
+#pragma unroll
+            for (int c = 0; c < NBT; ++c)
+                if (c < nbk) Pn[pos[r] * ldp + c] = a[r][c];
+            rsrc[pos[r]] = li;
+        }
+    }
+    return bad;
+}
+
 // ---- LU of Ebar and X = Ebar^{-1} [Fbar | r_u] on the Ebar rows ------------------------------
 // Works on the top nu rows of T only (row stride C): [Ebar | Fbar | r_u] becomes
-// [U | X | x_r] with P Ebar = L U. The trace rows are not touched: they keep
-// [Hbar | Jbar | r_t] for the Schur product Kbar = Jbar - Hbar X.
-//   1. right-looking blocked LU over the first nu columns, panels of NB columns: the panel
-//      (rows k0.., NB columns) is factorised in LDS by one wave, with no block barrier per
-//      column (the pivot of a column is one DPP arg-max over the Ebar rows); then the
-//      panel's interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread per
-//      column) and the trailing update A22 -= L21 U12 (the panel's multipliers times the
-//      new U rows) on the matrix cores;
-//   2. back substitution X = U^{-1} Y by row panels from the bottom: the panel's rows take
-//      the solved rows below them (matrix cores), then its NB x NB triangle (one thread
-//      per column, the triangle in LDS).
-// NBT: compile-time bound of the panel width. Dynamic LDS: the nu x (NB+1) panel, then
-// nu + 2*NBT ints for the row interchanges.
-template <int NBT, int LBS>
-__global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd, int NB, double* __restrict__ top, int* bad_elem,
-                                                 int e_off, int32_t* __restrict__ ipiv_out, int keep) {
+// [L\U | X | x_r] with P Ebar = L U. The trace rows are not touched: they keep
+// [Hbar | Jbar | r_t] for the Schur product Kbar = Jbar - Hbar X. Three kernels:
+//   1. k_cond_getrf, one block per element: right-looking blocked LU of the nu x nu block
+//      with partial pivoting, panels of NB columns. The panel is factorised by one wave (in
+//      its registers, or in LDS for large elements), then the panel's interchanges are
+//      applied to every other column of the block (the earlier columns of L included, so L
+//      ends as LAPACK's getrf leaves it), U12 = L11^{-1} A12 (one thread per column) and the
+//      trailing update A22 -= L21 U12 runs on the matrix cores. The interchanges go to ipiv
+//      (step k exchanged positions k and ipiv[k]) and, composed, to perm (row i of P Ebar is
+//      row perm[i] of Ebar);
+//   2. k_cond_trinv, one block per (element, 32-row block): the inverses of the unit lower
+//      and upper 32 x 32 diagonal blocks of L and U;
+//   3. k_cond_getrs, one block per (element, slab of the nt + 1 right-hand-side columns): the
+//      slab is gathered in the interchanged row order into LDS, and Y = U^{-1} L^{-1} Y runs
+//      by 32-row blocks, each a product with the inverted diagonal block and an update of
+//      the remaining rows, all on the matrix cores.
+
+// Kernel 1: LU of the nu x nu block of the Ebar rows (see above). NBT: compile-time bound of
+// the panel width; RPL: rows per lane of the register panel (0: the panel is factorised in
+// LDS). Dynamic LDS: the nu x (NB+1) panel, then ints: rsrc [nu] (row interchanges of the
+// panel), dsrc/ddst [NBT] (displaced rows), gperm/gtmp [nu] (composed interchanges).
+template <int NBT, int LBS, int RPL>
+__global__ __launch_bounds__(LBS, LBS == 256 ? (RPL * NBT >= 64 ? 2 : 3) : 1) void k_cond_getrf(
+    CondDims cd, int NB, double* __restrict__ top, int* bad_elem, int e_off, int32_t* __restrict__ ipiv_out,
+    int32_t* __restrict__ perm_out) {
     extern __shared__ double sm[];
     __shared__ int ndisp;
     __shared__ int sing;
@@ -529,12 +638,15 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
     const int nu = cd.nu, C = cd.C;
     double* Te = top + (size_t)e * nu * C;
     const int ldp = NB + 1;
-    double* Pn = sm;                                   // nu x ldp: the panel, later a triangle of U
-    int* rsrc = (int*)(sm + (size_t)nu * ldp);         // [nu]: row interchanges of the panel
-    int* dsrc = rsrc + nu;                             // [NBT]: displaced rows (source)
-    int* ddst = dsrc + NBT;                            // [NBT]: displaced rows (destination)
+    double* Pn = sm;                                   // nu x ldp: the panel
+    int* rsrc = (int*)(sm + (size_t)nu * ldp);         // [nu]
+    int* dsrc = rsrc + nu;                             // [NBT]
+    int* ddst = dsrc + NBT;                            // [NBT]
+    int* gperm = ddst + NBT;                           // [nu]
+    int* gtmp = gperm + nu;                            // [nu]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x == 0) sing = 0;
+    for (int r = threadIdx.x; r < nu; r += LBS) gperm[r] = r;
     for (int k0 = 0; k0 < nu; k0 += NB) {
         const int nbk = (nu - k0) < NB ? (nu - k0) : NB;
         const int nrow = nu - k0;
@@ -557,8 +669,14 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
         for (int r = threadIdx.x; r < nrow; r += LBS) rsrc[r] = r;
         if (threadIdx.x == 0) ndisp = 0;
         __syncthreads();
-        // 2. one wave factorises the panel (pivot rows among the panel's Ebar rows)
-        if (wave == 0) {
+        // 2. one wave factorises the panel (pivot rows among the panel's rows): in its registers
+        //    when every lane holds at most RPL rows, else in LDS
+        if (RPL > 0 && wave == 0) {
+            const bool bad = panel_lu_regs<NBT, (RPL > 0 ? RPL : 1)>(Pn, ldp, nrow, nbk, rsrc,
+                                                                     ipiv_out + (size_t)e * nu + k0, k0);
+            if (bad && lane == 0) sing = 1;
+        }
+        if (RPL == 0 && wave == 0) {
             bool bad = false;
             for (int kk = 0; kk < nbk; ++kk) {
                 double best = -1.0;
@@ -628,24 +746,20 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
                 ddst[q] = r;
             }
         }
-        // 3. the panel's U11 rows back to T (rows k0..k0+nbk-1 are final); with keep also the
-        //    multipliers below them (unit lower L, in this panel's row order; later
-        //    interchanges move only the trailing columns)
-        for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
+        // 3. the factorised panel back to T (U11 and the multipliers L21), and the panel's
+        //    interchanges composed into gperm
+        for (int idx = threadIdx.x; idx < nrow * nbk; idx += LBS) {
             const int li = idx / nbk, kk = idx - li * nbk;
             Te[(size_t)(k0 + li) * C + k0 + kk] = Pn[li * ldp + kk];
         }
-        if (keep) {
-            for (int idx = threadIdx.x; idx < (nrow - nbk) * nbk; idx += LBS) {
-                const int li = nbk + idx / nbk, kk = idx - (li - nbk) * nbk;
-                Te[(size_t)(k0 + li) * C + k0 + kk] = Pn[li * ldp + kk];
-            }
-        }
+        for (int r = threadIdx.x; r < nrow; r += LBS) gtmp[r] = gperm[k0 + rsrc[r]];
         __syncthreads();
-        // 4. row interchanges and U12 = L11^{-1} A12 on the trailing columns (one thread
-        //    per column)
+        for (int r = threadIdx.x; r < nrow; r += LBS) gperm[k0 + r] = gtmp[r];
+        // 4. the panel's interchanges on every other column of the block (rows k0..): the
+        //    columns left of the panel (earlier multipliers) are only permuted, the trailing
+        //    ones also get U12 = L11^{-1} A12 (one thread per column)
         const int cbeg = k0 + nbk;
-        const int ncol = C - cbeg;
+        const int ncol = k0 + (nu - cbeg);
         const int nd = ndisp;
         // the pivot rows' offsets from row k0 are read from LDS once, before any global load
         // (reads past the valid entries stay inside the LDS allocation and are replaced by row 0)
@@ -655,13 +769,13 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
 #pragma unroll
         for (int t = 0; t < NBT; ++t) rs[t] = (t < nbk ? rs[t] : 0) * C;
         for (int cl = threadIdx.x; cl < ncol; cl += LBS) {
-            double* Tc = Te + (size_t)k0 * C + cbeg + cl;   // this column, from row k0 on
+            const bool trailing = cl >= k0;
+            double* Tc = Te + (size_t)k0 * C + (trailing ? cbeg + (cl - k0) : cl);   // this column, from row k0 on
             double u[NBT];
 #pragma unroll
             for (int t = 0; t < NBT; ++t) u[t] = Tc[rs[t]];
             // displaced rows: sources lie among the first nbk rows, destinations below them, and
             // the pivot rows are already loaded; eight moves at a time, their loads issued together
-            // (one global round trip per eight moves instead of one per move)
             for (int q0 = 0; q0 < nd; q0 += 8) {
                 double mv[8];
 #pragma unroll
@@ -670,14 +784,16 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
                 for (int q = 0; q < 8; ++q)
                     if (q0 + q < nd) Tc[(size_t)ddst[q0 + q] * C] = mv[q];
             }
-            // forward substitution with the unit lower L11
+            if (trailing) {
+                // forward substitution with the unit lower L11
 #pragma unroll
-            for (int kk = 1; kk < NBT; ++kk) {
-                if (kk < nbk) {
-                    double v = u[kk];
+                for (int kk = 1; kk < NBT; ++kk) {
+                    if (kk < nbk) {
+                        double v = u[kk];
 #pragma unroll
-                    for (int q = 0; q < kk; ++q) v -= Pn[kk * ldp + q] * u[q];
-                    u[kk] = v;
+                        for (int q = 0; q < kk; ++q) v -= Pn[kk * ldp + q] * u[q];
+                        u[kk] = v;
+                    }
                 }
             }
 #pragma unroll
@@ -685,11 +801,10 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
                 if (t < nbk) Tc[(size_t)t * C] = u[t];
         }
         __syncthreads();
-        // 5. trailing update of the Ebar rows over every trailing column (MFMA, 32x32 tiles
-        //    per wave)
+        // 5. trailing update of the block (MFMA, 32x32 tiles per wave)
         const int na = nu - cbeg;
-        const int ta_c = (ncol + 31) / 32;
-        const int tA = ((na + 31) / 32) * ta_c;
+        const int ta_c = (na + 31) / 32;
+        const int tA = ta_c * ta_c;
         for (int tile = wave; tile < tA; tile += LBS / 64) {
             const int r0 = cbeg + (tile / ta_c) * 32;
             const int c0 = cbeg + (tile % ta_c) * 32;
@@ -702,7 +817,7 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        const bool ok = r < nu && c < C;
+                        const bool ok = r < nu && c < nu;
                         const double v = Te[ok ? (size_t)r * C + c : (size_t)cbeg * C + cbeg];
                         acc[bi][bj][q] = ok ? v : 0.0;
                     }
@@ -714,7 +829,7 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
             };
             auto lb = [&](int k, int j) -> double {
                 const int c = c0 + j;
-                const bool ok = k < nbk && c < C;
+                const bool ok = k < nbk && c < nu;
                 const double v = Te[ok ? (size_t)(k0 + k) * C + c : (size_t)k0 * C + cbeg];
                 return ok ? v : 0.0;
             };
@@ -727,93 +842,315 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? 3 : 1) void k_cond_lu(CondDims cd
                     for (int q = 0; q < 4; ++q) {
                         const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
                         const int c = c0 + 16 * bj + (lane & 15);
-                        if (r < nu && c < C) Te[(size_t)r * C + c] = acc[bi][bj][q];
+                        if (r < nu && c < nu) Te[(size_t)r * C + c] = acc[bi][bj][q];
                     }
         }
         __syncthreads();
     }
-    // back substitution X = U^{-1} Y on the columns nu..C-1, row panels from the bottom
-    const int ncx = C - nu;
-    const int npan = (nu + NB - 1) / NB;
-    for (int pk = npan - 1; pk >= 0; --pk) {
-        const int kb = pk * NB;
-        const int nbk = (nu - kb) < NB ? (nu - kb) : NB;
-        const int kend = kb + nbk;
-        // a. Y_kb -= U[kb:kend, kend:nu] X[kend:nu, :] (MFMA, 32x32 tiles per wave)
-        if (kend < nu) {
-            const int tr = (nbk + 31) / 32, tc = (ncx + 31) / 32;
-            const int K = nu - kend;
-            for (int tile = wave; tile < tr * tc; tile += LBS / 64) {
-                const int r0 = kb + (tile / tc) * 32;
-                const int c0 = nu + (tile % tc) * 32;
-                double4_t acc[2][2];
+    for (int r = threadIdx.x; r < nu; r += LBS) perm_out[(size_t)e * nu + r] = gperm[r];
+    if (sing && threadIdx.x == 0) atomicMin(bad_elem, e_off + (int)e);
+}
+
+// Kernel 2: inverses of the 32 x 32 diagonal blocks of L (unit lower) and U (upper), one
+// block of 64 threads per (element, block row): thread t < 32 forms column t of inv(L_kb),
+// thread 32 + t column t of inv(U_kb), with the blocks in LDS. A last partial block (nu not
+// a multiple of 32) is completed with the identity. Output dinv[e][kb][0 / 1][32][32]
+// (row-major).
+__global__ __launch_bounds__(64) void k_cond_trinv(CondDims cd, const double* __restrict__ top,
+                                                   double* __restrict__ dinv) {
+    __shared__ double blk[32][33];
+    const int nu = cd.nu, C = cd.C;
+    const int nkb = (nu + 31) / 32;
+    const long long e = blockIdx.x / nkb;
+    const int kb = (int)(blockIdx.x - e * nkb);
+    const int r0 = kb * 32, rb = (nu - r0) < 32 ? (nu - r0) : 32;
+    const double* Te = top + (size_t)e * nu * C;
+    for (int idx = threadIdx.x; idx < 32 * 32; idx += 64) {
+        const int i = idx >> 5, j = idx & 31;
+        const bool ok = i < rb && j < rb;
+        const double v = Te[ok ? (size_t)(r0 + i) * C + r0 + j : 0];
+        blk[i][j] = ok ? v : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    const int t = threadIdx.x & 31;
+    double x[32];
+    if (threadIdx.x < 32) {
+        // L x = e_t, L unit lower
 #pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
+        for (int i = 0; i < 32; ++i) {
+            double v = i == t ? 1.0 : 0.0;
 #pragma unroll
-                    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
-                            const int c = c0 + 16 * bj + (lane & 15);
-                            const bool ok = r < kend && c < C;
-                            const double v = Te[ok ? (size_t)r * C + c : (size_t)kb * C + nu];
-                            acc[bi][bj][q] = ok ? v : 0.0;
-                        }
-                auto la = [&](int i, int k) -> double {
-                    const int r = r0 + i;
-                    const bool ok = r < kend && k < K;
-                    const double v = Te[ok ? (size_t)r * C + kend + k : (size_t)kb * C + kend];
-                    return ok ? -v : 0.0;
-                };
-                auto lb = [&](int k, int j) -> double {
-                    const int c = c0 + j;
-                    const bool ok = k < K && c < C;
-                    const double v = Te[ok ? (size_t)(kend + k) * C + c : (size_t)kend * C + nu];
-                    return ok ? v : 0.0;
-                };
-                mfma_32x32(la, lb, K, acc);
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
-                            const int c = c0 + 16 * bj + (lane & 15);
-                            if (r < kend && c < C) Te[(size_t)r * C + c] = acc[bi][bj][q];
-                        }
-            }
+            for (int j = 0; j < i; ++j) v -= blk[i][j] * x[j];
+            x[i] = v;
         }
-        // the panel's triangle of U into LDS, with the reciprocals of its diagonal in place of it
-        for (int idx = threadIdx.x; idx < nbk * nbk; idx += LBS) {
-            const int li = idx / nbk, c = idx - li * nbk;
-            const double v = Te[(size_t)(kb + li) * C + kb + c];
-            Pn[li * ldp + c] = li == c ? 1.0 / v : v;
+    } else {
+        // U x = e_t, U upper
+#pragma unroll
+        for (int i = 31; i >= 0; --i) {
+            double v = i == t ? 1.0 : 0.0;
+#pragma unroll
+            for (int j = i + 1; j < 32; ++j) v -= blk[i][j] * x[j];
+            x[i] = v / blk[i][i];
         }
-        __syncthreads();
-        // b. X_kb = U_kb^{-1} Y_kb, one thread per column
-        for (int cl = threadIdx.x; cl < ncx; cl += LBS) {
-            double* Tc = Te + (size_t)kb * C + nu + cl;
-            double u[NBT];
+    }
+    double* out = dinv + ((size_t)e * nkb + kb) * 2048 + (threadIdx.x < 32 ? 0 : 1024);
 #pragma unroll
-            for (int t = 0; t < NBT; ++t) u[t] = t < nbk ? Tc[(size_t)t * C] : 0.0;
+    for (int i = 0; i < 32; ++i) out[i * 32 + t] = x[i];
+}
+
+// Kernel 3: Y = U^{-1} L^{-1} P Y on the right-hand-side columns, one block per (element,
+// slab of sw <= 32 columns). LDS: the slab, nu rows x SLAB_LD.
+constexpr int SLAB_LD = 33;
+
+__global__ __launch_bounds__(256, 2) void k_cond_getrs(CondDims cd, long long nblk, int nsl, int sw,
+                                                       double* __restrict__ top, const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ dinv) {
+    extern __shared__ double Y[];
+    const long long Lb = xcd_linear(gridDim.x);
+    if (Lb >= nblk) return;
+    const long long e = Lb / nsl;
+    const int s = (int)(Lb - e * nsl);
+    const int nu = cd.nu, C = cd.C;
+    const int c0 = nu + s * sw;
+    const int ncs = (C - c0) < sw ? (C - c0) : sw;
+    double* Te = top + (size_t)e * nu * C;
+    const int32_t* pe = perm + (size_t)e * nu;
+    const int nkb = (nu + 31) / 32;
+    const double* De = dinv + (size_t)e * nkb * 2048;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the slab's rows in the interchanged order
+    for (int idx = threadIdx.x; idx < nu * 32; idx += 256) {
+        const int i = idx >> 5, j = idx & 31;
+        const bool ok = j < ncs;
+        const double v = Te[(size_t)pe[i] * C + c0 + (ok ? j : 0)];
+        Y[i * SLAB_LD + j] = ok ? v : 0.0;
+    }
+    __syncthreads();
+    // Y_kb <- inv(diagonal block) Y_kb, by one wave (a 32 x 32 x 32 product)
+    auto diag = [&](int kb, int which) {
+        const int r0 = kb * 32;
+        const int rb = (nu - r0) < 32 ? (nu - r0) : 32;
+        const double* Di = De + (size_t)kb * 2048 + which * 1024;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        auto la = [&](int i, int k) -> double {
+            const bool ok = k < 32;
+            const double v = Di[i * 32 + (ok ? k : 0)];
+            return ok ? v : 0.0;
+        };
+        auto lb = [&](int k, int j) -> double {
+            const bool ok = k < rb;
+            const double v = Y[(r0 + (ok ? k : 0)) * SLAB_LD + j];
+            return ok ? v : 0.0;
+        };
+        mfma_32x32(la, lb, 32, acc);
+        wave_lds_sync();
 #pragma unroll
-            for (int t = NBT - 1; t >= 0; --t) {
-                if (t < nbk) {
-                    double v = u[t];
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                    for (int q = t + 1; q < NBT; ++q)
-                        if (q < nbk) v -= Pn[t * ldp + q] * u[q];
-                    u[t] = v * Pn[t * ldp + t];
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 16 * bi + 4 * q + (lane >> 4);
+                    const int c = 16 * bj + (lane & 15);
+                    if (r < rb) Y[(r0 + r) * SLAB_LD + c] = acc[bi][bj][q];
                 }
-            }
+    };
+    // Y_t -= A[rows of block t][columns of block kb] Y_kb (A = L below the diagonal, U above)
+    auto update = [&](int t, int kb) {
+        const int rr = t * 32, r0 = kb * 32;
+        const int rb = (nu - r0) < 32 ? (nu - r0) : 32;
+        double4_t acc[2][2];
 #pragma unroll
-            for (int t = 0; t < NBT; ++t)
-                if (t < nbk) Tc[(size_t)t * C] = u[t];
-        }
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = rr + 16 * bi + 4 * q + (lane >> 4);
+                    const int c = 16 * bj + (lane & 15);
+                    const bool ok = r < nu;
+                    const double v = Y[(ok ? r : 0) * SLAB_LD + c];
+                    acc[bi][bj][q] = ok ? v : 0.0;
+                }
+        auto la = [&](int i, int k) -> double {
+            const int r = rr + i;
+            const bool ok = r < nu && k < rb;
+            const double v = Te[ok ? (size_t)r * C + r0 + k : 0];
+            return ok ? -v : 0.0;
+        };
+        auto lb = [&](int k, int j) -> double {
+            const bool ok = k < rb;
+            const double v = Y[(r0 + (ok ? k : 0)) * SLAB_LD + j];
+            return ok ? v : 0.0;
+        };
+        mfma_32x32(la, lb, rb, acc);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = rr + 16 * bi + 4 * q + (lane >> 4);
+                    const int c = 16 * bj + (lane & 15);
+                    if (r < nu) Y[r * SLAB_LD + c] = acc[bi][bj][q];
+                }
+    };
+    // forward: L (unit lower), 32-row blocks from the top
+    for (int kb = 0; kb < nkb; ++kb) {
+        if (wave == 0) diag(kb, 0);
+        __syncthreads();
+        for (int t = kb + 1 + wave; t < nkb; t += 4) update(t, kb);
         __syncthreads();
     }
-    if (sing && threadIdx.x == 0) atomicMin(bad_elem, e_off + (int)e);
+    // backward: U, 32-row blocks from the bottom
+    for (int kb = nkb - 1; kb >= 0; --kb) {
+        if (wave == 0) diag(kb, 1);
+        __syncthreads();
+        for (int t = wave; t < kb; t += 4) update(t, kb);
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < nu * 32; idx += 256) {
+        const int i = idx >> 5, j = idx & 31;
+        if (j < ncs) Te[(size_t)i * C + c0 + j] = Y[i * SLAB_LD + j];
+    }
+}
+
+// Kernel 3 for elements of NKB <= 6 blocks of 32 rows (nu <= 192): the same solve with one
+// wave per slab of 16 columns and the slab in the wave's registers, in the matrix cores'
+// accumulator layout (row 16 bi + 4 q + lane/16, column lane%16 of 32-row block t in
+// Y[t][bi][q]). That layout is also the B-operand layout of a product whose k runs as
+// 16 bi + 4 q + lane/16, so each product A Y_kb reads Y_kb where it lies: no LDS and no
+// barrier. The products (inverted diagonal block, or a block of -L / -U from T, times Y_kb)
+// run in a fixed order, and the A operands of the next two products are loaded while the
+// current one runs.
+struct SolveOp {
+    int kind;   // 0: Y_kb <- inv(L_kb) Y_kb, 1: Y_kb <- inv(U_kb) Y_kb, 2: Y_t -= T_t,kb Y_kb
+    int t, kb;
+};
+
+template <int NKB>
+struct SolvePlan {
+    static constexpr int N = NKB * (NKB + 1);
+    SolveOp op[N];
+    constexpr SolvePlan() : op() {
+        int n = 0;
+        for (int kb = 0; kb < NKB; ++kb) {
+            op[n++] = SolveOp{0, kb, kb};
+            for (int t = kb + 1; t < NKB; ++t) op[n++] = SolveOp{2, t, kb};
+        }
+        for (int kb = NKB - 1; kb >= 0; --kb) {
+            op[n++] = SolveOp{1, kb, kb};
+            for (int t = 0; t < kb; ++t) op[n++] = SolveOp{2, t, kb};
+        }
+    }
+};
+
+constexpr int SLAB_W = 16;   // columns per wave
+
+template <int NKB>
+__global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nslab, int nsl, int sw,
+                                                     double* __restrict__ top, const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ dinv) {
+    const long long Lb = xcd_linear(gridDim.x);
+    if (Lb >= nslab) return;
+    const long long e = Lb / nsl;
+    const int s = (int)(Lb - e * nsl);
+    const int nu = cd.nu, C = cd.C;
+    const int c0 = nu + s * sw;
+    const int ncs = (C - c0) < sw ? (C - c0) : sw;
+    double* Te = top + (size_t)e * nu * C;
+    const int32_t* pe = perm + (size_t)e * nu;
+    const double* De = dinv + (size_t)e * NKB * 2048;
+    const int lane = threadIdx.x & 63, i16 = lane & 15, kq = lane >> 4;
+    double4_t Y[NKB][2];
+    // the slab's rows in the interchanged order
+#pragma unroll
+    for (int t = 0; t < NKB; ++t)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 32 * t + 16 * bi + 4 * q + kq;
+                const bool ok = r < nu && i16 < ncs;
+                const int pr = pe[r < nu ? r : 0];
+                const double v = Te[(size_t)(ok ? pr : 0) * C + c0 + (ok ? i16 : 0)];
+                Y[t][bi][q] = ok ? v : 0.0;
+            }
+    // A operand of a product: lane (i16, kq) holds A[16 ai + i16][16 bi + 4 q + kq]
+    auto load_a = [&](const SolveOp& o, double (&a)[2][4][2]) {
+        if (o.kind < 2) {
+            const double* Di = De + (size_t)o.kb * 2048 + o.kind * 1024;
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int ai = 0; ai < 2; ++ai) a[bi][q][ai] = Di[(16 * ai + i16) * 32 + 16 * bi + 4 * q + kq];
+        } else {
+            const int rr = 32 * o.t, r0 = 32 * o.kb;
+            const int rb = (nu - r0) < 32 ? (nu - r0) : 32;
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int ai = 0; ai < 2; ++ai) {
+                        const int r = rr + 16 * ai + i16, k = 16 * bi + 4 * q + kq;
+                        const bool ok = r < nu && k < rb;
+                        const double v = Te[ok ? (size_t)r * C + r0 + k : 0];
+                        a[bi][q][ai] = ok ? -v : 0.0;
+                    }
+        }
+    };
+    // out += A B, B (32 x 16) in the accumulator layout
+    auto mma = [&](double4_t (&out)[2], const double (&a)[2][4][2], const double4_t (&B)[2]) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int ai = 0; ai < 2; ++ai)
+                    out[ai] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi][q][ai], B[bi][q], out[ai], 0, 0, 0);
+    };
+    constexpr SolvePlan<NKB> plan;
+    // operands of the current product and of the next two (loads two products ahead)
+    double acur[2][4][2], anx[2][4][2], anx2[2][4][2];
+    load_a(plan.op[0], acur);
+    if (SolvePlan<NKB>::N > 1) load_a(plan.op[1 < SolvePlan<NKB>::N ? 1 : 0], anx);
+#pragma unroll
+    for (int i = 0; i < SolvePlan<NKB>::N; ++i) {
+        if (i + 2 < SolvePlan<NKB>::N) load_a(plan.op[i + 2 < SolvePlan<NKB>::N ? i + 2 : 0], anx2);
+        __builtin_amdgcn_sched_barrier(0);
+        const SolveOp o = plan.op[i];
+        if (o.kind == 2) {
+            mma(Y[o.t], acur, Y[o.kb]);
+        } else {
+            double4_t nw[2] = {double4_t{0.0, 0.0, 0.0, 0.0}, double4_t{0.0, 0.0, 0.0, 0.0}};
+            mma(nw, acur, Y[o.kb]);
+            Y[o.kb][0] = nw[0];
+            Y[o.kb][1] = nw[1];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int ai = 0; ai < 2; ++ai) {
+                    acur[bi][q][ai] = anx[bi][q][ai];
+                    anx[bi][q][ai] = anx2[bi][q][ai];
+                }
+    }
+#pragma unroll
+    for (int t = 0; t < NKB; ++t)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 32 * t + 16 * bi + 4 * q + kq;
+                if (r < nu && i16 < ncs) Te[(size_t)r * C + c0 + i16] = Y[t][bi][q];
+            }
 }
 
 // ---- Kbar = Jbar - Hbar X, rbar = r_t - Hbar x_r   per (element, 64x64 tile) ----------------
@@ -889,8 +1226,8 @@ __global__ __launch_bounds__(BS) void k_copy_hbar(CondDims cd, const double* __r
 // Right-hand side of the condensation for a new (r_u, r_t) with the factors a previous
 // elimination of the same element matrices left (the stages of a DIRK step solve systems
 // with the same matrix and new right-hand sides, Section 2.2):
-//     c = L^{-1} P r_u   panel by panel as the elimination went (the panel's interchanges,
-//                         its unit lower triangle, then its multipliers below it),
+//     c = L^{-1} P r_u   (all interchanges in order, then the unit lower L by blocks of NB
+//                         rows: the block's triangle, then its multipliers below it),
 //     x_r = U^{-1} c,    rbar = r_t - Hbar x_r.
 // x_r replaces the last column of `local` (recovery reads it). One block per element, the
 // vector in LDS.
@@ -899,7 +1236,6 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
                                                  const double* __restrict__ ru, const double* __restrict__ rt,
                                                  double* __restrict__ rbar) {
     extern __shared__ double y[];          // nu
-    __shared__ int sp[64];
     const long long e = blockIdx.x;
     const int nu = cd.nu, nt = cd.nt, C = cd.C;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -907,21 +1243,21 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
     const int32_t* pv = ipiv + (size_t)e * nu;
     for (int i = threadIdx.x; i < nu; i += BS) y[i] = ru[(size_t)e * nu + i];
     __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int kk = 0; kk < nu; ++kk) {
+            const int p = pv[kk];
+            if (p != kk) {
+                const double a = y[kk];
+                y[kk] = y[p];
+                y[p] = a;
+            }
+        }
+    }
+    __syncthreads();
     for (int k0 = 0; k0 < nu; k0 += NB) {
         const int nbk = (nu - k0) < NB ? (nu - k0) : NB;
         if (wave == 0) {
-            if (lane < nbk) sp[lane] = pv[k0 + lane];
-            if (lane == 0) {
-                for (int t = 0; t < nbk; ++t) {
-                    const int kk = k0 + t, p = sp[t];
-                    if (p != kk) {
-                        const double a = y[kk];
-                        y[kk] = y[p];
-                        y[p] = a;
-                    }
-                }
-            }
-            // the panel's unit lower triangle: lane t holds y[k0+t]
+            // the block's unit lower triangle: lane t holds y[k0+t]
             double yt = lane < nbk ? y[k0 + lane] : 0.0;
             for (int kk = 0; kk + 1 < nbk; ++kk) {
                 const bool below = lane > kk && lane < nbk;
@@ -932,7 +1268,7 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
             if (lane < nbk) y[k0 + lane] = yt;
         }
         __syncthreads();
-        // rows below the panel
+        // rows below the block
         for (int i = k0 + nbk + threadIdx.x; i < nu; i += BS) {
             const double* li = Te + (size_t)i * C + k0;
             double acc = 0.0;
@@ -968,40 +1304,62 @@ __global__ __launch_bounds__(BS) void k_cond_rhs(CondDims cd, int NB, double* __
 }
 
 size_t lu_lds_bytes(const CondDims& cd, int NB) {
-    return sizeof(double) * (size_t)cd.nu * (NB + 1) + sizeof(int) * ((size_t)cd.nu + 2 * 64);
+    return sizeof(double) * (size_t)cd.nu * (NB + 1) + sizeof(int) * (3 * (size_t)cd.nu + 2 * 64);
 }
 
-// Panel width of the elimination: all nu columns when nu <= 64 and the panel fits in LDS,
-// else 32, 16 or 8 columns; 0 when even 8 does not fit.
+// LDS of the right-hand-side solve: one slab of the element's nu rows
+size_t getrs_lds_bytes(const CondDims& cd) { return sizeof(double) * (size_t)cd.nu * SLAB_LD; }
+
+// Workspace of the elimination per element: the inverted diagonal blocks, perm and ipiv.
+size_t lu_ws_bytes_per_elem(const CondDims& cd) {
+    const size_t nkb = (cd.nu + 31) / 32;
+    return sizeof(double) * nkb * 2048 + 2 * sizeof(int32_t) * cd.nu;
+}
+
+// Panel width of the factorisation: all nu columns when nu <= 32 (one panel), else 16 (8 when
+// the panel does not fit in LDS); 0 when even 8 does not fit or a slab of the right-hand-side
+// solve does not. (Measured on the 192-unknown elasticity elements: panels of 16 factorised in
+// registers condense in 90 ms, of 32 in registers in 94 ms, of 16 / 32 in LDS in 92 / 98 ms;
+// on the 50-unknown Navier-Stokes tets, panels of 16 on 256 threads in 112 ms where one panel
+// of 50 on 128 threads took 203 ms.)
 int pick_panel(const CondDims& cd) {
     const size_t lds_cap = 150 * 1024;
-    const int cands[4] = {cd.nu, 32, 16, 8};
-    for (int k = 0; k < 4; ++k) {
-        const int nb = cands[k] < cd.nu ? cands[k] : cd.nu;
-        if (nb <= 64 && lu_lds_bytes(cd, nb) <= lds_cap) return nb;
-    }
+    if (getrs_lds_bytes(cd) > lds_cap) return 0;
+    if (cd.nu <= 32) return cd.nu;
+    if (lu_lds_bytes(cd, 16) <= lds_cap) return 16;
+    if (lu_lds_bytes(cd, 8) <= lds_cap) return 8;
     return 0;
 }
 
-// Threads of the elimination kernel: 128 when Ebar is one panel (nu <= 64: more elements in
+// Threads of the factorisation kernel: 128 when Ebar is one panel (nu <= 32: more elements in
 // flight per CU), else 256 (four waves share the trailing updates while several elements
 // share a CU: the panel of one element is factorised while others run on the matrix cores).
-const void* lu_kernel(const CondDims& cd, int NB, int* threads) {
+// Panels of at most 256 rows are factorised in one wave's registers (at most four rows per
+// lane), larger ones in LDS.
+const void* getrf_kernel(const CondDims& cd, int NB, int* threads) {
     if (NB >= cd.nu) {
         *threads = 128;
-        return NB <= 16 ? (const void*)k_cond_lu<16, 128> : NB <= 32 ? (const void*)k_cond_lu<32, 128>
-                                                                     : (const void*)k_cond_lu<64, 128>;
+        return NB <= 16 ? (const void*)k_cond_getrf<16, 128, 1> : (const void*)k_cond_getrf<32, 128, 1>;
     }
     *threads = 256;
-    return NB <= 16 ? (const void*)k_cond_lu<16, 256> : (const void*)k_cond_lu<32, 256>;
+    switch ((cd.nu + 63) / 64) {
+        case 1: return (const void*)k_cond_getrf<16, 256, 1>;
+        case 2: return (const void*)k_cond_getrf<16, 256, 2>;
+        case 3: return (const void*)k_cond_getrf<16, 256, 3>;
+        case 4: return (const void*)k_cond_getrf<16, 256, 4>;
+        default: return (const void*)k_cond_getrf<16, 256, 0>;
+    }
 }
 
 hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
     const size_t lds = lu_lds_bytes(cd, NB);
     int threads = 0;
-    const void* lu_fn = lu_kernel(cd, NB, &threads);
+    const void* lu_fn = getrf_kernel(cd, NB, &threads);
     if (lds > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (getrs_lds_bytes(cd) > 64 * 1024)
+        HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_getrs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)getrs_lds_bytes(cd)));
     HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_qelim, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)GEMM_LDS));
     HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1010,20 +1368,54 @@ hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
 }
 
 // Stages 2 and 3 on n elements whose matrices T are in place (top rows at `top`, row stride
-// cd.C, trace rows at `bot`): LU of Ebar and X = Ebar^{-1}[Fbar | r_u] on the top rows, then
-// the Schur product into Kout [n][nt][nt] and rout [n][nt]. A zero pivot records e_off +
-// element in status. ipiv (optional, [n][nu]) receives the row interchanges; keep = 1 also
-// leaves the Ebar multipliers below the diagonal of the top rows.
+// cd.C, trace rows at `bot`): LU of Ebar (L and U left in the first nu columns of the top
+// rows) and X = Ebar^{-1}[Fbar | r_u] in their other columns, then the Schur product into
+// Kout [n][nt][nt] and rout [n][nt]. A zero pivot records e_off + element in status. ipiv
+// (optional, [n][nu]) receives the row interchanges; without it they go to the workspace.
 hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t n, double* top, double* bot,
-                               double* Kout, double* rout, int* status, int64_t e_off, int32_t* ipiv = nullptr,
-                               int keep = 0) {
+                               double* Kout, double* rout, int* status, int64_t e_off, int32_t* ipiv = nullptr) {
+    hdg_status st;
+    const int nkb = (cd.nu + 31) / 32;
+    double* dinv = (double*)ws_get(ctx, WS_LU, lu_ws_bytes_per_elem(cd) * (size_t)n, &st);
+    if (!dinv) return st;
+    int32_t* perm = (int32_t*)(dinv + (size_t)n * nkb * 2048);
+    int32_t* ipw = ipiv ? ipiv : perm + (size_t)n * cd.nu;
     const size_t lds = lu_lds_bytes(cd, NB);
     int threads = 0;
-    const void* lu_fn = lu_kernel(cd, NB, &threads);
+    const void* lu_fn = getrf_kernel(cd, NB, &threads);
     int e_off_i = (int)e_off;
-    void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&status, (void*)&e_off_i, (void*)&ipiv, (void*)&keep};
+    void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&status, (void*)&e_off_i, (void*)&ipw, (void*)&perm};
     HDG_HIP_CHECK(ctx, hipLaunchKernel(lu_fn, dim3((unsigned)n), dim3(threads), args, lds, ctx->stream));
     HDG_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_cond_trinv, dim3((unsigned)(n * nkb)), dim3(64), 0, ctx->stream, cd, (const double*)top,
+                       dinv);
+    HDG_LAUNCH_CHECK(ctx);
+    {
+        // slabs of at most 16 (one wave, registers) or 32 (one block, LDS) columns, balanced,
+        // none empty
+        const int nkb_ = (cd.nu + 31) / 32;
+        const int wmax = nkb_ <= 6 ? SLAB_W : 32;
+        const int ncx = cd.C - cd.nu;
+        const int sw = div_up(ncx, div_up(ncx, wmax));
+        const int nsl = div_up(ncx, sw);
+        const long long nslab = (long long)n * nsl;
+        const long long grid = (nslab + 7) / 8 * 8;
+        if (nkb_ <= 6) {
+            // one wave per slab, the slab in registers
+            const void* fns[6] = {(const void*)k_cond_getrs_w<1>, (const void*)k_cond_getrs_w<2>,
+                                  (const void*)k_cond_getrs_w<3>, (const void*)k_cond_getrs_w<4>,
+                                  (const void*)k_cond_getrs_w<5>, (const void*)k_cond_getrs_w<6>};
+            const void* fn = fns[nkb_ - 1];
+            const int32_t* pc = perm;
+            const double* dc = dinv;
+            void* a2[] = {(void*)&cd, (void*)&nslab, (void*)&nsl, (void*)&sw, (void*)&top, (void*)&pc, (void*)&dc};
+            HDG_HIP_CHECK(ctx, hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), a2, 0, ctx->stream));
+        } else {
+            hipLaunchKernelGGL(k_cond_getrs, dim3((unsigned)grid), dim3(BS), getrs_lds_bytes(cd), ctx->stream, cd,
+                               nslab, nsl, sw, top, (const int32_t*)perm, (const double*)dinv);
+        }
+        HDG_LAUNCH_CHECK(ctx);
+    }
     const int tm_n = div_up(cd.nt, GT);
     const long long ntile = (long long)n * tm_n * tm_n;
     const long long nblk = (ntile + 7) / 8 * 8;
@@ -1101,7 +1493,7 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
         return HDG_ERR_SHAPE;
     }
     // chunk elements so the workspace stays bounded (about 4 GiB)
-    const size_t per_elem = sizeof(double) * ((size_t)cd.nt * cd.C + (size_t)cd.KD * cd.NW);
+    const size_t per_elem = sizeof(double) * ((size_t)cd.nt * cd.C + (size_t)cd.KD * cd.NW) + lu_ws_bytes_per_elem(cd);
     int64_t chunk = (int64_t)((size_t)4 << 30) / (int64_t)per_elem;
     if (chunk < 1) chunk = 1;
     if (chunk > ne) chunk = ne;
@@ -1134,8 +1526,7 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
         }
         const bool keep = Hbar_out != nullptr;
         if ((st = eliminate_and_schur(ctx, cd, NB, n, local + e0 * cd.nu * cd.C, bot, Kbar + e0 * cd.nt * cd.nt,
-                                      rbar + e0 * cd.nt, status, e0, keep ? ipiv + e0 * cd.nu : nullptr,
-                                      keep ? 1 : 0)) != HDG_OK)
+                                      rbar + e0 * cd.nt, status, e0, keep ? ipiv + e0 * cd.nu : nullptr)) != HDG_OK)
             return st;
         if (keep) {
             hipLaunchKernelGGL(k_copy_hbar, dim3((unsigned)n), dim3(BS), 0, ctx->stream, cd, bot,
@@ -1169,7 +1560,7 @@ hdg_status asm_setup_run(hdg_ctx ctx, const hdg_dims* d, const double* Kbar, con
         return HDG_ERR_SHAPE;
     }
     const size_t per_elem = sizeof(double) * ((size_t)2 * cd.nt * cd.C + (size_t)cd.nt * cd.nt + cd.nt);
-    int64_t chunk = (int64_t)((size_t)4 << 30) / (int64_t)per_elem;
+    int64_t chunk = (int64_t)((size_t)4 << 30) / (int64_t)(per_elem + lu_ws_bytes_per_elem(cd));
     if (chunk < 1) chunk = 1;
     if (chunk > ne) chunk = ne;
     hdg_status st;

@@ -60,6 +60,38 @@ def test_condense_keep_leaves_the_condensation_unchanged(ctx, name):
     assert ((ip >= np.arange(nu)[None, :]) & (ip < nu)).all()
 
 
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2"])
+def test_kept_factors_reproduce_ebar(ctx, name):
+    """The factors left in `local` are those of partial pivoting in LAPACK's form: with P the
+    interchanges of ipiv applied in order, P Ebar = L U, where Ebar = E - D A^{-1} B is formed
+    here from the oracle's dense local matrices (Section 4.1 eq. w15-w19); every multiplier is at
+    most 1 in modulus."""
+    import oracle
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, out = case_data(name)
+    say("factors", name)
+    d = pb.dims()
+    pl = Pipeline(ctx, d, pb.mesh.f2e, pb.mesh.e2f)
+    pl.condense(to_dev(out["blk"]), keep=True)
+    torch.cuda.synchronize()
+    nu = pl.nu
+    loc = pl.local[:, :, :nu].cpu().numpy()
+    ip = pl.ipiv.cpu().numpy()
+    worst = 0.0
+    for e in range(min(d["ne"], 12)):
+        A, Bm, _ = oracle.condense.full_local(out["blk"], e, d)
+        Eb = out["blk"]["E"][e] - out["blk"]["D"][e] @ np.linalg.solve(A, Bm)
+        PE = Eb.copy()
+        for k in range(nu):
+            PE[[k, ip[e, k]]] = PE[[ip[e, k], k]]
+        Lm = np.tril(loc[e], -1) + np.eye(nu)
+        Um = np.triu(loc[e])
+        assert np.abs(np.tril(loc[e], -1)).max() <= 1.0 + 1e-14
+        worst = max(worst, np.abs(Lm @ Um - PE).max() / np.abs(Eb).max())
+    say("  max |LU - P Ebar| / max |Ebar|", worst)
+    assert worst < 1e-12, worst
+
+
 @pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4"])
 def test_condense_rhs_matches_oracle(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
