@@ -1021,9 +1021,9 @@ __global__ __launch_bounds__(256, 2) void k_cond_getrs(CondDims cd, long long nb
 // accumulator layout (row 16 bi + 4 q + lane/16, column lane%16 of 32-row block t in
 // Y[t][bi][q]). That layout is also the B-operand layout of a product whose k runs as
 // 16 bi + 4 q + lane/16, so each product A Y_kb reads Y_kb where it lies: no LDS and no
-// barrier. The products (inverted diagonal block, or a block of -L / -U from T, times Y_kb)
-// run in a fixed order, and the A operands of the next two products are loaded while the
-// current one runs.
+// barrier. The products (inverted diagonal block times Y_kb, or a block of L / U from T
+// times -Y_kb) run in a fixed order, and the A operands of the next two products are loaded
+// while the current one runs.
 struct SolveOp {
     int kind;   // 0: Y_kb <- inv(L_kb) Y_kb, 1: Y_kb <- inv(U_kb) Y_kb, 2: Y_t -= T_t,kb Y_kb
     int t, kb;
@@ -1048,7 +1048,11 @@ struct SolvePlan {
 
 constexpr int SLAB_W = 16;   // columns per wave
 
-template <int NKB>
+// FULL: nu is a multiple of 32 (no partial block: no clamped indices or masks). Every load is
+// unconditional (indices clamped into the element, masked values multiplied by 0) and
+// addressed by a 32-bit offset from the element's base, so the unrolled sequence needs no
+// branches and no 64-bit address arithmetic.
+template <int NKB, bool FULL>
 __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nslab, int nsl, int sw,
                                                      double* __restrict__ top, const int32_t* __restrict__ perm,
                                                      const double* __restrict__ dinv) {
@@ -1059,10 +1063,12 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
     const int nu = cd.nu, C = cd.C;
     const int c0 = nu + s * sw;
     const int ncs = (C - c0) < sw ? (C - c0) : sw;
-    double* Te = top + (size_t)e * nu * C;
-    const int32_t* pe = perm + (size_t)e * nu;
-    const double* De = dinv + (size_t)e * NKB * 2048;
+    double* __restrict__ Te = top + (size_t)e * nu * C;
+    const int32_t* __restrict__ pe = perm + (size_t)e * nu;
+    const double* __restrict__ De = dinv + (size_t)e * NKB * 2048;
     const int lane = threadIdx.x & 63, i16 = lane & 15, kq = lane >> 4;
+    const int cc = i16 < ncs ? i16 : ncs - 1;
+    const double cmask = i16 < ncs ? 1.0 : 0.0;
     double4_t Y[NKB][2];
     // the slab's rows in the interchanged order
 #pragma unroll
@@ -1072,35 +1078,42 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = 32 * t + 16 * bi + 4 * q + kq;
-                const bool ok = r < nu && i16 < ncs;
-                const int pr = pe[r < nu ? r : 0];
-                const double v = Te[(size_t)(ok ? pr : 0) * C + c0 + (ok ? i16 : 0)];
-                Y[t][bi][q] = ok ? v : 0.0;
+                const int rc = FULL ? r : (r < nu ? r : nu - 1);
+                const int pr = pe[rc];
+                const double v = Te[pr * C + c0 + cc];
+                Y[t][bi][q] = v * (FULL || r < nu ? cmask : 0.0);
             }
     // A operand of a product: lane (i16, kq) holds A[16 ai + i16][16 bi + 4 q + kq]
     auto load_a = [&](const SolveOp& o, double (&a)[2][4][2]) {
         if (o.kind < 2) {
-            const double* Di = De + (size_t)o.kb * 2048 + o.kind * 1024;
+            const double* __restrict__ Di = De + o.kb * 2048 + o.kind * 1024 + i16 * 32 + kq;
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int ai = 0; ai < 2; ++ai) a[bi][q][ai] = Di[(16 * ai + i16) * 32 + 16 * bi + 4 * q + kq];
+                    for (int ai = 0; ai < 2; ++ai) a[bi][q][ai] = Di[16 * ai * 32 + 16 * bi + 4 * q];
         } else {
             const int rr = 32 * o.t, r0 = 32 * o.kb;
-            const int rb = (nu - r0) < 32 ? (nu - r0) : 32;
+            const int rb = FULL ? 32 : ((nu - r0) < 32 ? (nu - r0) : 32);
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int ai = 0; ai < 2; ++ai) {
+                const int r = rr + 16 * ai + i16;
+                const int rc = FULL ? r : (r < nu ? r : nu - 1);
+                const double* __restrict__ row = Te + rc * C + r0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                    for (int ai = 0; ai < 2; ++ai) {
-                        const int r = rr + 16 * ai + i16, k = 16 * bi + 4 * q + kq;
-                        const bool ok = r < nu && k < rb;
-                        const double v = Te[ok ? (size_t)r * C + r0 + k : 0];
-                        a[bi][q][ai] = ok ? -v : 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = 16 * bi + 4 * q + kq;
+                        if (FULL) {
+                            a[bi][q][ai] = row[k];
+                        } else {
+                            const double v = row[k < rb ? k : rb - 1];
+                            a[bi][q][ai] = v * ((r < nu && k < rb) ? 1.0 : 0.0);
+                        }
                     }
+            }
         }
     };
     // out += A B, B (32 x 16) in the accumulator layout
@@ -1114,6 +1127,7 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
                     out[ai] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi][q][ai], B[bi][q], out[ai], 0, 0, 0);
     };
     constexpr SolvePlan<NKB> plan;
+    double4_t nY[2];   // -Y_kb of the latest diagonal step
     // operands of the current product and of the next two (loads two products ahead)
     double acur[2][4][2], anx[2][4][2], anx2[2][4][2];
     load_a(plan.op[0], acur);
@@ -1124,12 +1138,14 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
         __builtin_amdgcn_sched_barrier(0);
         const SolveOp o = plan.op[i];
         if (o.kind == 2) {
-            mma(Y[o.t], acur, Y[o.kb]);
+            mma(Y[o.t], acur, nY);
         } else {
             double4_t nw[2] = {double4_t{0.0, 0.0, 0.0, 0.0}, double4_t{0.0, 0.0, 0.0, 0.0}};
             mma(nw, acur, Y[o.kb]);
             Y[o.kb][0] = nw[0];
             Y[o.kb][1] = nw[1];
+            nY[0] = -nw[0];   // the updates that follow subtract T Y_kb
+            nY[1] = -nw[1];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1149,7 +1165,7 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = 32 * t + 16 * bi + 4 * q + kq;
-                if (r < nu && i16 < ncs) Te[(size_t)r * C + c0 + i16] = Y[t][bi][q];
+                if ((FULL || r < nu) && i16 < ncs) Te[r * C + c0 + i16] = Y[t][bi][q];
             }
 }
 
@@ -1402,10 +1418,14 @@ hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t 
         const long long grid = (nslab + 7) / 8 * 8;
         if (nkb_ <= 6) {
             // one wave per slab, the slab in registers
-            const void* fns[6] = {(const void*)k_cond_getrs_w<1>, (const void*)k_cond_getrs_w<2>,
-                                  (const void*)k_cond_getrs_w<3>, (const void*)k_cond_getrs_w<4>,
-                                  (const void*)k_cond_getrs_w<5>, (const void*)k_cond_getrs_w<6>};
-            const void* fn = fns[nkb_ - 1];
+            const void* fns[2][6] = {
+                {(const void*)k_cond_getrs_w<1, false>, (const void*)k_cond_getrs_w<2, false>,
+                 (const void*)k_cond_getrs_w<3, false>, (const void*)k_cond_getrs_w<4, false>,
+                 (const void*)k_cond_getrs_w<5, false>, (const void*)k_cond_getrs_w<6, false>},
+                {(const void*)k_cond_getrs_w<1, true>, (const void*)k_cond_getrs_w<2, true>,
+                 (const void*)k_cond_getrs_w<3, true>, (const void*)k_cond_getrs_w<4, true>,
+                 (const void*)k_cond_getrs_w<5, true>, (const void*)k_cond_getrs_w<6, true>}};
+            const void* fn = fns[cd.nu % 32 == 0 ? 1 : 0][nkb_ - 1];
             const int32_t* pc = perm;
             const double* dc = dinv;
             void* a2[] = {(void*)&cd, (void*)&nslab, (void*)&nsl, (void*)&sw, (void*)&top, (void*)&pc, (void*)&dc};
