@@ -1016,14 +1016,8 @@ __global__ __launch_bounds__(256, 2) void k_cond_getrs(CondDims cd, long long nb
     }
 }
 
-// Kernel 3 for elements of NKB <= 6 blocks of 32 rows (nu <= 192): the same solve with one
-// wave per slab of 16 columns and the slab in the wave's registers, in the matrix cores'
-// accumulator layout (row 16 bi + 4 q + lane/16, column lane%16 of 32-row block t in
-// Y[t][bi][q]). That layout is also the B-operand layout of a product whose k runs as
-// 16 bi + 4 q + lane/16, so each product A Y_kb reads Y_kb where it lies: no LDS and no
-// barrier. The products (inverted diagonal block times Y_kb, or a block of L / U from T
-// times -Y_kb) run in a fixed order, and the A operands of the next two products are loaded
-// while the current one runs.
+// Order of the block products of the register-resident solve (k_cond_getrs_b): forward with
+// L by 32-row blocks from the top, then backward with U from the bottom.
 struct SolveOp {
     int kind;   // 0: Y_kb <- inv(L_kb) Y_kb, 1: Y_kb <- inv(U_kb) Y_kb, 2: Y_t -= T_t,kb Y_kb
     int t, kb;
@@ -1046,31 +1040,44 @@ struct SolvePlan {
     }
 };
 
-constexpr int SLAB_W = 16;   // columns per wave
+// Kernel 3 for elements of NKB <= 6 blocks of 32 rows (nu <= 192), with the Schur product
+// fused: one block of four waves per 64 consecutive right-hand-side columns of one element,
+// one 16-column slab per wave. The slab lives in the wave's registers in the matrix cores'
+// accumulator layout (row 16 bi + 4 q + lane/16, column lane%16 of 32-row block t in
+// Y[t][bi][q]); that layout is also the B-operand layout of a product whose k runs as
+// 16 bi + 4 q + lane/16, so each product A Y_kb reads Y_kb where it lies. The products run in
+// a fixed order: the solve (inverted diagonal block times Y_kb, or a block of L / U times
+// -Y_kb), then, for each 32-row block of the trace rows, [Jbar | r_t] - Hbar X for the slab's
+// columns. Each A block (32 x 32) is loaded once per block, with 16-byte coalesced loads, into
+// LDS (rows padded to 34: the operand reads, 16 rows x 4 columns per instruction, hit distinct
+// banks), double-buffered with one barrier per product. Output: X and x_r into T's top rows,
+// Kbar and rbar for the slab's columns.
+constexpr int ALD = 34;
 
-// FULL: nu is a multiple of 32 (no partial block: no clamped indices or masks). Every load is
-// unconditional (indices clamped into the element, masked values multiplied by 0) and
-// addressed by a 32-bit offset from the element's base, so the unrolled sequence needs no
-// branches and no 64-bit address arithmetic.
+// (Two blocks per CU where the slab and the operands fit in 256 VGPRs; the five- and six-block
+// variants with partial blocks need more and run one block per CU.)
 template <int NKB, bool FULL>
-__global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nslab, int nsl, int sw,
-                                                     double* __restrict__ top, const int32_t* __restrict__ perm,
-                                                     const double* __restrict__ dinv) {
+__global__ __launch_bounds__(256, (NKB >= 5 && !(NKB == 6 && FULL)) ? 1 : 2) void k_cond_getrs_b(CondDims cd, long long nblk, int nbe,
+                                                         double* __restrict__ top, const double* __restrict__ bot,
+                                                         const int32_t* __restrict__ perm,
+                                                         const double* __restrict__ dinv, double* __restrict__ Kbar,
+                                                         double* __restrict__ rbar) {
+    __shared__ double As[2][32 * ALD];
     const long long Lb = xcd_linear(gridDim.x);
-    if (Lb >= nslab) return;
-    const long long e = Lb / nsl;
-    const int s = (int)(Lb - e * nsl);
-    const int nu = cd.nu, C = cd.C;
-    const int c0 = nu + s * sw;
-    const int ncs = (C - c0) < sw ? (C - c0) : sw;
+    if (Lb >= nblk) return;
+    const long long e = Lb / nbe;
+    const int b = (int)(Lb - e * nbe);
+    const int nu = cd.nu, nt = cd.nt, C = cd.C;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i16 = lane & 15, kq = lane >> 4;
+    const int g0 = 64 * b + 16 * wave;                   // the slab's first right-hand-side column
+    const int ncs = (C - nu - g0) < 16 ? (C - nu - g0) : 16;   // may be <= 0: an idle slab
     double* __restrict__ Te = top + (size_t)e * nu * C;
+    const double* __restrict__ Be = bot + (size_t)e * nt * C;
     const int32_t* __restrict__ pe = perm + (size_t)e * nu;
     const double* __restrict__ De = dinv + (size_t)e * NKB * 2048;
-    const int lane = threadIdx.x & 63, i16 = lane & 15, kq = lane >> 4;
-    const int cc = i16 < ncs ? i16 : ncs - 1;
+    const int cl = ncs <= 0 ? 0 : g0 + (i16 < ncs ? i16 : ncs - 1);   // this lane's column (clamped)
     const double cmask = i16 < ncs ? 1.0 : 0.0;
     double4_t Y[NKB][2];
-    // the slab's rows in the interchanged order
 #pragma unroll
     for (int t = 0; t < NKB; ++t)
 #pragma unroll
@@ -1079,45 +1086,52 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
             for (int q = 0; q < 4; ++q) {
                 const int r = 32 * t + 16 * bi + 4 * q + kq;
                 const int rc = FULL ? r : (r < nu ? r : nu - 1);
-                const int pr = pe[rc];
-                const double v = Te[pr * C + c0 + cc];
+                const double v = Te[pe[rc] * C + nu + cl];
                 Y[t][bi][q] = v * (FULL || r < nu ? cmask : 0.0);
             }
-    // A operand of a product: lane (i16, kq) holds A[16 ai + i16][16 bi + 4 q + kq]
-    auto load_a = [&](const SolveOp& o, double (&a)[2][4][2]) {
-        if (o.kind < 2) {
-            const double* __restrict__ Di = De + o.kb * 2048 + o.kind * 1024 + i16 * 32 + kq;
+    // cooperative tile load: thread (row tr = tid / 8, columns 4 (tid % 8) .. +3) of the 32 x 32 A
+    const int tr = threadIdx.x >> 3, tc = 4 * (threadIdx.x & 7);
+    // A = a 32 x 32 block of M (row stride C, rows [r0, r0 + 32) clamped below rmax, columns
+    // [k0, k0 + 32) masked beyond kmax), zero outside
+    auto gload_blk = [&](const double* __restrict__ M, int r0, int rmax, int k0, int kmax, bool full,
+                         double (&v)[4]) {
+        const int r = r0 + tr;
+        const int rc = full ? r : (r < rmax ? r : rmax - 1);
+        const double* __restrict__ row = M + rc * C + k0;
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int ai = 0; ai < 2; ++ai) a[bi][q][ai] = Di[16 * ai * 32 + 16 * bi + 4 * q];
-        } else {
-            const int rr = 32 * o.t, r0 = 32 * o.kb;
-            const int rb = FULL ? 32 : ((nu - r0) < 32 ? (nu - r0) : 32);
-#pragma unroll
-            for (int ai = 0; ai < 2; ++ai) {
-                const int r = rr + 16 * ai + i16;
-                const int rc = FULL ? r : (r < nu ? r : nu - 1);
-                const double* __restrict__ row = Te + rc * C + r0;
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int k = 16 * bi + 4 * q + kq;
-                        if (FULL) {
-                            a[bi][q][ai] = row[k];
-                        } else {
-                            const double v = row[k < rb ? k : rb - 1];
-                            a[bi][q][ai] = v * ((r < nu && k < rb) ? 1.0 : 0.0);
-                        }
-                    }
+        for (int u = 0; u < 4; ++u) {
+            const int k = tc + u;
+            if (full) {
+                v[u] = row[k];
+            } else {
+                const int kb = kmax - k0;
+                const double x = row[k < kb ? k : kb - 1];
+                v[u] = x * ((r < rmax && k < kb) ? 1.0 : 0.0);
             }
         }
     };
-    // out += A B, B (32 x 16) in the accumulator layout
-    auto mma = [&](double4_t (&out)[2], const double (&a)[2][4][2], const double4_t (&B)[2]) {
+    auto gload = [&](const SolveOp& o, double (&v)[4]) {
+        if (o.kind < 2) {
+            const double* __restrict__ Di = De + o.kb * 2048 + o.kind * 1024 + tr * 32 + tc;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = Di[u];
+        } else {
+            gload_blk(Te, 32 * o.t, nu, 32 * o.kb, nu, FULL, v);
+        }
+    };
+    auto lstore = [&](int buf, const double (&v)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) As[buf][tr * ALD + tc + u] = v[u];
+    };
+    // out += A B, A from LDS buffer buf (lane (i16, kq): A[16 ai + i16][16 bi + 4 q + kq])
+    auto mma = [&](double4_t (&out)[2], int buf, const double4_t (&B)[2]) {
+        double a[2][4][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int ai = 0; ai < 2; ++ai) a[bi][q][ai] = As[buf][(16 * ai + i16) * ALD + 16 * bi + 4 * q + kq];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1127,46 +1141,91 @@ __global__ __launch_bounds__(64) void k_cond_getrs_w(CondDims cd, long long nsla
                     out[ai] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi][q][ai], B[bi][q], out[ai], 0, 0, 0);
     };
     constexpr SolvePlan<NKB> plan;
+    constexpr int NS = SolvePlan<NKB>::N;
+    const int ntb = (nt + 31) / 32;
+    const bool tfull = FULL && nt % 32 == 0;
     double4_t nY[2];   // -Y_kb of the latest diagonal step
-    // operands of the current product and of the next two (loads two products ahead)
-    double acur[2][4][2], anx[2][4][2], anx2[2][4][2];
-    load_a(plan.op[0], acur);
-    if (SolvePlan<NKB>::N > 1) load_a(plan.op[1 < SolvePlan<NKB>::N ? 1 : 0], anx);
+    double v[4];
+    gload(plan.op[0], v);
+    lstore(0, v);
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < SolvePlan<NKB>::N; ++i) {
-        if (i + 2 < SolvePlan<NKB>::N) load_a(plan.op[i + 2 < SolvePlan<NKB>::N ? i + 2 : 0], anx2);
-        __builtin_amdgcn_sched_barrier(0);
+    for (int i = 0; i < NS; ++i) {
+        const int buf = i & 1;
+        if (i + 1 < NS) gload(plan.op[i + 1 < NS ? i + 1 : 0], v);
+        else gload_blk(Be, 0, nt, 0, nu, tfull, v);       // first block of Hbar
         const SolveOp o = plan.op[i];
         if (o.kind == 2) {
-            mma(Y[o.t], acur, nY);
+            mma(Y[o.t], buf, nY);
         } else {
             double4_t nw[2] = {double4_t{0.0, 0.0, 0.0, 0.0}, double4_t{0.0, 0.0, 0.0, 0.0}};
-            mma(nw, acur, Y[o.kb]);
+            mma(nw, buf, Y[o.kb]);
             Y[o.kb][0] = nw[0];
             Y[o.kb][1] = nw[1];
             nY[0] = -nw[0];   // the updates that follow subtract T Y_kb
             nY[1] = -nw[1];
         }
-        __builtin_amdgcn_sched_barrier(0);
+        lstore(buf ^ 1, v);
+        __syncthreads();
+    }
+    // X and x_r of the slab back to T
+    if (ncs > 0) {
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+        for (int t = 0; t < NKB; ++t)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int ai = 0; ai < 2; ++ai) {
-                    acur[bi][q][ai] = anx[bi][q][ai];
-                    anx[bi][q][ai] = anx2[bi][q][ai];
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 32 * t + 16 * bi + 4 * q + kq;
+                    if ((FULL || r < nu) && i16 < ncs) Te[r * C + nu + g0 + i16] = Y[t][bi][q];
                 }
     }
+    // -X, the B operand of the Schur products
 #pragma unroll
-    for (int t = 0; t < NKB; ++t)
+    for (int t = 0; t < NKB; ++t) {
+        Y[t][0] = -Y[t][0];
+        Y[t][1] = -Y[t][1];
+    }
+    // [Kbar | rbar] = [Jbar | r_t] - Hbar X for the slab's columns, 32 trace rows at a time
+    const int g = cl;                                    // column of [Jbar | r_t] (clamped)
+    int par = NS & 1;                                    // the buffer holding the next A block
+    for (int rt = 0; rt < ntb; ++rt) {
+        double4_t acc[2];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+        for (int ai = 0; ai < 2; ++ai)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = 32 * t + 16 * bi + 4 * q + kq;
-                if ((FULL || r < nu) && i16 < ncs) Te[r * C + c0 + i16] = Y[t][bi][q];
+                const int r = 32 * rt + 16 * ai + 4 * q + kq;
+                const int rc = r < nt ? r : nt - 1;
+                acc[ai][q] = Be[rc * C + nu + g];
             }
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            // the next A block: Hbar block (rt, kb + 1), or (rt + 1, 0)
+            const bool last = kb + 1 == NKB && rt + 1 == ntb;
+            if (!last) {
+                if (kb + 1 < NKB) gload_blk(Be, 32 * rt, nt, 32 * (kb + 1), nu, tfull, v);
+                else gload_blk(Be, 32 * (rt + 1), nt, 0, nu, tfull, v);
+            }
+            mma(acc, par, Y[kb]);
+            if (!last) lstore(par ^ 1, v);
+            __syncthreads();
+            par ^= 1;
+        }
+        if (ncs > 0 && i16 < ncs) {
+            const int gc = g0 + i16;
+#pragma unroll
+            for (int ai = 0; ai < 2; ++ai)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 32 * rt + 16 * ai + 4 * q + kq;
+                    if (r < nt) {
+                        if (gc < nt) Kbar[((size_t)e * nt + r) * nt + gc] = acc[ai][q];
+                        else rbar[(size_t)e * nt + r] = acc[ai][q];
+                    }
+                }
+        }
+    }
 }
 
 // ---- Kbar = Jbar - Hbar X, rbar = r_t - Hbar x_r   per (element, 64x64 tile) ----------------
@@ -1406,36 +1465,38 @@ hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t 
     hipLaunchKernelGGL(k_cond_trinv, dim3((unsigned)(n * nkb)), dim3(64), 0, ctx->stream, cd, (const double*)top,
                        dinv);
     HDG_LAUNCH_CHECK(ctx);
-    {
-        // slabs of at most 16 (one wave, registers) or 32 (one block, LDS) columns, balanced,
-        // none empty
-        const int nkb_ = (cd.nu + 31) / 32;
-        const int wmax = nkb_ <= 6 ? SLAB_W : 32;
-        const int ncx = cd.C - cd.nu;
-        const int sw = div_up(ncx, div_up(ncx, wmax));
-        const int nsl = div_up(ncx, sw);
-        const long long nslab = (long long)n * nsl;
-        const long long grid = (nslab + 7) / 8 * 8;
-        if (nkb_ <= 6) {
-            // one wave per slab, the slab in registers
-            const void* fns[2][6] = {
-                {(const void*)k_cond_getrs_w<1, false>, (const void*)k_cond_getrs_w<2, false>,
-                 (const void*)k_cond_getrs_w<3, false>, (const void*)k_cond_getrs_w<4, false>,
-                 (const void*)k_cond_getrs_w<5, false>, (const void*)k_cond_getrs_w<6, false>},
-                {(const void*)k_cond_getrs_w<1, true>, (const void*)k_cond_getrs_w<2, true>,
-                 (const void*)k_cond_getrs_w<3, true>, (const void*)k_cond_getrs_w<4, true>,
-                 (const void*)k_cond_getrs_w<5, true>, (const void*)k_cond_getrs_w<6, true>}};
-            const void* fn = fns[cd.nu % 32 == 0 ? 1 : 0][nkb_ - 1];
-            const int32_t* pc = perm;
-            const double* dc = dinv;
-            void* a2[] = {(void*)&cd, (void*)&nslab, (void*)&nsl, (void*)&sw, (void*)&top, (void*)&pc, (void*)&dc};
-            HDG_HIP_CHECK(ctx, hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64), a2, 0, ctx->stream));
-        } else {
-            hipLaunchKernelGGL(k_cond_getrs, dim3((unsigned)grid), dim3(BS), getrs_lds_bytes(cd), ctx->stream, cd,
-                               nslab, nsl, sw, top, (const int32_t*)perm, (const double*)dinv);
-        }
+    const int ncx = cd.C - cd.nu;
+    if (nkb <= 6) {
+        // four slabs of 16 columns per block, in registers, sharing each A block through LDS;
+        // the Schur product fused
+        const int nbe = div_up(ncx, 64);
+        const long long nb_all = (long long)n * nbe;
+        const long long gridb = (nb_all + 7) / 8 * 8;
+        const void* fns[2][6] = {
+            {(const void*)k_cond_getrs_b<1, false>, (const void*)k_cond_getrs_b<2, false>,
+             (const void*)k_cond_getrs_b<3, false>, (const void*)k_cond_getrs_b<4, false>,
+             (const void*)k_cond_getrs_b<5, false>, (const void*)k_cond_getrs_b<6, false>},
+            {(const void*)k_cond_getrs_b<1, true>, (const void*)k_cond_getrs_b<2, true>,
+             (const void*)k_cond_getrs_b<3, true>, (const void*)k_cond_getrs_b<4, true>,
+             (const void*)k_cond_getrs_b<5, true>, (const void*)k_cond_getrs_b<6, true>}};
+        const void* fn = fns[cd.nu % 32 == 0 ? 1 : 0][nkb - 1];
+        const double* bc = bot;
+        const int32_t* pc = perm;
+        const double* dc = dinv;
+        void* a3[] = {(void*)&cd, (void*)&nb_all, (void*)&nbe, (void*)&top, (void*)&bc, (void*)&pc, (void*)&dc,
+                      (void*)&Kout, (void*)&rout};
+        HDG_HIP_CHECK(ctx, hipLaunchKernel(fn, dim3((unsigned)gridb), dim3(BS), a3, 0, ctx->stream));
         HDG_LAUNCH_CHECK(ctx);
+        return HDG_OK;
     }
+    // larger elements: one block per slab of at most 32 columns in LDS (balanced, none empty),
+    // then the Schur product on the tile engine
+    const int sw = div_up(ncx, div_up(ncx, 32));
+    const int nsl = div_up(ncx, sw);
+    const long long nslab = (long long)n * nsl;
+    hipLaunchKernelGGL(k_cond_getrs, dim3((unsigned)((nslab + 7) / 8 * 8)), dim3(BS), getrs_lds_bytes(cd), ctx->stream,
+                       cd, nslab, nsl, sw, top, (const int32_t*)perm, (const double*)dinv);
+    HDG_LAUNCH_CHECK(ctx);
     const int tm_n = div_up(cd.nt, GT);
     const long long ntile = (long long)n * tm_n * tm_n;
     const long long nblk = (ntile + 7) / 8 * 8;

@@ -188,12 +188,17 @@ def test_full_size_sampled(ctx, name):
         assert list(nbr_g[a]) == list(faces)
         blk0 = oasm._elem_block(Kfull, e1, l1, l1, d, None)
         rv = oasm._elem_vec(rfull, e1, l1, d, None)
+        rscale = np.abs(rv).max()
         if e2 >= 0:
             blk0 = blk0 + oasm._elem_block(Kfull, e2, l2, l2, d, None)
-            rv = rv + oasm._elem_vec(rfull, e2, l2, d, None)
+            rv2 = oasm._elem_vec(rfull, e2, l2, d, None)
+            rscale = max(rscale, np.abs(rv2).max())
+            rv = rv + rv2
         scale = np.abs(blk0).max()
         worst_k = max(worst_k, np.abs(K_g[a, 0].T - blk0).max() / scale)
-        worst_k = max(worst_k, np.abs(r_g[a] - rv).max() / max(np.abs(rv).max(), 1e-300))
+        # the face residual sums the two elements' contributions, which nearly cancel where the
+        # state is close to a steady one: its rounding is bounded relative to the contributions
+        worst_k = max(worst_k, np.abs(r_g[a] - rv).max() / max(rscale, 1e-300))
         row = blk0 @ x[f * nb:(f + 1) * nb]
         for s in range(1, len(faces)):
             if src[s] is None:
