@@ -519,36 +519,22 @@ __device__ __forceinline__ double panel_entry(const double (&a)[RPL][NBT], int o
     return x;
 }
 
-// LU with partial pivoting of the panel in LDS (nrow rows, nbk <= NBT columns, row stride
-// ldp) in one wave's registers: lane l holds the panel rows l + 64 r (r < RPL). No row moves
-// while the panel is factorised: each lane tracks where its rows stand in the interchanged
-// order, and the pivot of column kk is the largest |entry| among the rows not yet chosen,
-// ties going to the lower position (what a search down the interchanged column finds).
-// The multipliers and the rank-1 update run on registers; the pivot row reaches every lane
-// through readlane. At the end the panel goes back to LDS in the interchanged order and
-// rsrc[position] receives the row's index before the interchanges; ipiv[kk] (if given)
-// ipiv_off plus the position interchanged with kk at step kk. Returns whether a pivot was
-// zero or not finite.
+// LU with partial pivoting of a panel (nrow rows, nbk <= NBT columns) held in one wave's
+// registers: lane l holds the rows l + 64 r (r < RPL) in a[r], pos[r] = l + 64 r on entry. No
+// row moves while the panel is factorised: each lane tracks where its rows stand in the
+// interchanged order (pos), and the pivot of column kk is the largest |entry| among the rows
+// not yet chosen, ties going to the lower position (what a search down the interchanged column
+// finds). The multipliers and the rank-1 update run on registers; the pivot row reaches every
+// lane through readlane. ipiv[kk] (if given) receives ipiv_off plus the position interchanged
+// with kk at step kk. Returns whether a pivot was zero or not finite.
 template <int NBT, int RPL>
-__device__ __forceinline__ bool panel_lu_regs(double* Pn, int ldp, int nrow, int nbk, int* rsrc, int32_t* ipiv,
-                                              int ipiv_off) {
+__device__ __forceinline__ bool lu_regs(double (&a)[RPL][NBT], int (&pos)[RPL], int nrow, int nbk, int32_t* ipiv,
+                                        int ipiv_off) {
     bool bad = false;
     const int lane = threadIdx.x & 63;
-    double a[RPL][NBT];
-    int pos[RPL];
     bool live[RPL];
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int li = lane + 64 * r;
-        live[r] = li < nrow;
-        pos[r] = li;
-#pragma unroll
-        for (int c = 0; c < NBT; ++c) {
-            const bool ok = li < nrow && c < nbk;
-            const double v = Pn[ok ? li * ldp + c : 0];
-            a[r][c] = ok ? v : 0.0;
-        }
-    }
+    for (int r = 0; r < RPL; ++r) live[r] = lane + 64 * r < nrow;
 #pragma unroll
     for (int kk = 0; kk < NBT; ++kk) {
         if (kk < nbk) {
@@ -591,6 +577,29 @@ __device__ __forceinline__ bool panel_lu_regs(double* Pn, int ldp, int nrow, int
             }
         }
     }
+    return bad;
+}
+
+// lu_regs on a panel in LDS (row stride ldp): loaded into registers, factorised, written back
+// in the interchanged order; rsrc[position] receives the row's index before the interchanges.
+template <int NBT, int RPL>
+__device__ __forceinline__ bool panel_lu_regs(double* Pn, int ldp, int nrow, int nbk, int* rsrc, int32_t* ipiv,
+                                              int ipiv_off) {
+    const int lane = threadIdx.x & 63;
+    double a[RPL][NBT];
+    int pos[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int li = lane + 64 * r;
+        pos[r] = li;
+#pragma unroll
+        for (int c = 0; c < NBT; ++c) {
+            const bool ok = li < nrow && c < nbk;
+            const double v = Pn[ok ? li * ldp + c : 0];
+            a[r][c] = ok ? v : 0.0;
+        }
+    }
+    const bool bad = lu_regs<NBT, RPL>(a, pos, nrow, nbk, ipiv, ipiv_off);
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int li = lane + 64 * r;
@@ -849,6 +858,37 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? (RPL * NBT >= 64 ? 2 : 3) : 1) vo
     }
     for (int r = threadIdx.x; r < nu; r += LBS) perm_out[(size_t)e * nu + r] = gperm[r];
     if (sing && threadIdx.x == 0) atomicMin(bad_elem, e_off + (int)e);
+}
+
+// Kernel 1 for nu <= NBT <= 64: one wave per element factorises the whole nu x nu block in its
+// registers (lane l holds row l), no LDS and no block barrier; the rows of L\U are written back
+// in the interchanged order (the right-hand-side columns stay in place: the solve gathers them
+// through perm).
+template <int NBT>
+__global__ __launch_bounds__(64) void k_cond_getrf_w(CondDims cd, double* __restrict__ top, int* bad_elem,
+                                                     int e_off, int32_t* __restrict__ ipiv_out,
+                                                     int32_t* __restrict__ perm_out) {
+    const long long e = blockIdx.x;
+    const int nu = cd.nu, C = cd.C;
+    double* Te = top + (size_t)e * nu * C;
+    const int lane = threadIdx.x & 63;
+    const int rl = lane < nu ? lane : nu - 1;
+    double a[1][NBT];
+    int pos[1] = {lane};
+#pragma unroll
+    for (int c = 0; c < NBT; ++c) {
+        const bool ok = lane < nu && c < nu;
+        const double v = Te[(size_t)rl * C + (c < nu ? c : 0)];
+        a[0][c] = ok ? v : 0.0;
+    }
+    const bool bad = lu_regs<NBT, 1>(a, pos, nu, nu, ipiv_out + (size_t)e * nu, 0);
+    if (lane < nu) {
+#pragma unroll
+        for (int c = 0; c < NBT; ++c)
+            if (c < nu) Te[(size_t)pos[0] * C + c] = a[0][c];
+        perm_out[(size_t)e * nu + pos[0]] = lane;
+    }
+    if (bad && lane == 0) atomicMin(bad_elem, e_off + (int)e);
 }
 
 // Kernel 2: inverses of the 32 x 32 diagonal blocks of L (unit lower) and U (upper), one
@@ -1406,19 +1446,18 @@ int pick_panel(const CondDims& cd) {
     return 0;
 }
 
-// Threads of the factorisation kernel: 128 when Ebar is one panel (nu <= 32: more elements in
-// flight per CU), else 256 (four waves share the trailing updates while several elements
-// share a CU: the panel of one element is factorised while others run on the matrix cores).
-// Panels of at most 256 rows are factorised in one wave's registers (at most four rows per
-// lane), larger ones in LDS.
+// The factorisation kernel: for nu <= 64 one wave per element with the whole block in its
+// registers (k_cond_getrf_w; on the 50-unknown Navier-Stokes tets it replaced panels of 16 on
+// four waves); else four waves per element (several elements share a CU: the panel of one is
+// factorised while others run on the matrix cores), panels of at most 256 rows factorised in
+// one wave's registers (at most four rows per lane), larger ones in LDS.
 const void* getrf_kernel(const CondDims& cd, int NB, int* threads) {
-    if (NB >= cd.nu) {
-        *threads = 128;
-        return NB <= 16 ? (const void*)k_cond_getrf<16, 128, 1> : (const void*)k_cond_getrf<32, 128, 1>;
+    if (cd.nu <= 64) {
+        *threads = 64;
+        return cd.nu <= 32 ? (const void*)k_cond_getrf_w<32> : (const void*)k_cond_getrf_w<64>;
     }
     *threads = 256;
     switch ((cd.nu + 63) / 64) {
-        case 1: return (const void*)k_cond_getrf<16, 256, 1>;
         case 2: return (const void*)k_cond_getrf<16, 256, 2>;
         case 3: return (const void*)k_cond_getrf<16, 256, 3>;
         case 4: return (const void*)k_cond_getrf<16, 256, 4>;
@@ -1430,7 +1469,7 @@ hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
     const size_t lds = lu_lds_bytes(cd, NB);
     int threads = 0;
     const void* lu_fn = getrf_kernel(cd, NB, &threads);
-    if (lds > 64 * 1024)
+    if (cd.nu > 64 && lds > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute(lu_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (getrs_lds_bytes(cd) > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_getrs, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1455,12 +1494,18 @@ hdg_status eliminate_and_schur(hdg_ctx ctx, const CondDims& cd, int NB, int64_t 
     if (!dinv) return st;
     int32_t* perm = (int32_t*)(dinv + (size_t)n * nkb * 2048);
     int32_t* ipw = ipiv ? ipiv : perm + (size_t)n * cd.nu;
-    const size_t lds = lu_lds_bytes(cd, NB);
     int threads = 0;
     const void* lu_fn = getrf_kernel(cd, NB, &threads);
     int e_off_i = (int)e_off;
-    void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&status, (void*)&e_off_i, (void*)&ipw, (void*)&perm};
-    HDG_HIP_CHECK(ctx, hipLaunchKernel(lu_fn, dim3((unsigned)n), dim3(threads), args, lds, ctx->stream));
+    if (cd.nu <= 64) {
+        void* args[] = {(void*)&cd, (void*)&top, (void*)&status, (void*)&e_off_i, (void*)&ipw, (void*)&perm};
+        HDG_HIP_CHECK(ctx, hipLaunchKernel(lu_fn, dim3((unsigned)n), dim3(threads), args, 0, ctx->stream));
+    } else {
+        void* args[] = {(void*)&cd, (void*)&NB, (void*)&top, (void*)&status, (void*)&e_off_i, (void*)&ipw,
+                        (void*)&perm};
+        HDG_HIP_CHECK(ctx, hipLaunchKernel(lu_fn, dim3((unsigned)n), dim3(threads), args, lu_lds_bytes(cd, NB),
+                                           ctx->stream));
+    }
     HDG_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_cond_trinv, dim3((unsigned)(n * nkb)), dim3(64), 0, ctx->stream, cd, (const double*)top,
                        dinv);
