@@ -92,6 +92,24 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
 #pragma unroll
         for (int u = 0; u < U; ++u) m0[u] = __builtin_nontemporal_load(p + u * step);
     }
+    // second product (HAS_M2): thread (row row2, column group grp2 of G2) needs the entries
+    // Bf[k][row2], k = grp2 + j G2; the first K2 of them do not depend on x and are loaded
+    // here, so their latency overlaps the first product instead of following it
+    constexpr int K2 = 16;
+    const int G2 = HAS_M2 ? TEAM / nb : 1;
+    const int grp2 = HAS_M2 ? t / nb : 0;
+    const int row2 = t - grp2 * nb;
+    const bool act2 = HAS_M2 && valid && grp2 < G2;
+    T2 b2[HAS_M2 ? K2 : 1];
+    if (HAS_M2 && act2) {
+        const T2* Bf = static_cast<const T2*>(A.M2) + (size_t)f * nb * nb;
+#pragma unroll
+        for (int j = 0; j < K2; ++j) {
+            const int k = grp2 + j * G2;
+            const T2 b = Bf[(size_t)(k < nb ? k : grp2) * nb + row2];
+            b2[j] = k < nb ? b : T2(0);
+        }
+    }
     double ex[3], ey[3];
 #pragma unroll
     for (int o = 0; o < 3; ++o) ex[o] = ey[o] = 0.0;
@@ -160,16 +178,19 @@ __global__ __launch_bounds__(256) void k_face_op(FaceArgs A) {
         for (int g2 = 0; g2 < G; ++g2) u += redt[g2 * nb + t];
     }
     if (HAS_M2) {
-        // second product (one thread per row and column group, scalar loads)
-        const int G2 = TEAM / nb;
-        const int grp2 = t / nb;
-        const int row2 = t - grp2 * nb;
+        // second product (one thread per row and column group; entries from b2, the rest, if
+        // any, loaded here), k ascending as in a plain loop
         if (valid && t < nb) uf[t] = u;
         __syncthreads();
         double acc2 = 0.0;
-        if (valid && grp2 < G2) {
+        if (act2) {
+#pragma unroll
+            for (int j = 0; j < K2; ++j) {
+                const int k = grp2 + j * G2;
+                if (k < nb) acc2 += (double)b2[j] * uf[k];
+            }
             const T2* Bf = static_cast<const T2*>(A.M2) + (size_t)f * nb * nb;
-            for (int k = grp2; k < nb; k += G2) acc2 += (double)Bf[(size_t)k * nb + row2] * uf[k];
+            for (int k = grp2 + K2 * G2; k < nb; k += G2) acc2 += (double)Bf[(size_t)k * nb + row2] * uf[k];
         }
         redt[t] = acc2;
         __syncthreads();
