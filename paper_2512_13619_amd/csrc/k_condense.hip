@@ -309,50 +309,54 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
     const int nch = (KD + GK - 1) / GK;
     const int nall = M * nch;
     // staging roles: A rows m0 + (tid>>5) + 8u at depth k0 + (tid&31); B rows k0 + (tid>>6) + 4u at
-    // column n0 + (tid&63)
+    // column n0 + (tid&63). Rows of A past R and columns of B past NW are read at clamped addresses
+    // and left unmasked: they only reach rows and columns of the tile that are never stored. Depth
+    // past KD (a ragged last slice) reads clamped A and zeroed B, so those products vanish.
     const int ka = tid & 31, jb = tid & 63;
     const double* arow[8];
-    unsigned aokm = 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int r = m0 + (tid >> 5) + 8 * u;
-        aokm |= (r < R ? 1u : 0u) << u;
-        const int rr = r < R ? r : 0;
+        const int rr = r < R ? r : R - 1;
         arow[u] = rr < nu ? Dm + ((size_t)e * nu + rr) * nq : Gm + ((size_t)e * nt + (rr - nu)) * nq;
     }
-    const bool bok_c = n0 + jb < NW;
-    const double* bcol = We + (bok_c ? n0 + jb : 0);
+    const double* bcol = We + (n0 + jb < NW ? n0 + jb : NW - 1);
+    const bool ragged = (KD % GK) != 0;
     double ra[2][8], rb[2][8];
     int kst[2] = {0, 0};
-    // loads of stream chunk c into register set s (clamped addresses; masks applied at the LDS store)
+    // loads of stream chunk c (past the stream: its last chunk again) into register set s; every
+    // pass of the loop issues the same loads, so the waits before each LDS store cover exactly the
+    // set that store writes
     auto gload = [&](int s, int c) __attribute__((always_inline)) {
+        c = c < nall ? c : nall - 1;
         const int m = c / nch, k0 = (c - m * nch) * GK;
         kst[s] = k0;
         const int k = k0 + ka;
-        const int kc = m * KD + (k < KD ? k : 0);
+        const int kc = m * KD + (k < KD ? k : KD - 1);
 #pragma unroll
         for (int u = 0; u < 8; ++u) ra[s][u] = arow[u][kc];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int kb = k0 + (tid >> 6) + 4 * u;
-            rb[s][u] = bcol[(size_t)(kb < KD ? kb : 0) * NW];
+            rb[s][u] = bcol[(size_t)(kb < KD ? kb : KD - 1) * NW];
         }
     };
     auto lstore = [&](int s, int b) __attribute__((always_inline)) {
         double* As = lds + b * (GK * GLDA);
         double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
-        const bool kok = kst[s] + ka < KD;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = (kok && ((aokm >> u) & 1u)) ? ra[s][u] : 0.0;
+        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = ra[s][u];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int kb = kst[s] + (tid >> 6) + 4 * u;
-            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (bok_c && kb < KD) ? rb[s][u] : 0.0;
+            const int kb = kst[s] + (tid >> 6) + 4 * u;      // uniform over the wave
+            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (ragged && kb >= KD) ? 0.0 : rb[s][u];
         }
     };
     double4_t acc[2][2];
     acc_zero(acc);
+    const bool wact = r0 < R && c0 < NW;   // the wave's quadrant holds part of the element's block
     auto compute = [&](int b) __attribute__((always_inline)) {
+        if (!wact) return;
         const double* As = lds + b * (GK * GLDA);
         const double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
         // two halves of the slice: half the operand registers of loading all eight k-steps first
@@ -389,14 +393,13 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
         cb[bj] = cu[bj] ? c : nu + l * M * PF + j;
         cs[bj] = cu[bj] ? P : PF;
     }
-    // T = T0 - product for component m: T0 is E, F, H or J at T's column, read when the
-    // component's product is complete
-    auto store_t = [&](int m) __attribute__((always_inline)) {
-        // one 16-row half at a time (eight T0 loads in flight, then eight stores): the next
-        // slices' prefetched operands are live here, so the half keeps the register count down
+    // T = T0 - product for component m. T0 (E, F, H or J at T's column) is loaded when the
+    // component's last slice is issued, so its latency is covered by that slice's products.
+    double t0[2][4][2];
+    auto load_t0 = [&](int m) __attribute__((always_inline)) {
+        if (!wact) return;
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
-            double t0[4][2];
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
@@ -407,9 +410,14 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
                     const double* src = top_row ? (cu[bj] ? Ee + (size_t)r * nu + tcol : Fe + (size_t)r * nt + (tcol - nu))
                                                 : (cu[bj] ? He + (size_t)(r - nu) * nu + tcol
                                                           : Je + (size_t)(r - nu) * nt + (tcol - nu));
-                    t0[q][bj] = *((rok && cin[bj]) ? src : Ee);
+                    t0[bi][q][bj] = *((rok && cin[bj]) ? src : Ee);
                 }
             }
+    };
+    auto store_t = [&](int m) __attribute__((always_inline)) {
+        if (!wact) return;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
@@ -418,35 +426,34 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
                 for (int bj = 0; bj < 2; ++bj) {
                     if (!cin[bj]) continue;
                     const int tcol = cb[bj] + m * cs[bj];
-                    const double v = t0[q][bj] - acc[bi][bj][q];
+                    const double v = t0[bi][q][bj] - acc[bi][bj][q];
                     if (r < nu) Te[(size_t)r * C + tcol] = v;
                     else Be[(size_t)(r - nu) * C + tcol] = v;
                 }
             }
-        }
         acc_zero(acc);
     };
-    // even stream chunks in LDS buffer 0 (their loads in set 0), odd ones in buffer 1 (set 1)
+    // even stream chunks in LDS buffer 0 (their loads in set 0), odd ones in buffer 1 (set 1); a
+    // store into a buffer past the stream is never read
     gload(0, 0);
-    if (nall > 1) gload(1, 1);
+    gload(1, 1);
     lstore(0, 0);
     __syncthreads();
-    auto finish = [&](int cc) __attribute__((always_inline)) {                 // after chunk cc: component m complete?
-        const int m = cc / nch;
-        if (cc - m * nch == nch - 1) store_t(m);
-    };
 #pragma unroll 1
     for (int c = 0; c < nall; c += 2) {
-        if (c + 2 < nall) gload(0, c + 2);
+        const bool last0 = (c % nch) == nch - 1, last1 = ((c + 1) % nch) == nch - 1;
+        gload(0, c + 2);
+        if (last0) load_t0(c / nch);
         compute(0);
-        if (c + 1 < nall) lstore(1, 1);
-        finish(c);
+        lstore(1, 1);
+        if (last0) store_t(c / nch);
         __syncthreads();
         if (c + 1 >= nall) break;
-        if (c + 3 < nall) gload(1, c + 3);
+        gload(1, c + 3);
+        if (last1) load_t0((c + 1) / nch);
         compute(1);
-        if (c + 2 < nall) lstore(0, 0);
-        finish(c + 1);
+        lstore(0, 0);
+        if (last1) store_t((c + 1) / nch);
         __syncthreads();
     }
     // the right-hand-side column (once per element and row tile)
