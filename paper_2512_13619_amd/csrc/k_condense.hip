@@ -273,13 +273,17 @@ __device__ __forceinline__ int qelim_col(int c, int m, int P, int PF, int M, int
 
 // ---- T = T0 - [D;G][:, q(m,:,:)] W   per (element, 64x64 tile), every component m ------------
 // One block per (element, row tile, column tile); the M components' products run through one
-// pipeline: chunk c of the stream is component c / nch, depth slice (c % nch) * GK of the
+// pipeline: chunk c of the stream is component c / nch, depth slice (c % nch) * QK of the
 // product [D;G][:, q(m,:,:)] (rows m0.., columns m KD..) times W (the same W for every
 // component), so the next component's first slices are loaded while the current one's last
 // ones are multiplied, and a block fills its pipeline once instead of once per component.
 // Each component's result, T0 minus the product, goes to its own columns of T (qelim_col)
-// when its last slice is done. nblk is a multiple of 8 (trailing blocks exit).
-__global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
+// when its last slice is done. Slices are 16 deep (33 KB of LDS, double-buffered), so three
+// blocks share a CU and hide each other's barrier and load waits. nblk is a multiple of 8
+// (trailing blocks exit).
+constexpr int QK = 16;
+constexpr size_t QLDS = sizeof(double) * 2 * (QK * GLDA + QK * GLDB);
+__global__ __launch_bounds__(BS, 3) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
                                                    const double* __restrict__ Dm, const double* __restrict__ Em,
                                                    const double* __restrict__ Fm, const double* __restrict__ Gm,
                                                    const double* __restrict__ Hm, const double* __restrict__ Jm,
@@ -306,50 +310,50 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
     const int i16 = lane & 15, kq = lane >> 4;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int r0 = m0 + wr, c0 = n0 + wc;
-    const int nch = (KD + GK - 1) / GK;
+    const int nch = (KD + QK - 1) / QK;
     const int nall = M * nch;
-    // staging roles: A rows m0 + (tid>>5) + 8u at depth k0 + (tid&31); B rows k0 + (tid>>6) + 4u at
+    // staging roles: A rows m0 + (tid>>4) + 16u at depth k0 + (tid&15); B rows k0 + (tid>>6) + 4u at
     // column n0 + (tid&63). Rows of A past R and columns of B past NW are read at clamped addresses
     // and left unmasked: they only reach rows and columns of the tile that are never stored. Depth
     // past KD (a ragged last slice) reads clamped A and zeroed B, so those products vanish.
-    const int ka = tid & 31, jb = tid & 63;
-    const double* arow[8];
+    const int ka = tid & 15, jb = tid & 63;
+    const double* arow[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int r = m0 + (tid >> 5) + 8 * u;
+    for (int u = 0; u < 4; ++u) {
+        const int r = m0 + (tid >> 4) + 16 * u;
         const int rr = r < R ? r : R - 1;
         arow[u] = rr < nu ? Dm + ((size_t)e * nu + rr) * nq : Gm + ((size_t)e * nt + (rr - nu)) * nq;
     }
     const double* bcol = We + (n0 + jb < NW ? n0 + jb : NW - 1);
-    const bool ragged = (KD % GK) != 0;
-    double ra[2][8], rb[2][8];
-    int kst[2] = {0, 0};
-    // loads of stream chunk c (past the stream: its last chunk again) into register set s; every
-    // pass of the loop issues the same loads, so the waits before each LDS store cover exactly the
-    // set that store writes
-    auto gload = [&](int s, int c) __attribute__((always_inline)) {
+    const bool ragged = (KD % QK) != 0;
+    double ra[4], rb[4];
+    int kst = 0;
+    // loads of stream chunk c (past the stream: its last chunk again) into the staging registers;
+    // every pass of the loop issues the same loads, so the wait before each LDS store covers
+    // exactly the chunk that store writes
+    auto gload = [&](int c) __attribute__((always_inline)) {
         c = c < nall ? c : nall - 1;
-        const int m = c / nch, k0 = (c - m * nch) * GK;
-        kst[s] = k0;
+        const int m = c / nch, k0 = (c - m * nch) * QK;
+        kst = k0;
         const int k = k0 + ka;
         const int kc = m * KD + (k < KD ? k : KD - 1);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ra[s][u] = arow[u][kc];
+        for (int u = 0; u < 4; ++u) ra[u] = arow[u][kc];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int kb = k0 + (tid >> 6) + 4 * u;
-            rb[s][u] = bcol[(size_t)(kb < KD ? kb : KD - 1) * NW];
+            rb[u] = bcol[(size_t)(kb < KD ? kb : KD - 1) * NW];
         }
     };
-    auto lstore = [&](int s, int b) __attribute__((always_inline)) {
-        double* As = lds + b * (GK * GLDA);
-        double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
+    auto lstore = [&](int b) __attribute__((always_inline)) {
+        double* As = lds + b * (QK * GLDA);
+        double* Bs = lds + 2 * QK * GLDA + b * (QK * GLDB);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) As[ka * GLDA + (tid >> 5) + 8 * u] = ra[s][u];
+        for (int u = 0; u < 4; ++u) As[ka * GLDA + (tid >> 4) + 16 * u] = ra[u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int kb = kst[s] + (tid >> 6) + 4 * u;      // uniform over the wave
-            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (ragged && kb >= KD) ? 0.0 : rb[s][u];
+        for (int u = 0; u < 4; ++u) {
+            const int kb = kst + (tid >> 6) + 4 * u;      // uniform over the wave
+            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (ragged && kb >= KD) ? 0.0 : rb[u];
         }
     };
     double4_t acc[2][2];
@@ -357,15 +361,13 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
     const bool wact = r0 < R && c0 < NW;   // the wave's quadrant holds part of the element's block
     auto compute = [&](int b) __attribute__((always_inline)) {
         if (!wact) return;
-        const double* As = lds + b * (GK * GLDA);
-        const double* Bs = lds + 2 * GK * GLDA + b * (GK * GLDB);
-        // two halves of the slice: half the operand registers of loading all eight k-steps first
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        const double* As = lds + b * (QK * GLDA);
+        const double* Bs = lds + 2 * QK * GLDA + b * (QK * GLDB);
+        {   // one 16-deep slice: four k-steps of four products
             double a[4][2], bb[4][2];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                const int k = 4 * (4 * h + ks) + kq;
+                const int k = 4 * ks + kq;
                 a[ks][0] = As[k * GLDA + wr + i16];
                 a[ks][1] = As[k * GLDA + wr + 16 + i16];
                 bb[ks][0] = Bs[k * GLDB + wc + i16];
@@ -398,11 +400,13 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
     double t0[2][4][2];
     auto load_t0 = [&](int m) __attribute__((always_inline)) {
         if (!wact) return;
+        int rl = r0 + (lane >> 4);
+        asm volatile("" : "+v"(rl));   // the row addresses are formed here, not kept live across the loop
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                const int r = rl + 16 * bi + 4 * q;
                 const bool rok = r < R, top_row = r < nu;
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) {
@@ -416,11 +420,13 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
     };
     auto store_t = [&](int m) __attribute__((always_inline)) {
         if (!wact) return;
+        int rl = r0 + (lane >> 4);
+        asm volatile("" : "+v"(rl));
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + 16 * bi + 4 * q + (lane >> 4);
+                const int r = rl + 16 * bi + 4 * q;
                 if (r >= R) continue;
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) {
@@ -433,27 +439,25 @@ __global__ __launch_bounds__(BS, 2) void k_cond_qelim(CondDims cd, long long nti
             }
         acc_zero(acc);
     };
-    // even stream chunks in LDS buffer 0 (their loads in set 0), odd ones in buffer 1 (set 1); a
-    // store into a buffer past the stream is never read
-    gload(0, 0);
-    gload(1, 1);
-    lstore(0, 0);
+    // stream chunk c in LDS buffer c % 2; chunk c + 1's loads are in flight while chunk c is
+    // multiplied (a store into a buffer past the stream is never read)
+    gload(0);
+    lstore(0);
+    gload(1);
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < nall; c += 2) {
         const bool last0 = (c % nch) == nch - 1, last1 = ((c + 1) % nch) == nch - 1;
-        gload(0, c + 2);
-        if (last0) load_t0(c / nch);
         compute(0);
-        lstore(1, 1);
-        if (last0) store_t(c / nch);
+        lstore(1);
+        gload(c + 2);
+        if (last0) { load_t0(c / nch); store_t(c / nch); }
         __syncthreads();
         if (c + 1 >= nall) break;
-        gload(1, c + 3);
-        if (last1) load_t0((c + 1) / nch);
         compute(1);
-        lstore(0, 0);
-        if (last1) store_t((c + 1) / nch);
+        lstore(0);
+        gload(c + 3);
+        if (last1) { load_t0((c + 1) / nch); store_t((c + 1) / nch); }
         __syncthreads();
     }
     // the right-hand-side column (once per element and row tile)
@@ -1481,8 +1485,6 @@ hdg_status set_kernel_lds(hdg_ctx ctx, const CondDims& cd, int NB) {
     if (getrs_lds_bytes(cd) > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_getrs, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)getrs_lds_bytes(cd)));
-    HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_qelim, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)GEMM_LDS));
     HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_cond_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)GEMM_LDS));
     return HDG_OK;
@@ -1650,7 +1652,7 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
             const int tm_n = div_up(cd.R, GT), tn_n = div_up(cd.NW, GT);
             const long long ntile = (long long)n * tm_n * tn_n;
             const long long nblk = (ntile + 7) / 8 * 8;
-            hipLaunchKernelGGL(k_cond_qelim, dim3((unsigned)nblk), dim3(BS), GEMM_LDS, ctx->stream, cd, ntile, tm_n,
+            hipLaunchKernelGGL(k_cond_qelim, dim3((unsigned)nblk), dim3(BS), QLDS, ctx->stream, cd, ntile, tm_n,
                                tn_n, in->D + e0 * cd.nu * cd.nq, in->E + e0 * cd.nu * cd.nu,
                                in->F + e0 * cd.nu * cd.nt, in->G + e0 * cd.nt * cd.nq, in->H + e0 * cd.nt * cd.nu,
                                in->J + e0 * cd.nt * cd.nt, in->ru + e0 * cd.nu, in->rt + e0 * cd.nt, W,
