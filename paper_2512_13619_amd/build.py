@@ -20,8 +20,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.jo
 # per-source flags: the condensation's register-resident solve unrolls its whole sequence of
 # block products (up to 42 for six 32-row blocks), above the default full-unroll size limit,
 # and keeps its slab in VGPRs, where the products read it as their B operand (accumulators in
-# AGPRs would be copied back before every product)
-EXTRA = {"k_condense.hip": ["-mllvm", "-pragma-unroll-threshold=200000", "-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# AGPRs would be copied back before every product); the block-Jacobi inversion keeps a face
+# block row per lane and unrolls its elimination steps over the whole row
+EXTRA = {"k_condense.hip": ["-mllvm", "-pragma-unroll-threshold=200000", "-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "k_bj.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 
 
 def _compile(src):

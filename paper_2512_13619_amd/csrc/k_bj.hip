@@ -1,10 +1,12 @@
 // Block-Jacobi setup (Section 4.5): invert every diagonal face block K_ff by
-// Gauss-Jordan elimination with partial pivoting, one workgroup per face, the
-// augmented [K_ff | I] held in LDS. Inverses are written column-major like K
-// (Binv[f][col][row]) in FP64 and optionally rounded to FP32.
+// Gauss-Jordan elimination with partial pivoting. Blocks of edge <= 64: one wave per face
+// with the block in its registers; larger ones: one workgroup per face, the augmented
+// [K_ff | I] held in LDS. Inverses are written column-major like K (Binv[f][col][row]) in
+// FP64 and optionally rounded to FP32.
 #include <cmath>
 
 #include "hdg_internal.hpp"
+#include "wave_ops.hpp"
 
 namespace {
 
@@ -76,6 +78,84 @@ __global__ __launch_bounds__(BS) void k_bj_invert(int nf, int nb, int S, const d
         const double v = A[r * lda + nb + c];
         B64[(size_t)f * nb * nb + idx] = v;
         if (B32) B32[(size_t)f * nb * nb + idx] = (float)v;
+    }
+}
+
+// The same inversion for nb <= NBT <= 64, one wave per face and four faces per workgroup: lane
+// r holds row r of the block in registers, and the elimination runs in place (the column of
+// the unit vector that the augmented form would carry is stored in the column just
+// eliminated). Rows never move: each lane tracks the position its row has in the
+// interchanged order, the pivot of column k is the largest |entry| among the rows not yet
+// chosen (ties to the lower position, a NaN entry wins so that the face is flagged), and
+// the pivot row reaches every lane through readlane. The same operations in the same order
+// as the LDS kernel: the results agree bit for bit on finite blocks. At the end, row
+// position i of the registers is row i of the inverse with its columns interchanged by the
+// pivots; the inverse's column for each register column is found by undoing those
+// interchanges in reverse order.
+template <int NBT>
+__global__ __launch_bounds__(BS) void k_bj_invert_w(int nf, int nb, int S, const double* __restrict__ K,
+                                                    double* __restrict__ B64, float* __restrict__ B32,
+                                                    int* bad_face) {
+    const long long f = (long long)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (f >= nf) return;
+    const int lane = threadIdx.x & 63;
+    const bool row_ok = lane < nb;
+    const double* Kf = K + (size_t)f * S * nb * nb;   // slot 0, column-major
+    double a[NBT];
+#pragma unroll
+    for (int c = 0; c < NBT; ++c) {
+        const bool ok = row_ok && c < nb;
+        const double v = Kf[ok ? c * nb + lane : 0];
+        a[c] = ok ? v : 0.0;
+    }
+    int pos = lane;          // position of this lane's row in the interchanged order
+    bool live = row_ok;      // the row has not been a pivot row yet
+    int pk = 0;              // in lane k: the position interchanged with k at step k
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < NBT; ++k) {
+        if (k < nb) {
+            double v = live ? fabs(a[k]) : -1.0;
+            if (live && !(v >= 0.0)) v = INFINITY;
+            int key = live ? (pos << 8) | lane : 0x7fffffff;
+            wave_ops::wave_argmax(v, key);
+            const int ol = key & 255, p = key >> 8;      // the pivot row's lane and position
+            if (lane == k) pk = p;
+            double pv = wave_ops::read_lane(a[k], ol);
+            if (pos == k) pos = p;
+            const bool prow = lane == ol;
+            if (prow) { pos = k; live = false; }
+            if (!(fabs(pv) > 0.0) || !isfinite(pv)) { bad = true; pv = 1.0; }
+            const double inv = 1.0 / pv;
+            const double m = prow ? 0.0 : a[k];
+            a[k] = prow ? inv : -m * inv;
+#pragma unroll
+            for (int c = 0; c < NBT; ++c) {
+                if (c != k && c < nb) {
+                    const double pc = wave_ops::read_lane(a[c], ol) * inv;   // the scaled pivot row
+                    a[c] = prow ? pc : fma(-m, pc, a[c]);
+                }
+            }
+        }
+    }
+    if (bad && lane == 0) atomicMin(bad_face, (int)f);
+    // lane j: the inverse's column that register column j holds
+    int d = lane;
+    for (int k = nb - 1; k >= 0; --k) {
+        const int p = __builtin_amdgcn_readlane(pk, k);
+        d = d == k ? p : (d == p ? k : d);
+    }
+    double* Bo = B64 + (size_t)f * nb * nb;
+    float* Bo32 = B32 ? B32 + (size_t)f * nb * nb : nullptr;
+#pragma unroll
+    for (int c = 0; c < NBT; ++c) {
+        if (c < nb) {
+            const int col = __builtin_amdgcn_readlane(d, c);
+            if (row_ok) {
+                Bo[(size_t)col * nb + pos] = a[c];
+                if (Bo32) Bo32[(size_t)col * nb + pos] = (float)a[c];
+            }
+        }
     }
 }
 
@@ -277,6 +357,19 @@ hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const 
 hdg_status bj_invert(hdg_ctx ctx, int nf, int nb, int S, const double* K64, double* B64, float* B32,
                      int* bad_face) {
     if (nf == 0) return HDG_OK;
+    if (nb <= 64) {
+        const dim3 grid((unsigned)div_up((long long)nf, BS / 64));
+        if (nb <= 16)
+            hipLaunchKernelGGL(k_bj_invert_w<16>, grid, dim3(BS), 0, ctx->stream, nf, nb, S, K64, B64, B32, bad_face);
+        else if (nb <= 32)
+            hipLaunchKernelGGL(k_bj_invert_w<32>, grid, dim3(BS), 0, ctx->stream, nf, nb, S, K64, B64, B32, bad_face);
+        else if (nb <= 48)
+            hipLaunchKernelGGL(k_bj_invert_w<48>, grid, dim3(BS), 0, ctx->stream, nf, nb, S, K64, B64, B32, bad_face);
+        else
+            hipLaunchKernelGGL(k_bj_invert_w<64>, grid, dim3(BS), 0, ctx->stream, nf, nb, S, K64, B64, B32, bad_face);
+        HDG_LAUNCH_CHECK(ctx);
+        return HDG_OK;
+    }
     const size_t lds = sizeof(double) * (size_t)nb * (2 * nb + 1);
     if (lds > 150 * 1024) {
         ctx->err = "block-Jacobi: face block too large for LDS";

@@ -469,38 +469,6 @@ __global__ __launch_bounds__(BS, 3) void k_cond_qelim(CondDims cd, long long nti
     }
 }
 
-// Largest v over the wave (ties: smallest i), returned in every lane. Within each row of
-// 16 lanes the partners come through DPP (xor 1, xor 2, half-row and row mirrors, no LDS
-// round trip); the four row results are then read as uniform values.
-template <int CTRL>
-__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
-    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false);
-    const double ov = __hiloint2double(ohi, olo);
-    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
-}
-
-__device__ __forceinline__ void wave_argmax(double& v, int& i) {
-    argmax_dpp_step<0xB1>(v, i);   // quad_perm [1,0,3,2]
-    argmax_dpp_step<0x4E>(v, i);   // quad_perm [2,3,0,1]
-    argmax_dpp_step<0x141>(v, i);  // row_half_mirror
-    argmax_dpp_step<0x140>(v, i);  // row_mirror
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-#pragma unroll
-    for (int r = 1; r < 4; ++r) {
-        const double ov = __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r), __builtin_amdgcn_readlane(lo, 16 * r));
-        const int oi = __builtin_amdgcn_readlane(i, 16 * r);
-        if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
-    }
-    // row 0's lanes started from their own row value; make every lane agree on the result
-    const double v0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
-                                       __builtin_amdgcn_readlane(__double2loint(v), 0));
-    i = __builtin_amdgcn_readlane(i, 0);
-    v = v0;
-}
-
 // v from lane l (l uniform), as a uniform value
 __device__ __forceinline__ double lane_value(double v, int l) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
@@ -560,7 +528,7 @@ __device__ __forceinline__ bool lu_regs(double (&a)[RPL][NBT], int (&pos)[RPL], 
                 const int k = (pos[r] << 8) | (lane + 64 * r);
                 if (v > best || (v == best && k < key)) { best = v; key = k; }
             }
-            wave_argmax(best, key);
+            wave_ops::wave_argmax(best, key);
             const int ob = key & 255, p = key >> 8;
             const int ol = ob & 63, os = ob >> 6;
             double pv = panel_entry(a, os, kk, ol);
@@ -705,7 +673,7 @@ __global__ __launch_bounds__(LBS, LBS == 256 ? (RPL * NBT >= 64 ? 2 : 3) : 1) vo
                     const double v = fabs(Pn[li * ldp + kk]);
                     if (v > best || (v == best && li < bi)) { best = v; bi = li; }
                 }
-                wave_argmax(best, bi);
+                wave_ops::wave_argmax(best, bi);
                 double pv = Pn[bi * ldp + kk];
                 if (lane == 0) {
                     if (ipiv_out) ipiv_out[(size_t)e * nu + k0 + kk] = k0 + bi;

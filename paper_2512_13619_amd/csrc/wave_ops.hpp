@@ -1,4 +1,4 @@
-// Wave-level helpers shared by the recovery and condensation kernels (64-lane waves).
+// Wave-level helpers shared by the recovery, condensation and block-Jacobi kernels (64-lane waves).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,6 +15,38 @@ __device__ __forceinline__ double dpp_mov(double v) {
 __device__ __forceinline__ double read_lane(double v, int l) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                             __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Largest v over the wave (ties: smallest i), returned in every lane. Within each row of
+// 16 lanes the partners come through DPP (xor 1, xor 2, half-row and row mirrors, no LDS
+// round trip); the four row results are then read as uniform values.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false);
+    const double ov = __hiloint2double(ohi, olo);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+    argmax_dpp_step<0xB1>(v, i);   // quad_perm [1,0,3,2]
+    argmax_dpp_step<0x4E>(v, i);   // quad_perm [2,3,0,1]
+    argmax_dpp_step<0x141>(v, i);  // row_half_mirror
+    argmax_dpp_step<0x140>(v, i);  // row_mirror
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const double ov = __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r), __builtin_amdgcn_readlane(lo, 16 * r));
+        const int oi = __builtin_amdgcn_readlane(i, 16 * r);
+        if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+    }
+    // row 0's lanes started from their own row value; make every lane agree on the result
+    const double v0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 0));
+    i = __builtin_amdgcn_readlane(i, 0);
+    v = v0;
 }
 
 // Sum over the wave, the same value in every lane: within each row of 16 lanes the
