@@ -215,7 +215,7 @@ __global__ __launch_bounds__(BS) void k_fold_bj(int nf, int nb, int S, const dou
         }
 }
 
-// The same product for blocks of edge <= 16 KG (KG <= 3), computed as C^T = Binv^T A^T so
+// The same product for blocks of edge <= 16 KG (KG <= 2), computed as C^T = Binv^T A^T so
 // that both operands are read along their contiguous direction and the output tile columns
 // are written 16 rows at a time: Binv goes through the wave's own LDS region (coalesced
 // loads, column stride nb+1), every A operand of the block is loaded from global memory up
@@ -304,6 +304,72 @@ __global__ __launch_bounds__(BS) void k_fold_bj_lds(int nf, int nb, int S, const
     }
 }
 
+// The same product for blocks of edge 33..48 (KG = 3) with every operand in registers: the
+// wave loads all of its A block up front (the B operand of C^T = Binv^T A^T, each lane 16
+// consecutive rows of a column), then, per 16-column tile of the output, the Binv^T
+// operands of that tile (four consecutive k of one column of Binv per lane) and the KG row
+// tiles' products. Without LDS staging the kernel holds two waves per SIMD (the LDS form
+// needs all of a block's Binv in registers before its store and holds one).
+template <typename T, int KG>
+__global__ __launch_bounds__(BS) void k_fold_bj_r(int nf, int nb, int S, const double* __restrict__ K,
+                                                  const int32_t* __restrict__ nbr,
+                                                  const double* __restrict__ Binv, T* __restrict__ out) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long pair = (long long)blockIdx.x * (BS / 64) + wave;
+    if (pair >= (long long)nf * S) return;
+    const int g = nbr[pair];
+    if (g < 0) return;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int bsz = nb * nb;
+    const double* A = K + (size_t)pair * bsz;
+    const double* B = Binv + (size_t)g * bsz;
+    T* C = out + (size_t)pair * bsz;
+    double ao[KG][KG][4];
+#pragma unroll
+    for (int ti = 0; ti < KG; ++ti)
+#pragma unroll
+        for (int gi = 0; gi < KG; ++gi)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int row = 16 * ti + i16, k = 16 * gi + 4 * kq + u;
+                ao[ti][gi][u] = A[(row < nb && k < nb) ? k * nb + row : 0];
+            }
+#pragma unroll
+    for (int tj = 0; tj < KG; ++tj) {
+        const int col = 16 * tj + i16;
+        double bo[KG][4];
+#pragma unroll
+        for (int gi = 0; gi < KG; ++gi)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 16 * gi + 4 * kq + u;
+                bo[gi][u] = B[(col < nb && k < nb) ? col * nb + k : 0];
+            }
+        double4_t acc[KG];
+#pragma unroll
+        for (int ti = 0; ti < KG; ++ti) acc[ti] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int gi = 0; gi < KG; ++gi)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 16 * gi + 4 * kq + u;
+                const double bv = (col < nb && k < nb) ? bo[gi][u] : 0.0;
+#pragma unroll
+                for (int ti = 0; ti < KG; ++ti) {
+                    const double av = (16 * ti + i16 < nb && k < nb) ? ao[ti][gi][u] : 0.0;
+                    acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc[ti], 0, 0, 0);
+                }
+            }
+#pragma unroll
+        for (int ti = 0; ti < KG; ++ti)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = 16 * tj + 4 * q + (lane >> 4);
+                const int r = 16 * ti + (lane & 15);
+                if (r < nb && c < nb) C[(size_t)c * nb + r] = (T)acc[ti][q];
+            }
+    }
+}
 }  // namespace
 
 hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const int32_t* nbr, const double* B64,
@@ -317,38 +383,41 @@ hdg_status fold_bj(hdg_ctx ctx, int nf, int nb, int S, const double* K64, const 
     }
 #define HDG_FOLD(T, KG) \
     hipLaunchKernelGGL((k_fold_bj<T, KG>), dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64, (T*)out)
+#define HDG_FOLD_R(T, KG) \
+    hipLaunchKernelGGL((k_fold_bj_r<T, KG>), dim3(grid), dim3(BS), 0, ctx->stream, nf, nb, S, K64, nbr, B64, (T*)out)
 #define HDG_FOLD_LDS(T, KG) \
     hipLaunchKernelGGL((k_fold_bj_lds<T, KG>), dim3(grid), dim3(BS), lds, ctx->stream, nf, nb, S, K64, nbr, B64, \
                        (T*)out)
     // KG groups of 16 k cover the (padded) block edge
     const int kg = (nb + 15) / 16;
-    if (kg <= 3) {
+    if (kg == 3) {
+        if (out_fp32) HDG_FOLD_R(float, 3); else HDG_FOLD_R(double, 3);
+        HDG_LAUNCH_CHECK(ctx);
+        return HDG_OK;
+    }
+    if (kg <= 2) {
         const size_t lds = sizeof(double) * (BS / 64) * (size_t)nb * (nb + 1);
         if (lds > 64 * 1024) {
-            const void* fn = out_fp32 ? (kg <= 1 ? (const void*)k_fold_bj_lds<float, 1>
-                                                 : kg <= 2 ? (const void*)k_fold_bj_lds<float, 2>
-                                                           : (const void*)k_fold_bj_lds<float, 3>)
-                                      : (kg <= 1 ? (const void*)k_fold_bj_lds<double, 1>
-                                                 : kg <= 2 ? (const void*)k_fold_bj_lds<double, 2>
-                                                           : (const void*)k_fold_bj_lds<double, 3>);
+            const void* fn = out_fp32 ? (kg <= 1 ? (const void*)k_fold_bj_lds<float, 1> : (const void*)k_fold_bj_lds<float, 2>)
+                                      : (kg <= 1 ? (const void*)k_fold_bj_lds<double, 1> : (const void*)k_fold_bj_lds<double, 2>);
             HDG_HIP_CHECK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         }
         if (out_fp32) {
-            if (kg <= 1) HDG_FOLD_LDS(float, 1); else if (kg <= 2) HDG_FOLD_LDS(float, 2); else HDG_FOLD_LDS(float, 3);
+            if (kg <= 1) HDG_FOLD_LDS(float, 1); else HDG_FOLD_LDS(float, 2);
         } else {
-            if (kg <= 1) HDG_FOLD_LDS(double, 1); else if (kg <= 2) HDG_FOLD_LDS(double, 2); else HDG_FOLD_LDS(double, 3);
+            if (kg <= 1) HDG_FOLD_LDS(double, 1); else HDG_FOLD_LDS(double, 2);
         }
         HDG_LAUNCH_CHECK(ctx);
         return HDG_OK;
     }
+    // larger blocks: tile by tile
     if (out_fp32) {
-        if (kg <= 1) HDG_FOLD(float, 1); else if (kg <= 2) HDG_FOLD(float, 2); else if (kg <= 3) HDG_FOLD(float, 3);
-        else if (kg <= 4) HDG_FOLD(float, 4); else if (kg <= 8) HDG_FOLD(float, 8); else HDG_FOLD(float, 16);
+        if (kg <= 4) HDG_FOLD(float, 4); else if (kg <= 8) HDG_FOLD(float, 8); else HDG_FOLD(float, 16);
     } else {
-        if (kg <= 1) HDG_FOLD(double, 1); else if (kg <= 2) HDG_FOLD(double, 2); else if (kg <= 3) HDG_FOLD(double, 3);
-        else if (kg <= 4) HDG_FOLD(double, 4); else if (kg <= 8) HDG_FOLD(double, 8); else HDG_FOLD(double, 16);
+        if (kg <= 4) HDG_FOLD(double, 4); else if (kg <= 8) HDG_FOLD(double, 8); else HDG_FOLD(double, 16);
     }
 #undef HDG_FOLD
+#undef HDG_FOLD_R
 #undef HDG_FOLD_LDS
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
