@@ -50,9 +50,102 @@ __global__ __launch_bounds__(BS) void k_recover(int ne, int M, int D, int P, int
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nu; i += BS) du[(size_t)e * nu + i] = t[i];
-    // dq_{m,d} = -Minv (B_d du_m + C_d uhat_m): one d per wave, all components together
-    // (B_d, C_d and Minv are read once per d)
     const double* Mi = Minv + (size_t)e * P * P;
+    if (M <= MMAX && P >= 32) {
+        // dq_{m,d} = -Minv (B_d du_m + C_d uhat_m): the rows of [B_d | C_d], then of Minv, are
+        // read along their length by the 64 lanes (coalesced), four rows per wave at a time,
+        // against all M vectors in LDS; each row-vector sum is then reduced over the wave.
+        // (Rows shorter than half a wave leave most lanes idle: those elements take the
+        // row-per-lane form below.)
+        double* sd = sq;                       // [D][M][P]: B_d du_m + C_d uhat_m
+        const int nbt = (P + 3) / 4;
+        for (int bt = wave; bt < D * nbt; bt += NW) {
+            const int d = bt / nbt, i0 = (bt - d * nbt) * 4;
+            const int nr = P - i0 < 4 ? P - i0 : 4;
+            const double* B = Bd + ((size_t)e * D + d) * P * P;
+            const double* Cm = Cd + ((size_t)e * D + d) * P * LPF;
+            double acc[4][MMAX];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q) acc[r][q] = 0.0;
+            for (int k0 = 0; k0 < P; k0 += 64) {
+                const int k = k0 + lane;
+                const bool ok = k < P;
+                const int kc = ok ? k : 0;
+                double a[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = B[(size_t)(i0 + (r < nr ? r : 0)) * P + kc];
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q)
+                    if (q < M) {
+                        const double v = t[q * P + kc];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r][q] += ok ? a[r] * v : 0.0;
+                    }
+            }
+            for (int c0 = 0; c0 < LPF; c0 += 64) {
+                const int c = c0 + lane;
+                const bool ok = c < LPF;
+                const int cc = ok ? c : 0;
+                const int l = cc / PF, j = cc - l * PF;
+                double a[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = Cm[(size_t)(i0 + (r < nr ? r : 0)) * LPF + cc];
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q)
+                    if (q < M) {
+                        const double v = xe[(l * M + q) * PF + j];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r][q] += ok ? a[r] * v : 0.0;
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q)
+                    if (q < M) {
+                        const double v = wave_sum_all(acc[r][q]);
+                        if (lane == 0 && r < nr) sd[(d * M + q) * P + i0 + r] = v;
+                    }
+        }
+        __syncthreads();
+        for (int bt = wave; bt < D * nbt; bt += NW) {
+            const int d = bt / nbt, i0 = (bt - d * nbt) * 4;
+            const int nr = P - i0 < 4 ? P - i0 : 4;
+            double acc[4][MMAX];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q) acc[r][q] = 0.0;
+            for (int k0 = 0; k0 < P; k0 += 64) {
+                const int k = k0 + lane;
+                const bool ok = k < P;
+                const int kc = ok ? k : 0;
+                double a[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) a[r] = Mi[(size_t)(i0 + (r < nr ? r : 0)) * P + kc];
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q)
+                    if (q < M) {
+                        const double v = sd[(d * M + q) * P + kc];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r][q] += ok ? a[r] * v : 0.0;
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < MMAX; ++q)
+                    if (q < M) {
+                        const double v = wave_sum_all(acc[r][q]);
+                        if (lane == 0 && r < nr) dq[(size_t)e * M * D * P + (size_t)(q * D + d) * P + i0 + r] = -v;
+                    }
+        }
+        return;
+    }
+    // one row per lane, one d per wave, MMAX components at a time (B_d, C_d and Minv re-read
+    // per group)
     double* s = sq + (size_t)wave * M * P;
     for (int d = wave; d < D; d += NW) {
         const double* B = Bd + ((size_t)e * D + d) * P * P;
