@@ -13,7 +13,7 @@ __global__ __launch_bounds__(BS) void k_assemble(int nf, int M, int PF, int L, c
                                                  const int32_t* __restrict__ e2f, const int32_t* __restrict__ perm,
                                                  const double* __restrict__ Kbar, const double* __restrict__ rbar,
                                                  double* __restrict__ K64, float* __restrict__ K32,
-                                                 int32_t* __restrict__ nbr, double* __restrict__ r) {
+                                                 int32_t* __restrict__ nbr, double* __restrict__ r, int nbuf) {
     const int nb = M * PF;
     const int S = 2 * L - 1;
     const int nt = L * nb;
@@ -49,40 +49,78 @@ __global__ __launch_bounds__(BS) void k_assemble(int nf, int M, int PF, int L, c
         return (l * M + m) * PF + jl;
     };
     const size_t blk = (size_t)nb * nb;
-    extern __shared__ double tile[];     // nb x (nb+1): row-major gather, column-major write
+    // dynamic LDS: nbuf tiles of nb x (nb+1) (row-major gather, column-major write), then the
+    // row and column trace indices of every slot's block (and of the second element's
+    // diagonal block), formed once so that the gathers read Kbar without a perm lookup
+    extern __shared__ double tile[];
     const int ldt = nb + 1;
-    for (int s = 0; s < S; ++s) {
+    int* ridx = reinterpret_cast<int*>(tile + (size_t)nbuf * nb * ldt);   // [S + 1][nb]
+    int* cidx = ridx + (size_t)(S + 1) * nb;                              // [S + 1][nb]
+    for (int idx = threadIdx.x; idx < (S + 1) * nb; idx += BS) {
+        const int s = idx / nb, rr = idx - s * nb;
+        const int m = rr / PF, j = rr - m * PF;
+        if (s < S) {
+            const int e = se[s];
+            ridx[idx] = e >= 0 ? tix(e, slr[s], m, j) : 0;
+            cidx[idx] = e >= 0 ? tix(e, slc[s], m, j) : 0;
+        } else {
+            ridx[idx] = e2 >= 0 ? tix(e2, l2, m, j) : 0;
+            cidx[idx] = ridx[idx];
+        }
+    }
+    __syncthreads();
+    // slot s's block gathered into tile buffer s % nbuf (consecutive threads read consecutive
+    // columns of a row of Kbar)
+    auto gather = [&](int s) {
         const int e = se[s];
+        if (e < 0) return;
+        double* tb = tile + (size_t)(s % nbuf) * nb * ldt;
+        const double* Ke = Kbar + (size_t)e * nt * nt;
+        const double* K2 = (s == 0 && e2 >= 0) ? Kbar + (size_t)e2 * nt * nt : nullptr;
+        const int* ri = ridx + s * nb;
+        const int* ci = cidx + s * nb;
+        const int* ri2 = ridx + S * nb;
+        for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
+            const int rr = idx / nb, c = idx - rr * nb;
+            double v = Ke[(size_t)ri[rr] * nt + ci[c]];
+            if (K2) v += K2[(size_t)ri2[rr] * nt + ri2[c]];
+            tb[rr * ldt + c] = v;
+        }
+    };
+    auto write = [&](int s) {
         double* out = K64 + ((size_t)f * S + s) * blk;
         float* out32 = K32 ? K32 + ((size_t)f * S + s) * blk : nullptr;
-        if (e < 0) {
+        if (se[s] < 0) {
             for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
                 out[idx] = 0.0;
                 if (out32) out32[idx] = 0.0f;
             }
-            continue;
+            return;
         }
-        // gather rows of the element block (consecutive threads read consecutive columns)
-        for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
-            const int rr = idx / nb, c = idx - rr * nb;
-            const int mr = rr / PF, jr = rr - mr * PF;
-            const int mc = c / PF, jc = c - mc * PF;
-            const double* Ke = Kbar + (size_t)e * nt * nt;
-            double v = Ke[(size_t)tix(e, slr[s], mr, jr) * nt + tix(e, slc[s], mc, jc)];
-            if (s == 0 && e2 >= 0) {
-                const double* K2 = Kbar + (size_t)e2 * nt * nt;
-                v += K2[(size_t)tix(e2, l2, mr, jr) * nt + tix(e2, l2, mc, jc)];
-            }
-            tile[rr * ldt + c] = v;
-        }
-        __syncthreads();
+        const double* tb = tile + (size_t)(s % nbuf) * nb * ldt;
         for (int idx = threadIdx.x; idx < (int)blk; idx += BS) {
             const int c = idx / nb, rr = idx - c * nb;          // column-major: idx = c*nb + rr
-            const double v = tile[rr * ldt + c];
+            const double v = tb[rr * ldt + c];
             out[idx] = v;
             if (out32) out32[idx] = (float)v;
         }
+    };
+    if (nbuf == 2) {
+        // the next slot's loads are in flight while this slot's block is written
+        gather(0);
         __syncthreads();
+        for (int s = 0; s < S; ++s) {
+            if (s + 1 < S) gather(s + 1);
+            write(s);
+            __syncthreads();
+        }
+    } else {
+        for (int s = 0; s < S; ++s) {
+            gather(s);
+            __syncthreads();
+            write(s);
+            __syncthreads();
+        }
     }
     for (int rr = threadIdx.x; rr < nb; rr += BS) {
         const int m = rr / PF, j = rr - m * PF;
@@ -132,12 +170,18 @@ hdg_status assemble_run(hdg_ctx ctx, const hdg_dims* d, const int32_t* f2e, cons
                         int32_t* nbr, double* r) {
     if (d->nf == 0) return HDG_OK;
     const int nb = d->ncomp * d->npf;
-    const size_t lds = sizeof(double) * (size_t)nb * (nb + 1);
+    // two tile buffers for small blocks (at most 32 KiB of LDS in all, so that several faces
+    // still share a CU), else one
+    const int S = 2 * d->nlfe - 1;
+    const size_t tile = sizeof(double) * (size_t)nb * (nb + 1);
+    const size_t tabs = sizeof(int) * 2 * (size_t)(S + 1) * nb;
+    const int nbuf = 2 * tile + tabs <= 32 * 1024 ? 2 : 1;
+    const size_t lds = nbuf * tile + tabs;
     if (lds > 64 * 1024)
         HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_assemble, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)lds));
     hipLaunchKernelGGL(k_assemble, dim3(d->nf), dim3(BS), lds, ctx->stream, d->nf, d->ncomp, d->npf, d->nlfe, f2e,
-                       e2f, perm, Kbar, rbar, K64, K32, nbr, r);
+                       e2f, perm, Kbar, rbar, K64, K32, nbr, r, nbuf);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }

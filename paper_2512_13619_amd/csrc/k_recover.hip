@@ -14,6 +14,9 @@ constexpr int MMAX = 8;     // components handled together in the q part
 
 using namespace wave_ops;
 
+// ROWS: the q part reads the rows of [B_d | C_d] and M^{-1} along their length (M <= MMAX and
+// P >= 32); otherwise one row per lane. (Two kernels: the first needs more registers.)
+template <bool ROWS>
 __global__ __launch_bounds__(BS) void k_recover(int ne, int M, int D, int P, int PF, int L,
                                                 const double* __restrict__ local, const double* __restrict__ Minv,
                                                 const double* __restrict__ Bd, const double* __restrict__ Cd,
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(BS) void k_recover(int ne, int M, int D, int P, int
     __syncthreads();
     for (int i = threadIdx.x; i < nu; i += BS) du[(size_t)e * nu + i] = t[i];
     const double* Mi = Minv + (size_t)e * P * P;
-    if (M <= MMAX && P >= 32) {
+    if constexpr (ROWS) {
         // dq_{m,d} = -Minv (B_d du_m + C_d uhat_m): the rows of [B_d | C_d], then of Minv, are
         // read along their length by the 64 lanes (coalesced), four rows per wave at a time,
         // against all M vectors in LDS; each row-vector sum is then reduced over the wave.
@@ -206,11 +209,16 @@ hdg_status recover_run(hdg_ctx ctx, const hdg_dims* d, const double* local, cons
     if (d->ne == 0) return HDG_OK;
     const int nu = d->ncomp * d->npe, nt = d->nlfe * d->ncomp * d->npf;
     const size_t lds = sizeof(double) * ((size_t)nt + nu + (size_t)(BS / 64) * nu);
+    const bool rows = d->ncomp <= MMAX && d->npe >= 32;
+    const void* fn = rows ? (const void*)k_recover<true> : (const void*)k_recover<false>;
     if (lds > 64 * 1024)
-        HDG_HIP_CHECK(ctx, hipFuncSetAttribute((const void*)k_recover, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds));
-    hipLaunchKernelGGL(k_recover, dim3(d->ne), dim3(BS), lds, ctx->stream, d->ne, d->ncomp, d->dim, d->npe, d->npf,
-                       d->nlfe, local, Minv, Bd, Cd, e2f, perm, xhat, du, dq);
+        HDG_HIP_CHECK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (rows)
+        hipLaunchKernelGGL(k_recover<true>, dim3(d->ne), dim3(BS), lds, ctx->stream, d->ne, d->ncomp, d->dim, d->npe,
+                           d->npf, d->nlfe, local, Minv, Bd, Cd, e2f, perm, xhat, du, dq);
+    else
+        hipLaunchKernelGGL(k_recover<false>, dim3(d->ne), dim3(BS), lds, ctx->stream, d->ne, d->ncomp, d->dim, d->npe,
+                           d->npf, d->nlfe, local, Minv, Bd, Cd, e2f, perm, xhat, du, dq);
     HDG_LAUNCH_CHECK(ctx);
     return HDG_OK;
 }
