@@ -14,13 +14,14 @@
 // one (nu+nt) x (D P_E) by (D P_E) x (P_E + N_lfe P_F) product per component,
 // with W = M^{-1}[B_d | C_d] formed first. All products run on the FP64 matrix
 // cores (v_mfma_f64_16x16x4f64). Three stages:
-//   1. q-elimination: LDS-staged 64x64 tiles (one block per element, component and
-//      tile), giving [[Ebar Fbar r_u], [Hbar Jbar r_t]];
-//   2. on the Ebar rows only: right-looking blocked LU of the first nu columns (panel
-//      factorised in LDS by one wave, trailing updates on the matrix cores), then block
-//      back substitution X = U^{-1} (L^{-1} P [Fbar | r_u]);
-//   3. Schur product Kbar = Jbar - Hbar X, rbar = r_t - Hbar x_r: one product of depth
-//      nu in LDS-staged 64x64 tiles.
+//   1. q-elimination: LDS-staged 64x64 tiles (one block per element and tile, the M
+//      components' products in one pipeline), giving [[Ebar Fbar r_u], [Hbar Jbar r_t]];
+//   2. on the Ebar rows only: right-looking blocked LU of the first nu columns (panels
+//      factorised in one wave's registers, trailing updates on the matrix cores; for
+//      nu <= 64 one wave per element holds the whole block), then block substitution
+//      X = U^{-1} (L^{-1} P [Fbar | r_u]) with inverted 32x32 diagonal blocks;
+//   3. Schur product Kbar = Jbar - Hbar X, rbar = r_t - Hbar x_r, of depth nu: fused into
+//      the substitution's slabs for nu <= 192, else LDS-staged 64x64 tiles.
 //
 // Storage of T per element: the top nu rows live directly in the caller's
 // `local` buffer (row stride nu+nt+1), the bottom nt rows in a workspace.
