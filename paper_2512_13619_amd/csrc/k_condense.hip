@@ -1074,10 +1074,12 @@ struct SolvePlan {
 // Kbar and rbar for the slab's columns.
 constexpr int ALD = 34;
 
-// (Two blocks per CU where the slab and the operands fit in 256 VGPRs; the five- and six-block
-// variants with partial blocks need more and run one block per CU.)
+// (Two blocks per CU, 256 VGPRs each; the five-block variants spill a few registers at that
+// size and still run faster than at one block per CU: 18.4 -> 15.8 ms for the Navier-Stokes
+// hexes. The six-block variant with a partial last block would spill far more and runs one
+// block per CU.)
 template <int NKB, bool FULL>
-__global__ __launch_bounds__(256, (NKB >= 5 && !(NKB == 6 && FULL)) ? 1 : 2) void k_cond_getrs_b(CondDims cd, long long nblk, int nbe,
+__global__ __launch_bounds__(256, (NKB == 6 && !FULL) ? 1 : 2) void k_cond_getrs_b(CondDims cd, long long nblk, int nbe,
                                                          double* __restrict__ top, const double* __restrict__ bot,
                                                          const int32_t* __restrict__ perm,
                                                          const double* __restrict__ dinv, double* __restrict__ Kbar,
