@@ -47,6 +47,8 @@ def make_case(name):
         return HDGProblem(Mh.structured_hexes(2, 0.05, 2), 3, Ph.Elasticity(exact=Ph.elasticity_manufactured))
     if name == "ns_hex_p2":
         return HDGProblem(Mh.structured_hexes(2, 0.0, 3), 2, configs.navier_stokes(3, 0.07))
+    if name == "ns_hex_p3":
+        return HDGProblem(Mh.structured_hexes(2, 0.05, 7), 3, configs.navier_stokes(3, 0.07))
     if name == "ns_tet_p2":
         return HDGProblem(Mh.kuhn_tets(1, 0.1, 5), 2, configs.navier_stokes(5, 0.035))
     if name == "burgers_tri_p4":
@@ -54,7 +56,11 @@ def make_case(name):
     raise KeyError(name)
 
 
-CASES = ["c1", "poisson_quad_p3", "elast_hex_p1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4"]
+# ns_hex_p3 (nu = 320, 80x80 face blocks) takes the large-element paths: LU panels in LDS,
+# substitution in LDS slabs with a separate Schur product, block-Jacobi inverses in LDS, the
+# tile-by-tile fold
+CASES = ["c1", "poisson_quad_p3", "elast_hex_p1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4",
+         "ns_hex_p3"]
 _cache = {}
 
 
@@ -110,7 +116,7 @@ def test_condense_matches_oracle(ctx, name):
     assert ek < 1e-11 and er < 1e-11, (ek, er)
 
 
-@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_tet_p2"])
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_tet_p2", "ns_hex_p3"])
 def test_assemble_is_exact(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
     pb, out = case_data(name)
@@ -173,7 +179,7 @@ def _dev_matrix(out):
     return K, K.float().contiguous(), torch.as_tensor(out["nbr"].astype(np.int32)).cuda().contiguous()
 
 
-@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4"])
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "burgers_tri_p4", "ns_hex_p3"])
 def test_matvec_fp64_and_fp32(ctx, name):
     pb, out = case_data(name)
     say("matvec", name)
@@ -193,7 +199,7 @@ def test_matvec_fp64_and_fp32(ctx, name):
     assert np.all(np.abs(y.cpu().numpy() - ref) <= bound * 1.01 + 1e-15 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_tet_p2"])
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_tet_p2", "ns_hex_p3"])
 def test_bj_inverse_and_apply(ctx, name):
     pb, out = case_data(name)
     say("bj", name)
@@ -411,7 +417,7 @@ def test_condense_empty_and_ragged_chunks(ctx):
     assert torch.equal(Kc, Kall) and torch.equal(rc, rall) and torch.equal(lc, lall)
 
 
-@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2"])
+@pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "ns_hex_p3"])
 def test_pipeline_end_to_end(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
     pb, out = case_data(name)
@@ -434,6 +440,22 @@ def test_pipeline_end_to_end(ctx, name):
     torch.cuda.synchronize()
     assert torch.equal(state, pl.x)
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_folded_solve_large_blocks(ctx, precision):
+    """80x80 face blocks: the tile-by-tile fold of the block-Jacobi inverses (from LDS-kernel
+    inverses) into the operator, solved with delayed CGS2, against the oracle's direct solution."""
+    from paper_2512_13619_amd.pipeline import Pipeline
+    pb, out = case_data("ns_hex_p3")
+    say("fold large", precision)
+    pl = Pipeline(ctx, pb.dims(), pb.mesh.f2e, pb.mesh.e2f)
+    pl.condense(to_dev(out["blk"]))
+    pl.assemble()
+    st = pl.solve(restart=50, max_iters=3000, rtol=1e-12, prec="bj", orth="dcgs2", fold_prec=True,
+                  precision=precision)
+    assert st["converged"], st
+    assert relerr(pl.x.cpu().numpy(), out["x"]) < 1e-9
 
 def test_failure_paths(ctx):
     from paper_2512_13619_amd import hdg
