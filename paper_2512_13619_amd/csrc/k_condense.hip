@@ -284,6 +284,7 @@ __device__ __forceinline__ int qelim_col(int c, int m, int P, int PF, int M, int
 // (trailing blocks exit).
 constexpr int QK = 16;
 constexpr size_t QLDS = sizeof(double) * 2 * (QK * GLDA + QK * GLDB);
+template <bool V2>
 __global__ __launch_bounds__(BS, 3) void k_cond_qelim(CondDims cd, long long ntile, int tm_n, int tn_n,
                                                    const double* __restrict__ Dm, const double* __restrict__ Em,
                                                    const double* __restrict__ Fm, const double* __restrict__ Gm,
@@ -313,22 +314,31 @@ __global__ __launch_bounds__(BS, 3) void k_cond_qelim(CondDims cd, long long nti
     const int r0 = m0 + wr, c0 = n0 + wc;
     const int nch = (KD + QK - 1) / QK;
     const int nall = M * nch;
-    // staging roles: A rows m0 + (tid>>4) + 16u at depth k0 + (tid&15); B rows k0 + (tid>>6) + 4u at
-    // column n0 + (tid&63). Rows of A past R and columns of B past NW are read at clamped addresses
-    // and left unmasked: they only reach rows and columns of the tile that are never stored. Depth
-    // past KD (a ragged last slice) reads clamped A and zeroed B, so those products vanish.
-    const int ka = tid & 15, jb = tid & 63;
-    const double* arow[4];
+    // staging roles (8-byte form): A rows m0 + (tid>>4) + 16u at depth k0 + (tid&15); B rows
+    // k0 + (tid>>6) + 4u at column n0 + (tid&63); the 16-byte form halves the threads per row and
+    // doubles the rows per thread. Rows of A past R and columns of B past NW are read at clamped
+    // addresses and left unmasked: they only reach rows and columns of the tile that are never
+    // stored. Depth past KD (a ragged last slice) reads clamped A and zeroed B, so those products
+    // vanish.
+    const bool ragged = (KD % QK) != 0;
+    int kst = 0;
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    // V2 (nq, KD and NW even): 16-byte loads of two consecutive depths of a row of [D;G] and of
+    // two consecutive columns of W, half the load instructions of the 8-byte form
+    const int ka = V2 ? 2 * (tid & 7) : (tid & 15), jb = V2 ? 2 * (tid & 31) : (tid & 63);
+    constexpr int NA = V2 ? 2 : 4;                 // rows of [D;G] per thread
+    const int arow0 = V2 ? (tid >> 3) : (tid >> 4), astep = V2 ? 32 : 16;
+    const double* arow[NA];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = m0 + (tid >> 4) + 16 * u;
+    for (int u = 0; u < NA; ++u) {
+        const int r = m0 + arow0 + astep * u;
         const int rr = r < R ? r : R - 1;
         arow[u] = rr < nu ? Dm + ((size_t)e * nu + rr) * nq : Gm + ((size_t)e * nt + (rr - nu)) * nq;
     }
-    const double* bcol = We + (n0 + jb < NW ? n0 + jb : NW - 1);
-    const bool ragged = (KD % QK) != 0;
+    const int brow0 = V2 ? (tid >> 5) : (tid >> 6), bstep = V2 ? 8 : 4;
+    const int jc = V2 ? (n0 + jb < NW ? n0 + jb : NW - 2) : (n0 + jb < NW ? n0 + jb : NW - 1);
+    const double* bcol = We + jc;
     double ra[4], rb[4];
-    int kst = 0;
     // loads of stream chunk c (past the stream: its last chunk again) into the staging registers;
     // every pass of the loop issues the same loads, so the wait before each LDS store covers
     // exactly the chunk that store writes
@@ -337,24 +347,58 @@ __global__ __launch_bounds__(BS, 3) void k_cond_qelim(CondDims cd, long long nti
         const int m = c / nch, k0 = (c - m * nch) * QK;
         kst = k0;
         const int k = k0 + ka;
-        const int kc = m * KD + (k < KD ? k : KD - 1);
+        if constexpr (V2) {
+            const int kc = m * KD + (k < KD ? k : KD - 2);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) ra[u] = arow[u][kc];
+            for (int u = 0; u < 2; ++u) {
+                const d2_t v = *reinterpret_cast<const d2_t*>(arow[u] + kc);
+                ra[2 * u] = v.x;
+                ra[2 * u + 1] = v.y;
+            }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int kb = k0 + (tid >> 6) + 4 * u;
-            rb[u] = bcol[(size_t)(kb < KD ? kb : KD - 1) * NW];
+            for (int u = 0; u < 2; ++u) {
+                const int kb = k0 + brow0 + bstep * u;
+                const d2_t v = *reinterpret_cast<const d2_t*>(bcol + (size_t)(kb < KD ? kb : KD - 1) * NW);
+                rb[2 * u] = v.x;
+                rb[2 * u + 1] = v.y;
+            }
+        } else {
+            const int kc = m * KD + (k < KD ? k : KD - 1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ra[u] = arow[u][kc];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kb = k0 + brow0 + bstep * u;
+                rb[u] = bcol[(size_t)(kb < KD ? kb : KD - 1) * NW];
+            }
         }
     };
     auto lstore = [&](int b) __attribute__((always_inline)) {
         double* As = lds + b * (QK * GLDA);
         double* Bs = lds + 2 * QK * GLDA + b * (QK * GLDB);
+        if constexpr (V2) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) As[ka * GLDA + (tid >> 4) + 16 * u] = ra[u];
+            for (int u = 0; u < 2; ++u) {
+                As[ka * GLDA + arow0 + astep * u] = ra[2 * u];
+                As[(ka + 1) * GLDA + arow0 + astep * u] = ra[2 * u + 1];
+            }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int kb = kst + (tid >> 6) + 4 * u;      // uniform over the wave
-            Bs[((tid >> 6) + 4 * u) * GLDB + jb] = (ragged && kb >= KD) ? 0.0 : rb[u];
+            for (int u = 0; u < 2; ++u) {
+                const int kl = brow0 + bstep * u;
+                const bool z = ragged && kst + kl >= KD;
+                d2_t v;
+                v.x = z ? 0.0 : rb[2 * u];
+                v.y = z ? 0.0 : rb[2 * u + 1];
+                *reinterpret_cast<d2_t*>(Bs + kl * GLDB + jb) = v;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) As[ka * GLDA + arow0 + astep * u] = ra[u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kb = kst + brow0 + bstep * u;      // uniform over the wave
+                Bs[(brow0 + bstep * u) * GLDB + jb] = (ragged && kb >= KD) ? 0.0 : rb[u];
+            }
         }
     };
     double4_t acc[2][2];
@@ -1623,11 +1667,20 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
             const int tm_n = div_up(cd.R, GT), tn_n = div_up(cd.NW, GT);
             const long long ntile = (long long)n * tm_n * tn_n;
             const long long nblk = (ntile + 7) / 8 * 8;
-            hipLaunchKernelGGL(k_cond_qelim, dim3((unsigned)nblk), dim3(BS), QLDS, ctx->stream, cd, ntile, tm_n,
-                               tn_n, in->D + e0 * cd.nu * cd.nq, in->E + e0 * cd.nu * cd.nu,
-                               in->F + e0 * cd.nu * cd.nt, in->G + e0 * cd.nt * cd.nq, in->H + e0 * cd.nt * cd.nu,
-                               in->J + e0 * cd.nt * cd.nt, in->ru + e0 * cd.nu, in->rt + e0 * cd.nt, W,
-                               local + e0 * cd.nu * cd.C, bot);
+            // 16-byte staging loads where every row start and pair of [D;G] and W is 16-byte aligned
+            const bool v2 = cd.nq % 2 == 0 && cd.KD % 2 == 0 && cd.NW % 2 == 0;
+            const void* qfn = v2 ? (const void*)k_cond_qelim<true> : (const void*)k_cond_qelim<false>;
+            const double *Dp = in->D + e0 * cd.nu * cd.nq, *Ep = in->E + e0 * cd.nu * cd.nu,
+                         *Fp = in->F + e0 * cd.nu * cd.nt, *Gp = in->G + e0 * cd.nt * cd.nq,
+                         *Hp = in->H + e0 * cd.nt * cd.nu, *Jp = in->J + e0 * cd.nt * cd.nt, *rup = in->ru + e0 * cd.nu,
+                         *rtp = in->rt + e0 * cd.nt;
+            double* topp = local + e0 * cd.nu * cd.C;
+            int tm_i = tm_n, tn_i = tn_n;
+            long long ntile_l = ntile;
+            void* qargs[] = {(void*)&cd, (void*)&ntile_l, (void*)&tm_i, (void*)&tn_i, (void*)&Dp, (void*)&Ep,
+                             (void*)&Fp, (void*)&Gp, (void*)&Hp, (void*)&Jp, (void*)&rup, (void*)&rtp, (void*)&W,
+                             (void*)&topp, (void*)&bot};
+            HDG_HIP_CHECK(ctx, hipLaunchKernel(qfn, dim3((unsigned)nblk), dim3(BS), qargs, QLDS, ctx->stream));
             HDG_LAUNCH_CHECK(ctx);
         }
         const bool keep = Hbar_out != nullptr;
