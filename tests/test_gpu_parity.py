@@ -100,6 +100,16 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def blockerr(a, b, nblocks, floor=1e-8):
+    """Largest error of a block (element or face) relative to that block's own largest entry
+    (at least floor times the whole array's), so that blocks of small magnitude are checked on
+    their own scale rather than on the array's."""
+    a = np.asarray(a).reshape(nblocks, -1)
+    b = np.asarray(b).reshape(nblocks, -1)
+    scale = np.maximum(np.abs(b).max(axis=1), floor * max(np.abs(b).max(), 1e-300))
+    return float((np.abs(a - b).max(axis=1) / scale).max())
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_condense_matches_oracle(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
@@ -112,8 +122,11 @@ def test_condense_matches_oracle(ctx, name):
     Kb = pl.Kbar.cpu().numpy()
     rb = pl.rbar.cpu().numpy()
     ek, er = relerr(Kb, out["Kbar"]), relerr(rb, out["rbar"])
-    say("condense errors", ek, er)
+    ne = pb.dims()["ne"]
+    bk, br = blockerr(Kb, out["Kbar"], ne), blockerr(rb, out["rbar"], ne)
+    say("condense errors", ek, er, "per element", bk, br)
     assert ek < 1e-11 and er < 1e-11, (ek, er)
+    assert bk < 1e-10 and br < 1e-10, (bk, br)
 
 
 @pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_tet_p2", "ns_hex_p3"])
@@ -210,6 +223,9 @@ def test_bj_inverse_and_apply(ctx, name):
     ctx.bj_setup(pb.dims(), K, B64, B32)
     ref = krylov.bj_inverses(out["K"])
     assert relerr(B64.cpu().numpy(), ref) < 1e-10
+    eb = blockerr(B64.cpu().numpy(), ref, nf)
+    say("bj per face", eb)
+    assert eb < 1e-10, eb
     assert np.array_equal(B32.cpu().numpy(), B64.cpu().numpy().astype(np.float32))
     y = torch.as_tensor(np.random.default_rng(2).standard_normal(nf * nb)).cuda()
     z = torch.zeros_like(y)
@@ -432,8 +448,15 @@ def test_pipeline_end_to_end(ctx, name):
     torch.cuda.synchronize()
     ex = relerr(pl.x.cpu().numpy(), out["x"])
     eu, eq = relerr(pl.du.cpu().numpy(), out["du"]), relerr(pl.dq.cpu().numpy(), out["dq"])
-    say("e2e errors", st["iters"], ex, eu, eq)
+    d = pb.dims()
+    # the solve stops on a residual relative to the whole right-hand side, so a face whose trace
+    # values are near zero (a homogeneous boundary) carries an error on the global scale: faces
+    # are held to their own scale down to 1e-3 of the largest trace value
+    bx = blockerr(pl.x.cpu().numpy(), out["x"], d["nf"], floor=1e-3)
+    bu, bq = blockerr(pl.du.cpu().numpy(), out["du"], d["ne"]), blockerr(pl.dq.cpu().numpy(), out["dq"], d["ne"])
+    say("e2e errors", st["iters"], ex, eu, eq, "per face / element", bx, bu, bq)
     assert ex < 1e-10 and eu < 1e-10 and eq < 1e-10, (ex, eu, eq)
+    assert bx < 1e-9 and bu < 1e-9 and bq < 1e-9, (bx, bu, bq)
     # Newton update of the trace state (alpha = 1 for a single linearisation)
     state = torch.zeros_like(pl.x)
     ctx.newton_update(1.0, pl.x, state)
