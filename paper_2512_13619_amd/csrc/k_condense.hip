@@ -1668,7 +1668,9 @@ hdg_status condense_run(hdg_ctx ctx, const hdg_dims* d, int64_t ne, const hdg_el
             const long long ntile = (long long)n * tm_n * tn_n;
             const long long nblk = (ntile + 7) / 8 * 8;
             // 16-byte staging loads where every row start and pair of [D;G] and W is 16-byte aligned
-            const bool v2 = cd.nq % 2 == 0 && cd.KD % 2 == 0 && cd.NW % 2 == 0;
+            // (even strides and 16-byte aligned base pointers)
+            const bool v2 = cd.nq % 2 == 0 && cd.KD % 2 == 0 && cd.NW % 2 == 0 &&
+                            (((uintptr_t)in->D | (uintptr_t)in->G | (uintptr_t)W) & 15) == 0;
             const void* qfn = v2 ? (const void*)k_cond_qelim<true> : (const void*)k_cond_qelim<false>;
             const double *Dp = in->D + e0 * cd.nu * cd.nq, *Ep = in->E + e0 * cd.nu * cd.nu,
                          *Fp = in->F + e0 * cd.nu * cd.nt, *Gp = in->G + e0 * cd.nt * cd.nq,
