@@ -433,6 +433,34 @@ def test_condense_empty_and_ragged_chunks(ctx):
     assert torch.equal(Kc, Kall) and torch.equal(rc, rall) and torch.equal(lc, lall)
 
 
+
+def test_condense_with_8_byte_aligned_blocks(ctx):
+    """[D;G] blocks whose storage starts 8 bytes past a 16-byte boundary take the 8-byte staging
+    form of the q-elimination and give the same bits as aligned ones."""
+    pb, out = case_data("elast_hex_p1")
+    d = pb.dims()
+    ne = d["ne"]
+    M, P, PF, L = d["ncomp"], d["npe"], d["npf"], d["nlfe"]
+    nu, nt = M * P, L * M * PF
+    blk = to_dev(out["blk"])
+    odd = dict(blk)
+    for k in ("D", "G"):
+        buf = torch.empty(blk[k].numel() + 1, dtype=torch.float64, device="cuda")
+        v = buf[1:].view(blk[k].shape)
+        v.copy_(blk[k])
+        assert v.data_ptr() % 16 == 8
+        odd[k] = v
+    res = []
+    for b in (blk, odd):
+        K = torch.empty(ne, nt, nt, dtype=torch.float64, device="cuda")
+        r = torch.empty(ne, nt, dtype=torch.float64, device="cuda")
+        lo = torch.empty(ne, nu * (nu + nt + 1), dtype=torch.float64, device="cuda")
+        ctx.condense(d, b, K, r, lo)
+        res.append((K, r, lo))
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(*res))
+    assert relerr(res[1][0].cpu().numpy(), out["Kbar"]) < 1e-11
+
 @pytest.mark.parametrize("name", ["c1", "elast_hex_p3", "ns_hex_p2", "ns_tet_p2", "ns_hex_p3"])
 def test_pipeline_end_to_end(ctx, name):
     from paper_2512_13619_amd.pipeline import Pipeline
