@@ -348,21 +348,33 @@ __global__ __launch_bounds__(BS) void k_multidot2(const double* __restrict__ V, 
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    constexpr int U = 8;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    constexpr int U = 4;
     for (int i = wave; i < J; i += BS / 64) {
         const double* v = V + (size_t)i * ldv + k0;
         double acc1 = 0.0, acc2 = 0.0;
-        for (int k = lane; k < len; k += 64 * U) {
-            double m[U];
+        // two consecutive entries per lane (16-byte loads); len is even except at the vector's end
+        for (int k = 2 * lane; k < len; k += 128 * U) {
+            d2 m[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) m[u] = (k + 64 * u < len) ? v[k + 64 * u] : 0.0;
+            for (int u = 0; u < U; ++u) {
+                const int kk = k + 128 * u;
+                if (kk + 1 < len) m[u] = *reinterpret_cast<const d2*>(v + kk);
+                else { m[u].x = kk < len ? v[kk] : 0.0; m[u].y = 0.0; }
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (k + 64 * u < len) {
-                    acc1 += m[u] * xs[0][k + 64 * u];
-                    if (NRHS == 2) acc2 += m[u] * xs[NRHS - 1][k + 64 * u];
+            for (int u = 0; u < U; ++u) {
+                const int kk = k + 128 * u;
+                if (kk < len) {
+                    acc1 += m[u].x * xs[0][kk];
+                    if (NRHS == 2) acc2 += m[u].x * xs[NRHS - 1][kk];
                 }
+                if (kk + 1 < len) {
+                    acc1 += m[u].y * xs[0][kk + 1];
+                    if (NRHS == 2) acc2 += m[u].y * xs[NRHS - 1][kk + 1];
+                }
+            }
         }
         acc1 = wave_sum(acc1);
         if (NRHS == 2) acc2 = wave_sum(acc2);
